@@ -1,0 +1,294 @@
+"""CPU oracle for the population-annealing hot path (Python side).
+
+TEST INFRASTRUCTURE ONLY: only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this module.  It drives ``pa_oracle.c`` (plain C:
+Philox, the deterministic exponential, initial sampling, Metropolis sweeps,
+Q and the resampling counts) and adds the plain population averages of
+step 4 of the algorithm (Sec. 2), the family statistics of Eq. (6), the
+sampling variance of Eq. (5) and the free energy of Eq. (7).
+
+The step cycle follows the enumerated algorithm of Sec. 2: ``reweight`` to the
+next inverse temperature (step 2, Q of Eq. (1)), ``resample`` (step 2, Sec. 3),
+``sweep`` (step 3), ``observables`` (step 4).
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+MULTINOMIAL, POISSON, NEAREST_INT, SYSTEMATIC = 0, 1, 2, 3
+SCHEMES = {"multinomial": MULTINOMIAL, "poisson": POISSON, "nearest": NEAREST_INT,
+           "systematic": SYSTEMATIC}
+FIXED_SIZE = (MULTINOMIAL, SYSTEMATIC)
+
+_i8p = np.ctypeslib.ndpointer(dtype=np.int8, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+_c = ctypes
+
+
+def lib():
+    """Load (building first if needed) the oracle's C library."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_build.LIB) or (
+                os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC)):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        L.orc_philox.argtypes = [_c.c_uint32, _c.c_uint32, _u32p, _u32p]
+        L.orc_philox.restype = None
+        L.orc_exp.argtypes = [_c.c_double]
+        L.orc_exp.restype = _c.c_double
+        L.orc_threshold.argtypes = [_c.c_double, _c.c_int]
+        L.orc_threshold.restype = _c.c_uint64
+        L.orc_energy.argtypes = [_c.c_int, _c.c_int, _i8p, _i8p]
+        L.orc_energy.restype = _c.c_int64
+        L.orc_init.argtypes = [_c.c_int, _c.c_int, _c.c_int64, _i64p, _c.c_uint32, _c.c_uint32,
+                               _i8p, _i8p, _i32p, _u32p]
+        L.orc_init.restype = None
+        L.orc_sweep.argtypes = [_c.c_int, _c.c_int, _i8p, _c.c_int64, _i64p, _i8p, _i32p,
+                                _c.c_uint32, _c.c_uint32, _c.c_uint32, _c.c_uint32, _c.c_int32,
+                                _c.c_double]
+        L.orc_sweep.restype = None
+        L.orc_reweight.argtypes = [_c.c_int64, _i32p, _c.c_double, _c.POINTER(_c.c_double), _u64p,
+                                   _c.POINTER(_c.c_uint64)]
+        L.orc_reweight.restype = None
+        L.orc_counts.argtypes = [_c.c_int, _c.c_int64, _c.c_int64, _u64p, _c.c_uint64, _c.c_uint32,
+                                 _c.c_uint32, _c.c_uint32, _u32p]
+        L.orc_counts.restype = _c.c_int
+        L.orc_apply.argtypes = [_c.c_int64, _c.c_int64, _u32p, _i8p, _i32p, _u32p, _i8p, _i32p,
+                                _u32p]
+        L.orc_apply.restype = None
+        _LIB = L
+    return _LIB
+
+
+# --------------------------------------------------------------------------- primitives
+def philox(k0, k1, ctr):
+    """Philox4x32-10 of a 4-word counter under key (k0, k1)."""
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox(k0 & 0xFFFFFFFF, k1 & 0xFFFFFFFF, np.asarray(ctr, np.uint32), out)
+    return out
+
+
+def pa_exp(x):
+    """Deterministic exp used wherever exp() decides something."""
+    return lib().orc_exp(float(x))
+
+
+def threshold(beta, dE):
+    """Metropolis acceptance threshold T(dE) = min(2^32, floor(2^32 pa_exp(-beta dE)))."""
+    return int(lib().orc_threshold(float(beta), int(dE)))
+
+
+def n_sites(d, L):
+    return L ** d
+
+
+def ferromagnet(d, L):
+    """Couplings J = +1 on every bond, layout J[s*d + mu]."""
+    return np.ones(n_sites(d, L) * d, np.int8)
+
+
+def energy(d, L, J, spins):
+    """H of Eq. (4) (with bond-wise J) for one replica's int8 spins."""
+    return int(lib().orc_energy(d, L, np.ascontiguousarray(J, np.int8),
+                                np.ascontiguousarray(spins, np.int8)))
+
+
+def init_rows(d, L, rows, seed, run_id, J):
+    """Exact beta_0 = 0 samples for the replicas listed in ``rows``."""
+    rows = np.ascontiguousarray(rows, np.int64)
+    N = n_sites(d, L)
+    spins = np.zeros((len(rows), N), np.int8)
+    E = np.zeros(len(rows), np.int32)
+    label = np.zeros(len(rows), np.uint32)
+    lib().orc_init(d, L, len(rows), rows, seed, run_id, np.ascontiguousarray(J, np.int8), spins, E,
+                   label)
+    return spins, E, label
+
+
+def sweep_rows(d, L, J, rows, spins, E, seed, run_id, step, t0, theta, beta):
+    """theta Metropolis sweeps (in place) of the replicas listed in ``rows``."""
+    rows = np.ascontiguousarray(rows, np.int64)
+    assert np.all(np.diff(rows) > 0) if len(rows) > 1 else True
+    assert spins.dtype == np.int8 and spins.flags.c_contiguous and E.dtype == np.int32
+    lib().orc_sweep(d, L, np.ascontiguousarray(J, np.int8), len(rows), rows, spins, E, seed,
+                    run_id, step, t0, theta, float(beta))
+
+
+def reweight(E, dbeta):
+    """ln Q of Eq. (1), the integer weights W_j and their sum S."""
+    E = np.ascontiguousarray(E, np.int32)
+    W = np.zeros(len(E), np.uint64)
+    lnQ = ctypes.c_double()
+    S = ctypes.c_uint64()
+    lib().orc_reweight(len(E), E, float(dbeta), ctypes.byref(lnQ), W, ctypes.byref(S))
+    return lnQ.value, W, S.value
+
+
+def counts(scheme, W, S, R_target, seed, run_id, step):
+    """Copy numbers r_j of one resampling step (Sec. 3)."""
+    W = np.ascontiguousarray(W, np.uint64)
+    r = np.zeros(len(W), np.uint32)
+    rc = lib().orc_counts(scheme, len(W), R_target, W, S, seed, run_id, step, r)
+    if rc != 0:
+        raise ValueError("orc_counts rejected its arguments")
+    return r
+
+
+def apply_counts(N, r, spins, E, label):
+    """New population: r_j copies of replica j, in ascending j."""
+    Rn = int(r.sum(dtype=np.int64))
+    so = np.zeros((Rn, N), np.int8)
+    eo = np.zeros(Rn, np.int32)
+    lo = np.zeros(Rn, np.uint32)
+    lib().orc_apply(N, len(r), np.ascontiguousarray(r, np.uint32), spins, E, label, so, eo, lo)
+    return so, eo, lo
+
+
+def tau_hat(W, S, R_target):
+    """tauhat_j = R W_j / S as doubles (Eq. (3) with the quantised weights)."""
+    return (W.astype(np.float64) / float(S)) * float(R_target)
+
+
+# --------------------------------------------------------------------------- one PA run
+class PAError(Exception):
+    pass
+
+
+class CapacityError(PAError):
+    pass
+
+
+class ExtinctError(PAError):
+    pass
+
+
+class OracleRun:
+    """One population-annealing run, step by step (Sec. 2).
+
+    State: replicas' int8 spins (row = replica), energies, family labels, the
+    current inverse temperature, the step index i, the sweep counter t within
+    the step and ln Z_hat = ln Z_0 + sum_k ln Q_k (Eq. (7)).
+    """
+
+    def __init__(self, d, L, R, seed=1, run_id=0, J=None, capacity=None):
+        if d not in (2, 3) or L < 2 or L % 2 or R < 1:
+            raise ValueError("need d in {2,3}, even L >= 2, R >= 1")
+        self.d, self.L, self.R = d, L, int(R)
+        self.N = n_sites(d, L)
+        self.seed, self.run_id = seed, run_id
+        self.J = ferromagnet(d, L) if J is None else np.ascontiguousarray(J, np.int8)
+        self.capacity = int(capacity) if capacity is not None else default_capacity(R)
+        self.spins, self.E, self.label = init_rows(d, L, np.arange(R), seed, run_id, self.J)
+        self.beta = 0.0
+        self.step = 0
+        self.t = 0
+        self.R0 = int(R)
+        # ln Z_0 at beta_0 = 0 is N ln 2 (2^N states)
+        self.lnZ = float(self.N) * math.log(2.0)
+        self.pending = None
+        self.last_sv = 0.0
+        self.last_counts = None
+
+    @property
+    def Rcur(self):
+        return len(self.E)
+
+    def import_state(self, spins, E, label):
+        self.spins = np.ascontiguousarray(spins, np.int8).copy()
+        self.E = np.ascontiguousarray(E, np.int32).copy()
+        self.label = np.ascontiguousarray(label, np.uint32).copy()
+
+    def reweight(self, beta_next):
+        if beta_next < self.beta:
+            raise ValueError("beta must not decrease")
+        dbeta = float(beta_next) - self.beta
+        lnQ, W, S = reweight(self.E, dbeta)
+        self.pending = dict(beta=float(beta_next), lnQ=lnQ, W=W, S=S)
+        return lnQ
+
+    def resample(self, scheme):
+        if self.pending is None:
+            raise PAError("resample before reweight")
+        p = self.pending
+        step = self.step + 1
+        r = counts(scheme, p["W"], p["S"], self.R, self.seed, self.run_id, step)
+        Rn = int(r.sum(dtype=np.int64))
+        if Rn > self.capacity:
+            raise CapacityError(Rn)
+        if Rn == 0:
+            raise ExtinctError()
+        tau = tau_hat(p["W"], p["S"], self.R)
+        self.last_sv = float(np.mean((r.astype(np.float64) - tau) ** 2))
+        self.last_counts = r
+        self.spins, self.E, self.label = apply_counts(self.N, r, self.spins, self.E, self.label)
+        self.lnZ += p["lnQ"]
+        self.beta = p["beta"]
+        self.step = step
+        self.t = 0
+        self.pending = None
+        return Rn
+
+    def sweep(self, theta):
+        sweep_rows(self.d, self.L, self.J, np.arange(self.Rcur), self.spins, self.E, self.seed,
+                   self.run_id, self.step, self.t, theta, self.beta)
+        self.t += theta
+
+    def magnetization(self):
+        return self.spins.astype(np.int64).sum(axis=1)
+
+    def observables(self):
+        return population_observables(self.N, self.E, self.magnetization(), self.label, self.R0,
+                                      self.last_sv)
+
+    def free_energy(self):
+        """ln Z_hat = -beta_i F_hat_i, Eq. (7)."""
+        return self.lnZ
+
+
+def default_capacity(R):
+    """R + 8 ceil(sqrt R) + 64, rounded up to a multiple of 64 (fluctuations ~ sqrt R, Sec. 3)."""
+    R = int(R)
+    ceil_sqrt = math.isqrt(R - 1) + 1
+    c = R + 8 * ceil_sqrt + 64
+    return (c + 63) // 64 * 64
+
+
+def population_observables(N, E, M, label, R0, sv):
+    """Plain population averages (step 4 of Sec. 2) and the family statistics.
+
+    Exact integer sums, then: e = <E>/N, e2 = <E^2>/N^2, |m|, m^2, the family
+    measure rho_t = R sum_k n_k^2 of Eq. (6) with n_k = c_k / R (so
+    rho_t = sum_k c_k^2 / R), the family entropy S_f = -sum_k n_k ln n_k and
+    the sampling variance of the last resampling, Eq. (5).
+    """
+    R = len(E)
+    E = np.asarray(E, np.int64)
+    M = np.asarray(M, np.int64)
+    sumE = int(E.sum())
+    sumE2 = int((E * E).sum())
+    sumAbsM = int(np.abs(M).sum())
+    sumM2 = int((M * M).sum())
+    c = np.bincount(np.asarray(label, np.int64), minlength=R0).astype(np.int64)
+    sumC2 = int((c * c).sum())
+    cpos = c[c > 0].astype(np.float64)
+    rho_t = sumC2 / R
+    S_f = math.log(R) - float(np.sum(cpos * np.log(cpos))) / R
+    Ef = E.astype(np.float64)
+    mean = sumE / R
+    var = sumE2 / R - mean * mean
+    m3 = float(np.mean((Ef - mean) ** 3))
+    skew = m3 / var ** 1.5 if var > 0 else 0.0
+    return dict(R=R, sumE=sumE, sumE2=sumE2, sumAbsM=sumAbsM, sumM2=sumM2, sumC2=sumC2,
+                families=int((c > 0).sum()), e=sumE / (N * R), e2=sumE2 / (N * N * R),
+                abs_m=sumAbsM / (N * R), m2=sumM2 / (N * N * R), rho_t=rho_t, S_f=S_f, sv=sv,
+                E_mean=mean, E_var=var, E_skew=skew)
