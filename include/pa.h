@@ -1,0 +1,175 @@
+/*
+ * pa.h -- C ABI of the population-annealing (PA) hot path on MI355X (gfx950).
+ *
+ * The calls follow the enumerated algorithm of Sec. 2 of "Optimized population
+ * Monte Carlo" (Ebert, Gessert, Janke, Weigel):
+ *
+ *   pa_init        step 1: R replicas drawn exactly at beta_0 = 0
+ *   pa_reweight    step 2: Q(beta_{i-1}, beta_i) of Eq. (1) for the next beta
+ *   pa_resample    step 2 + Sec. 3: copy numbers with <r_j> = tau_j (Eq. (3))
+ *                  and the new population; beta_i becomes current
+ *   pa_sweep       step 3: theta Metropolis sweeps at the current beta
+ *   pa_observables step 4: plain population averages, family statistics
+ *                  (Eq. (6)) and the sampling variance (Eq. (5))
+ *   pa_free_energy ln Z_hat = ln Z_{beta_0} + sum_k ln Q_k, Eq. (7)
+ *
+ * Conventions (every call):
+ *  - The return value is a pa_status; nothing aborts or throws across the ABI.
+ *    On any status other than PA_OK, pa_last_error(ctx) holds a message.
+ *  - Arguments are checked before any launch.  A failed call leaves the run's
+ *    state as it was (PA_E_CAPACITY and PA_E_EXTINCT included).
+ *  - Device memory is owned by the caller: pa_init receives one device buffer
+ *    of pa_required_bytes() bytes and a hipStream_t; every kernel of the run
+ *    goes to that stream.  The context owns only host memory (pa_destroy).
+ *  - A context is not thread-safe; distinct contexts may run concurrently on
+ *    distinct streams.  Calls that return results to the host (pa_reweight,
+ *    pa_resample, pa_observables, pa_free_energy, pa_export_state) synchronise
+ *    the stream; pa_sweep only enqueues.
+ *
+ * Spin layout in device memory (and in pa_host_state): replica r = 64 w + b is
+ * bit b of word [w][s] (uint64, site-minor: word index w * N + s).  Bit 1 means
+ * sigma = -1.  Sites s = x + L y + L^2 z of the periodic hypercubic lattice.
+ */
+#ifndef PA_H
+#define PA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PA_OK = 0,
+    PA_E_INVAL = 1,     /* bad argument (shape, range, NULL, too small a buffer) */
+    PA_E_NOMEM = 2,     /* host allocation failed */
+    PA_E_STATE = 3,     /* call out of order, e.g. pa_resample before pa_reweight */
+    PA_E_CAPACITY = 4,  /* resampled population would exceed the capacity */
+    PA_E_EXTINCT = 5,   /* resampled population would be empty */
+    PA_E_NONFINITE = 6, /* ln Q is not finite */
+    PA_E_DEVICE = 7     /* a HIP call failed; the run should be destroyed */
+} pa_status;
+
+/* Sec. 3: the four schemes.  Multinomial and systematic keep R fixed (Fig. 2);
+ * Poisson and nearest integer let it fluctuate around the target R. */
+typedef enum {
+    PA_RS_MULTINOMIAL = 0,
+    PA_RS_POISSON = 1,
+    PA_RS_NEAREST_INT = 2,
+    PA_RS_SYSTEMATIC = 3
+} pa_resampler;
+
+typedef struct {
+    int32_t dim;       /* 2 or 3 */
+    int32_t L;         /* even, >= 2; N = L^dim <= 16384 */
+    int64_t R;         /* target population size, >= 1 */
+    int64_t capacity;  /* max replicas after a resampling (>= R, < 2^24);
+                          0 = R + 8 ceil(sqrt R) + 64 rounded up to 64 */
+    uint32_t seed;     /* Philox key word 0 */
+    uint32_t run_id;   /* Philox key word 1: independent runs differ here */
+    /* Bond couplings J(s, mu) in {+1, -1} of H = -sum J sigma_s sigma_{s+e_mu}
+       (Eq. (4); a +-J Edwards-Anderson sample when random), host memory,
+       int8[N * dim] at index s * dim + mu.  NULL = ferromagnet (all +1).
+       Copied during pa_init; the caller keeps ownership. */
+    const int8_t *couplings;
+} pa_config;
+
+/* Population averages after the latest step (Sec. 2, step 4). */
+typedef struct {
+    int64_t R;            /* replicas in the population, R_i */
+    double beta;          /* current inverse temperature */
+    int64_t sum_E;        /* exact sums over replicas */
+    int64_t sum_E2;
+    int64_t sum_absM;     /* M = sum_s sigma_s */
+    int64_t sum_M2;
+    int64_t sum_c2;       /* sum over families of (family size)^2 */
+    int64_t families;     /* families with at least one member */
+    double e, e2;         /* <E>/N, <E^2>/N^2 */
+    double abs_m, m2;     /* <|M|>/N, <M^2>/N^2 */
+    double rho_t;         /* Eq. (6): R sum_k n_k^2 = sum_k c_k^2 / R_i */
+    double S_f;           /* family entropy -sum_k n_k ln n_k */
+    double sv;            /* Eq. (5) of the latest resampling, over R_{i-1} */
+} pa_obs;
+
+/* Host copy of a run's state (pa_export_state / pa_import_state).  Array
+ * pointers may be NULL to skip them; non-NULL arrays must hold R entries
+ * (spins: ceil(R/64) * N words).  Memory is the caller's. */
+typedef struct {
+    int64_t R;
+    uint32_t step;        /* temperature index i */
+    uint32_t sweeps;      /* sweeps done at step i */
+    double beta;
+    double lnZ;
+    uint64_t *spins;
+    int32_t *energy;
+    int32_t *magnetization;
+    uint32_t *label;      /* family: index of the ancestor at beta_0 */
+} pa_host_state;
+
+typedef struct pa_ctx pa_ctx;
+
+/* Device bytes a run of this configuration needs (pa_init's workspace).
+ * PA_E_INVAL if the configuration is invalid. */
+pa_status pa_required_bytes(const pa_config *cfg, uint64_t *bytes);
+
+/* Step 1 of Sec. 2 at beta_0 = 0: exact sampling, R i.i.d. uniform spin states
+ * (replica r = 64w+b takes bit b of Philox4x32-10 with counter (s, w, 0, 1<<28)
+ * under key (seed, run_id) at site s); energies, magnetisations, family labels
+ * f_j = j; ln Z_0 = N ln 2.  workspace: device pointer, >= pa_required_bytes,
+ * 256-byte aligned.  stream: a hipStream_t (NULL = default stream). */
+pa_status pa_init(const pa_config *cfg, void *workspace, uint64_t workspace_bytes,
+                  void *stream, pa_ctx **out);
+
+/* Step 3 of Sec. 2: theta >= 0 Metropolis sweeps at the current beta (each
+ * sweep: sites with x+y+z even, then odd).  A flip raising the energy by dE is
+ * taken iff the replica's 32-bit uniform u < min(2^32, floor(2^32 exp(-beta dE))),
+ * u's bit 31-k being bit b of plane k of Philox counters
+ * (s, w, i, 2<<28 | t<<8 | q), q = k/2, t = the sweep index within step i. */
+pa_status pa_sweep(pa_ctx *ctx, int32_t theta);
+
+/* Step 2 of Sec. 2: for beta_next >= beta, ln Q of Eq. (1) over the current
+ * population, written as -dbeta E_min + ln((1/R) sum_j exp(-dbeta (E_j - E_min))).
+ * Also fixes the integer resampling weights floor(2^40 exp(-dbeta (E_j - E_min))).
+ * The population is unchanged; a second call replaces the first. */
+pa_status pa_reweight(pa_ctx *ctx, double beta_next, double *lnQ_out);
+
+/* Step 2 of Sec. 2 with a scheme of Sec. 3: copy numbers r_j with
+ * <r_j> = tauhat_j = R W_j / S (Eq. (3), R the target size), the new
+ * population (r_j copies of replica j, in ascending j; spins, energies,
+ * magnetisations and labels copied), then beta := beta_next, i := i + 1,
+ * ln Z_hat += ln Q.  Needs a pa_reweight first.  R_new_out may be NULL. */
+pa_status pa_resample(pa_ctx *ctx, pa_resampler scheme, int64_t *R_new_out);
+
+/* Step 4 of Sec. 2 over the current population. */
+pa_status pa_observables(pa_ctx *ctx, pa_obs *out);
+
+/* -beta_i F_hat_i = ln Z_{beta_0} + sum_{k<=i} ln Q_k (Eq. (7)). */
+pa_status pa_free_energy(pa_ctx *ctx, double *lnZ_out);
+
+/* Copies the state to the host (arrays optional, see pa_host_state). */
+pa_status pa_export_state(pa_ctx *ctx, pa_host_state *st);
+
+/* Replaces the population (1 <= st->R <= capacity; spins, energy,
+ * magnetization and label all required) and the scalars step, sweeps, beta,
+ * lnZ.  Energies and magnetisations are taken as given. */
+pa_status pa_import_state(pa_ctx *ctx, const pa_host_state *st);
+
+/* Overlap distribution between two runs of the same lattice: replica d of a
+ * paired with replica d of b, d < min(R_a, R_b); q = (N - 2 popcount(a ^ b)) / N.
+ * hist_out: host, int64[N + 1], entry k counts pairs with N - 2 popcount = 2k - N
+ * (i.e. k = N - popcount). */
+pa_status pa_overlap(pa_ctx *a, pa_ctx *b, int64_t *hist_out);
+
+/* Releases the context's host memory (not the caller's workspace). */
+void pa_destroy(pa_ctx *ctx);
+
+/* Message of the latest failed call on ctx (or of the latest failed pa_init
+ * when ctx is NULL).  Valid until the next call on ctx. */
+const char *pa_last_error(const pa_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PA_H */

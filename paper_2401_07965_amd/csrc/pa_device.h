@@ -1,0 +1,201 @@
+// Device-side building blocks of the population-annealing library (gfx950).
+//
+// * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), the counter-based
+//   generator every random decision of the method draws from.
+// * pa_exp: the exponential used wherever exp() decides something (Metropolis
+//   thresholds, resampling weights, Poisson probabilities): Cody-Waite
+//   reduction by ln 2 and a degree-13 Taylor polynomial in Horner form, every
+//   double operation rounded on its own (the library is built with
+//   -ffp-contract=off), so its bits are fixed by IEEE-754 alone.
+// * 128-bit helpers for the exact integer resampling arithmetic and the
+//   fixed-order wavefront reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef unsigned __int128 pa_u128;
+
+// Counter purpose codes, held in bits 31..28 of counter word 3.
+#define PA_PURPOSE_INIT 1u
+#define PA_PURPOSE_METRO 2u
+#define PA_PURPOSE_RS_NI 4u
+#define PA_PURPOSE_RS_POIS 5u
+#define PA_PURPOSE_RS_MULT 6u
+#define PA_PURPOSE_RS_SYS 7u
+
+struct pa_philox_out {
+    uint32_t x0, x1, x2, x3;
+};
+
+// Philox4x32-10: ten rounds of (x0,x1,x2,x3) -> (hi(B x2) ^ x1 ^ k0, lo(B x2),
+// hi(A x0) ^ x3 ^ k1, lo(A x0)) with A = 0xD2511F53, B = 0xCD9E8D57 and the key
+// advanced by (0x9E3779B9, 0xBB67AE85) between rounds.
+__device__ __forceinline__ pa_philox_out pa_philox(uint32_t k0, uint32_t k1, uint32_t x0,
+                                                   uint32_t x1, uint32_t x2, uint32_t x3)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * x0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+        const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        const uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        x1 = (uint32_t)p1;
+        x3 = (uint32_t)p0;
+        x0 = y0;
+        x2 = y2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return {x0, x1, x2, x3};
+}
+
+// 1/n! rounded to nearest, n = 0..13 (n! is exact in double).
+__device__ __forceinline__ double pa_inv_fact(int n)
+{
+    double f = 1.0;
+    for (int k = 2; k <= n; ++k)
+        f *= (double)k;
+    return 1.0 / f;
+}
+
+// exp(x) for x in [-700, 0]; 0 below -700 and for NaN.
+__device__ __forceinline__ double pa_exp(double x)
+{
+    if (!(x >= -700.0))
+        return 0.0;
+    const double inv_ln2 = 0x1.71547652b82fep+0; // 1/ln 2, nearest double
+    const double ln2_hi = 0x1.62e42fee00000p-1;  // ln 2 cut to 32 significant bits
+    const double ln2_lo = 0x1.a39ef35793c76p-33; // ln 2 - ln2_hi, nearest double
+    const double k = rint(x * inv_ln2);
+    const double r = (x - k * ln2_hi) - k * ln2_lo;
+    constexpr double c2 = 1.0 / 2.0, c3 = 1.0 / 6.0, c4 = 1.0 / 24.0, c5 = 1.0 / 120.0,
+                     c6 = 1.0 / 720.0, c7 = 1.0 / 5040.0, c8 = 1.0 / 40320.0,
+                     c9 = 1.0 / 362880.0, c10 = 1.0 / 3628800.0, c11 = 1.0 / 39916800.0,
+                     c12 = 1.0 / 479001600.0, c13 = 1.0 / 6227020800.0;
+    double p = c13;
+    p = p * r + c12;
+    p = p * r + c11;
+    p = p * r + c10;
+    p = p * r + c9;
+    p = p * r + c8;
+    p = p * r + c7;
+    p = p * r + c6;
+    p = p * r + c5;
+    p = p * r + c4;
+    p = p * r + c3;
+    p = p * r + c2;
+    p = p * r + 1.0;
+    p = p * r + 1.0;
+    return ldexp(p, (int)k);
+}
+
+// Metropolis threshold T(dE) = min(2^32, floor(2^32 pa_exp(-beta dE))): a move
+// that raises the energy by dE is taken iff the replica's 32-bit uniform u < T.
+__device__ __forceinline__ uint64_t pa_threshold(double beta, int dE)
+{
+    const double p = pa_exp(-(beta * (double)dE));
+    uint64_t T = (uint64_t)floor(ldexp(p, 32));
+    return T > (1ull << 32) ? (1ull << 32) : T;
+}
+
+// Integer resampling weight of an energy gap g = E - E_min >= 0:
+// floor(2^40 pa_exp(-dbeta g)), at most 2^40.
+__device__ __forceinline__ uint64_t pa_weight(double dbeta, int32_t gap)
+{
+    return (uint64_t)floor(ldexp(pa_exp(-(dbeta * (double)gap)), 40));
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ uint64_t pa_shfl_xor_u64(uint64_t v, int m)
+{
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ double pa_shfl_xor_f64(double v, int m)
+{
+    return __longlong_as_double((long long)pa_shfl_xor_u64((uint64_t)__double_as_longlong(v), m));
+}
+
+// Butterfly sum over the 64 lanes of a wavefront: the same pairing in every
+// call, so a double result is the same bits on every run.
+__device__ __forceinline__ double pa_wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        v = v + pa_shfl_xor_f64(v, m);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t pa_wave_sum_u64(uint64_t v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        v += pa_shfl_xor_u64(v, m);
+    return v;
+}
+
+__device__ __forceinline__ int64_t pa_wave_min_i64(int64_t v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const int64_t o = (int64_t)pa_shfl_xor_u64((uint64_t)v, m);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int64_t pa_wave_max_i64(int64_t v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const int64_t o = (int64_t)pa_shfl_xor_u64((uint64_t)v, m);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Block-wide fixed-order double sum (blockDim.x a multiple of 64, <= 1024):
+// wave butterflies, then the wave totals in wave order.  Every thread gets it.
+__device__ __forceinline__ double pa_block_sum_f64(double v, double *lds /* >= 16 */)
+{
+    v = pa_wave_sum_f64(v);
+    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        lds[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < nwaves; ++k)
+        t = t + lds[k];
+    __syncthreads();
+    return t;
+}
+
+__device__ __forceinline__ uint64_t pa_block_sum_u64(uint64_t v, uint64_t *lds /* >= 16 */)
+{
+    v = pa_wave_sum_u64(v);
+    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        lds[wave] = v;
+    __syncthreads();
+    uint64_t t = 0;
+    for (int k = 0; k < nwaves; ++k)
+        t += lds[k];
+    __syncthreads();
+    return t;
+}
+
+// ---------------------------------------------------------------- agent-scope flags
+__device__ __forceinline__ void pa_store_release(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t pa_load_acquire(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}

@@ -1,0 +1,262 @@
+"""Python binding of the population-annealing C ABI (include/pa.h).
+
+Argument marshalling only: every step runs in the HIP library ``libpa.so``
+built beside this file.  PyTorch provides the device workspace and the HIP
+stream.  There is no fallback: without the built library every call raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpa.so")
+
+PA_OK, PA_E_INVAL, PA_E_NOMEM, PA_E_STATE, PA_E_CAPACITY, PA_E_EXTINCT, PA_E_NONFINITE, \
+    PA_E_DEVICE = range(8)
+MULTINOMIAL, POISSON, NEAREST_INT, SYSTEMATIC = 0, 1, 2, 3
+SCHEMES = {"multinomial": MULTINOMIAL, "poisson": POISSON, "nearest": NEAREST_INT,
+           "systematic": SYSTEMATIC}
+
+
+class pa_config(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("L", ctypes.c_int32), ("R", ctypes.c_int64),
+                ("capacity", ctypes.c_int64), ("seed", ctypes.c_uint32),
+                ("run_id", ctypes.c_uint32), ("couplings", ctypes.c_void_p)]
+
+
+class pa_obs(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_int64), ("beta", ctypes.c_double), ("sum_E", ctypes.c_int64),
+                ("sum_E2", ctypes.c_int64), ("sum_absM", ctypes.c_int64),
+                ("sum_M2", ctypes.c_int64), ("sum_c2", ctypes.c_int64),
+                ("families", ctypes.c_int64), ("e", ctypes.c_double), ("e2", ctypes.c_double),
+                ("abs_m", ctypes.c_double), ("m2", ctypes.c_double), ("rho_t", ctypes.c_double),
+                ("S_f", ctypes.c_double), ("sv", ctypes.c_double)]
+
+
+class pa_host_state(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_int64), ("step", ctypes.c_uint32), ("sweeps", ctypes.c_uint32),
+                ("beta", ctypes.c_double), ("lnZ", ctypes.c_double),
+                ("spins", ctypes.c_void_p), ("energy", ctypes.c_void_p),
+                ("magnetization", ctypes.c_void_p), ("label", ctypes.c_void_p)]
+
+
+class PAError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+class CapacityError(PAError):
+    pass
+
+
+class ExtinctError(PAError):
+    pass
+
+
+class StateError(PAError):
+    pass
+
+
+_ERRORS = {PA_E_CAPACITY: CapacityError, PA_E_EXTINCT: ExtinctError, PA_E_STATE: StateError}
+_lib = None
+
+
+def lib():
+    """The loaded HIP library; raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
+                               "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        v = ctypes.c_void_p
+        L.pa_required_bytes.argtypes = [P(pa_config), P(ctypes.c_uint64)]
+        L.pa_init.argtypes = [P(pa_config), v, ctypes.c_uint64, v, P(v)]
+        L.pa_sweep.argtypes = [v, ctypes.c_int32]
+        L.pa_reweight.argtypes = [v, ctypes.c_double, P(ctypes.c_double)]
+        L.pa_resample.argtypes = [v, ctypes.c_int, P(ctypes.c_int64)]
+        L.pa_observables.argtypes = [v, P(pa_obs)]
+        L.pa_free_energy.argtypes = [v, P(ctypes.c_double)]
+        L.pa_export_state.argtypes = [v, P(pa_host_state)]
+        L.pa_import_state.argtypes = [v, P(pa_host_state)]
+        L.pa_overlap.argtypes = [v, v, v]
+        L.pa_destroy.argtypes = [v]
+        L.pa_destroy.restype = None
+        L.pa_last_error.argtypes = [v]
+        L.pa_last_error.restype = ctypes.c_char_p
+        for name in ("pa_required_bytes", "pa_init", "pa_sweep", "pa_reweight", "pa_resample",
+                     "pa_observables", "pa_free_energy", "pa_export_state", "pa_import_state",
+                     "pa_overlap"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status, ctx):
+    if status != PA_OK:
+        msg = lib().pa_last_error(ctx)
+        raise _ERRORS.get(status, PAError)(status, msg.decode() if msg else "")
+
+
+def make_config(dim, L, R, seed=1, run_id=0, capacity=0, couplings=None):
+    """A pa_config; ``couplings`` (int8[N*dim] or None) must outlive pa_init."""
+    cfg = pa_config(dim, L, int(R), int(capacity), seed & 0xFFFFFFFF, run_id & 0xFFFFFFFF, None)
+    if couplings is not None:
+        assert couplings.dtype == np.int8 and couplings.flags.c_contiguous
+        cfg.couplings = couplings.ctypes.data
+    return cfg
+
+
+def pa_required_bytes(cfg):
+    n = ctypes.c_uint64()
+    _check(lib().pa_required_bytes(ctypes.byref(cfg), ctypes.byref(n)), None)
+    return n.value
+
+
+def pa_init(cfg, workspace_ptr, workspace_bytes, stream_ptr):
+    ctx = ctypes.c_void_p()
+    _check(lib().pa_init(ctypes.byref(cfg), workspace_ptr, workspace_bytes, stream_ptr,
+                         ctypes.byref(ctx)), None)
+    return ctx
+
+
+def pa_sweep(ctx, theta):
+    _check(lib().pa_sweep(ctx, int(theta)), ctx)
+
+
+def pa_reweight(ctx, beta_next):
+    q = ctypes.c_double()
+    _check(lib().pa_reweight(ctx, float(beta_next), ctypes.byref(q)), ctx)
+    return q.value
+
+
+def pa_resample(ctx, scheme):
+    n = ctypes.c_int64()
+    _check(lib().pa_resample(ctx, int(scheme), ctypes.byref(n)), ctx)
+    return n.value
+
+
+def pa_observables(ctx):
+    o = pa_obs()
+    _check(lib().pa_observables(ctx, ctypes.byref(o)), ctx)
+    return {name: getattr(o, name) for name, _ in pa_obs._fields_}
+
+
+def pa_free_energy(ctx):
+    z = ctypes.c_double()
+    _check(lib().pa_free_energy(ctx, ctypes.byref(z)), ctx)
+    return z.value
+
+
+def pa_export_state(ctx, N, arrays=True):
+    st = pa_host_state()
+    _check(lib().pa_export_state(ctx, ctypes.byref(st)), ctx)
+    out = dict(R=st.R, step=st.step, sweeps=st.sweeps, beta=st.beta, lnZ=st.lnZ)
+    if arrays:
+        R = st.R
+        spins = np.zeros(((R + 63) // 64, N), np.uint64)
+        E = np.zeros(R, np.int32)
+        M = np.zeros(R, np.int32)
+        lab = np.zeros(R, np.uint32)
+        st.spins, st.energy = spins.ctypes.data, E.ctypes.data
+        st.magnetization, st.label = M.ctypes.data, lab.ctypes.data
+        _check(lib().pa_export_state(ctx, ctypes.byref(st)), ctx)
+        out.update(spins=spins, energy=E, magnetization=M, label=lab)
+    return out
+
+
+def pa_import_state(ctx, R, step, sweeps, beta, lnZ, spins, energy, magnetization, label):
+    spins = np.ascontiguousarray(spins, np.uint64)
+    energy = np.ascontiguousarray(energy, np.int32)
+    magnetization = np.ascontiguousarray(magnetization, np.int32)
+    label = np.ascontiguousarray(label, np.uint32)
+    st = pa_host_state(int(R), int(step), int(sweeps), float(beta), float(lnZ), spins.ctypes.data,
+                       energy.ctypes.data, magnetization.ctypes.data, label.ctypes.data)
+    _check(lib().pa_import_state(ctx, ctypes.byref(st)), ctx)
+
+
+def pa_overlap(a, b, N):
+    h = np.zeros(N + 1, np.int64)
+    _check(lib().pa_overlap(a, b, h.ctypes.data), a)
+    return h
+
+
+def pa_destroy(ctx):
+    lib().pa_destroy(ctx)
+
+
+# ------------------------------------------------------------------ conveniences
+def unpack_spins(words, R):
+    """[W][N] uint64 words -> int8 spins [R][N] (+1/-1), replica 64w+b = bit b."""
+    W, N = words.shape
+    bits = np.unpackbits(np.ascontiguousarray(words).view(np.uint8).reshape(W, N, 8),
+                         axis=2, bitorder="little")  # [W, N, 64]
+    bits = bits.transpose(0, 2, 1).reshape(W * 64, N)[:R]
+    return (1 - 2 * bits.astype(np.int8)).astype(np.int8)
+
+
+def pack_spins(spins):
+    """int8 spins [R][N] (+1/-1) -> [ceil(R/64)][N] uint64 words."""
+    R, N = spins.shape
+    W = (R + 63) // 64
+    bits = np.zeros((W * 64, N), np.uint8)
+    bits[:R] = (spins < 0)
+    by = np.packbits(bits.reshape(W, 64, N).transpose(0, 2, 1), axis=2, bitorder="little")
+    return np.ascontiguousarray(by).view(np.uint64).reshape(W, N)
+
+
+class PARun:
+    """One PA run on the GPU: a torch-owned workspace, a stream and a context."""
+
+    def __init__(self, dim, L, R, seed=1, run_id=0, capacity=0, couplings=None, device=None,
+                 stream=None):
+        import torch
+        self.dim, self.L, self.R = dim, L, int(R)
+        self.N = L ** dim
+        self.couplings = None if couplings is None else np.ascontiguousarray(couplings, np.int8)
+        cfg = make_config(dim, L, R, seed, run_id, capacity, self.couplings)
+        nbytes = pa_required_bytes(cfg)
+        self.device = torch.device("cuda", 0) if device is None else torch.device(device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if self.workspace.data_ptr() % 256:
+            raise RuntimeError("workspace not 256-byte aligned")
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        self.ctx = pa_init(cfg, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
+
+    def reweight(self, beta_next):
+        return pa_reweight(self.ctx, beta_next)
+
+    def resample(self, scheme):
+        return pa_resample(self.ctx, SCHEMES.get(scheme, scheme))
+
+    def sweep(self, theta):
+        pa_sweep(self.ctx, theta)
+
+    def observables(self):
+        return pa_observables(self.ctx)
+
+    def free_energy(self):
+        return pa_free_energy(self.ctx)
+
+    def export(self, arrays=True):
+        return pa_export_state(self.ctx, self.N, arrays)
+
+    def import_state(self, **kw):
+        pa_import_state(self.ctx, **kw)
+
+    def overlap(self, other):
+        return pa_overlap(self.ctx, other.ctx, self.N)
+
+    def close(self):
+        if self.ctx is not None:
+            pa_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,118 @@
+"""Helpers shared by the GPU parity tests: run the HIP library and the oracle
+side by side on the same seeded inputs and compare them."""
+import math
+
+import numpy as np
+
+from oracle import oracle as O
+
+REL = 1e-10  # ln Q, ln Z_hat and the finalised averages (relative error)
+
+
+def rel_ok(a, b, tol=REL):
+    if a == b:
+        return True
+    return abs(a - b) <= tol * max(abs(a), abs(b))
+
+
+def rows_from_words(words, rows):
+    """int8 spins of the replicas ``rows`` from [W][N] uint64 words."""
+    rows = np.asarray(rows, np.int64)
+    w = words[rows >> 6]
+    bits = (w >> (rows & 63).astype(np.uint64)[:, None]) & np.uint64(1)
+    return (1 - 2 * bits.astype(np.int8)).astype(np.int8)
+
+
+def compare_state(g, o, where=""):
+    from paper_2401_07965_amd import pa
+    st = g.export()
+    assert st["R"] == o.Rcur, where
+    spins = pa.unpack_spins(st["spins"], st["R"])
+    assert np.array_equal(spins, o.spins), f"spins differ {where}"
+    assert np.array_equal(st["energy"], o.E), f"energies differ {where}"
+    assert np.array_equal(st["magnetization"], o.magnetization().astype(np.int32)), where
+    assert np.array_equal(st["label"], o.label), f"labels differ {where}"
+    assert rel_ok(st["lnZ"], o.free_energy()), (st["lnZ"], o.free_energy(), where)
+    return st
+
+
+def compare_observables(g, o, where=""):
+    a = g.observables()
+    b = o.observables()
+    assert a["R"] == b["R"], where
+    assert a["sum_E"] == b["sumE"] and a["sum_E2"] == b["sumE2"], where
+    assert a["sum_absM"] == b["sumAbsM"] and a["sum_M2"] == b["sumM2"], where
+    assert a["sum_c2"] == b["sumC2"] and a["families"] == b["families"], where
+    for k in ("e", "e2", "abs_m", "m2", "rho_t", "S_f"):
+        assert rel_ok(a[k], b[k]), (k, a[k], b[k], where)
+    assert rel_ok(a["sv"], b["sv"], 1e-9) or abs(a["sv"] - b["sv"]) < 1e-14, (a["sv"], b["sv"])
+    return a
+
+
+def run_pair(d, L, R, scheme, betas, theta, seed=1, run_id=0, J=None, capacity=None,
+             check_every=1, observables=True):
+    """Anneal on the GPU and in the oracle in lock step; compare as it goes."""
+    from paper_2401_07965_amd import pa
+    cap = capacity if capacity else O.default_capacity(R)
+    print(f"[parity] d={d} L={L} R={R} scheme={scheme} steps={len(betas) - 1} theta={theta}",
+          flush=True)
+    g = pa.PARun(d, L, R, seed=seed, run_id=run_id, capacity=cap, couplings=J)
+    o = O.OracleRun(d, L, R, seed=seed, run_id=run_id, J=J, capacity=cap)
+    try:
+        compare_state(g, o, "init")
+        if observables:
+            compare_observables(g, o, "init")
+        for i, b in enumerate(betas[1:], 1):
+            qg, qo = g.reweight(b), o.reweight(b)
+            assert rel_ok(qg, qo), (i, qg, qo)
+            rg, ro = g.resample(scheme), o.resample(scheme)
+            assert rg == ro, (i, rg, ro)
+            g.sweep(theta)
+            o.sweep(theta)
+            if i % check_every == 0 or i == len(betas) - 1:
+                compare_state(g, o, f"step {i}")
+                if observables:
+                    compare_observables(g, o, f"step {i}")
+        return g, o
+    except Exception:
+        g.close()
+        raise
+
+
+def schedule(beta_f, points):
+    return [i * beta_f / (points - 1) for i in range(points)]
+
+
+def ea_couplings(d, L, seed):
+    rng = np.random.default_rng(seed)
+    return np.where(rng.random(L ** d * d) < 0.5, -1, 1).astype(np.int8)
+
+
+def sampled_step(g, d, L, J, scheme, beta_next, theta, rows, seed, run_id, R_target):
+    """One GPU step checked on sampled replicas: the oracle redoes reweight and
+    the copy numbers over the whole exported population, then sweeps only the
+    sampled destination rows."""
+    st0 = g.export()
+    N = L ** d
+    Jo = O.ferromagnet(d, L) if J is None else J
+    lnq_g = g.reweight(beta_next)
+    rn_g = g.resample(scheme)
+    g.sweep(theta)
+    st1 = g.export()
+    dbeta = float(beta_next) - st0["beta"]
+    lnq_o, W, S = O.reweight(st0["energy"], dbeta)
+    assert rel_ok(lnq_g, lnq_o), (lnq_g, lnq_o)
+    step = st0["step"] + 1
+    r = O.counts(scheme, W, S, R_target, seed, run_id, step)
+    assert int(r.sum()) == rn_g
+    anc = np.repeat(np.arange(len(r)), r.astype(np.int64))
+    assert np.array_equal(st1["label"], st0["label"][anc])
+    assert rel_ok(st1["lnZ"], st0["lnZ"] + lnq_o)
+    rows = np.asarray(sorted(set(int(x) for x in rows if x < rn_g)), np.int64)
+    spins = rows_from_words(st0["spins"], anc[rows])
+    E = st0["energy"][anc[rows]].copy()
+    O.sweep_rows(d, L, Jo, rows, spins, E, seed, run_id, step, 0, theta, beta_next)
+    assert np.array_equal(rows_from_words(st1["spins"], rows), spins)
+    assert np.array_equal(st1["energy"][rows], E)
+    assert np.array_equal(st1["magnetization"][rows], spins.astype(np.int64).sum(axis=1))
+    return st1

@@ -1,0 +1,67 @@
+"""CPU checks of the C ABI: the built library exports every function that
+include/pa.h declares, and the argument checks that need no GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from tests.conftest import ROOT
+
+
+@pytest.fixture(scope="module")
+def libpa():
+    from paper_2401_07965_amd import build, pa
+    if not os.path.exists(pa.LIB_PATH):
+        build.build()
+    return pa
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "pa.h")).read()
+    return re.findall(r"^(?:pa_status|void|const char \*)\s*\**\s*(pa_\w+)\s*\(", text, re.M)
+
+
+def test_header_declares_the_boundary():
+    names = set(declared_functions())
+    for n in ("pa_init", "pa_sweep", "pa_reweight", "pa_resample", "pa_observables",
+              "pa_free_energy", "pa_required_bytes", "pa_export_state", "pa_import_state",
+              "pa_overlap", "pa_destroy", "pa_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(libpa):
+    so = ctypes.CDLL(libpa.LIB_PATH)
+    for n in declared_functions():
+        assert hasattr(so, n), n
+
+
+def test_required_bytes_and_validation_without_gpu(libpa):
+    pa = libpa
+    small = pa.pa_required_bytes(pa.make_config(2, 8, 1000))
+    big = pa.pa_required_bytes(pa.make_config(2, 64, 100000))
+    assert 0 < small < big
+    # two ping-pong spin buffers of ceil(cap/64) * N words dominate
+    cap = 100000 + 8 * 317 + 64
+    cap = (cap + 63) // 64 * 64
+    assert big >= 2 * (cap // 64) * 4096 * 8
+    for bad in (dict(dim=1, L=4, R=10), dict(dim=2, L=3, R=10), dict(dim=2, L=4, R=0),
+                dict(dim=2, L=4, R=100, capacity=99), dict(dim=2, L=4, R=10, capacity=1 << 24),
+                dict(dim=3, L=26, R=10), dict(dim=2, L=0, R=1)):
+        with pytest.raises(pa.PAError) as ei:
+            pa.pa_required_bytes(pa.make_config(**bad))
+        assert ei.value.status == pa.PA_E_INVAL
+
+
+def test_spin_packing_roundtrip(libpa):
+    pa = libpa
+    rng = np.random.default_rng(0)
+    for R, N in ((1, 4), (64, 16), (65, 9), (200, 64)):
+        s = rng.choice(np.array([-1, 1], np.int8), size=(R, N))
+        w = pa.pack_spins(s)
+        assert w.shape == ((R + 63) // 64, N)
+        assert np.array_equal(pa.unpack_spins(w, R), s)
+        # replica r is bit r % 64 of word r // 64; bit 1 means sigma = -1
+        r = R - 1
+        assert ((int(w[r // 64, 0]) >> (r % 64)) & 1) == (1 if s[r, 0] < 0 else 0)

@@ -1,0 +1,215 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on the
+same seeded inputs.  Spins, energies, magnetisations, labels, population
+sizes and the exact integer sums must be bit-identical; ln Q, ln Z_hat and the
+finalised averages agree to 1e-10 relative."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from tests.paritylib import (compare_state, ea_couplings, rel_ok, run_pair, sampled_step,
+                             schedule)
+
+pytestmark = pytest.mark.gpu
+
+SCHEMES = [O.MULTINOMIAL, O.POISSON, O.NEAREST_INT, O.SYSTEMATIC]
+
+
+def test_config1_every_step():
+    """2D Ising FM, L = 8, R = 1000, beta 0 -> 1 in 101 points, theta = 10, nearest integer."""
+    g, o = run_pair(2, 8, 1000, O.NEAREST_INT, schedule(1.0, 101), 10, seed=1, run_id=0)
+    assert rel_ok(g.free_energy(), o.free_energy())
+    g.close()
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_schemes_2d_ragged(scheme):
+    g, _ = run_pair(2, 8, 300, scheme, schedule(1.2, 21), 5, seed=7, run_id=scheme)
+    g.close()
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_schemes_3d_spin_glass(scheme):
+    J = ea_couplings(3, 4, 3)
+    g, _ = run_pair(3, 4, 200, scheme, schedule(2.0, 16), 3, seed=2, run_id=10 + scheme, J=J)
+    g.close()
+
+
+@pytest.mark.parametrize("d,L,R", [(2, 6, 130), (2, 2, 70), (3, 2, 70), (2, 4, 1), (2, 4, 64),
+                                   (2, 4, 65), (3, 6, 129)])
+def test_shapes_and_edge_sizes(d, L, R):
+    J = ea_couplings(d, L, 5)
+    for scheme in (O.SYSTEMATIC, O.NEAREST_INT):
+        g, _ = run_pair(d, L, R, scheme, schedule(1.5, 9), 2, seed=3, run_id=scheme, J=J)
+        g.close()
+
+
+def test_large_steps_and_poisson_pieces():
+    # few, large steps: broad weights, tauhat > 32 for the lowest energies
+    for scheme in SCHEMES:
+        g, _ = run_pair(2, 8, 400, scheme, [0.0, 0.5, 1.5, 3.0], 2, seed=4, run_id=scheme,
+                        capacity=4096)
+        g.close()
+
+
+def test_zero_step_and_zero_sweeps():
+    from paper_2401_07965_amd import pa
+    g = pa.PARun(2, 6, 100, seed=9, capacity=256)
+    o = O.OracleRun(2, 6, 100, seed=9, capacity=256)
+    for b in (0.0, 0.0, 0.3, 0.3):
+        qg, qo = g.reweight(b), o.reweight(b)
+        assert rel_ok(qg, qo)
+        assert g.resample(O.SYSTEMATIC) == o.resample(O.SYSTEMATIC)
+        g.sweep(0)
+        compare_state(g, o)
+    g.close()
+
+
+def test_capacity_and_extinction_leave_state_unchanged():
+    from paper_2401_07965_amd import pa
+    g = pa.PARun(2, 4, 64, seed=5, capacity=64)
+    o = O.OracleRun(2, 4, 64, seed=5, capacity=64)
+    g.reweight(0.0)
+    o.reweight(0.0)
+    before = g.export()
+    raised = False
+    for step in range(30):
+        b = 0.5 * (step + 1)
+        g.reweight(b)
+        o.reweight(b)
+        try:
+            rg = g.resample(O.POISSON)
+        except pa.CapacityError:
+            with pytest.raises(O.CapacityError):
+                o.resample(O.POISSON)
+            raised = True
+            break
+        assert rg == o.resample(O.POISSON)
+        before = g.export()
+    assert raised
+    after = g.export()
+    for k in ("spins", "energy", "label", "magnetization"):
+        assert np.array_equal(before[k], after[k])
+    assert before["lnZ"] == after["lnZ"] and before["beta"] == after["beta"]
+    g.close()
+
+
+def test_call_order_and_argument_errors():
+    from paper_2401_07965_amd import pa
+    g = pa.PARun(2, 4, 10, seed=1)
+    with pytest.raises(pa.StateError):
+        g.resample(O.SYSTEMATIC)
+    g.reweight(0.5)
+    with pytest.raises(pa.PAError):
+        g.reweight(0.1)  # beta must not decrease
+    with pytest.raises(pa.PAError):
+        g.sweep(-1)
+    g.close()
+    for bad in (dict(dim=4, L=4, R=10), dict(dim=2, L=5, R=10), dict(dim=2, L=4, R=0),
+                dict(dim=2, L=4, R=100, capacity=50), dict(dim=3, L=32, R=10)):
+        with pytest.raises(pa.PAError):
+            pa.pa_required_bytes(pa.make_config(**bad))
+
+
+def test_export_import_roundtrip_continues_identically():
+    from paper_2401_07965_amd import pa
+    J = ea_couplings(2, 6, 8)
+    betas = schedule(1.0, 11)
+    g, o = run_pair(2, 6, 150, O.NEAREST_INT, betas[:6], 3, seed=6, J=J, observables=False)
+    st = g.export()
+    h = pa.PARun(2, 6, 150, seed=6, couplings=J)
+    h.import_state(R=st["R"], step=st["step"], sweeps=st["sweeps"], beta=st["beta"],
+                   lnZ=st["lnZ"], spins=st["spins"], energy=st["energy"],
+                   magnetization=st["magnetization"], label=st["label"])
+    for b in betas[6:]:
+        assert g.reweight(b) == h.reweight(b)
+        assert g.resample(O.NEAREST_INT) == h.resample(O.NEAREST_INT)
+        g.sweep(3)
+        h.sweep(3)
+    a, c = g.export(), h.export()
+    for k in ("spins", "energy", "magnetization", "label"):
+        assert np.array_equal(a[k], c[k])
+    assert a["lnZ"] == c["lnZ"]
+    # an oracle state imported into the GPU continues like the oracle
+    h.import_state(R=o.Rcur, step=o.step, sweeps=o.t, beta=o.beta, lnZ=o.free_energy(),
+                   spins=pa.pack_spins(o.spins), energy=o.E,
+                   magnetization=o.magnetization().astype(np.int32), label=o.label)
+    for b in betas[6:]:
+        assert rel_ok(h.reweight(b), o.reweight(b))
+        assert h.resample(O.SYSTEMATIC) == o.resample(O.SYSTEMATIC)
+        h.sweep(3)
+        o.sweep(3)
+    compare_state(h, o)
+    g.close()
+    h.close()
+
+
+def test_repeat_runs_are_bit_identical():
+    """Any race in the kernels would flip a bit between two identical runs."""
+    from paper_2401_07965_amd import pa
+    out = []
+    for _ in range(2):
+        g = pa.PARun(2, 16, 3000, seed=11, run_id=2)
+        for b in schedule(0.8, 9)[1:]:
+            g.reweight(b)
+            g.resample(O.MULTINOMIAL)
+            g.sweep(4)
+        out.append((g.export(), g.observables()))
+        g.close()
+    for k in ("spins", "energy", "magnetization", "label"):
+        assert np.array_equal(out[0][0][k], out[1][0][k])
+    assert out[0][0]["lnZ"] == out[1][0]["lnZ"]
+    assert out[0][1] == out[1][1]
+
+
+def test_overlap_distribution():
+    from paper_2401_07965_amd import pa
+    J = ea_couplings(3, 4, 12)
+    betas = schedule(1.0, 6)
+    ga, oa = run_pair(3, 4, 300, O.SYSTEMATIC, betas, 2, seed=1, run_id=0, J=J,
+                      observables=False)
+    gb, ob = run_pair(3, 4, 250, O.NEAREST_INT, betas, 2, seed=1, run_id=1, J=J,
+                      observables=False)
+    h = ga.overlap(gb)
+    R = min(oa.Rcur, ob.Rcur)
+    N = 64
+    same = (oa.spins[:R] == ob.spins[:R]).sum(axis=1)  # N - popcount(a ^ b)
+    ref = np.bincount(same, minlength=N + 1)
+    assert np.array_equal(h, ref)
+    ga.close()
+    gb.close()
+
+
+def test_config2_sampled_full_size():
+    """2D Ising FM, L = 64, R = 10^5, theta = 10, beta_i = 0.6 i/200: sampled steps, all schemes."""
+    from paper_2401_07965_amd import pa
+    betas = schedule(0.6, 201)
+    rng = np.random.default_rng(0)
+    for scheme in SCHEMES:
+        print(f"[parity] config 2 scheme {scheme}", flush=True)
+        g = pa.PARun(2, 64, 100000, seed=1, run_id=scheme)
+        for i in range(1, 4):
+            g.reweight(betas[i])
+            g.resample(scheme)
+            g.sweep(10)
+        rows = np.concatenate([np.arange(64), np.arange(99936, 100000),
+                               rng.integers(0, 99000, 64)])
+        sampled_step(g, 2, 64, None, scheme, betas[4], 10, rows, 1, scheme, 100000)
+        g.close()
+
+
+def test_config3_sampled_full_size():
+    """3D +-J glass, L = 10, R = 5 10^5, systematic, theta = 10, beta_i = 3 i/300: sampled step."""
+    from paper_2401_07965_amd import pa
+    J = ea_couplings(3, 10, 1)
+    betas = schedule(3.0, 301)
+    g = pa.PARun(3, 10, 500000, seed=1, run_id=0, couplings=J)
+    for i in range(1, 3):
+        g.reweight(betas[i])
+        g.resample(O.SYSTEMATIC)
+        g.sweep(10)
+    rows = np.concatenate([np.arange(64), np.arange(499900, 500000),
+                           np.random.default_rng(1).integers(0, 499000, 64)])
+    sampled_step(g, 3, 10, J, O.SYSTEMATIC, betas[3], 10, rows, 1, 0, 500000)
+    g.close()
