@@ -934,6 +934,8 @@ hipError_t pa_launch_set_beta(const PaLaunch &p, const PaDev &dv, double beta, d
     return hipGetLastError();
 }
 
+// ROCm lets a launch use dynamic LDS up to the device's per-workgroup limit
+// without a per-function attribute; only the limit is needed here.
 hipError_t pa_configure_kernels(int *max_lds)
 {
     int dev = 0, v = 0;
@@ -943,11 +945,5 @@ hipError_t pa_configure_kernels(int *max_lds)
     if (e != hipSuccess)
         return e;
     *max_lds = v;
-    if ((e = hipFuncSetAttribute((const void *)k_sweep<2>, hipFuncAttributeMaxDynamicSharedMemorySize, v)) !=
-        hipSuccess)
-        return e;
-    if ((e = hipFuncSetAttribute((const void *)k_sweep<3>, hipFuncAttributeMaxDynamicSharedMemorySize, v)) !=
-        hipSuccess)
-        return e;
-    return hipFuncSetAttribute((const void *)k_hist, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+    return hipSuccess;
 }

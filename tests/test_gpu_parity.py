@@ -101,8 +101,12 @@ def test_call_order_and_argument_errors():
     with pytest.raises(pa.StateError):
         g.resample(O.SYSTEMATIC)
     g.reweight(0.5)
+    g.reweight(0.1)  # a second reweight replaces the first
+    g.resample(O.SYSTEMATIC)
     with pytest.raises(pa.PAError):
-        g.reweight(0.1)  # beta must not decrease
+        g.reweight(0.05)  # beta must not decrease
+    with pytest.raises(pa.PAError):
+        g.reweight(float("nan"))
     with pytest.raises(pa.PAError):
         g.sweep(-1)
     g.close()
