@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Throughput of the population-annealing hot path on one MI355X.
+
+Workload (the 2D resampling-scheme study): 2D Ising ferromagnet, L = 64
+periodic, target population R = 10^5, theta = 10 checkerboard Metropolis
+sweeps per temperature, beta_i = 0.6 i / 200 (201 points), run once with each
+of the four resampling schemes (multinomial, Poisson, nearest integer,
+systematic; run_id = scheme index, seed 1).  Synthetic lattices, seeded.
+
+One step = one temperature step of all four runs: reweight (Q of Eq. (1)),
+resample (copy numbers, prefix sums, gather), theta sweeps, observables.
+``value`` = spin-flip attempts (theta N R_i summed over the runs) per ns of
+wall time over the timed steps, inputs resident in HBM throughout.
+
+Prints one JSON line.  Only one GPU is used; --gpus above 1 is refused.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+D, L, R, THETA, BETA_F, POINTS, SEED = 2, 64, 100000, 10, 0.6, 201, 1
+SCHEMES = (("multinomial", 0), ("poisson", 1), ("nearest", 2), ("systematic", 3))
+
+# Roofline of the sweep kernel (integer VALU bound):
+# peak = 256 CUs x 64 int32 lanes/clock x 2.4 GHz.
+PEAK_INT_OPS = 256 * 64 * 2.4e9
+OPS_PER_PHILOX = 120      # 80 for Philox4x32-10 + 40 to consume its two bit planes
+OPS_PER_SITE_UPDATE = 60  # 2D neighbour bonds, dE classes, accept mask, store (64 replicas)
+
+
+def betas():
+    return [i * BETA_F / (POINTS - 1) for i in range(POINTS)]
+
+
+def make_runs(pa):
+    return [pa.PARun(D, L, R, seed=SEED, run_id=rid) for _, rid in SCHEMES]
+
+
+def gpu_bench(steps, warmup):
+    import torch
+    from paper_2401_07965_amd import pa
+    pa.lib()
+    sched = betas()
+    runs = make_runs(pa)
+    stream = torch.cuda.current_stream()
+    state = {"i": 0, "runs": runs}
+
+    def one_step(timed, acc):
+        i = state["i"] + 1
+        if i == POINTS:  # anneal finished: start the next anneal (step 1 of the method)
+            for g in state["runs"]:
+                g.close()
+            state["runs"] = make_runs(pa)
+            i = 1
+        state["i"] = i
+        attempts = 0
+        for (name, rid), g in zip(SCHEMES, state["runs"]):
+            t0 = time.perf_counter()
+            g.reweight(sched[i])
+            Rn = g.resample(rid)
+            t1 = time.perf_counter()
+            if timed:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                g.sweep(THETA)
+                e1.record(stream)
+                acc["sweep_events"].append((e0, e1))
+                acc["resample_s"] += t1 - t0
+                acc["resample_bytes"] += resample_bytes(Rn, g)
+            else:
+                g.sweep(THETA)
+            g.observables()
+            attempts += THETA * (L ** D) * Rn
+        return attempts
+
+    acc = {"sweep_events": [], "resample_s": 0.0, "resample_bytes": 0.0}
+    for _ in range(warmup):
+        one_step(False, acc)
+    c0 = [g.counters() for g in state["runs"]]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    attempts = 0
+    for _ in range(steps):
+        attempts += one_step(True, acc)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    c1 = [g.counters() for g in state["runs"]]
+    sweep_ms = [a.elapsed_time(b) for a, b in acc["sweep_events"]]
+    calls = sum(b["philox_calls"] - a["philox_calls"] for a, b in zip(c0, c1))
+    updates = sum(b["site_updates"] - a["site_updates"] for a, b in zip(c0, c1))
+    if any(b["sweeps"] < a["sweeps"] for a, b in zip(c0, c1)):
+        calls = updates = 0  # an anneal restarted inside the window: counters reset
+    for g in state["runs"]:
+        g.close()
+    return dict(elapsed=elapsed, attempts=attempts, sweep_ms=sweep_ms, calls=calls,
+                updates=updates, resample_s=acc["resample_s"],
+                resample_bytes=acc["resample_bytes"])
+
+
+def resample_bytes(Rn, g):
+    """Algorithmic HBM bytes of one resampling: per old replica
+    the energy read and the copy number / offset writes and reads; per new
+    replica the spins read and written (2 N/8 bytes) plus energy,
+    magnetisation and label read and written."""
+    N = L ** D
+    return g.R * (4 + 4 + 4 + 4 + 4) + Rn * (2 * N / 8 + 3 * 4 * 2 + 4)
+
+
+def cpu_baseline(budget_s=15.0):
+    """The oracle as it stands, on a sample of the same workload: a population
+    of R_s = 2048 replicas (same lattice, theta, schedule), whole steps."""
+    from oracle import oracle as O
+    Rs = 2048
+    sched = betas()
+    run = O.OracleRun(D, L, Rs, seed=SEED, run_id=3)
+    t0 = time.perf_counter()
+    attempts = 0
+    i = 0
+    while True:
+        i += 1
+        run.reweight(sched[i])
+        Rn = run.resample(O.SYSTEMATIC)
+        run.sweep(THETA)
+        run.observables()
+        attempts += THETA * (L ** D) * Rn
+        if time.perf_counter() - t0 > budget_s or i == POINTS - 1:
+            break
+    el = time.perf_counter() - t0
+    return {"value": attempts / el / 1e9, "unit": "attempts/ns", "cores": O.threads(),
+            "kind": "oracle",
+            "sample": f"{i} temperature steps of one systematic-resampling run with R = {Rs} "
+                      f"replicas of the same L = 64 lattice, theta = {THETA}, beta_i = 0.6 i/200 "
+                      f"({el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=190)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
+              "(the multi-GPU split is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+    r = gpu_bench(a.steps, a.warmup)
+    value = r["attempts"] / r["elapsed"] / 1e9
+    sweep_s = sum(r["sweep_ms"]) / 1e3
+    avg_launch = sweep_s / len(r["sweep_ms"])
+    ops = OPS_PER_PHILOX * r["calls"] + OPS_PER_SITE_UPDATE * r["updates"]
+    achieved = ops / sweep_s if r["calls"] else None
+    out = {
+        "metric": "spin-flip attempts/ns (whole PA temperature step)",
+        "value": value,
+        "unit": "attempts/ns",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": r["elapsed"] / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": "2D Ising ferromagnet L=64 periodic, R=100000, theta=10, "
+                        "beta_i=0.6 i/200 (201 points), four runs: multinomial, Poisson, "
+                        "nearest-integer, systematic resampling",
+            "dim": D, "L": L, "R": R, "theta": THETA, "runs_per_step": len(SCHEMES),
+        },
+        "sweep_attempts_per_ns": r["attempts"] / sweep_s / 1e9,
+        "resample_GB_per_s": r["resample_bytes"] / r["resample_s"] / 1e9,
+        "philox_calls_per_attempt": (r["calls"] / (64.0 * r["updates"])) if r["updates"] else None,
+        "roofline": {
+            "kernel": "k_sweep<2>",
+            "bound": "alu",
+            "achieved": achieved / 1e12 if achieved else None,
+            "peak": PEAK_INT_OPS / 1e12,
+            "unit": "Tops/s (int32)",
+            "frac": achieved / PEAK_INT_OPS if achieved else None,
+            "avg_launch_ms": avg_launch * 1e3,
+            "traffic": None,
+        },
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

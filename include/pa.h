@@ -107,6 +107,16 @@ typedef struct {
     uint32_t *label;      /* family: index of the ancestor at beta_0 */
 } pa_host_state;
 
+/* Work counters of a run since pa_init (for throughput accounting). */
+typedef struct {
+    uint64_t philox_calls;  /* Philox4x32-10 evaluations the sweeps needed: per
+                               64-replica word and site visit, plane pairs until
+                               every replica's u < T is decided */
+    uint64_t site_updates;  /* 64-replica word-site updates (64 attempts each,
+                               dead replicas of the last word included) */
+    uint64_t sweeps;        /* sweeps over all sites, summed over pa_sweep calls */
+} pa_counters;
+
 typedef struct pa_ctx pa_ctx;
 
 /* Device bytes a run of this configuration needs (pa_init's workspace).
@@ -160,6 +170,9 @@ pa_status pa_import_state(pa_ctx *ctx, const pa_host_state *st);
  * hist_out: host, int64[N + 1], entry k counts pairs with N - 2 popcount = 2k - N
  * (i.e. k = N - popcount). */
 pa_status pa_overlap(pa_ctx *a, pa_ctx *b, int64_t *hist_out);
+
+/* Work counters since pa_init; synchronises the stream. */
+pa_status pa_get_counters(pa_ctx *ctx, pa_counters *out);
 
 /* Releases the context's host memory (not the caller's workspace). */
 void pa_destroy(pa_ctx *ctx);

@@ -66,8 +66,15 @@ def lib():
         L.orc_apply.argtypes = [_c.c_int64, _c.c_int64, _u32p, _i8p, _i32p, _u32p, _i8p, _i32p,
                                 _u32p]
         L.orc_apply.restype = None
+        L.orc_threads.argtypes = []
+        L.orc_threads.restype = _c.c_int
         _LIB = L
     return _LIB
+
+
+def threads():
+    """OpenMP threads the oracle's sweeps run on."""
+    return int(lib().orc_threads())
 
 
 # --------------------------------------------------------------------------- primitives

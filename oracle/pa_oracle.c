@@ -25,6 +25,7 @@
  *    double operations (Cody-Waite reduction + degree-13 Taylor polynomial).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -69,6 +70,9 @@ static void philox4(uint32_t seed, uint32_t run_id, uint32_t c0, uint32_t c1,
 #define PURPOSE_RS_POIS 5u
 #define PURPOSE_RS_MULT 6u
 #define PURPOSE_RS_SYS 7u
+
+/* Threads the oracle's OpenMP loops use (reported with its timings). */
+int orc_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------ */
 /* Deterministic exponential for every exp() whose value feeds a decision.  */

@@ -20,6 +20,7 @@ struct pa_ctx {
     double beta = 0.0;   // current inverse temperature
     uint32_t step = 0;   // temperature index i
     uint32_t sweeps = 0; // sweeps done at step i
+    uint64_t sweeps_total = 0;
     bool reweighted = false;
     double beta_next = 0.0;
     PaRecord *hrec = nullptr; // pinned host copy of the device record
@@ -270,6 +271,7 @@ pa_status pa_sweep(pa_ctx *c, int32_t theta)
     if (e != hipSuccess)
         return hip_fail(c, e, "pa_sweep");
     c->sweeps += (uint32_t)theta;
+    c->sweeps_total += (uint64_t)theta;
     return PA_OK;
 }
 
@@ -475,6 +477,21 @@ pa_status pa_overlap(pa_ctx *a, pa_ctx *b, int64_t *hist_out)
         return hip_fail(a, e, "pa_overlap");
     for (int k = 0; k <= N; ++k)
         hist_out[k] = (int64_t)h[(size_t)k];
+    return PA_OK;
+}
+
+pa_status pa_get_counters(pa_ctx *c, pa_counters *out)
+{
+    if (!c)
+        return fail(nullptr, PA_E_INVAL, "ctx is NULL");
+    if (!out)
+        return fail(c, PA_E_INVAL, "out is NULL");
+    pa_status s = fetch_record(c, "pa_get_counters");
+    if (s != PA_OK)
+        return s;
+    out->philox_calls = c->hrec->philox_calls;
+    out->site_updates = c->hrec->site_updates;
+    out->sweeps = c->sweeps_total;
     return PA_OK;
 }
 

@@ -23,6 +23,8 @@ struct PaRecord {
     unsigned long long sumE, sumE2, sumAbsM, sumM2, sumC2, families;
     double sumClnC;
     double e, e2, abs_m, m2, rho_t, S_f;
+    unsigned long long philox_calls; // Philox4x32-10 evaluations of all sweeps so far
+    unsigned long long site_updates; // word-site updates (64 attempts each) so far
     uint32_t err; // bit 0: scan look-back gave up waiting
     uint32_t pad;
 };

@@ -94,7 +94,7 @@ template <int D>
 __global__ __launch_bounds__(kThreads) void k_sweep(uint64_t *__restrict__ spins,
                                                     const uint8_t *__restrict__ jmask, int L, int N,
                                                     int32_t *__restrict__ E, int32_t *__restrict__ M,
-                                                    int64_t Rlive, const PaRecord *__restrict__ rec,
+                                                    int64_t Rlive, PaRecord *__restrict__ rec,
                                                     uint32_t seed, uint32_t run_id, uint32_t step,
                                                     uint32_t t0, int theta)
 {
@@ -121,6 +121,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(uint64_t *__restrict__ spins
                    draw8 = (T8 > 0 && T8 < two32) ? ~0ull : 0ull,
                    draw12 = (T12 > 0 && T12 < two32) ? ~0ull : 0ull;
     const int half = L >> 1, nh = N >> 1, LL = L * L;
+    uint32_t calls = 0; // Philox evaluations this lane's words needed
 
     for (int tt = 0; tt < theta; ++tt) {
         const uint32_t t = t0 + (uint32_t)tt;
@@ -164,6 +165,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(uint64_t *__restrict__ spins
                 uint64_t und = (m4 & draw4) | (m8 & draw8) | (m12 & draw12);
                 // u < T decided plane by plane from the most significant bit
                 for (uint32_t q = 0; und != 0 && q < 16; ++q) {
+                    ++calls;
                     const pa_philox_out o = pa_philox(seed, run_id, (uint32_t)s, w, step,
                                                       (PA_PURPOSE_METRO << 28) | (t << 8) | q);
                     const uint64_t P0 = (uint64_t)o.x0 | ((uint64_t)o.x1 << 32);
@@ -199,6 +201,13 @@ __global__ __launch_bounds__(kThreads) void k_sweep(uint64_t *__restrict__ spins
             vadd8(ve, S ^ lat[z == L - 1 ? s - LL * (L - 1) : s + LL] ^ jbit(jb, 2));
         vadd8(vm, S);
         g[s] = S;
+    }
+    if (theta > 0) {
+        const uint64_t tot = pa_wave_sum_u64(calls);
+        if ((tid & 63) == 0)
+            atomicAdd(&rec->philox_calls, (unsigned long long)tot);
+        if (tid == 0)
+            atomicAdd(&rec->site_updates, (unsigned long long)theta * (unsigned long long)N);
     }
     uint64_t ce[16], cm[16];
 #pragma unroll

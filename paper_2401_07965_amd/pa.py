@@ -41,6 +41,11 @@ class pa_host_state(ctypes.Structure):
                 ("magnetization", ctypes.c_void_p), ("label", ctypes.c_void_p)]
 
 
+class pa_counters(ctypes.Structure):
+    _fields_ = [("philox_calls", ctypes.c_uint64), ("site_updates", ctypes.c_uint64),
+                ("sweeps", ctypes.c_uint64)]
+
+
 class PAError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"status {status}: {msg}")
@@ -83,13 +88,14 @@ def lib():
         L.pa_export_state.argtypes = [v, P(pa_host_state)]
         L.pa_import_state.argtypes = [v, P(pa_host_state)]
         L.pa_overlap.argtypes = [v, v, v]
+        L.pa_get_counters.argtypes = [v, P(pa_counters)]
         L.pa_destroy.argtypes = [v]
         L.pa_destroy.restype = None
         L.pa_last_error.argtypes = [v]
         L.pa_last_error.restype = ctypes.c_char_p
         for name in ("pa_required_bytes", "pa_init", "pa_sweep", "pa_reweight", "pa_resample",
                      "pa_observables", "pa_free_energy", "pa_export_state", "pa_import_state",
-                     "pa_overlap"):
+                     "pa_overlap", "pa_get_counters"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -184,6 +190,12 @@ def pa_overlap(a, b, N):
     return h
 
 
+def pa_get_counters(ctx):
+    c = pa_counters()
+    _check(lib().pa_get_counters(ctx, ctypes.byref(c)), ctx)
+    return {name: getattr(c, name) for name, _ in pa_counters._fields_}
+
+
 def pa_destroy(ctx):
     lib().pa_destroy(ctx)
 
@@ -249,6 +261,9 @@ class PARun:
 
     def overlap(self, other):
         return pa_overlap(self.ctx, other.ctx, self.N)
+
+    def counters(self):
+        return pa_get_counters(self.ctx)
 
     def close(self):
         if self.ctx is not None:
