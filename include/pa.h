@@ -171,6 +171,21 @@ pa_status pa_import_state(pa_ctx *ctx, const pa_host_state *st);
  * (i.e. k = N - popcount). */
 pa_status pa_overlap(pa_ctx *a, pa_ctx *b, int64_t *hist_out);
 
+/* Adaptive temperature steps (Sec. 5 names them; the rule is a reading):
+ * overlap of the current population with its reweighting by dbeta,
+ *   alpha(dbeta) = (1/R) sum_j min(1, tau_j),  tau_j = R w_j / sum_k w_k,
+ *   w_j = exp(-dbeta (E_j - E_min))  (tau of Eq. (1)),
+ * i.e. one minus the total-variation distance between the population and
+ * its reweighted version; alpha(0) = 1.  Synchronises the stream. */
+pa_status pa_step_alpha(pa_ctx *ctx, double dbeta, double *alpha_out);
+
+/* Largest dbeta in [0, dbeta_max] with alpha(dbeta) >= alpha_star: dbeta_max
+ * itself if it qualifies, else `iterations` halvings of [0, dbeta_max]
+ * keeping the lower end qualified (0 < alpha_star < 1, 1 <= iterations <= 200).
+ * The population is unchanged; pass beta + dbeta to pa_reweight. */
+pa_status pa_step_rule(pa_ctx *ctx, double alpha_star, double dbeta_max, int32_t iterations,
+                       double *dbeta_out);
+
 /* Work counters since pa_init; synchronises the stream. */
 pa_status pa_get_counters(pa_ctx *ctx, pa_counters *out);
 

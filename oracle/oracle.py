@@ -66,6 +66,9 @@ def lib():
         L.orc_apply.argtypes = [_c.c_int64, _c.c_int64, _u32p, _i8p, _i32p, _u32p, _i8p, _i32p,
                                 _u32p]
         L.orc_apply.restype = None
+        _f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+        L.orc_exp_array.argtypes = [_c.c_int64, _f64p, _f64p]
+        L.orc_exp_array.restype = None
         L.orc_threads.argtypes = []
         L.orc_threads.restype = _c.c_int
         _LIB = L
@@ -88,6 +91,14 @@ def philox(k0, k1, ctr):
 def pa_exp(x):
     """Deterministic exp used wherever exp() decides something."""
     return lib().orc_exp(float(x))
+
+
+def pa_exp_array(x):
+    """pa_exp elementwise."""
+    x = np.ascontiguousarray(x, np.float64)
+    out = np.empty_like(x)
+    lib().orc_exp_array(len(x), x, out)
+    return out
 
 
 def threshold(beta, dE):

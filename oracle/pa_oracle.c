@@ -105,6 +105,12 @@ double orc_exp(double x)
     return ldexp(p, (int)k);
 }
 
+void orc_exp_array(int64_t n, const double *x, double *out)
+{
+    for (int64_t k = 0; k < n; ++k)
+        out[k] = orc_exp(x[k]);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Lattice: hypercubic, side L, dimension d in {2,3}, periodic.  Site       */
 /* s = x + L*y + L*L*z.  Bond (s,mu) joins s and s+e_mu with coupling        */

@@ -480,6 +480,39 @@ pa_status pa_overlap(pa_ctx *a, pa_ctx *b, int64_t *hist_out)
     return PA_OK;
 }
 
+pa_status pa_step_alpha(pa_ctx *c, double dbeta, double *alpha_out)
+{
+    if (!c)
+        return fail(nullptr, PA_E_INVAL, "ctx is NULL");
+    if (!alpha_out || !std::isfinite(dbeta) || dbeta < 0.0)
+        return fail(c, PA_E_INVAL, "dbeta must be finite and >= 0; alpha_out non-NULL");
+    hipError_t e = pa_launch_rule(c->lp, c->dv, c->cur, c->Rcur, 0.0, dbeta, 0, 0);
+    if (e != hipSuccess)
+        return hip_fail(c, e, "pa_step_alpha");
+    pa_status s = fetch_record(c, "pa_step_alpha");
+    if (s != PA_OK)
+        return s;
+    *alpha_out = c->hrec->rule_alpha;
+    return PA_OK;
+}
+
+pa_status pa_step_rule(pa_ctx *c, double alpha_star, double dbeta_max, int32_t iterations, double *dbeta_out)
+{
+    if (!c)
+        return fail(nullptr, PA_E_INVAL, "ctx is NULL");
+    if (!dbeta_out || !(alpha_star > 0.0 && alpha_star < 1.0) || !std::isfinite(dbeta_max) || dbeta_max <= 0.0 ||
+        iterations < 1 || iterations > 200)
+        return fail(c, PA_E_INVAL, "need 0 < alpha_star < 1, dbeta_max > 0, 1 <= iterations <= 200");
+    hipError_t e = pa_launch_rule(c->lp, c->dv, c->cur, c->Rcur, alpha_star, dbeta_max, iterations, 1);
+    if (e != hipSuccess)
+        return hip_fail(c, e, "pa_step_rule");
+    pa_status s = fetch_record(c, "pa_step_rule");
+    if (s != PA_OK)
+        return s;
+    *dbeta_out = c->hrec->rule_dbeta;
+    return PA_OK;
+}
+
 pa_status pa_get_counters(pa_ctx *c, pa_counters *out)
 {
     if (!c)

@@ -23,6 +23,7 @@ struct PaRecord {
     unsigned long long sumE, sumE2, sumAbsM, sumM2, sumC2, families;
     double sumClnC;
     double e, e2, abs_m, m2, rho_t, S_f;
+    double rule_dbeta, rule_alpha; // adaptive step: chosen dbeta and its overlap
     unsigned long long philox_calls; // Philox4x32-10 evaluations of all sweeps so far
     unsigned long long site_updates; // word-site updates (64 attempts each) so far
     uint32_t err; // bit 0: scan look-back gave up waiting
@@ -76,6 +77,8 @@ hipError_t pa_launch_apply(const PaLaunch &p, const PaDev &dv, int cur, int64_t 
 hipError_t pa_launch_observables(const PaLaunch &p, const PaDev &dv, int cur, int64_t Rcur);
 hipError_t pa_launch_overlap(const PaLaunch &p, const uint64_t *a, const uint64_t *b, int64_t R,
                              unsigned long long *hist);
+hipError_t pa_launch_rule(const PaLaunch &p, const PaDev &dv, int cur, int64_t Rcur, double alpha_star,
+                          double dbeta_max, int iterations, int bisect);
 hipError_t pa_launch_set_beta(const PaLaunch &p, const PaDev &dv, double beta, double lnZ);
 hipError_t pa_configure_kernels(int *max_lds); // largest LDS a workgroup may use
 size_t pa_sweep_lds_bytes(int N);

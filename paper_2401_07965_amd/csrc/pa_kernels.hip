@@ -320,6 +320,69 @@ __global__ __launch_bounds__(1024) void k_reweight(const uint32_t *__restrict__ 
     }
 }
 
+// ------------------------------------------------------------------ adaptive step
+// Overlap of the population with its reweighting by dbeta,
+// alpha = (1/R) sum_j min(1, R w_j / sum_k w_k), w_j = pa_exp(-dbeta (E_j - E_min)),
+// evaluated per energy level (fixed chunk per thread, fixed tree), and the
+// bisection for the largest dbeta in [0, dbeta_max] with alpha >= alpha_star.
+constexpr int kRuleThreads = 1024;
+constexpr int kRuleCache = 4096; // levels whose weights stay in LDS between the two sums
+
+__device__ double rule_alpha(const uint32_t *__restrict__ hist, int hmin, int nlev, double R, double dbeta,
+                             double *wcache, double *sd)
+{
+    const int chunk = (nlev + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int lo = (int)threadIdx.x * chunk;
+    const int hi = lo + chunk < nlev ? lo + chunk : nlev;
+    double wsum = 0.0;
+    for (int k = lo; k < hi; ++k) {
+        const double wv = pa_exp(-(dbeta * (double)(4 * k)));
+        if (k < kRuleCache)
+            wcache[k] = wv;
+        wsum = wsum + (double)hist[hmin + k] * wv;
+    }
+    const double W = pa_block_sum_f64(wsum, sd);
+    double a = 0.0;
+    for (int k = lo; k < hi; ++k) {
+        const double wv = k < kRuleCache ? wcache[k] : pa_exp(-(dbeta * (double)(4 * k)));
+        const double tau = (R * wv) / W;
+        a = a + (double)hist[hmin + k] * (tau < 1.0 ? tau : 1.0);
+    }
+    return pa_block_sum_f64(a, sd) / R;
+}
+
+__global__ __launch_bounds__(kRuleThreads) void k_rule(const uint32_t *__restrict__ hist, PaRecord *rec, int DN,
+                                                       int64_t Rcur, double alpha_star, double dbeta_max,
+                                                       int iterations, int bisect)
+{
+    __shared__ double sd[16];
+    __shared__ double wcache[kRuleCache];
+    const int hmin = (rec->emin + DN) >> 2, hmax = (rec->emax + DN) >> 2;
+    const int nlev = hmax - hmin + 1;
+    const double R = (double)Rcur;
+    double a = rule_alpha(hist, hmin, nlev, R, dbeta_max, wcache, sd);
+    double lo = 0.0, hi = dbeta_max, best = dbeta_max, abest = a;
+    if (bisect && !(a >= alpha_star)) {
+        best = 0.0;
+        abest = 1.0;
+        for (int it = 0; it < iterations; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            const double am = rule_alpha(hist, hmin, nlev, R, mid, wcache, sd);
+            if (am >= alpha_star) {
+                lo = mid;
+                abest = am;
+            } else {
+                hi = mid;
+            }
+        }
+        best = lo;
+    }
+    if (threadIdx.x == 0) {
+        rec->rule_dbeta = best;
+        rec->rule_alpha = abest;
+    }
+}
+
 // ------------------------------------------------------------------ resampling
 __device__ __forceinline__ uint64_t weight_of(int32_t e, int DN, int hmin, const uint64_t *wtab)
 {
@@ -934,6 +997,17 @@ hipError_t pa_launch_overlap(const PaLaunch &p, const uint64_t *a, const uint64_
 {
     const unsigned W = (unsigned)((R + 63) / 64);
     k_overlap<<<W, kThreads, 0, p.stream>>>(a, b, p.N, R, hist);
+    return hipGetLastError();
+}
+
+hipError_t pa_launch_rule(const PaLaunch &p, const PaDev &dv, int cur, int64_t Rcur, double alpha_star,
+                          double dbeta_max, int iterations, int bisect)
+{
+    const int DN = p.d * p.N;
+    k_hist_prep<<<grid_for(p.H), kThreads, 0, p.stream>>>(dv.hist, p.H, dv.rec);
+    k_hist<<<grid_for(Rcur, 4096, 1024), kThreads, (size_t)p.H * 4, p.stream>>>(dv.E[cur], Rcur, DN, p.H, dv.hist,
+                                                                                dv.rec);
+    k_rule<<<1, kRuleThreads, 0, p.stream>>>(dv.hist, dv.rec, DN, Rcur, alpha_star, dbeta_max, iterations, bisect);
     return hipGetLastError();
 }
 

@@ -89,13 +89,16 @@ def lib():
         L.pa_import_state.argtypes = [v, P(pa_host_state)]
         L.pa_overlap.argtypes = [v, v, v]
         L.pa_get_counters.argtypes = [v, P(pa_counters)]
+        L.pa_step_alpha.argtypes = [v, ctypes.c_double, P(ctypes.c_double)]
+        L.pa_step_rule.argtypes = [v, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                   P(ctypes.c_double)]
         L.pa_destroy.argtypes = [v]
         L.pa_destroy.restype = None
         L.pa_last_error.argtypes = [v]
         L.pa_last_error.restype = ctypes.c_char_p
         for name in ("pa_required_bytes", "pa_init", "pa_sweep", "pa_reweight", "pa_resample",
                      "pa_observables", "pa_free_energy", "pa_export_state", "pa_import_state",
-                     "pa_overlap", "pa_get_counters"):
+                     "pa_overlap", "pa_get_counters", "pa_step_alpha", "pa_step_rule"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -190,6 +193,19 @@ def pa_overlap(a, b, N):
     return h
 
 
+def pa_step_alpha(ctx, dbeta):
+    a = ctypes.c_double()
+    _check(lib().pa_step_alpha(ctx, float(dbeta), ctypes.byref(a)), ctx)
+    return a.value
+
+
+def pa_step_rule(ctx, alpha_star, dbeta_max, iterations=60):
+    d = ctypes.c_double()
+    _check(lib().pa_step_rule(ctx, float(alpha_star), float(dbeta_max), int(iterations),
+                              ctypes.byref(d)), ctx)
+    return d.value
+
+
 def pa_get_counters(ctx):
     c = pa_counters()
     _check(lib().pa_get_counters(ctx, ctypes.byref(c)), ctx)
@@ -261,6 +277,12 @@ class PARun:
 
     def overlap(self, other):
         return pa_overlap(self.ctx, other.ctx, self.N)
+
+    def step_alpha(self, dbeta):
+        return pa_step_alpha(self.ctx, dbeta)
+
+    def step_rule(self, alpha_star, dbeta_max, iterations=60):
+        return pa_step_rule(self.ctx, alpha_star, dbeta_max, iterations)
 
     def counters(self):
         return pa_get_counters(self.ctx)

@@ -1,0 +1,62 @@
+"""Pins of the adaptive-step oracle (overlap alpha and its bisection), CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import schedule as S
+
+
+def test_alpha_at_zero_step_is_one():
+    E = np.random.default_rng(0).integers(-100, 100, 500) * 4
+    assert S.alpha(E, 0.0) == 1.0
+
+
+def test_two_level_closed_form():
+    n0, n1 = 300, 700
+    E = np.array([-8] * n0 + [-4] * n1)
+    R = n0 + n1
+    for db in (0.01, 0.1, 0.5, 2.0):
+        w1 = math.exp(-4 * db)
+        W = n0 + n1 * w1
+        ref = (n0 * min(1.0, R / W) + n1 * min(1.0, R * w1 / W)) / R
+        assert abs(S.alpha(E, db) - ref) < 1e-12
+
+
+def test_alpha_is_one_minus_total_variation():
+    rng = np.random.default_rng(1)
+    E = rng.integers(-2000, 0, 3000) * 4
+    for db in (0.001, 0.01, 0.05):
+        w = np.exp(-db * (E - E.min()).astype(np.float64))
+        p = w / w.sum()
+        tv = 0.5 * np.abs(p - 1.0 / len(E)).sum()
+        assert abs(S.alpha(E, db) - (1 - tv)) < 1e-12
+
+
+def test_alpha_decreases_with_the_step():
+    E = np.random.default_rng(2).normal(-5000, 60, 20000).round().astype(np.int64) * 4
+    a = [S.alpha(E, db) for db in np.linspace(0, 0.05, 26)]
+    assert all(x >= y - 1e-15 for x, y in zip(a, a[1:]))
+
+
+def test_gaussian_energies_closed_form():
+    """Normal energies of width sigma: alpha -> 2 Phi(-dbeta sigma / 2) for large R."""
+    sigma, R = 40.0, 400000
+    E = np.random.default_rng(3).normal(0, sigma, R)
+    E = (np.round(E / 4) * 4).astype(np.int64)
+    s = E.std()
+    for db in (0.005, 0.02, 0.05):
+        ref = math.erfc(db * s / 2 / math.sqrt(2))
+        assert abs(S.alpha(E, db) - ref) < 0.01
+
+
+@pytest.mark.parametrize("astar", [0.5, 0.8, 0.95])
+def test_step_rule_brackets_the_target(astar):
+    E = np.random.default_rng(4).normal(-3000, 50, 5000).round().astype(np.int64) * 4
+    dmax = 1.0
+    d = S.step_rule(E, astar, dmax, iterations=60)
+    assert 0.0 <= d < dmax
+    assert S.alpha(E, d) >= astar
+    assert S.alpha(E, d + 4 * dmax * 2.0 ** -60 + 1e-12) < astar or d == dmax
+    # a tiny population spread admits the whole range
+    assert S.step_rule(np.full(10, -40), astar, dmax) == dmax
