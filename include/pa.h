@@ -196,6 +196,79 @@ void pa_destroy(pa_ctx *ctx);
  * when ctx is NULL).  Valid until the next call on ctx. */
 const char *pa_last_error(const pa_ctx *ctx);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent runs (own lattice shape, R, couplings, seeds)
+ * annealed together on one stream.  Every kernel serves all runs of the batch
+ * at once; run state stays on the device, so an anneal needs no host round
+ * trip and can be captured whole in one HIP graph.  A batch gives the same
+ * bits as running each of its runs alone through the calls above.
+ * ------------------------------------------------------------------------- */
+typedef struct pa_batch pa_batch;
+
+/* One row per run and temperature point of a batched anneal (Sec. 2 step 4
+ * and Eq. (7) at beta_i). */
+typedef struct {
+    double beta, lnQ, lnZ, sv, e, e2, abs_m, m2, rho_t, S_f;
+    int64_t R, sum_E, sum_E2, sum_absM, sum_M2, sum_c2, families;
+    uint32_t status;      /* bit 1 capacity, 2 extinct, 3 non-finite, 4 frozen */
+    uint32_t pad;
+} pa_step_record;
+
+/* Free-energy-weighted combination of the runs of one group (Sec. 4,
+ * Eqs. (9)-(12)). */
+typedef struct {
+    double lnZ;          /* ln of the pooled Z estimate: ln(sum_m R_m Z_m / sum_m R_m) */
+    double e, e2, abs_m, m2; /* W[O] = sum_m omega_m O_m, omega of Eq. (10) */
+    double c;            /* W_var of the specific heat, Eq. (11) */
+    double chi;          /* W_var of the susceptibility, Eq. (12), with |m| */
+    double n_eff;        /* 1 / sum_m omega_m^2 */
+    double beta;
+    int32_t runs, pad;
+} pa_combined;
+
+/* Device bytes for a batch of nruns configurations (each as for pa_init) whose
+ * anneals have at most max_points temperature points. */
+pa_status pa_batch_required_bytes(const pa_config *cfgs, int32_t nruns, int32_t max_points,
+                                  uint64_t *bytes);
+
+/* Lays out the batch in the caller's workspace (256-byte aligned) and draws
+ * every run's initial population (step 1 of Sec. 2).  At most 16 distinct
+ * lattice shapes. */
+pa_status pa_batch_create(const pa_config *cfgs, int32_t nruns, int32_t max_points, void *workspace,
+                          uint64_t workspace_bytes, void *stream, pa_batch **out);
+
+/* Autotuner: times the sweep workgroup size (64..512 lanes, where the
+ * lattice allows) per lattice shape with theta sweeps, keeps the fastest and
+ * re-draws the initial populations.  Results do not depend on the choice.
+ * threads_out (optional): one entry per shape group. */
+pa_status pa_batch_tune(pa_batch *b, int32_t theta, int32_t *threads_out);
+
+/* Shape groups of the batch and their sweep workgroup sizes. */
+pa_status pa_batch_groups(pa_batch *b, int32_t *ngroups, int32_t *threads);
+
+/* A whole anneal of every run from a fresh initial population: betas[0] = 0,
+ * then for i >= 1 reweight to betas[i], resample with `scheme`, theta sweeps,
+ * observables into the records.  A run whose resampling fails (capacity,
+ * extinction) is frozen at its last good step (status bits in its records).
+ * use_graph != 0 captures the anneal in one HIP graph and launches it once. */
+pa_status pa_batch_anneal(pa_batch *b, const double *betas, int32_t npoints, int32_t theta,
+                          pa_resampler scheme, int32_t use_graph);
+
+/* Records of the last anneal: out[run * npoints + i]. */
+pa_status pa_batch_records(pa_batch *b, pa_step_record *out);
+
+/* Final state of one run (as pa_export_state). */
+pa_status pa_batch_export_run(pa_batch *b, int32_t run, pa_host_state *st);
+
+/* Eqs. (9)-(10) at temperature point `point` of the last anneal: runs m with
+ * group_of_run[m] = g (-1: none) are combined into out[g], g < ngroups;
+ * frozen runs are left out. */
+pa_status pa_batch_combine(pa_batch *b, const int32_t *group_of_run, int32_t ngroups, int32_t point,
+                           pa_combined *out);
+
+void pa_batch_destroy(pa_batch *b);
+const char *pa_batch_last_error(const pa_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

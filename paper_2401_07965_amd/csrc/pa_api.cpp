@@ -1,54 +1,29 @@
 // Host side of the C ABI declared in include/pa.h: argument checks, the
-// per-run state machine (init -> [reweight -> resample] -> sweep ...), the
-// layout of the caller's device workspace, and the few small device-to-host
-// copies each step needs (ln Q, the new population size, averages).
+// layout of the caller's device workspace, the block maps of a batch, the
+// per-run state machine of the single-run calls, the batched anneal (with
+// optional capture of the whole anneal in one HIP graph) and the autotuner.
+// A single run (pa_ctx) is a batch of one.
 #include "pa.h"
 #include "pa_internal.h"
 
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
-
-struct pa_ctx {
-    PaLaunch lp;
-    PaDev dv;
-    int cur = 0;         // which ping-pong buffer holds the population
-    int64_t Rcur = 0;    // replicas in the population
-    double beta = 0.0;   // current inverse temperature
-    uint32_t step = 0;   // temperature index i
-    uint32_t sweeps = 0; // sweeps done at step i
-    uint64_t sweeps_total = 0;
-    bool reweighted = false;
-    double beta_next = 0.0;
-    PaRecord *hrec = nullptr; // pinned host copy of the device record
-    std::string err;
-};
 
 namespace {
 
 thread_local std::string g_init_err;
-bool g_kernels_configured = false;
 int g_max_lds = 0;
 
 constexpr int64_t kMaxCapacity = (1ll << 24) - 64; // R W_j < 2^64 for W_j <= 2^40
 constexpr int kMaxSites = 16384;                  // LDS and 8-plane counters per thread
-
-pa_status fail(pa_ctx *c, pa_status s, const std::string &msg)
-{
-    if (c)
-        c->err = msg;
-    else
-        g_init_err = msg;
-    return s;
-}
-
-pa_status hip_fail(pa_ctx *c, hipError_t e, const char *where)
-{
-    return fail(c, PA_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
-}
+constexpr int kMaxRuns = 65536;
 
 int64_t default_capacity(int64_t R)
 {
@@ -106,17 +81,39 @@ pa_status check_config(const pa_config *cfg, Geometry *g, std::string *msg)
     return PA_OK;
 }
 
-// Carves the workspace (base may be null to only measure it).
-uint64_t carve(const Geometry &g, char *base, PaDev *dv)
+// Sweep workgroup size: enough lanes for a colour's sites, and at most 255
+// unsatisfied bonds per lane for its 8-plane counters.
+int default_sweep_threads(int N, int d)
+{
+    int t = ((N / 2 + 63) / 64) * 64;
+    if (t > 256)
+        t = 256;
+    if (t < 64)
+        t = 64;
+    while (t < 512 && (int64_t)((N + t - 1) / t) * d > 255)
+        t += 64;
+    return t;
+}
+
+bool sweep_threads_ok(int N, int d, int t)
+{
+    return t >= 64 && t <= 512 && t % 64 == 0 && (int64_t)((N + t - 1) / t) * d <= 255;
+}
+
+uint64_t round256(uint64_t b) { return (b + 255) / 256 * 256; }
+
+// Buffers of one run (base may be null to only measure them).
+uint64_t carve_run(const Geometry &g, char *base, PaDev *dv)
 {
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) -> char * {
         char *p = base ? base + off : nullptr;
-        off += (bytes + 255) / 256 * 256;
+        off += round256(bytes);
         return p;
     };
     const uint64_t words = (uint64_t)g.W * g.N;
     const uint64_t slots = (uint64_t)g.W * 64;
+    const uint64_t chunks = (uint64_t)((g.cap + PA_CHUNK - 1) / PA_CHUNK);
     PaDev d{};
     for (int k = 0; k < 2; ++k) {
         d.spins[k] = (uint64_t *)take(words * 8);
@@ -132,40 +129,361 @@ uint64_t carve(const Geometry &g, char *base, PaDev *dv)
     d.anc = (uint32_t *)take(slots * 4);
     d.C = (uint64_t *)take(slots * 8);
     d.qhist = (unsigned long long *)take((uint64_t)(g.N + 1) * 8);
-    d.tiles = (PaScanTile *)take((uint64_t)((slots + PA_SCAN_TILE - 1) / PA_SCAN_TILE) * sizeof(PaScanTile));
-    d.ticket = (uint32_t *)take(4);
+    d.tiles = (PaScanTile *)take((uint64_t)((g.cap + PA_SCAN_TILE - 1) / PA_SCAN_TILE) * sizeof(PaScanTile));
+    d.partial = (double *)take(chunks * 8);
     d.fam = (uint32_t *)take((uint64_t)g.R * 4);
-    d.partial = (double *)take(PA_RED_BLOCKS * 8);
     d.rec = (PaRecord *)take(sizeof(PaRecord));
     if (dv)
         *dv = d;
     return off;
 }
 
-pa_status fetch_record(pa_ctx *c, const char *where)
+} // namespace
+
+// A batch of independent runs sharing one workspace and one stream.
+struct Batch {
+    int M = 0;
+    std::vector<Geometry> geo;
+    std::vector<PaRunDesc> hdesc;
+    std::vector<std::vector<uint8_t>> jmask;
+    PaBatchView v{};
+    PaRunDesc *ddesc = nullptr;
+    int32_t *dgroup = nullptr, *dNs = nullptr;
+    double *dcomb = nullptr;
+    PaRecord *hrec = nullptr; // pinned host copies of the M device records
+    int max_points = 0;
+    std::string err;
+    // host bookkeeping of the single-run calls
+    double beta = 0.0, beta_next = 0.0;
+    uint64_t sweeps_total = 0;
+    uint32_t sweeps = 0;
+    bool reweighted = false;
+    int anneal_points = 0;
+};
+
+struct pa_ctx {
+    Batch b;
+};
+
+struct pa_batch {
+    Batch b;
+};
+
+namespace {
+
+pa_status fail(Batch *b, pa_status s, const std::string &msg)
 {
-    hipError_t e = hipMemcpyAsync(c->hrec, c->dv.rec, sizeof(PaRecord), hipMemcpyDeviceToHost, c->lp.stream);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(c->lp.stream);
-    if (e != hipSuccess)
-        return hip_fail(c, e, where);
+    if (b)
+        b->err = msg;
+    else
+        g_init_err = msg;
+    return s;
+}
+
+pa_status hip_fail(Batch *b, hipError_t e, const char *where)
+{
+    return fail(b, PA_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Whole layout of a batch: tables first, then each run's buffers.
+struct Tables {
+    std::vector<PaBlk> rep, fam, col, tile;
+    std::vector<std::vector<PaBlk>> gcol;
+    std::vector<int> gd, gN, gthreads;
+};
+
+uint64_t layout(const std::vector<Geometry> &geo, int max_points, char *base, Batch *b, Tables *t)
+{
+    const int M = (int)geo.size();
+    Tables tb;
+    std::map<std::pair<int, int>, int> group_of_shape;
+    std::vector<int> run_group(M);
+    for (int m = 0; m < M; ++m) {
+        const Geometry &g = geo[m];
+        for (int64_t c = 0; c < (g.cap + PA_CHUNK - 1) / PA_CHUNK; ++c)
+            tb.rep.push_back({(uint32_t)m, (uint32_t)c});
+        for (int64_t c = 0; c < (g.R + PA_CHUNK - 1) / PA_CHUNK; ++c)
+            tb.fam.push_back({(uint32_t)m, (uint32_t)c});
+        for (int64_t w = 0; w < g.W; ++w)
+            tb.col.push_back({(uint32_t)m, (uint32_t)w});
+        for (int64_t k = 0; k < (g.cap + PA_SCAN_TILE - 1) / PA_SCAN_TILE; ++k)
+            tb.tile.push_back({(uint32_t)m, (uint32_t)k});
+        const auto key = std::make_pair(g.d, g.L);
+        auto it = group_of_shape.find(key);
+        if (it == group_of_shape.end()) {
+            it = group_of_shape.emplace(key, (int)tb.gcol.size()).first;
+            tb.gcol.emplace_back();
+            tb.gd.push_back(g.d);
+            tb.gN.push_back(g.N);
+            tb.gthreads.push_back(default_sweep_threads(g.N, g.d));
+        }
+        for (int64_t w = 0; w < g.W; ++w)
+            tb.gcol[it->second].push_back({(uint32_t)m, (uint32_t)w});
+    }
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += round256(bytes);
+        return p;
+    };
+    char *p_desc = take(sizeof(PaRunDesc) * (uint64_t)M);
+    char *p_rep = take(sizeof(PaBlk) * tb.rep.size());
+    char *p_fam = take(sizeof(PaBlk) * tb.fam.size());
+    char *p_col = take(sizeof(PaBlk) * tb.col.size());
+    char *p_tile = take(sizeof(PaBlk) * tb.tile.size());
+    std::vector<char *> p_g;
+    for (auto &gc : tb.gcol)
+        p_g.push_back(take(sizeof(PaBlk) * gc.size()));
+    char *p_ticket = take(4);
+    char *p_steprec = take(sizeof(PaStepRecord) * (uint64_t)M * (uint64_t)(max_points > 0 ? max_points : 0));
+    char *p_group = take(4ull * M);
+    char *p_Ns = take(4ull * M);
+    char *p_comb = take(80ull * M);
+    std::vector<PaDev> devs(M);
+    for (int m = 0; m < M; ++m) {
+        char *rb = take(0); // current offset
+        const uint64_t n = carve_run(geo[m], rb, &devs[m]);
+        off += n;
+    }
+    if (b) {
+        b->M = M;
+        b->geo = geo;
+        b->hdesc.resize(M);
+        int maxH = 0;
+        for (int m = 0; m < M; ++m) {
+            PaRunDesc &d = b->hdesc[m];
+            d.d = geo[m].d;
+            d.L = geo[m].L;
+            d.N = geo[m].N;
+            d.H = geo[m].H;
+            d.R0 = geo[m].R;
+            d.cap = geo[m].cap;
+            d.dv = devs[m];
+            maxH = geo[m].H > maxH ? geo[m].H : maxH;
+        }
+        b->ddesc = (PaRunDesc *)p_desc;
+        PaBatchView &v = b->v;
+        v.runs = (const PaRunDesc *)p_desc;
+        v.nruns = (uint32_t)M;
+        v.rep = (const PaBlk *)p_rep;
+        v.nrep = (uint32_t)tb.rep.size();
+        v.fam = (const PaBlk *)p_fam;
+        v.nfam = (uint32_t)tb.fam.size();
+        v.col = (const PaBlk *)p_col;
+        v.ncol = (uint32_t)tb.col.size();
+        v.tile = (const PaBlk *)p_tile;
+        v.ntile = (uint32_t)tb.tile.size();
+        v.ticket = (uint32_t *)p_ticket;
+        v.maxH = maxH;
+        v.ngroups = (int)tb.gcol.size();
+        for (int g = 0; g < v.ngroups; ++g) {
+            v.gcol[g] = (const PaBlk *)p_g[g];
+            v.gncol[g] = (uint32_t)tb.gcol[g].size();
+            v.gd[g] = tb.gd[g];
+            v.gN[g] = tb.gN[g];
+            v.gthreads[g] = tb.gthreads[g];
+        }
+        v.steprec = (PaStepRecord *)p_steprec;
+        v.npoints = max_points;
+        b->dgroup = (int32_t *)p_group;
+        b->dNs = (int32_t *)p_Ns;
+        b->dcomb = (double *)p_comb;
+        b->max_points = max_points;
+    }
+    if (t)
+        *t = std::move(tb);
+    return off;
+}
+
+pa_status check_batch(const pa_config *cfgs, int32_t nruns, int32_t max_points, std::vector<Geometry> *geo,
+                      std::string *msg)
+{
+    if (!cfgs || nruns < 1 || nruns > kMaxRuns) {
+        *msg = "need 1 <= nruns <= 65536 configurations";
+        return PA_E_INVAL;
+    }
+    if (max_points < 0 || max_points > 1000000) {
+        *msg = "max_points out of range";
+        return PA_E_INVAL;
+    }
+    geo->resize(nruns);
+    std::map<std::pair<int, int>, int> shapes;
+    for (int m = 0; m < nruns; ++m) {
+        pa_status s = check_config(&cfgs[m], &(*geo)[m], msg);
+        if (s != PA_OK) {
+            *msg = "run " + std::to_string(m) + ": " + *msg;
+            return s;
+        }
+        shapes[{cfgs[m].dim, cfgs[m].L}] = 1;
+    }
+    if ((int)shapes.size() > PA_MAX_GROUPS) {
+        *msg = "at most 16 distinct lattice shapes per batch";
+        return PA_E_INVAL;
+    }
     return PA_OK;
+}
+
+// couplings -> per-site masks of the 2d incident bonds
+pa_status coupling_masks(const pa_config &cfg, const Geometry &g, std::vector<uint8_t> *jm, std::string *msg)
+{
+    jm->assign((size_t)g.N, 0);
+    if (!cfg.couplings)
+        return PA_OK;
+    for (int64_t s0 = 0; s0 < g.N; ++s0) {
+        int64_t stride = 1;
+        for (int mu = 0; mu < g.d; ++mu) {
+            const int8_t J = cfg.couplings[s0 * g.d + mu];
+            if (J != 1 && J != -1) {
+                *msg = "couplings must be +1 or -1";
+                return PA_E_INVAL;
+            }
+            if (J == -1) {
+                const int64_t x = (s0 / stride) % g.L;
+                const int64_t s1 = s0 + ((x + 1) % g.L - x) * stride;
+                (*jm)[(size_t)s0] |= (uint8_t)(1u << mu);
+                (*jm)[(size_t)s1] |= (uint8_t)(1u << (g.d + mu));
+            }
+            stride *= g.L;
+        }
+    }
+    return PA_OK;
+}
+
+pa_status make_batch(const pa_config *cfgs, int32_t nruns, int32_t max_points, void *workspace, uint64_t bytes,
+                     void *stream, Batch *b)
+{
+    std::vector<Geometry> geo;
+    std::string msg;
+    pa_status s = check_batch(cfgs, nruns, max_points, &geo, &msg);
+    if (s != PA_OK)
+        return fail(nullptr, s, msg);
+    const uint64_t need = layout(geo, max_points, nullptr, nullptr, nullptr);
+    if (!workspace || bytes < need)
+        return fail(nullptr, PA_E_INVAL, "workspace missing or smaller than the required bytes");
+    if (((uintptr_t)workspace & 255u) != 0)
+        return fail(nullptr, PA_E_INVAL, "workspace must be 256-byte aligned");
+    hipError_t e;
+    if (g_max_lds == 0 && (e = pa_query_lds(&g_max_lds)) != hipSuccess)
+        return hip_fail(nullptr, e, "device query");
+    for (const Geometry &g : geo)
+        if (pa_sweep_lds_bytes(g.N) > (size_t)g_max_lds || (size_t)g.H * 4 > (size_t)g_max_lds)
+            return fail(nullptr, PA_E_INVAL, "lattice too large for the workgroup LDS of this device");
+    b->jmask.resize(nruns);
+    for (int m = 0; m < nruns; ++m)
+        if ((s = coupling_masks(cfgs[m], geo[m], &b->jmask[m], &msg)) != PA_OK)
+            return fail(nullptr, s, "run " + std::to_string(m) + ": " + msg);
+    Tables t;
+    layout(geo, max_points, (char *)workspace, b, &t);
+    for (int m = 0; m < nruns; ++m) {
+        b->hdesc[m].seed = cfgs[m].seed;
+        b->hdesc[m].run_id = cfgs[m].run_id;
+    }
+    b->v.stream = (hipStream_t)stream;
+    if ((e = hipHostMalloc((void **)&b->hrec, sizeof(PaRecord) * (size_t)nruns, hipHostMallocDefault)) !=
+        hipSuccess)
+        return hip_fail(nullptr, e, "pinned records");
+    const hipStream_t st = b->v.stream;
+    auto up = [&](const void *dst, const void *src, size_t n) {
+        if (e == hipSuccess && n)
+            e = hipMemcpyAsync(const_cast<void *>(dst), src, n, hipMemcpyHostToDevice, st);
+    };
+    e = hipSuccess;
+    up(b->ddesc, b->hdesc.data(), sizeof(PaRunDesc) * nruns);
+    up(b->v.rep, t.rep.data(), sizeof(PaBlk) * t.rep.size());
+    up(b->v.fam, t.fam.data(), sizeof(PaBlk) * t.fam.size());
+    up(b->v.col, t.col.data(), sizeof(PaBlk) * t.col.size());
+    up(b->v.tile, t.tile.data(), sizeof(PaBlk) * t.tile.size());
+    for (int g = 0; g < b->v.ngroups; ++g)
+        up(b->v.gcol[g], t.gcol[g].data(), sizeof(PaBlk) * t.gcol[g].size());
+    for (int m = 0; m < nruns; ++m)
+        up(b->hdesc[m].dv.jmask, b->jmask[m].data(), b->jmask[m].size());
+    if (e == hipSuccess)
+        e = pa_b_init(b->v);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipHostFree(b->hrec);
+        b->hrec = nullptr;
+        return hip_fail(nullptr, e, "batch set-up");
+    }
+    return PA_OK;
+}
+
+pa_status fetch_records(Batch *b, const char *where)
+{
+    hipError_t e = hipSuccess;
+    for (int m = 0; m < b->M && e == hipSuccess; ++m)
+        e = hipMemcpyAsync(b->hrec + m, b->hdesc[m].dv.rec, sizeof(PaRecord), hipMemcpyDeviceToHost, b->v.stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(b->v.stream);
+    if (e != hipSuccess)
+        return hip_fail(b, e, where);
+    return PA_OK;
+}
+
+pa_status status_error(Batch *b, uint32_t st)
+{
+    if (st & PA_ST_SCAN_TIMEOUT)
+        return fail(b, PA_E_DEVICE, "prefix-sum look-back timed out");
+    if (st & PA_ST_NONFINITE)
+        return fail(b, PA_E_NONFINITE, "ln Q is not finite");
+    if (st & PA_ST_CAPACITY)
+        return fail(b, PA_E_CAPACITY, "resampled population exceeds the capacity");
+    if (st & PA_ST_EXTINCT)
+        return fail(b, PA_E_EXTINCT, "resampled population is empty");
+    return PA_OK;
+}
+
+pa_status export_run(Batch *b, int m, pa_host_state *st)
+{
+    pa_status s = fetch_records(b, "export");
+    if (s != PA_OK)
+        return s;
+    const PaRecord &r = b->hrec[m];
+    const PaRunDesc &d = b->hdesc[m];
+    const int64_t R = (int64_t)r.Rcur;
+    const int k = r.cur;
+    hipError_t e = hipSuccess;
+    if (st->spins)
+        e = hipMemcpy(st->spins, d.dv.spins[k], (size_t)((R + 63) / 64) * d.N * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && st->energy)
+        e = hipMemcpy(st->energy, d.dv.E[k], (size_t)R * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && st->magnetization)
+        e = hipMemcpy(st->magnetization, d.dv.M[k], (size_t)R * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && st->label)
+        e = hipMemcpy(st->label, d.dv.label[k], (size_t)R * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return hip_fail(b, e, "export");
+    st->R = R;
+    st->step = r.step;
+    st->sweeps = r.sweeps;
+    st->beta = r.beta;
+    st->lnZ = r.lnZ;
+    return PA_OK;
+}
+
+void free_batch(Batch *b)
+{
+    if (b->hrec)
+        (void)hipHostFree(b->hrec);
+    b->hrec = nullptr;
 }
 
 } // namespace
 
 extern "C" {
 
+// ====================================================================== single run
 pa_status pa_required_bytes(const pa_config *cfg, uint64_t *bytes)
 {
-    Geometry g;
+    std::vector<Geometry> geo;
     std::string msg;
-    pa_status s = check_config(cfg, &g, &msg);
+    pa_status s = check_batch(cfg, 1, 0, &geo, &msg);
     if (s != PA_OK)
         return fail(nullptr, s, msg);
     if (!bytes)
         return fail(nullptr, PA_E_INVAL, "bytes is NULL");
-    *bytes = carve(g, nullptr, nullptr);
+    *bytes = layout(geo, 0, nullptr, nullptr, nullptr);
     return PA_OK;
 }
 
@@ -174,84 +492,13 @@ pa_status pa_init(const pa_config *cfg, void *workspace, uint64_t workspace_byte
     if (!out)
         return fail(nullptr, PA_E_INVAL, "out is NULL");
     *out = nullptr;
-    Geometry g;
-    std::string msg;
-    pa_status s = check_config(cfg, &g, &msg);
-    if (s != PA_OK)
-        return fail(nullptr, s, msg);
-    const uint64_t need = carve(g, nullptr, nullptr);
-    if (!workspace || workspace_bytes < need)
-        return fail(nullptr, PA_E_INVAL, "workspace missing or smaller than pa_required_bytes");
-    if (((uintptr_t)workspace & 255u) != 0)
-        return fail(nullptr, PA_E_INVAL, "workspace must be 256-byte aligned");
-
-    // couplings -> per-site masks of the 2d incident bonds
-    std::vector<uint8_t> jm((size_t)g.N, 0);
-    if (cfg->couplings) {
-        for (int64_t s0 = 0; s0 < g.N; ++s0) {
-            int64_t stride = 1;
-            for (int mu = 0; mu < g.d; ++mu) {
-                const int8_t J = cfg->couplings[s0 * g.d + mu];
-                if (J != 1 && J != -1)
-                    return fail(nullptr, PA_E_INVAL, "couplings must be +1 or -1");
-                if (J == -1) {
-                    const int64_t x = (s0 / stride) % g.L;
-                    const int64_t s1 = s0 + ((x + 1) % g.L - x) * stride;
-                    jm[(size_t)s0] |= (uint8_t)(1u << mu);
-                    jm[(size_t)s1] |= (uint8_t)(1u << (g.d + mu));
-                }
-                stride *= g.L;
-            }
-        }
-    }
-
     pa_ctx *c = new (std::nothrow) pa_ctx;
     if (!c)
         return fail(nullptr, PA_E_NOMEM, "out of host memory");
-    hipError_t e;
-    if (!g_kernels_configured) {
-        if ((e = pa_configure_kernels(&g_max_lds)) != hipSuccess) {
-            delete c;
-            return hip_fail(nullptr, e, "kernel attributes");
-        }
-        g_kernels_configured = true;
-    }
-    if (pa_sweep_lds_bytes(g.N) > (size_t)g_max_lds || (size_t)g.H * 4 > (size_t)g_max_lds) {
+    pa_status s = make_batch(cfg, 1, 0, workspace, workspace_bytes, stream, &c->b);
+    if (s != PA_OK) {
         delete c;
-        return fail(nullptr, PA_E_INVAL, "lattice too large for the workgroup LDS of this device");
-    }
-    if ((e = hipHostMalloc((void **)&c->hrec, sizeof(PaRecord), hipHostMallocDefault)) != hipSuccess) {
-        delete c;
-        return hip_fail(nullptr, e, "pinned record");
-    }
-    carve(g, (char *)workspace, &c->dv);
-    c->lp.d = g.d;
-    c->lp.L = g.L;
-    c->lp.N = g.N;
-    c->lp.H = g.H;
-    c->lp.seed = cfg->seed;
-    c->lp.run_id = cfg->run_id;
-    c->lp.R0 = g.R;
-    c->lp.cap = g.cap;
-    c->lp.stream = (hipStream_t)stream;
-    c->Rcur = g.R;
-
-    std::memset(c->hrec, 0, sizeof(PaRecord));
-    c->hrec->lnZ = (double)g.N * std::log(2.0); // Z_0 = 2^N at beta_0 = 0
-    for (int k = 0; k < 3; ++k)
-        c->hrec->T[k] = c->hrec->Tn[k] = 1ull << 32; // beta = 0 accepts every move
-    e = hipMemcpyAsync(c->dv.rec, c->hrec, sizeof(PaRecord), hipMemcpyHostToDevice, c->lp.stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(c->dv.jmask, jm.data(), jm.size(), hipMemcpyHostToDevice, c->lp.stream);
-    if (e == hipSuccess)
-        e = pa_launch_init(c->lp, c->dv, 0);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(c->lp.stream);
-    if (e != hipSuccess) {
-        hip_fail(nullptr, e, "pa_init");
-        (void)hipHostFree(c->hrec);
-        delete c;
-        return PA_E_DEVICE;
+        return s;
     }
     *out = c;
     return PA_OK;
@@ -261,17 +508,18 @@ pa_status pa_sweep(pa_ctx *c, int32_t theta)
 {
     if (!c)
         return fail(nullptr, PA_E_INVAL, "ctx is NULL");
+    Batch *b = &c->b;
     if (theta < 0)
-        return fail(c, PA_E_INVAL, "theta must be >= 0");
-    if ((uint64_t)c->sweeps + (uint64_t)theta > (1u << 20))
-        return fail(c, PA_E_INVAL, "more than 2^20 sweeps at one temperature");
+        return fail(b, PA_E_INVAL, "theta must be >= 0");
+    if ((uint64_t)b->sweeps + (uint64_t)theta > (1u << 20))
+        return fail(b, PA_E_INVAL, "more than 2^20 sweeps at one temperature");
     if (theta == 0)
         return PA_OK;
-    hipError_t e = pa_launch_sweep(c->lp, c->dv, c->cur, c->Rcur, c->step, c->sweeps, theta);
+    hipError_t e = pa_b_sweep(b->v, theta);
     if (e != hipSuccess)
-        return hip_fail(c, e, "pa_sweep");
-    c->sweeps += (uint32_t)theta;
-    c->sweeps_total += (uint64_t)theta;
+        return hip_fail(b, e, "pa_sweep");
+    b->sweeps += (uint32_t)theta;
+    b->sweeps_total += (uint64_t)theta;
     return PA_OK;
 }
 
@@ -279,23 +527,23 @@ pa_status pa_reweight(pa_ctx *c, double beta_next, double *lnQ_out)
 {
     if (!c)
         return fail(nullptr, PA_E_INVAL, "ctx is NULL");
-    if (!std::isfinite(beta_next) || beta_next < c->beta)
-        return fail(c, PA_E_INVAL, "beta_next must be finite and >= the current beta");
-    const double dbeta = beta_next - c->beta;
-    hipError_t e = pa_launch_reweight(c->lp, c->dv, c->cur, c->Rcur, dbeta, beta_next);
+    Batch *b = &c->b;
+    if (!std::isfinite(beta_next) || beta_next < b->beta)
+        return fail(b, PA_E_INVAL, "beta_next must be finite and >= the current beta");
+    hipError_t e = pa_b_reweight(b->v, beta_next);
     if (e != hipSuccess)
-        return hip_fail(c, e, "pa_reweight");
-    pa_status s = fetch_record(c, "pa_reweight");
+        return hip_fail(b, e, "pa_reweight");
+    pa_status s = fetch_records(b, "pa_reweight");
     if (s != PA_OK)
         return s;
-    if (!std::isfinite(c->hrec->lnQ)) {
-        c->reweighted = false;
-        return fail(c, PA_E_NONFINITE, "ln Q is not finite");
+    if (!std::isfinite(b->hrec[0].lnQ)) {
+        b->reweighted = false;
+        return fail(b, PA_E_NONFINITE, "ln Q is not finite");
     }
-    c->reweighted = true;
-    c->beta_next = beta_next;
+    b->reweighted = true;
+    b->beta_next = beta_next;
     if (lnQ_out)
-        *lnQ_out = c->hrec->lnQ;
+        *lnQ_out = b->hrec[0].lnQ;
     return PA_OK;
 }
 
@@ -303,36 +551,24 @@ pa_status pa_resample(pa_ctx *c, pa_resampler scheme, int64_t *R_new_out)
 {
     if (!c)
         return fail(nullptr, PA_E_INVAL, "ctx is NULL");
+    Batch *b = &c->b;
     if ((int)scheme < 0 || (int)scheme > 3)
-        return fail(c, PA_E_INVAL, "unknown resampling scheme");
-    if (!c->reweighted)
-        return fail(c, PA_E_STATE, "pa_resample needs a pa_reweight first");
-    const int64_t Rprev = c->Rcur, Rt = c->lp.R0;
-    const uint32_t step = c->step + 1;
-    hipError_t e = pa_launch_counts(c->lp, c->dv, c->cur, Rprev, Rt, (int)scheme, step);
+        return fail(b, PA_E_INVAL, "unknown resampling scheme");
+    if (!b->reweighted)
+        return fail(b, PA_E_STATE, "pa_resample needs a pa_reweight first");
+    hipError_t e = pa_b_resample(b->v, (int)scheme, 0);
     if (e != hipSuccess)
-        return hip_fail(c, e, "pa_resample counts");
-    pa_status s = fetch_record(c, "pa_resample");
+        return hip_fail(b, e, "pa_resample");
+    pa_status s = fetch_records(b, "pa_resample");
     if (s != PA_OK)
         return s;
-    if (c->hrec->err)
-        return fail(c, PA_E_DEVICE, "prefix-sum look-back timed out");
-    const int64_t Rnew = (int64_t)c->hrec->Rnew;
-    if (Rnew > c->lp.cap)
-        return fail(c, PA_E_CAPACITY, "resampled population exceeds the capacity");
-    if (Rnew == 0)
-        return fail(c, PA_E_EXTINCT, "resampled population is empty");
-    e = pa_launch_apply(c->lp, c->dv, c->cur, Rprev, Rnew);
-    if (e != hipSuccess)
-        return hip_fail(c, e, "pa_resample apply");
-    c->cur ^= 1;
-    c->Rcur = Rnew;
-    c->beta = c->beta_next;
-    c->step = step;
-    c->sweeps = 0;
-    c->reweighted = false;
+    if (b->hrec[0].skip)
+        return status_error(b, b->hrec[0].status);
+    b->beta = b->beta_next;
+    b->sweeps = 0;
+    b->reweighted = false;
     if (R_new_out)
-        *R_new_out = Rnew;
+        *R_new_out = (int64_t)b->hrec[0].Rcur;
     return PA_OK;
 }
 
@@ -340,17 +576,18 @@ pa_status pa_observables(pa_ctx *c, pa_obs *out)
 {
     if (!c)
         return fail(nullptr, PA_E_INVAL, "ctx is NULL");
+    Batch *b = &c->b;
     if (!out)
-        return fail(c, PA_E_INVAL, "out is NULL");
-    hipError_t e = pa_launch_observables(c->lp, c->dv, c->cur, c->Rcur);
+        return fail(b, PA_E_INVAL, "out is NULL");
+    hipError_t e = pa_b_observables(b->v, -1);
     if (e != hipSuccess)
-        return hip_fail(c, e, "pa_observables");
-    pa_status s = fetch_record(c, "pa_observables");
+        return hip_fail(b, e, "pa_observables");
+    pa_status s = fetch_records(b, "pa_observables");
     if (s != PA_OK)
         return s;
-    const PaRecord &r = *c->hrec;
-    out->R = c->Rcur;
-    out->beta = c->beta;
+    const PaRecord &r = b->hrec[0];
+    out->R = (int64_t)r.Rcur;
+    out->beta = r.beta;
     out->sum_E = (int64_t)r.sumE;
     out->sum_E2 = (int64_t)r.sumE2;
     out->sum_absM = (int64_t)r.sumAbsM;
@@ -371,12 +608,13 @@ pa_status pa_free_energy(pa_ctx *c, double *lnZ_out)
 {
     if (!c)
         return fail(nullptr, PA_E_INVAL, "ctx is NULL");
+    Batch *b = &c->b;
     if (!lnZ_out)
-        return fail(c, PA_E_INVAL, "lnZ_out is NULL");
-    pa_status s = fetch_record(c, "pa_free_energy");
+        return fail(b, PA_E_INVAL, "lnZ_out is NULL");
+    pa_status s = fetch_records(b, "pa_free_energy");
     if (s != PA_OK)
         return s;
-    *lnZ_out = c->hrec->lnZ;
+    *lnZ_out = b->hrec[0].lnZ;
     return PA_OK;
 }
 
@@ -385,96 +623,76 @@ pa_status pa_export_state(pa_ctx *c, pa_host_state *st)
     if (!c)
         return fail(nullptr, PA_E_INVAL, "ctx is NULL");
     if (!st)
-        return fail(c, PA_E_INVAL, "state is NULL");
-    pa_status s = fetch_record(c, "pa_export_state");
-    if (s != PA_OK)
-        return s;
-    const int64_t R = c->Rcur;
-    const int k = c->cur;
-    hipError_t e = hipSuccess;
-    if (st->spins)
-        e = hipMemcpy(st->spins, c->dv.spins[k], (size_t)((R + 63) / 64) * c->lp.N * 8, hipMemcpyDeviceToHost);
-    if (e == hipSuccess && st->energy)
-        e = hipMemcpy(st->energy, c->dv.E[k], (size_t)R * 4, hipMemcpyDeviceToHost);
-    if (e == hipSuccess && st->magnetization)
-        e = hipMemcpy(st->magnetization, c->dv.M[k], (size_t)R * 4, hipMemcpyDeviceToHost);
-    if (e == hipSuccess && st->label)
-        e = hipMemcpy(st->label, c->dv.label[k], (size_t)R * 4, hipMemcpyDeviceToHost);
-    if (e != hipSuccess)
-        return hip_fail(c, e, "pa_export_state");
-    st->R = R;
-    st->step = c->step;
-    st->sweeps = c->sweeps;
-    st->beta = c->beta;
-    st->lnZ = c->hrec->lnZ;
-    return PA_OK;
+        return fail(&c->b, PA_E_INVAL, "state is NULL");
+    return export_run(&c->b, 0, st);
 }
 
 pa_status pa_import_state(pa_ctx *c, const pa_host_state *st)
 {
     if (!c)
         return fail(nullptr, PA_E_INVAL, "ctx is NULL");
+    Batch *b = &c->b;
+    const PaRunDesc &d = b->hdesc[0];
     if (!st || !st->spins || !st->energy || !st->magnetization || !st->label)
-        return fail(c, PA_E_INVAL, "state and all four arrays are required");
-    if (st->R < 1 || st->R > c->lp.cap)
-        return fail(c, PA_E_INVAL, "state R must be in [1, capacity]");
+        return fail(b, PA_E_INVAL, "state and all four arrays are required");
+    if (st->R < 1 || st->R > d.cap)
+        return fail(b, PA_E_INVAL, "state R must be in [1, capacity]");
     if (!std::isfinite(st->beta) || st->beta < 0.0 || !std::isfinite(st->lnZ))
-        return fail(c, PA_E_INVAL, "beta and lnZ must be finite, beta >= 0");
+        return fail(b, PA_E_INVAL, "beta and lnZ must be finite, beta >= 0");
     if (st->sweeps > (1u << 20))
-        return fail(c, PA_E_INVAL, "sweeps out of range");
-    const int N = c->lp.N, DN = c->lp.d * c->lp.N;
+        return fail(b, PA_E_INVAL, "sweeps out of range");
+    const int N = d.N, DN = d.d * d.N;
     for (int64_t j = 0; j < st->R; ++j) {
-        if ((int64_t)st->label[j] >= c->lp.R0)
-            return fail(c, PA_E_INVAL, "label out of range");
+        if ((int64_t)st->label[j] >= d.R0)
+            return fail(b, PA_E_INVAL, "label out of range");
         const int32_t E = st->energy[j], M = st->magnetization[j];
         if (E < -DN || E > DN || ((E + DN) & 1) || M < -N || M > N)
-            return fail(c, PA_E_INVAL, "energy or magnetisation out of range");
+            return fail(b, PA_E_INVAL, "energy or magnetisation out of range");
     }
+    pa_status s = fetch_records(b, "pa_import_state");
+    if (s != PA_OK)
+        return s;
     const int64_t R = st->R;
-    const int k = c->cur;
-    hipError_t e = hipMemcpy(c->dv.spins[k], st->spins, (size_t)((R + 63) / 64) * N * 8, hipMemcpyHostToDevice);
+    const int k = b->hrec[0].cur;
+    hipError_t e = hipMemcpy(d.dv.spins[k], st->spins, (size_t)((R + 63) / 64) * N * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpy(c->dv.E[k], st->energy, (size_t)R * 4, hipMemcpyHostToDevice);
+        e = hipMemcpy(d.dv.E[k], st->energy, (size_t)R * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpy(c->dv.M[k], st->magnetization, (size_t)R * 4, hipMemcpyHostToDevice);
+        e = hipMemcpy(d.dv.M[k], st->magnetization, (size_t)R * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpy(c->dv.label[k], st->label, (size_t)R * 4, hipMemcpyHostToDevice);
+        e = hipMemcpy(d.dv.label[k], st->label, (size_t)R * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = pa_launch_set_beta(c->lp, c->dv, st->beta, st->lnZ);
+        e = pa_b_set_beta(b->v, st->beta, st->lnZ, st->step, st->sweeps, (uint64_t)R);
     if (e == hipSuccess)
-        e = hipStreamSynchronize(c->lp.stream);
+        e = hipStreamSynchronize(b->v.stream);
     if (e != hipSuccess)
-        return hip_fail(c, e, "pa_import_state");
-    c->Rcur = R;
-    c->step = st->step;
-    c->sweeps = st->sweeps;
-    c->beta = st->beta;
-    c->reweighted = false;
+        return hip_fail(b, e, "pa_import_state");
+    b->beta = st->beta;
+    b->sweeps = st->sweeps;
+    b->reweighted = false;
     return PA_OK;
 }
 
-pa_status pa_overlap(pa_ctx *a, pa_ctx *b, int64_t *hist_out)
+pa_status pa_overlap(pa_ctx *a, pa_ctx *c2, int64_t *hist_out)
 {
-    if (!a || !b)
-        return fail(a, PA_E_INVAL, "ctx is NULL");
+    if (!a || !c2)
+        return fail(a ? &a->b : nullptr, PA_E_INVAL, "ctx is NULL");
+    Batch *A = &a->b, *B = &c2->b;
     if (!hist_out)
-        return fail(a, PA_E_INVAL, "hist_out is NULL");
-    if (a->lp.d != b->lp.d || a->lp.L != b->lp.L)
-        return fail(a, PA_E_INVAL, "runs on different lattices");
-    const int64_t R = a->Rcur < b->Rcur ? a->Rcur : b->Rcur;
-    const int N = a->lp.N;
-    hipError_t e = hipStreamSynchronize(b->lp.stream);
+        return fail(A, PA_E_INVAL, "hist_out is NULL");
+    if (A->hdesc[0].d != B->hdesc[0].d || A->hdesc[0].L != B->hdesc[0].L)
+        return fail(A, PA_E_INVAL, "runs on different lattices");
+    const int N = A->hdesc[0].N;
+    hipError_t e = hipStreamSynchronize(B->v.stream);
     if (e == hipSuccess)
-        e = hipMemsetAsync(a->dv.qhist, 0, (size_t)(N + 1) * 8, a->lp.stream);
-    if (e == hipSuccess)
-        e = pa_launch_overlap(a->lp, a->dv.spins[a->cur], b->dv.spins[b->cur], R, a->dv.qhist);
+        e = pa_launch_overlap(A->ddesc, B->ddesc, N, A->v.ncol, A->hdesc[0].dv.qhist, A->v.stream);
     std::vector<unsigned long long> h((size_t)N + 1);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(h.data(), a->dv.qhist, h.size() * 8, hipMemcpyDeviceToHost, a->lp.stream);
+        e = hipMemcpyAsync(h.data(), A->hdesc[0].dv.qhist, h.size() * 8, hipMemcpyDeviceToHost, A->v.stream);
     if (e == hipSuccess)
-        e = hipStreamSynchronize(a->lp.stream);
+        e = hipStreamSynchronize(A->v.stream);
     if (e != hipSuccess)
-        return hip_fail(a, e, "pa_overlap");
+        return hip_fail(A, e, "pa_overlap");
     for (int k = 0; k <= N; ++k)
         hist_out[k] = (int64_t)h[(size_t)k];
     return PA_OK;
@@ -484,15 +702,16 @@ pa_status pa_step_alpha(pa_ctx *c, double dbeta, double *alpha_out)
 {
     if (!c)
         return fail(nullptr, PA_E_INVAL, "ctx is NULL");
+    Batch *b = &c->b;
     if (!alpha_out || !std::isfinite(dbeta) || dbeta < 0.0)
-        return fail(c, PA_E_INVAL, "dbeta must be finite and >= 0; alpha_out non-NULL");
-    hipError_t e = pa_launch_rule(c->lp, c->dv, c->cur, c->Rcur, 0.0, dbeta, 0, 0);
+        return fail(b, PA_E_INVAL, "dbeta must be finite and >= 0; alpha_out non-NULL");
+    hipError_t e = pa_b_rule(b->v, 0.0, dbeta, 0, 0);
     if (e != hipSuccess)
-        return hip_fail(c, e, "pa_step_alpha");
-    pa_status s = fetch_record(c, "pa_step_alpha");
+        return hip_fail(b, e, "pa_step_alpha");
+    pa_status s = fetch_records(b, "pa_step_alpha");
     if (s != PA_OK)
         return s;
-    *alpha_out = c->hrec->rule_alpha;
+    *alpha_out = b->hrec[0].rule_alpha;
     return PA_OK;
 }
 
@@ -500,16 +719,17 @@ pa_status pa_step_rule(pa_ctx *c, double alpha_star, double dbeta_max, int32_t i
 {
     if (!c)
         return fail(nullptr, PA_E_INVAL, "ctx is NULL");
+    Batch *b = &c->b;
     if (!dbeta_out || !(alpha_star > 0.0 && alpha_star < 1.0) || !std::isfinite(dbeta_max) || dbeta_max <= 0.0 ||
         iterations < 1 || iterations > 200)
-        return fail(c, PA_E_INVAL, "need 0 < alpha_star < 1, dbeta_max > 0, 1 <= iterations <= 200");
-    hipError_t e = pa_launch_rule(c->lp, c->dv, c->cur, c->Rcur, alpha_star, dbeta_max, iterations, 1);
+        return fail(b, PA_E_INVAL, "need 0 < alpha_star < 1, dbeta_max > 0, 1 <= iterations <= 200");
+    hipError_t e = pa_b_rule(b->v, alpha_star, dbeta_max, iterations, 1);
     if (e != hipSuccess)
-        return hip_fail(c, e, "pa_step_rule");
-    pa_status s = fetch_record(c, "pa_step_rule");
+        return hip_fail(b, e, "pa_step_rule");
+    pa_status s = fetch_records(b, "pa_step_rule");
     if (s != PA_OK)
         return s;
-    *dbeta_out = c->hrec->rule_dbeta;
+    *dbeta_out = b->hrec[0].rule_dbeta;
     return PA_OK;
 }
 
@@ -517,14 +737,15 @@ pa_status pa_get_counters(pa_ctx *c, pa_counters *out)
 {
     if (!c)
         return fail(nullptr, PA_E_INVAL, "ctx is NULL");
+    Batch *b = &c->b;
     if (!out)
-        return fail(c, PA_E_INVAL, "out is NULL");
-    pa_status s = fetch_record(c, "pa_get_counters");
+        return fail(b, PA_E_INVAL, "out is NULL");
+    pa_status s = fetch_records(b, "pa_get_counters");
     if (s != PA_OK)
         return s;
-    out->philox_calls = c->hrec->philox_calls;
-    out->site_updates = c->hrec->site_updates;
-    out->sweeps = c->sweeps_total;
+    out->philox_calls = b->hrec[0].philox_calls;
+    out->site_updates = b->hrec[0].site_updates;
+    out->sweeps = b->sweeps_total;
     return PA_OK;
 }
 
@@ -532,11 +753,249 @@ void pa_destroy(pa_ctx *c)
 {
     if (!c)
         return;
-    if (c->hrec)
-        (void)hipHostFree(c->hrec);
+    free_batch(&c->b);
     delete c;
 }
 
-const char *pa_last_error(const pa_ctx *c) { return c ? c->err.c_str() : g_init_err.c_str(); }
+const char *pa_last_error(const pa_ctx *c) { return c ? c->b.err.c_str() : g_init_err.c_str(); }
+
+// ====================================================================== batches
+pa_status pa_batch_required_bytes(const pa_config *cfgs, int32_t nruns, int32_t max_points, uint64_t *bytes)
+{
+    std::vector<Geometry> geo;
+    std::string msg;
+    pa_status s = check_batch(cfgs, nruns, max_points, &geo, &msg);
+    if (s != PA_OK)
+        return fail(nullptr, s, msg);
+    if (!bytes)
+        return fail(nullptr, PA_E_INVAL, "bytes is NULL");
+    *bytes = layout(geo, max_points, nullptr, nullptr, nullptr);
+    return PA_OK;
+}
+
+pa_status pa_batch_create(const pa_config *cfgs, int32_t nruns, int32_t max_points, void *workspace,
+                          uint64_t workspace_bytes, void *stream, pa_batch **out)
+{
+    if (!out)
+        return fail(nullptr, PA_E_INVAL, "out is NULL");
+    *out = nullptr;
+    pa_batch *p = new (std::nothrow) pa_batch;
+    if (!p)
+        return fail(nullptr, PA_E_NOMEM, "out of host memory");
+    pa_status s = make_batch(cfgs, nruns, max_points, workspace, workspace_bytes, stream, &p->b);
+    if (s != PA_OK) {
+        delete p;
+        return s;
+    }
+    *out = p;
+    return PA_OK;
+}
+
+pa_status pa_batch_tune(pa_batch *p, int32_t theta, int32_t *threads_out)
+{
+    if (!p)
+        return fail(nullptr, PA_E_INVAL, "batch is NULL");
+    Batch *b = &p->b;
+    if (theta < 1 || theta > 64)
+        return fail(b, PA_E_INVAL, "theta must be in [1, 64]");
+    // Each candidate sweeps the current populations; the populations are
+    // re-initialised afterwards (initial sampling is deterministic), so tuning
+    // leaves no trace.  Every candidate gives the same bits by construction.
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess)
+        e = hipEventCreate(&e1);
+    if (e != hipSuccess)
+        return hip_fail(b, e, "pa_batch_tune");
+    for (int g = 0; g < b->v.ngroups && e == hipSuccess; ++g) {
+        float best = 1e30f;
+        int best_t = b->v.gthreads[g];
+        for (int t = 64; t <= 512 && e == hipSuccess; t += 64) {
+            if (!sweep_threads_ok(b->v.gN[g], b->v.gd[g], t))
+                continue;
+            e = pa_b_sweep_group(b->v, g, theta, t); // warm-up
+            if (e == hipSuccess)
+                e = hipEventRecord(e0, b->v.stream);
+            if (e == hipSuccess)
+                e = pa_b_sweep_group(b->v, g, theta, t);
+            if (e == hipSuccess)
+                e = hipEventRecord(e1, b->v.stream);
+            if (e == hipSuccess)
+                e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess)
+                e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && ms < best) {
+                best = ms;
+                best_t = t;
+            }
+        }
+        b->v.gthreads[g] = best_t;
+        if (threads_out)
+            threads_out[g] = best_t;
+    }
+    if (e == hipSuccess)
+        e = pa_b_init(b->v);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(b->v.stream);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess)
+        return hip_fail(b, e, "pa_batch_tune");
+    return PA_OK;
+}
+
+pa_status pa_batch_groups(pa_batch *p, int32_t *ngroups, int32_t *threads)
+{
+    if (!p || !ngroups)
+        return fail(p ? &p->b : nullptr, PA_E_INVAL, "NULL argument");
+    *ngroups = p->b.v.ngroups;
+    if (threads)
+        for (int g = 0; g < p->b.v.ngroups; ++g)
+            threads[g] = p->b.v.gthreads[g];
+    return PA_OK;
+}
+
+pa_status pa_batch_anneal(pa_batch *p, const double *betas, int32_t npoints, int32_t theta, pa_resampler scheme,
+                          int32_t use_graph)
+{
+    if (!p)
+        return fail(nullptr, PA_E_INVAL, "batch is NULL");
+    Batch *b = &p->b;
+    if (!betas || npoints < 1 || npoints > b->max_points)
+        return fail(b, PA_E_INVAL, "need 1 <= npoints <= max_points of pa_batch_create");
+    if (betas[0] != 0.0)
+        return fail(b, PA_E_INVAL, "the anneal starts at beta_0 = 0");
+    for (int i = 1; i < npoints; ++i)
+        if (!std::isfinite(betas[i]) || betas[i] < betas[i - 1])
+            return fail(b, PA_E_INVAL, "betas must be finite and non-decreasing");
+    if (theta < 0 || theta > (1 << 20))
+        return fail(b, PA_E_INVAL, "theta out of range");
+    if ((int)scheme < 0 || (int)scheme > 3)
+        return fail(b, PA_E_INVAL, "unknown resampling scheme");
+    const hipStream_t st = b->v.stream;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipSuccess;
+    if (use_graph)
+        e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    const PaBatchView &v = b->v; // record rows keep the stride max_points
+    if (e == hipSuccess)
+        e = pa_b_init(v);
+    if (e == hipSuccess)
+        e = pa_b_observables(v, 0);
+    for (int i = 1; i < npoints && e == hipSuccess; ++i) {
+        e = pa_b_reweight(v, betas[i]);
+        if (e == hipSuccess)
+            e = pa_b_resample(v, (int)scheme, 1);
+        if (e == hipSuccess && theta > 0)
+            e = pa_b_sweep(v, theta);
+        if (e == hipSuccess)
+            e = pa_b_observables(v, i);
+    }
+    if (use_graph) {
+        hipError_t e2 = hipStreamEndCapture(st, &graph);
+        if (e == hipSuccess)
+            e = e2;
+        if (e == hipSuccess)
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e == hipSuccess)
+            e = hipGraphLaunch(exec, st);
+    }
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (exec)
+        (void)hipGraphExecDestroy(exec);
+    if (graph)
+        (void)hipGraphDestroy(graph);
+    if (e != hipSuccess)
+        return hip_fail(b, e, "pa_batch_anneal");
+    b->anneal_points = npoints;
+    return PA_OK;
+}
+
+pa_status pa_batch_records(pa_batch *p, pa_step_record *out)
+{
+    if (!p)
+        return fail(nullptr, PA_E_INVAL, "batch is NULL");
+    Batch *b = &p->b;
+    if (!out || b->anneal_points == 0)
+        return fail(b, PA_E_STATE, "no anneal recorded");
+    static_assert(sizeof(pa_step_record) == sizeof(PaStepRecord), "record layout");
+    std::vector<PaStepRecord> all((size_t)b->M * b->max_points);
+    hipError_t e = hipMemcpy(all.data(), b->v.steprec, all.size() * sizeof(PaStepRecord), hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return hip_fail(b, e, "pa_batch_records");
+    for (int m = 0; m < b->M; ++m)
+        std::memcpy(out + (size_t)m * b->anneal_points, all.data() + (size_t)m * b->max_points,
+                    sizeof(PaStepRecord) * (size_t)b->anneal_points);
+    return PA_OK;
+}
+
+pa_status pa_batch_export_run(pa_batch *p, int32_t run, pa_host_state *st)
+{
+    if (!p)
+        return fail(nullptr, PA_E_INVAL, "batch is NULL");
+    Batch *b = &p->b;
+    if (!st || run < 0 || run >= b->M)
+        return fail(b, PA_E_INVAL, "bad run index or NULL state");
+    return export_run(b, run, st);
+}
+
+pa_status pa_batch_combine(pa_batch *p, const int32_t *group_of_run, int32_t ngroups, int32_t point,
+                           pa_combined *out)
+{
+    if (!p)
+        return fail(nullptr, PA_E_INVAL, "batch is NULL");
+    Batch *b = &p->b;
+    if (!group_of_run || !out || ngroups < 1 || ngroups > b->M)
+        return fail(b, PA_E_INVAL, "need group_of_run, out and 1 <= ngroups <= nruns");
+    if (b->anneal_points == 0 || point < 0 || point >= b->anneal_points)
+        return fail(b, PA_E_INVAL, "point outside the recorded anneal");
+    std::vector<int32_t> Ns(b->M);
+    for (int m = 0; m < b->M; ++m) {
+        if (group_of_run[m] < -1 || group_of_run[m] >= ngroups)
+            return fail(b, PA_E_INVAL, "group index out of range (-1 = no group)");
+        Ns[m] = b->hdesc[m].N;
+    }
+    PaBatchView v = b->v;
+    v.npoints = b->max_points;
+    hipError_t e = hipMemcpyAsync(b->dgroup, group_of_run, 4ull * b->M, hipMemcpyHostToDevice, v.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->dNs, Ns.data(), 4ull * b->M, hipMemcpyHostToDevice, v.stream);
+    if (e == hipSuccess)
+        e = pa_launch_combine(v, point, b->dgroup, ngroups, b->dNs, b->dcomb);
+    std::vector<double> h((size_t)ngroups * 10);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h.data(), b->dcomb, h.size() * 8, hipMemcpyDeviceToHost, v.stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(v.stream);
+    if (e != hipSuccess)
+        return hip_fail(b, e, "pa_batch_combine");
+    for (int g = 0; g < ngroups; ++g) {
+        const double *o = h.data() + (size_t)g * 10;
+        out[g].lnZ = o[0];
+        out[g].e = o[1];
+        out[g].e2 = o[2];
+        out[g].abs_m = o[3];
+        out[g].m2 = o[4];
+        out[g].c = o[5];
+        out[g].chi = o[6];
+        out[g].n_eff = o[7];
+        out[g].runs = (int32_t)o[8];
+        out[g].beta = o[9];
+    }
+    return PA_OK;
+}
+
+void pa_batch_destroy(pa_batch *p)
+{
+    if (!p)
+        return;
+    free_batch(&p->b);
+    delete p;
+}
+
+const char *pa_batch_last_error(const pa_batch *p) { return p ? p->b.err.c_str() : g_init_err.c_str(); }
 
 } // extern "C"

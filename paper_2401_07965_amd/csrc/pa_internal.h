@@ -1,13 +1,34 @@
-// Internal interface between the host state machine (pa_api.cpp) and the
-// kernels (pa_kernels.hip).  Not part of the public C ABI.
+// Internal interface between the host side (pa_api.cpp) and the kernels
+// (pa_kernels.hip).  Not part of the public C ABI.
+//
+// Every kernel works on a batch of independent runs: the run a workgroup
+// serves comes from a per-launch block map in device memory, and each run's
+// state (population size, ping-pong index, temperature, step) lives in its
+// device record, so a whole anneal of many runs needs no host round trip and
+// can be captured in one HIP graph.  A single run is a batch of one.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Status bits of a run (PaRecord::status).
+#define PA_ST_SCAN_TIMEOUT 1u
+#define PA_ST_CAPACITY 2u
+#define PA_ST_EXTINCT 4u
+#define PA_ST_NONFINITE 8u
+#define PA_ST_FROZEN 16u // batch mode: a failed step froze the run
+
 // Per-run scalars that live in device memory, written by the kernels.
 struct PaRecord {
-    // histogram of the current population (pa_reweight)
+    int32_t cur;      // ping-pong buffer holding the population
+    uint32_t status;  // PA_ST_* bits of the latest resampling (sticky when frozen)
+    uint32_t skip;    // latest resampling was not applied
+    uint32_t step;    // temperature index i
+    uint32_t sweeps;  // sweeps done at step i
+    uint32_t pad0;
+    uint64_t Rcur;    // replicas in the population
+    double beta;      // current inverse temperature
+    // histogram of the current population (reweight, adaptive step)
     int32_t emin, emax;
     // Q(beta_cur, beta_next): Eq. (1) with the shift by E_min
     double qsum, lnQ, dbeta, beta_next;
@@ -15,10 +36,10 @@ struct PaRecord {
     uint64_t Tn[3]; // Metropolis thresholds at beta_next for dE = 4, 8, 12
     uint64_t T[3];  // thresholds at the current beta (used by the sweeps)
     // resampling
-    uint64_t Rprev, Rnew;
+    uint64_t Rprev;
+    unsigned long long Rnew, Ctot;
     double sv;
     double lnZ; // ln Z_0 + sum_k ln Q_k, Eq. (7)
-    unsigned long long Ctot; // total of the weight scan (equals S)
     // observables (exact integer sums, then the finalised averages)
     unsigned long long sumE, sumE2, sumAbsM, sumM2, sumC2, families;
     double sumClnC;
@@ -26,8 +47,13 @@ struct PaRecord {
     double rule_dbeta, rule_alpha; // adaptive step: chosen dbeta and its overlap
     unsigned long long philox_calls; // Philox4x32-10 evaluations of all sweeps so far
     unsigned long long site_updates; // word-site updates (64 attempts each) so far
-    uint32_t err; // bit 0: scan look-back gave up waiting
-    uint32_t pad;
+};
+
+// One row per run and temperature point of a batched anneal.
+struct PaStepRecord {
+    double beta, lnQ, lnZ, sv, e, e2, abs_m, m2, rho_t, S_f;
+    long long R, sumE, sumE2, sumAbsM, sumM2, sumC2, families;
+    uint32_t status, pad;
 };
 
 struct PaScanTile {
@@ -38,7 +64,7 @@ struct PaScanTile {
 #define PA_SCAN_THREADS 256
 #define PA_SCAN_ITEMS 8
 #define PA_SCAN_TILE (PA_SCAN_THREADS * PA_SCAN_ITEMS)
-#define PA_RED_BLOCKS 256 // partial sums of the fixed-order reductions
+#define PA_CHUNK 2048 // replicas (or families) per workgroup of the per-replica kernels
 
 // Device buffers of one run, carved from the caller's workspace.
 struct PaDev {
@@ -52,33 +78,61 @@ struct PaDev {
     uint64_t *C;
     unsigned long long *qhist; // [N+1] overlap histogram
     PaScanTile *tiles;
-    uint32_t *ticket;
-    uint32_t *fam; // [R0] replicas per family
-    double *partial; // [PA_RED_BLOCKS]
+    double *partial; // fixed-order partial sums, one per chunk
+    uint32_t *fam;   // [R0] replicas per family
     PaRecord *rec;
 };
 
-struct PaLaunch {
+struct PaRunDesc {
     int d, L, N, H;
     uint32_t seed, run_id;
     int64_t R0, cap;
+    PaDev dv;
+};
+
+// Block map entry: the run a workgroup serves and its index within the run.
+struct PaBlk {
+    uint32_t run, idx;
+};
+
+#define PA_MAX_GROUPS 16
+
+// What the launchers need to address a batch (device pointers + counts).
+struct PaBatchView {
+    const PaRunDesc *runs; // [nruns]
+    uint32_t nruns;
+    const PaBlk *rep;  // chunks of PA_CHUNK replica slots (capacity)
+    uint32_t nrep;
+    const PaBlk *fam;  // chunks of PA_CHUNK families
+    uint32_t nfam;
+    const PaBlk *col;  // all 64-replica columns (capacity)
+    uint32_t ncol;
+    const PaBlk *tile; // scan tiles, run-major
+    uint32_t ntile;
+    uint32_t *ticket;  // scan tile ticket
+    int maxH;
+    int ngroups;       // runs grouped by lattice shape for the sweeps
+    const PaBlk *gcol[PA_MAX_GROUPS];
+    uint32_t gncol[PA_MAX_GROUPS];
+    int gd[PA_MAX_GROUPS], gN[PA_MAX_GROUPS], gthreads[PA_MAX_GROUPS];
+    PaStepRecord *steprec; // batched anneal: [nruns][npoints]
+    int npoints;
     hipStream_t stream;
 };
 
-// kernels' host launchers (pa_kernels.hip); each returns the launch error
-hipError_t pa_launch_init(const PaLaunch &p, const PaDev &dv, int cur);
-hipError_t pa_launch_sweep(const PaLaunch &p, const PaDev &dv, int cur, int64_t Rcur, uint32_t step,
-                           uint32_t t0, int theta);
-hipError_t pa_launch_reweight(const PaLaunch &p, const PaDev &dv, int cur, int64_t Rcur, double dbeta,
-                              double beta_next);
-hipError_t pa_launch_counts(const PaLaunch &p, const PaDev &dv, int cur, int64_t Rprev, int64_t Rt,
-                            int scheme, uint32_t step);
-hipError_t pa_launch_apply(const PaLaunch &p, const PaDev &dv, int cur, int64_t Rprev, int64_t Rnew);
-hipError_t pa_launch_observables(const PaLaunch &p, const PaDev &dv, int cur, int64_t Rcur);
-hipError_t pa_launch_overlap(const PaLaunch &p, const uint64_t *a, const uint64_t *b, int64_t R,
-                             unsigned long long *hist);
-hipError_t pa_launch_rule(const PaLaunch &p, const PaDev &dv, int cur, int64_t Rcur, double alpha_star,
-                          double dbeta_max, int iterations, int bisect);
-hipError_t pa_launch_set_beta(const PaLaunch &p, const PaDev &dv, double beta, double lnZ);
-hipError_t pa_configure_kernels(int *max_lds); // largest LDS a workgroup may use
+// launchers (pa_kernels.hip); each returns the first launch error
+hipError_t pa_b_init(const PaBatchView &v);
+hipError_t pa_b_sweep(const PaBatchView &v, int theta);
+hipError_t pa_b_sweep_group(const PaBatchView &v, int g, int theta, int threads);
+hipError_t pa_b_reweight(const PaBatchView &v, double beta_next);
+hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze);
+hipError_t pa_b_observables(const PaBatchView &v, int point);
+hipError_t pa_b_rule(const PaBatchView &v, double alpha_star, double dbeta_max, int iterations, int bisect);
+hipError_t pa_b_set_beta(const PaBatchView &v, double beta, double lnZ, uint32_t step, uint32_t sweeps,
+                         uint64_t R);
+hipError_t pa_launch_combine(const PaBatchView &v, int point, const int32_t *group_of, int ngroups,
+                             const int32_t *Ns, double *out);
+hipError_t pa_launch_overlap(const PaRunDesc *a, const PaRunDesc *b, int N, uint32_t ncols_a,
+                             unsigned long long *hist, hipStream_t st);
+hipError_t pa_query_lds(int *max_lds);
 size_t pa_sweep_lds_bytes(int N);

@@ -3,6 +3,12 @@
 // Spins are multi-spin coded: bit b of word [w][s] is replica 64w+b at site s,
 // 1 meaning sigma = -1.  One workgroup owns one 64-replica word column: the
 // whole lattice of its 64 replicas (N words) sits in LDS while it is swept.
+//
+// Every kernel serves a batch of runs through a block map (PaBlk: run, index
+// within the run); a run's population size, ping-pong index, temperature and
+// step are read from its device record, so launches need no host knowledge
+// of the state and a whole anneal can be captured in a graph.  Grids cover
+// each run's capacity; workgroups past the live population return at once.
 #include "pa_device.h"
 #include "pa_internal.h"
 
@@ -11,7 +17,13 @@
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kSweepMaxThreads = 512;
+constexpr int kRuleThreads = 1024;
+constexpr int kRuleCache = 4096; // levels whose weights stay in LDS between the two sums
 
+__device__ __forceinline__ bool frozen(const PaRecord *rec) { return (rec->status & PA_ST_FROZEN) != 0u; }
+
+// ------------------------------------------------------------------ helpers
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -27,32 +39,54 @@ int grid_for(int64_t n, int threads = kThreads, int cap = 4096)
     return (int)(g > cap ? cap : g);
 }
 
-hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st)
+// ------------------------------------------------------------------ step 1: init
+// Record of a fresh run at beta_0 = 0: ln Z_0 = N ln 2, every move accepted.
+__global__ void k_init_rec(const PaRunDesc *__restrict__ runs)
 {
-    if (n <= 0)
-        return hipSuccess;
-    k_fill_u32<<<grid_for(n), kThreads, 0, st>>>(p, n, v);
-    return hipGetLastError();
+    const PaRunDesc &rd = runs[blockIdx.x];
+    if (threadIdx.x != 0)
+        return;
+    PaRecord *rec = rd.dv.rec;
+    rec->cur = 0;
+    rec->status = 0;
+    rec->skip = 0;
+    rec->step = 0;
+    rec->sweeps = 0;
+    rec->Rcur = (uint64_t)rd.R0;
+    rec->beta = 0.0;
+    rec->lnQ = 0.0;
+    rec->lnZ = (double)rd.N * 0x1.62e42fefa39efp-1; // N * RN(ln 2)
+    rec->sv = 0.0;
+    for (int k = 0; k < 3; ++k)
+        rec->T[k] = rec->Tn[k] = 1ull << 32;
+    rec->philox_calls = 0;
+    rec->site_updates = 0;
 }
 
-// ------------------------------------------------------------------ step 1: init
 // Replica 64w+b, site s: bit b of x0 | x1<<32 of Philox(s, w, 0, INIT<<28).
-__global__ void k_init_spins(uint64_t *spins, int N, int64_t W, uint32_t seed, uint32_t run_id)
+__global__ __launch_bounds__(kThreads) void k_init_spins(const PaRunDesc *__restrict__ runs,
+                                                         const PaBlk *__restrict__ map)
 {
-    const int64_t n = W * N;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t w = (uint32_t)(i / N), s = (uint32_t)(i - (int64_t)w * N);
-        const pa_philox_out o = pa_philox(seed, run_id, s, w, 0u, PA_PURPOSE_INIT << 28);
-        spins[i] = (uint64_t)o.x0 | ((uint64_t)o.x1 << 32);
+    const PaBlk b = map[blockIdx.x];
+    const PaRunDesc &rd = runs[b.run];
+    const uint32_t w = b.idx;
+    if ((int64_t)w * 64 >= rd.R0)
+        return;
+    uint64_t *g = rd.dv.spins[0] + (size_t)w * rd.N;
+    for (int s = threadIdx.x; s < rd.N; s += blockDim.x) {
+        const pa_philox_out o = pa_philox(rd.seed, rd.run_id, (uint32_t)s, w, 0u, PA_PURPOSE_INIT << 28);
+        g[s] = (uint64_t)o.x0 | ((uint64_t)o.x1 << 32);
     }
 }
 
-__global__ void k_init_labels(uint32_t *label, int64_t R)
+__global__ __launch_bounds__(kThreads) void k_init_labels(const PaRunDesc *__restrict__ runs,
+                                                          const PaBlk *__restrict__ map)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < R;
-         i += (int64_t)gridDim.x * blockDim.x)
-        label[i] = (uint32_t)i;
+    const PaBlk b = map[blockIdx.x];
+    const PaRunDesc &rd = runs[b.run];
+    const int64_t beg = (int64_t)b.idx * PA_CHUNK;
+    for (int64_t j = beg + threadIdx.x; j < beg + PA_CHUNK && j < rd.R0; j += blockDim.x)
+        rd.dv.label[0][j] = (uint32_t)j;
 }
 
 // ------------------------------------------------------------------ step 3: sweeps
@@ -87,27 +121,32 @@ __device__ __forceinline__ void wave_vsum16(uint64_t c[16])
 
 __device__ __forceinline__ uint64_t jbit(uint32_t jb, int k) { return 0ull - (uint64_t)((jb >> k) & 1u); }
 
-// One workgroup = one word column w (64 replicas); the lattice stays in LDS
-// for all theta sweeps, then each replica's unsatisfied-bond count U and
-// number of down spins are counted bit-sliced: E = 2U - dN, M = N - 2 n_down.
+// One workgroup = one word column w (64 replicas) of one run; the lattice
+// stays in LDS for all theta sweeps, then each replica's unsatisfied-bond
+// count U and number of down spins are counted bit-sliced: E = 2U - dN,
+// M = N - 2 n_down.  theta = 0 only measures.
 template <int D>
-__global__ __launch_bounds__(kThreads) void k_sweep(uint64_t *__restrict__ spins,
-                                                    const uint8_t *__restrict__ jmask, int L, int N,
-                                                    int32_t *__restrict__ E, int32_t *__restrict__ M,
-                                                    int64_t Rlive, PaRecord *__restrict__ rec,
-                                                    uint32_t seed, uint32_t run_id, uint32_t step,
-                                                    uint32_t t0, int theta)
+__global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__restrict__ runs,
+                                                            const PaBlk *__restrict__ map, int theta)
 {
     extern __shared__ uint64_t lat[];
+    __shared__ uint64_t red[kSweepMaxThreads / 64][32];
+    const PaBlk blk = map[blockIdx.x];
+    const PaRunDesc &rd = runs[blk.run];
+    PaRecord *rec = rd.dv.rec;
+    const uint32_t w = blk.idx;
+    const int64_t Rlive = (int64_t)rec->Rcur;
+    if ((int64_t)w * 64 >= Rlive || frozen(rec))
+        return;
+    const int L = rd.L, N = rd.N;
+    const int cur = rec->cur;
+    const uint32_t step = rec->step, t0 = rec->sweeps;
     uint8_t *jl = reinterpret_cast<uint8_t *>(lat + N);
-    __shared__ uint64_t red[kThreads / 64][32];
-
     const int tid = threadIdx.x, bs = blockDim.x;
-    const uint32_t w = blockIdx.x;
-    uint64_t *g = spins + (size_t)w * N;
+    uint64_t *g = rd.dv.spins[cur] + (size_t)w * N;
     for (int s = tid; s < N; s += bs) {
         lat[s] = g[s];
-        jl[s] = jmask[s];
+        jl[s] = rd.dv.jmask[s];
     }
     __syncthreads();
 
@@ -121,6 +160,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(uint64_t *__restrict__ spins
                    draw8 = (T8 > 0 && T8 < two32) ? ~0ull : 0ull,
                    draw12 = (T12 > 0 && T12 < two32) ? ~0ull : 0ull;
     const int half = L >> 1, nh = N >> 1, LL = L * L;
+    const uint32_t seed = rd.seed, run_id = rd.run_id;
     uint32_t calls = 0; // Philox evaluations this lane's words needed
 
     for (int tt = 0; tt < theta; ++tt) {
@@ -142,9 +182,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep(uint64_t *__restrict__ spins
                 uint64_t always, m4, m8, m12;
                 if (D == 2) {
                     const uint64_t s0 = a0 ^ a1, c0 = a0 & a1, s1 = a2 ^ a3, c1 = a2 & a3;
-                    always = c0 | c1 | (s0 & s1);     // u >= 2
-                    m4 = (s0 ^ s1) & ~(c0 | c1);      // u == 1
-                    m8 = ~(s0 | s1 | c0 | c1);        // u == 0
+                    always = c0 | c1 | (s0 & s1); // u >= 2
+                    m4 = (s0 ^ s1) & ~(c0 | c1);  // u == 1
+                    m8 = ~(s0 | s1 | c0 | c1);    // u == 0
                     m12 = 0;
                 } else {
                     const uint64_t a4 = S ^ lat[z == L - 1 ? s - LL * (L - 1) : s + LL] ^ jbit(jb, 2);
@@ -156,10 +196,10 @@ __global__ __launch_bounds__(kThreads) void k_sweep(uint64_t *__restrict__ spins
                     const uint64_t maj = (cA & cB) | (lc & (cA ^ cB));
                     const uint64_t odd = cA ^ cB ^ lc;
                     const uint64_t none = ~(cA | cB | lc);
-                    always = maj | (odd & ls);        // u >= 3
-                    m4 = odd & ~maj & ~ls;            // u == 2
-                    m8 = none & ls;                   // u == 1
-                    m12 = none & ~ls;                 // u == 0
+                    always = maj | (odd & ls); // u >= 3
+                    m4 = odd & ~maj & ~ls;     // u == 2
+                    m8 = none & ls;            // u == 1
+                    m12 = none & ~ls;          // u == 0
                 }
                 uint64_t acc = always | (m4 & sure4) | (m8 & sure8) | (m12 & sure12);
                 uint64_t und = (m4 & draw4) | (m8 & draw8) | (m12 & draw12);
@@ -235,35 +275,54 @@ __global__ __launch_bounds__(kThreads) void k_sweep(uint64_t *__restrict__ spins
             }
         const int64_t r = 64 * (int64_t)w + lane;
         if (r < Rlive) {
-            E[r] = 2 * (int32_t)U - D * N;
-            M[r] = N - 2 * (int32_t)nd;
+            rd.dv.E[cur][r] = 2 * (int32_t)U - D * N;
+            rd.dv.M[cur][r] = N - 2 * (int32_t)nd;
         }
     }
+}
+
+// The sweep counter advances after the sweeps (a separate launch, so that no
+// workgroup of the sweep reads a half-updated counter).
+__global__ void k_sweeps_add(const PaRunDesc *__restrict__ runs, int theta)
+{
+    PaRecord *rec = runs[blockIdx.x].dv.rec;
+    if (threadIdx.x == 0 && !frozen(rec))
+        rec->sweeps += (uint32_t)theta;
 }
 
 // ------------------------------------------------------------------ step 2: Q
 // Energy levels h = (E + dN) / 4: all energies of a run share E mod 4, since a
 // flip changes E by a multiple of 4.
-__global__ void k_hist_prep(uint32_t *hist, int H, PaRecord *rec)
+__global__ void k_hist_prep(const PaRunDesc *__restrict__ runs)
 {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < H; i += gridDim.x * blockDim.x)
-        hist[i] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        rec->emin = INT_MAX;
-        rec->emax = INT_MIN;
+    const PaRunDesc &rd = runs[blockIdx.x];
+    for (int i = threadIdx.x; i < rd.H; i += blockDim.x)
+        rd.dv.hist[i] = 0;
+    if (threadIdx.x == 0) {
+        rd.dv.rec->emin = INT_MAX;
+        rd.dv.rec->emax = INT_MIN;
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_hist(const int32_t *__restrict__ E, int64_t R, int DN,
-                                                   int H, uint32_t *hist, PaRecord *rec)
+__global__ __launch_bounds__(kThreads) void k_hist(const PaRunDesc *__restrict__ runs,
+                                                   const PaBlk *__restrict__ map)
 {
     extern __shared__ uint32_t lh[];
+    const PaBlk b = map[blockIdx.x];
+    const PaRunDesc &rd = runs[b.run];
+    PaRecord *rec = rd.dv.rec;
+    const int64_t R = (int64_t)rec->Rcur;
+    const int64_t beg = (int64_t)b.idx * PA_CHUNK;
+    if (beg >= R || frozen(rec))
+        return;
+    const int H = rd.H, DN = rd.d * rd.N;
+    const int32_t *E = rd.dv.E[rec->cur];
     for (int i = threadIdx.x; i < H; i += blockDim.x)
         lh[i] = 0;
     __syncthreads();
     int64_t lo = INT_MAX, hi = INT_MIN;
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < R;
-         j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t end = beg + PA_CHUNK < R ? beg + PA_CHUNK : R;
+    for (int64_t j = beg + threadIdx.x; j < end; j += blockDim.x) {
         const int32_t e = E[j];
         atomicAdd(&lh[(e + DN) >> 2], 1u);
         lo = e < lo ? e : lo;
@@ -272,7 +331,7 @@ __global__ __launch_bounds__(kThreads) void k_hist(const int32_t *__restrict__ E
     __syncthreads();
     for (int i = threadIdx.x; i < H; i += blockDim.x)
         if (lh[i])
-            atomicAdd(&hist[i], lh[i]);
+            atomicAdd(&rd.dv.hist[i], lh[i]);
     lo = pa_wave_min_i64(lo);
     hi = pa_wave_max_i64(hi);
     if ((threadIdx.x & 63) == 0) {
@@ -281,15 +340,19 @@ __global__ __launch_bounds__(kThreads) void k_hist(const int32_t *__restrict__ E
     }
 }
 
-// Single workgroup: weights per level above the lowest, the Q sum in a fixed
-// order (contiguous chunk per thread, then the block's fixed tree), S exactly,
-// ln Q and the Metropolis thresholds of the next beta.
-__global__ __launch_bounds__(1024) void k_reweight(const uint32_t *__restrict__ hist,
-                                                   uint64_t *__restrict__ wtab, PaRecord *rec, int DN,
-                                                   int64_t Rprev, double dbeta, double beta_next)
+// One workgroup per run: weights per level above the lowest, the Q sum in a
+// fixed order (contiguous chunk per thread, then the block's fixed tree), S
+// exactly, ln Q and the Metropolis thresholds of the next beta.
+__global__ __launch_bounds__(1024) void k_reweight(const PaRunDesc *__restrict__ runs, double beta_next)
 {
     __shared__ double sd[16];
     __shared__ uint64_t su[16];
+    const PaRunDesc &rd = runs[blockIdx.x];
+    PaRecord *rec = rd.dv.rec;
+    if (frozen(rec))
+        return;
+    const int DN = rd.d * rd.N;
+    const double dbeta = beta_next - rec->beta;
     const int32_t emin = rec->emin, emax = rec->emax;
     const int hmin = (emin + DN) >> 2, hmax = (emax + DN) >> 2;
     const int nlev = hmax - hmin + 1;
@@ -299,10 +362,10 @@ __global__ __launch_bounds__(1024) void k_reweight(const uint32_t *__restrict__ 
     double q = 0.0;
     uint64_t s = 0;
     for (int k = lo; k < hi; ++k) {
-        const uint32_t n = hist[hmin + k];
+        const uint32_t n = rd.dv.hist[hmin + k];
         const double wv = pa_exp(-(dbeta * (double)(4 * k)));
         const uint64_t W = (uint64_t)floor(ldexp(wv, 40));
-        wtab[k] = W;
+        rd.dv.wtab[k] = W;
         q = q + (double)n * wv;
         s += (uint64_t)n * W;
     }
@@ -313,7 +376,7 @@ __global__ __launch_bounds__(1024) void k_reweight(const uint32_t *__restrict__ 
         rec->S = S;
         rec->dbeta = dbeta;
         rec->beta_next = beta_next;
-        rec->lnQ = -dbeta * (double)emin + log(Q / (double)Rprev);
+        rec->lnQ = -dbeta * (double)emin + log(Q / (double)rec->Rcur);
         rec->Tn[0] = pa_threshold(beta_next, 4);
         rec->Tn[1] = pa_threshold(beta_next, 8);
         rec->Tn[2] = pa_threshold(beta_next, 12);
@@ -325,9 +388,6 @@ __global__ __launch_bounds__(1024) void k_reweight(const uint32_t *__restrict__ 
 // alpha = (1/R) sum_j min(1, R w_j / sum_k w_k), w_j = pa_exp(-dbeta (E_j - E_min)),
 // evaluated per energy level (fixed chunk per thread, fixed tree), and the
 // bisection for the largest dbeta in [0, dbeta_max] with alpha >= alpha_star.
-constexpr int kRuleThreads = 1024;
-constexpr int kRuleCache = 4096; // levels whose weights stay in LDS between the two sums
-
 __device__ double rule_alpha(const uint32_t *__restrict__ hist, int hmin, int nlev, double R, double dbeta,
                              double *wcache, double *sd)
 {
@@ -351,23 +411,27 @@ __device__ double rule_alpha(const uint32_t *__restrict__ hist, int hmin, int nl
     return pa_block_sum_f64(a, sd) / R;
 }
 
-__global__ __launch_bounds__(kRuleThreads) void k_rule(const uint32_t *__restrict__ hist, PaRecord *rec, int DN,
-                                                       int64_t Rcur, double alpha_star, double dbeta_max,
-                                                       int iterations, int bisect)
+__global__ __launch_bounds__(kRuleThreads) void k_rule(const PaRunDesc *__restrict__ runs, double alpha_star,
+                                                       double dbeta_max, int iterations, int bisect)
 {
     __shared__ double sd[16];
     __shared__ double wcache[kRuleCache];
+    const PaRunDesc &rd = runs[blockIdx.x];
+    PaRecord *rec = rd.dv.rec;
+    if (frozen(rec))
+        return;
+    const int DN = rd.d * rd.N;
     const int hmin = (rec->emin + DN) >> 2, hmax = (rec->emax + DN) >> 2;
     const int nlev = hmax - hmin + 1;
-    const double R = (double)Rcur;
-    double a = rule_alpha(hist, hmin, nlev, R, dbeta_max, wcache, sd);
-    double lo = 0.0, hi = dbeta_max, best = dbeta_max, abest = a;
+    const double R = (double)rec->Rcur;
+    const double a = rule_alpha(rd.dv.hist, hmin, nlev, R, dbeta_max, wcache, sd);
+    double best = dbeta_max, abest = a;
     if (bisect && !(a >= alpha_star)) {
-        best = 0.0;
+        double lo = 0.0, hi = dbeta_max;
         abest = 1.0;
         for (int it = 0; it < iterations; ++it) {
             const double mid = 0.5 * (lo + hi);
-            const double am = rule_alpha(hist, hmin, nlev, R, mid, wcache, sd);
+            const double am = rule_alpha(rd.dv.hist, hmin, nlev, R, mid, wcache, sd);
             if (am >= alpha_star) {
                 lo = mid;
                 abest = am;
@@ -389,39 +453,66 @@ __device__ __forceinline__ uint64_t weight_of(int32_t e, int DN, int hmin, const
     return wtab[((e + DN) >> 2) - hmin];
 }
 
+// Per-replica resampling kernels: chunk b.idx of run b.run, replicas
+// [idx*CHUNK, ...) below the pre-resampling size.
+struct RepCtx {
+    const PaRunDesc *rd;
+    PaRecord *rec;
+    int64_t beg, end;
+};
+
+__device__ __forceinline__ bool rep_ctx(const PaRunDesc *runs, const PaBlk *map, RepCtx *c)
+{
+    const PaBlk b = map[blockIdx.x];
+    c->rd = runs + b.run;
+    c->rec = c->rd->dv.rec;
+    const int64_t R = (int64_t)c->rec->Rcur;
+    c->beg = (int64_t)b.idx * PA_CHUNK;
+    c->end = c->beg + PA_CHUNK < R ? c->beg + PA_CHUNK : R;
+    return c->beg < R && !frozen(c->rec);
+}
+
 // Nearest integer: floor(tauhat) + [u S < (R W mod S) 2^32], u = x0 of
 // Philox(j, 0, i, RS_NI<<28).
-__global__ void k_counts_nearest(const int32_t *__restrict__ E, int64_t Rprev, uint64_t Rt,
-                                 const uint64_t *__restrict__ wtab, const PaRecord *__restrict__ rec,
-                                 int DN, uint32_t seed, uint32_t run_id, uint32_t step,
-                                 uint32_t *__restrict__ r)
+__global__ __launch_bounds__(kThreads) void k_counts_nearest(const PaRunDesc *__restrict__ runs,
+                                                             const PaBlk *__restrict__ map)
 {
-    const int hmin = (rec->emin + DN) >> 2;
-    const uint64_t S = rec->S;
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < Rprev;
-         j += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t W = weight_of(E[j], DN, hmin, wtab);
+    RepCtx c;
+    if (!rep_ctx(runs, map, &c))
+        return;
+    const PaRunDesc &rd = *c.rd;
+    const int DN = rd.d * rd.N;
+    const int hmin = (c.rec->emin + DN) >> 2;
+    const uint64_t S = c.rec->S, Rt = (uint64_t)rd.R0;
+    const uint32_t step = c.rec->step + 1;
+    const int32_t *E = rd.dv.E[c.rec->cur];
+    for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x) {
+        const uint64_t W = weight_of(E[j], DN, hmin, rd.dv.wtab);
         const uint64_t a = Rt * W;
         const uint64_t qt = a / S;
         const uint64_t rho = a - qt * S;
-        const pa_philox_out o = pa_philox(seed, run_id, (uint32_t)j, 0u, step, PA_PURPOSE_RS_NI << 28);
+        const pa_philox_out o = pa_philox(rd.seed, rd.run_id, (uint32_t)j, 0u, step, PA_PURPOSE_RS_NI << 28);
         const bool extra = ((pa_u128)o.x0 * S) < ((pa_u128)rho << 32);
-        r[j] = (uint32_t)qt + (extra ? 1u : 0u);
+        rd.dv.r[j] = (uint32_t)qt + (extra ? 1u : 0u);
     }
 }
 
 // Poisson by inversion; tauhat > 32 is cut into ceil(tauhat/32) equal pieces,
 // piece p using u from Philox(j, p, i, RS_POIS<<28).
-__global__ void k_counts_poisson(const int32_t *__restrict__ E, int64_t Rprev, uint64_t Rt,
-                                 const uint64_t *__restrict__ wtab, const PaRecord *__restrict__ rec,
-                                 int DN, uint32_t seed, uint32_t run_id, uint32_t step,
-                                 uint32_t *__restrict__ r)
+__global__ __launch_bounds__(kThreads) void k_counts_poisson(const PaRunDesc *__restrict__ runs,
+                                                             const PaBlk *__restrict__ map)
 {
-    const int hmin = (rec->emin + DN) >> 2;
-    const uint64_t S = rec->S;
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < Rprev;
-         j += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t W = weight_of(E[j], DN, hmin, wtab);
+    RepCtx c;
+    if (!rep_ctx(runs, map, &c))
+        return;
+    const PaRunDesc &rd = *c.rd;
+    const int DN = rd.d * rd.N;
+    const int hmin = (c.rec->emin + DN) >> 2;
+    const uint64_t S = c.rec->S, Rt = (uint64_t)rd.R0;
+    const uint32_t step = c.rec->step + 1;
+    const int32_t *E = rd.dv.E[c.rec->cur];
+    for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x) {
+        const uint64_t W = weight_of(E[j], DN, hmin, rd.dv.wtab);
         const double tau = ((double)W / (double)S) * (double)Rt;
         uint32_t m = 1;
         if (tau > 32.0)
@@ -429,7 +520,7 @@ __global__ void k_counts_poisson(const int32_t *__restrict__ E, int64_t Rprev, u
         const double mu = tau / (double)m;
         uint32_t tot = 0;
         for (uint32_t p = 0; p < m; ++p) {
-            const pa_philox_out o = pa_philox(seed, run_id, (uint32_t)j, p, step, PA_PURPOSE_RS_POIS << 28);
+            const pa_philox_out o = pa_philox(rd.seed, rd.run_id, (uint32_t)j, p, step, PA_PURPOSE_RS_POIS << 28);
             const double u = ((double)(o.x0 >> 5) * 67108864.0 + (double)(o.x1 >> 6)) *
                              (1.0 / 9007199254740992.0);
             uint32_t k = 0;
@@ -445,17 +536,22 @@ __global__ void k_counts_poisson(const int32_t *__restrict__ E, int64_t Rprev, u
             }
             tot += k;
         }
-        r[j] = tot;
+        rd.dv.r[j] = tot;
     }
 }
 
-__global__ void k_weights(const int32_t *__restrict__ E, int64_t Rprev, const uint64_t *__restrict__ wtab,
-                          const PaRecord *__restrict__ rec, int DN, uint64_t *__restrict__ C)
+__global__ __launch_bounds__(kThreads) void k_weights(const PaRunDesc *__restrict__ runs,
+                                                      const PaBlk *__restrict__ map)
 {
-    const int hmin = (rec->emin + DN) >> 2;
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < Rprev;
-         j += (int64_t)gridDim.x * blockDim.x)
-        C[j] = weight_of(E[j], DN, hmin, wtab);
+    RepCtx c;
+    if (!rep_ctx(runs, map, &c))
+        return;
+    const PaRunDesc &rd = *c.rd;
+    const int DN = rd.d * rd.N;
+    const int hmin = (c.rec->emin + DN) >> 2;
+    const int32_t *E = rd.dv.E[c.rec->cur];
+    for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x)
+        rd.dv.C[j] = weight_of(E[j], DN, hmin, rd.dv.wtab);
 }
 
 // Systematic: #points (k + U/2^32) S/R below c, k < R, is
@@ -475,77 +571,100 @@ __device__ __forceinline__ uint64_t sys_below(uint64_t c, uint64_t Rt, uint64_t 
     return n < Rt ? n : Rt;
 }
 
-__global__ void k_counts_systematic(const uint64_t *__restrict__ C, int64_t Rprev, uint64_t Rt,
-                                    const PaRecord *__restrict__ rec, uint32_t seed, uint32_t run_id,
-                                    uint32_t step, uint32_t *__restrict__ r)
+__global__ __launch_bounds__(kThreads) void k_counts_systematic(const PaRunDesc *__restrict__ runs,
+                                                                const PaBlk *__restrict__ map)
 {
-    const uint64_t S = rec->S;
-    const uint32_t U = pa_philox(seed, run_id, 0u, 0u, step, PA_PURPOSE_RS_SYS << 28).x0;
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < Rprev;
-         j += (int64_t)gridDim.x * blockDim.x) {
+    RepCtx c;
+    if (!rep_ctx(runs, map, &c))
+        return;
+    const PaRunDesc &rd = *c.rd;
+    const uint64_t S = c.rec->S, Rt = (uint64_t)rd.R0;
+    const uint32_t U = pa_philox(rd.seed, rd.run_id, 0u, 0u, c.rec->step + 1, PA_PURPOSE_RS_SYS << 28).x0;
+    const uint64_t *C = rd.dv.C;
+    for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x) {
         const uint64_t hi = sys_below(C[j], Rt, S, U);
         const uint64_t lo = j > 0 ? sys_below(C[j - 1], Rt, S, U) : 0;
-        r[j] = (uint32_t)(hi - lo);
+        rd.dv.r[j] = (uint32_t)(hi - lo);
     }
 }
 
-// Multinomial: U_k = floor(r S / 2^128), r = 128 bits of Philox(k, 0, i,
-// RS_MULT<<28); the box of replica j is [C_{j-1}, C_j).
-__global__ void k_counts_multinomial(const uint64_t *__restrict__ C, int64_t Rprev, uint64_t Rt,
-                                     const PaRecord *__restrict__ rec, uint32_t seed, uint32_t run_id,
-                                     uint32_t step, uint32_t *__restrict__ r)
+__global__ __launch_bounds__(kThreads) void k_clear_counts(const PaRunDesc *__restrict__ runs,
+                                                           const PaBlk *__restrict__ map)
 {
+    RepCtx c;
+    if (!rep_ctx(runs, map, &c))
+        return;
+    for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x)
+        c.rd->dv.r[j] = 0;
+}
+
+// Multinomial: U_k = floor(r S / 2^128), r = 128 bits of Philox(k, 0, i,
+// RS_MULT<<28), k < R; the box of replica j is [C_{j-1}, C_j).  The chunks of
+// the map cover the draws k (capacity >= R).
+__global__ __launch_bounds__(kThreads) void k_counts_multinomial(const PaRunDesc *__restrict__ runs,
+                                                                 const PaBlk *__restrict__ map)
+{
+    const PaBlk b = map[blockIdx.x];
+    const PaRunDesc &rd = runs[b.run];
+    PaRecord *rec = rd.dv.rec;
+    const int64_t Rt = rd.R0, Rprev = (int64_t)rec->Rcur;
+    const int64_t beg = (int64_t)b.idx * PA_CHUNK;
+    if (beg >= Rt || frozen(rec))
+        return;
+    const int64_t end = beg + PA_CHUNK < Rt ? beg + PA_CHUNK : Rt;
     const uint64_t S = rec->S;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < (int64_t)Rt;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        const pa_philox_out o = pa_philox(seed, run_id, (uint32_t)k, 0u, step, PA_PURPOSE_RS_MULT << 28);
+    const uint32_t step = rec->step + 1;
+    const uint64_t *C = rd.dv.C;
+    for (int64_t k = beg + threadIdx.x; k < end; k += blockDim.x) {
+        const pa_philox_out o = pa_philox(rd.seed, rd.run_id, (uint32_t)k, 0u, step, PA_PURPOSE_RS_MULT << 28);
         const uint64_t lo = (uint64_t)o.x0 | ((uint64_t)o.x1 << 32);
         const uint64_t hi = (uint64_t)o.x2 | ((uint64_t)o.x3 << 32);
         const pa_u128 A = (pa_u128)lo * S, B = (pa_u128)hi * S;
         const uint64_t U = (uint64_t)((B + (A >> 64)) >> 64);
-        int64_t a = 0, b = Rprev - 1;
-        while (a < b) {
-            const int64_t mid = a + ((b - a) >> 1);
+        int64_t a = 0, z = Rprev - 1;
+        while (a < z) {
+            const int64_t mid = a + ((z - a) >> 1);
             if (C[mid] > U)
-                b = mid;
+                z = mid;
             else
                 a = mid + 1;
         }
-        atomicAdd(&r[a], 1u);
+        atomicAdd(&rd.dv.r[a], 1u);
     }
 }
 
-// Sampling variance, Eq. (5): fixed blocks of contiguous replicas, fixed
-// per-thread stride, fixed tree; partial[b] of block b.
-__global__ __launch_bounds__(kThreads) void k_sv_partial(const int32_t *__restrict__ E, int64_t Rprev,
-                                                          uint64_t Rt, const uint64_t *__restrict__ wtab,
-                                                          const PaRecord *__restrict__ rec, int DN,
-                                                          const uint32_t *__restrict__ r,
-                                                          double *__restrict__ partial)
+// Sampling variance, Eq. (5): chunk c of the run sums its replicas with a
+// fixed per-thread stride and the block's fixed tree into partial[c].
+__global__ __launch_bounds__(kThreads) void k_sv_partial(const PaRunDesc *__restrict__ runs,
+                                                          const PaBlk *__restrict__ map)
 {
     __shared__ double sd[16];
-    const int hmin = (rec->emin + DN) >> 2;
-    const double S = (double)rec->S;
-    const int64_t chunk = (Rprev + gridDim.x - 1) / gridDim.x;
-    const int64_t beg = blockIdx.x * chunk;
-    const int64_t end = beg + chunk < Rprev ? beg + chunk : Rprev;
+    RepCtx c;
+    if (!rep_ctx(runs, map, &c))
+        return;
+    const PaRunDesc &rd = *c.rd;
+    const int DN = rd.d * rd.N;
+    const int hmin = (c.rec->emin + DN) >> 2;
+    const double S = (double)c.rec->S, Rt = (double)rd.R0;
+    const int32_t *E = rd.dv.E[c.rec->cur];
     double acc = 0.0;
-    for (int64_t j = beg + threadIdx.x; j < end; j += blockDim.x) {
-        const double tau = ((double)weight_of(E[j], DN, hmin, wtab) / S) * (double)Rt;
-        const double dlt = (double)r[j] - tau;
+    for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x) {
+        const double tau = ((double)weight_of(E[j], DN, hmin, rd.dv.wtab) / S) * Rt;
+        const double dlt = (double)rd.dv.r[j] - tau;
         acc = acc + dlt * dlt;
     }
     const double t = pa_block_sum_f64(acc, sd);
     if (threadIdx.x == 0)
-        partial[blockIdx.x] = t;
+        rd.dv.partial[c.beg / PA_CHUNK] = t;
 }
 
-// Decoupled look-back scan (Merrill & Garland 2016): tiles take their order
-// from an atomic ticket, so every tile a tile waits on is already running.
-template <typename T, bool INCLUSIVE>
-__global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const T *__restrict__ in, T *__restrict__ out,
-                                                          int64_t n, PaScanTile *tiles, uint32_t *ticket,
-                                                          unsigned long long *total, uint32_t *err)
+// Decoupled look-back scan (Merrill & Garland 2016) of each run's first
+// Rcur entries: tiles take their order from an atomic ticket over a
+// run-major tile map, so every tile a tile waits on (same run, lower index)
+// is already running.  Entries past Rcur count as 0.
+template <typename T, bool INCLUSIVE, int WHICH>
+__global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const PaRunDesc *__restrict__ runs,
+                                                          const PaBlk *__restrict__ map, uint32_t *ticket)
 {
     __shared__ uint32_t s_tile;
     __shared__ unsigned long long s_wave[PA_SCAN_THREADS / 64];
@@ -553,7 +672,18 @@ __global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const T *__restrict__ 
     if (threadIdx.x == 0)
         s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
-    const uint32_t tile = s_tile;
+    const PaBlk b = map[s_tile];
+    const PaRunDesc &rd = runs[b.run];
+    PaRecord *rec = rd.dv.rec;
+    if (frozen(rec))
+        return; // every tile of a frozen run returns: none waits
+    const uint32_t tile = b.idx;
+    const int64_t n = (int64_t)rec->Rcur;
+    const int64_t ntiles = (rd.cap + PA_SCAN_TILE - 1) / PA_SCAN_TILE;
+    const T *in = WHICH == 0 ? (const T *)rd.dv.C : (const T *)rd.dv.r;
+    T *out = WHICH == 0 ? (T *)rd.dv.C : (T *)rd.dv.P;
+    unsigned long long *total = WHICH == 0 ? &rec->Ctot : &rec->Rnew;
+    PaScanTile *tiles = rd.dv.tiles;
     const int64_t base = (int64_t)tile * PA_SCAN_TILE + (int64_t)threadIdx.x * PA_SCAN_ITEMS;
     unsigned long long v[PA_SCAN_ITEMS];
     unsigned long long run = 0;
@@ -563,7 +693,6 @@ __global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const T *__restrict__ 
         v[k] = i < n ? (unsigned long long)in[i] : 0ull;
         run += v[k];
     }
-    // exclusive prefix of the thread totals within the tile
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     unsigned long long incl = run;
 #pragma unroll
@@ -597,7 +726,7 @@ __global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const T *__restrict__ 
                 uint32_t spins = 0;
                 while ((f = pa_load_acquire(&tiles[p].flag)) == 0u) {
                     if (++spins > (1u << 26)) {
-                        atomicOr(err, 1u);
+                        atomicOr(&rec->status, PA_ST_SCAN_TIMEOUT);
                         break;
                     }
                     __builtin_amdgcn_s_sleep(1);
@@ -607,7 +736,7 @@ __global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const T *__restrict__ 
                     break;
                 }
                 if (f == 0u)
-                    break; // gave up; the error flag is set
+                    break; // gave up; the status bit is set
                 excl += tiles[p].agg;
                 --p;
             }
@@ -615,7 +744,7 @@ __global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const T *__restrict__ 
             pa_store_release(&me->flag, 2u);
         }
         s_excl = excl;
-        if ((int64_t)(tile + 1) * PA_SCAN_TILE >= n)
+        if ((int64_t)tile == ntiles - 1)
             *total = excl + agg;
     }
     __syncthreads();
@@ -632,64 +761,106 @@ __global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const T *__restrict__ 
     }
 }
 
-template <typename T, bool INCLUSIVE>
-hipError_t scan(const T *in, T *out, int64_t n, const PaDev &dv, unsigned long long *total,
-                hipStream_t st)
+__global__ void k_scan_prep(const PaRunDesc *__restrict__ runs)
 {
-    const int64_t ntiles = (n + PA_SCAN_TILE - 1) / PA_SCAN_TILE;
-    hipError_t e = fill_u32(reinterpret_cast<uint32_t *>(dv.tiles), ntiles * (int64_t)(sizeof(PaScanTile) / 4),
-                            0u, st);
-    if (e != hipSuccess)
-        return e;
-    if ((e = fill_u32(dv.ticket, 1, 0u, st)) != hipSuccess)
-        return e;
-    k_scan<T, INCLUSIVE><<<(unsigned)ntiles, PA_SCAN_THREADS, 0, st>>>(in, out, n, dv.tiles, dv.ticket,
-                                                                      total, &dv.rec->err);
-    return hipGetLastError();
+    const PaRunDesc &rd = runs[blockIdx.x];
+    const int64_t ntiles = (rd.cap + PA_SCAN_TILE - 1) / PA_SCAN_TILE;
+    for (int64_t t = threadIdx.x; t < ntiles; t += blockDim.x)
+        rd.dv.tiles[t].flag = 0u;
 }
 
-// ------------------------------------------------------------------ apply
-__global__ void k_ancestors(const uint32_t *__restrict__ r, const uint32_t *__restrict__ P, int64_t Rprev,
-                            uint32_t *__restrict__ anc)
+// A new resampling starts with a clean status (a frozen run stays frozen).
+__global__ void k_resample_prep(const PaRunDesc *__restrict__ runs)
 {
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < Rprev;
-         j += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t c = r[j], p = P[j];
-        for (uint32_t k = 0; k < c; ++k)
-            anc[p + k] = (uint32_t)j;
+    PaRecord *rec = runs[blockIdx.x].dv.rec;
+    if (threadIdx.x == 0 && !frozen(rec)) {
+        rec->status = 0;
+        rec->skip = 0;
     }
 }
 
-__global__ void k_gather_rep(const uint32_t *__restrict__ anc, int64_t Rnew, const int32_t *__restrict__ E0,
-                             const int32_t *__restrict__ M0, const uint32_t *__restrict__ L0,
-                             int32_t *__restrict__ E1, int32_t *__restrict__ M1, uint32_t *__restrict__ L1)
+// Capacity and extinction: a resampling that would not fit (or leave no
+// replica) is not applied; in batch mode the run is frozen from then on.
+__global__ void k_check(const PaRunDesc *__restrict__ runs, int freeze)
 {
-    for (int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; d < Rnew;
-         d += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t a = anc[d];
-        E1[d] = E0[a];
-        M1[d] = M0[a];
-        L1[d] = L0[a];
+    const PaRunDesc &rd = runs[blockIdx.x];
+    PaRecord *rec = rd.dv.rec;
+    if (threadIdx.x != 0 || frozen(rec))
+        return;
+    const uint64_t Rn = rec->Rnew;
+    uint32_t st = rec->status & PA_ST_SCAN_TIMEOUT;
+    if (Rn > (uint64_t)rd.cap)
+        st |= PA_ST_CAPACITY;
+    if (Rn == 0)
+        st |= PA_ST_EXTINCT;
+    if (!(rec->lnQ == rec->lnQ) || rec->lnQ - rec->lnQ != 0.0)
+        st |= PA_ST_NONFINITE;
+    rec->skip = st != 0u;
+    rec->status = (st != 0u && freeze) ? (st | PA_ST_FROZEN) : st;
+}
+
+// ------------------------------------------------------------------ apply
+__global__ __launch_bounds__(kThreads) void k_ancestors(const PaRunDesc *__restrict__ runs,
+                                                        const PaBlk *__restrict__ map)
+{
+    RepCtx c;
+    if (!rep_ctx(runs, map, &c) || c.rec->skip)
+        return;
+    const PaDev &dv = c.rd->dv;
+    for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x) {
+        const uint32_t n = dv.r[j], p = dv.P[j];
+        for (uint32_t k = 0; k < n; ++k)
+            dv.anc[p + k] = (uint32_t)j;
+    }
+}
+
+// New replica d takes energy, magnetisation and label of its ancestor.
+__global__ __launch_bounds__(kThreads) void k_gather_rep(const PaRunDesc *__restrict__ runs,
+                                                         const PaBlk *__restrict__ map)
+{
+    const PaBlk b = map[blockIdx.x];
+    const PaRunDesc &rd = runs[b.run];
+    PaRecord *rec = rd.dv.rec;
+    const int64_t Rn = (int64_t)rec->Rnew;
+    const int64_t beg = (int64_t)b.idx * PA_CHUNK;
+    if (frozen(rec) || rec->skip || beg >= Rn)
+        return;
+    const int64_t end = beg + PA_CHUNK < Rn ? beg + PA_CHUNK : Rn;
+    const int cur = rec->cur, nxt = cur ^ 1;
+    const PaDev &dv = rd.dv;
+    for (int64_t d = beg + threadIdx.x; d < end; d += blockDim.x) {
+        const uint32_t a = dv.anc[d];
+        dv.E[nxt][d] = dv.E[cur][a];
+        dv.M[nxt][d] = dv.M[cur][a];
+        dv.label[nxt][d] = dv.label[cur][a];
     }
 }
 
 // Destination word column w takes the bits of its 64 ancestors.  Ancestors are
 // non-decreasing, so the column splits into runs of consecutive source bits
 // within one source word; each run is one shift-and-mask per site.
-__global__ __launch_bounds__(kThreads) void k_gather_spins(const uint64_t *__restrict__ src,
-                                                           uint64_t *__restrict__ dst,
-                                                           const uint32_t *__restrict__ anc, int64_t Rnew,
-                                                           int N)
+__global__ __launch_bounds__(kThreads) void k_gather_spins(const PaRunDesc *__restrict__ runs,
+                                                           const PaBlk *__restrict__ map)
 {
     __shared__ uint32_t r_word[64];
     __shared__ uint32_t r_shift[64], r_b0[64], r_len[64];
     __shared__ int s_nruns;
-    const uint32_t w = blockIdx.x;
+    const PaBlk blk = map[blockIdx.x];
+    const PaRunDesc &rd = runs[blk.run];
+    PaRecord *rec = rd.dv.rec;
+    const int64_t Rnew = (int64_t)rec->Rnew;
+    const uint32_t w = blk.idx;
+    if (frozen(rec) || rec->skip || (int64_t)w * 64 >= Rnew)
+        return;
+    const int N = rd.N;
+    const int cur = rec->cur;
+    const uint64_t *src = rd.dv.spins[cur];
+    uint64_t *dst = rd.dv.spins[cur ^ 1];
     if (threadIdx.x < 64) {
         const int b = threadIdx.x;
         const int64_t d = 64 * (int64_t)w + b;
         const bool valid = d < Rnew;
-        const uint32_t a = valid ? anc[d] : 0u;
+        const uint32_t a = valid ? rd.dv.anc[d] : 0u;
         const uint32_t ap = (uint32_t)__shfl_up((int)a, 1, 64);
         const bool start = valid && (b == 0 || a != ap + 1u || (a & 63u) == 0u);
         const uint64_t sm = __ballot(start);
@@ -725,13 +896,21 @@ __global__ __launch_bounds__(kThreads) void k_gather_spins(const uint64_t *__res
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_commit(PaRecord *rec, const double *__restrict__ partial,
-                                                     int nparts, int64_t Rprev, int64_t Rnew)
+// Completes an applied resampling: SV (Eq. (5)) from the partials in fixed
+// order, ln Z_hat += ln Q (Eq. (7)), the new beta and its thresholds, the
+// buffer swap and the step count.
+__global__ __launch_bounds__(kThreads) void k_commit(const PaRunDesc *__restrict__ runs)
 {
     __shared__ double sd[16];
+    const PaRunDesc &rd = runs[blockIdx.x];
+    PaRecord *rec = rd.dv.rec;
+    if (frozen(rec) || rec->skip)
+        return;
+    const int64_t Rprev = (int64_t)rec->Rcur;
+    const int nlive = (int)((Rprev + PA_CHUNK - 1) / PA_CHUNK);
     double v = 0.0;
-    for (int k = threadIdx.x; k < nparts; k += blockDim.x)
-        v = v + partial[k];
+    for (int k = threadIdx.x; k < nlive; k += blockDim.x)
+        v = v + rd.dv.partial[k];
     const double t = pa_block_sum_f64(v, sd);
     if (threadIdx.x == 0) {
         rec->sv = t / (double)Rprev;
@@ -740,60 +919,73 @@ __global__ __launch_bounds__(kThreads) void k_commit(PaRecord *rec, const double
         rec->T[1] = rec->Tn[1];
         rec->T[2] = rec->Tn[2];
         rec->Rprev = (uint64_t)Rprev;
-        rec->Rnew = (uint64_t)Rnew;
+        rec->Rcur = rec->Rnew;
+        rec->cur ^= 1;
+        rec->beta = rec->beta_next;
+        rec->step += 1;
+        rec->sweeps = 0;
     }
 }
 
 // ------------------------------------------------------------------ step 4: observables
-__global__ void k_obs_prep(uint32_t *fam, int64_t R0, PaRecord *rec)
+__global__ void k_obs_prep(const PaRunDesc *__restrict__ runs)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < R0;
-         i += (int64_t)gridDim.x * blockDim.x)
-        fam[i] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const PaRunDesc &rd = runs[blockIdx.x];
+    PaRecord *rec = rd.dv.rec;
+    if (frozen(rec))
+        return;
+    for (int64_t i = threadIdx.x; i < rd.R0; i += blockDim.x)
+        rd.dv.fam[i] = 0;
+    if (threadIdx.x == 0)
         rec->sumE = rec->sumE2 = rec->sumAbsM = rec->sumM2 = rec->sumC2 = rec->families = 0;
-    }
 }
 
-__global__ __launch_bounds__(kThreads) void k_obs_rep(const int32_t *__restrict__ E, const int32_t *__restrict__ M,
-                                                      const uint32_t *__restrict__ label, int64_t R,
-                                                      uint32_t *fam, PaRecord *rec)
+__global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restrict__ runs,
+                                                      const PaBlk *__restrict__ map)
 {
     __shared__ uint64_t su[16];
+    RepCtx c;
+    if (!rep_ctx(runs, map, &c))
+        return;
+    const PaDev &dv = c.rd->dv;
+    const int cur = c.rec->cur;
     uint64_t sE = 0, sE2 = 0, sA = 0, sM2 = 0;
-    for (int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; d < R;
-         d += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t e = E[d], m = M[d];
+    for (int64_t d = c.beg + threadIdx.x; d < c.end; d += blockDim.x) {
+        const int64_t e = dv.E[cur][d], m = dv.M[cur][d];
         sE += (uint64_t)e;
         sE2 += (uint64_t)(e * e);
         sA += (uint64_t)(m < 0 ? -m : m);
         sM2 += (uint64_t)(m * m);
-        atomicAdd(&fam[label[d]], 1u);
+        atomicAdd(&dv.fam[dv.label[cur][d]], 1u);
     }
     sE = pa_block_sum_u64(sE, su);
     sE2 = pa_block_sum_u64(sE2, su);
     sA = pa_block_sum_u64(sA, su);
     sM2 = pa_block_sum_u64(sM2, su);
     if (threadIdx.x == 0) {
-        atomicAdd(&rec->sumE, (unsigned long long)sE);
-        atomicAdd(&rec->sumE2, (unsigned long long)sE2);
-        atomicAdd(&rec->sumAbsM, (unsigned long long)sA);
-        atomicAdd(&rec->sumM2, (unsigned long long)sM2);
+        atomicAdd(&c.rec->sumE, (unsigned long long)sE);
+        atomicAdd(&c.rec->sumE2, (unsigned long long)sE2);
+        atomicAdd(&c.rec->sumAbsM, (unsigned long long)sA);
+        atomicAdd(&c.rec->sumM2, (unsigned long long)sM2);
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_obs_fam(const uint32_t *__restrict__ fam, int64_t R0,
-                                                      PaRecord *rec, double *__restrict__ partial)
+__global__ __launch_bounds__(kThreads) void k_obs_fam(const PaRunDesc *__restrict__ runs,
+                                                      const PaBlk *__restrict__ map)
 {
     __shared__ uint64_t su[16];
     __shared__ double sd[16];
-    const int64_t chunk = (R0 + gridDim.x - 1) / gridDim.x;
-    const int64_t beg = blockIdx.x * chunk;
-    const int64_t end = beg + chunk < R0 ? beg + chunk : R0;
+    const PaBlk b = map[blockIdx.x];
+    const PaRunDesc &rd = runs[b.run];
+    PaRecord *rec = rd.dv.rec;
+    if (frozen(rec))
+        return;
+    const int64_t beg = (int64_t)b.idx * PA_CHUNK;
+    const int64_t end = beg + PA_CHUNK < rd.R0 ? beg + PA_CHUNK : rd.R0;
     uint64_t c2 = 0, nf = 0;
     double cl = 0.0;
     for (int64_t f = beg + threadIdx.x; f < end; f += blockDim.x) {
-        const uint64_t c = fam[f];
+        const uint64_t c = rd.dv.fam[f];
         c2 += c * c;
         if (c) {
             nf += 1;
@@ -806,22 +998,30 @@ __global__ __launch_bounds__(kThreads) void k_obs_fam(const uint32_t *__restrict
     if (threadIdx.x == 0) {
         atomicAdd(&rec->sumC2, (unsigned long long)c2);
         atomicAdd(&rec->families, (unsigned long long)nf);
-        partial[blockIdx.x] = cl;
+        rd.dv.partial[b.idx] = cl;
     }
 }
 
 // Averages of step 4 and the family statistics: rho_t = sum_k c_k^2 / R
-// (Eq. (6) with n_k = c_k / R), S_f = ln R - (1/R) sum_k c_k ln c_k.
-__global__ __launch_bounds__(kThreads) void k_obs_final(PaRecord *rec, const double *__restrict__ partial,
-                                                        int nparts, int N, int64_t R)
+// (Eq. (6) with n_k = c_k / R), S_f = ln R - (1/R) sum_k c_k ln c_k.  In a
+// batched anneal the row of temperature point `point` is written too.
+__global__ __launch_bounds__(kThreads) void k_obs_final(const PaRunDesc *__restrict__ runs, PaStepRecord *steprec,
+                                                        int npoints, int point)
 {
     __shared__ double sd[16];
+    const PaRunDesc &rd = runs[blockIdx.x];
+    PaRecord *rec = rd.dv.rec;
+    const bool fz = frozen(rec);
+    const int nparts = (int)((rd.R0 + PA_CHUNK - 1) / PA_CHUNK);
     double v = 0.0;
-    for (int k = threadIdx.x; k < nparts; k += blockDim.x)
-        v = v + partial[k];
+    if (!fz)
+        for (int k = threadIdx.x; k < nparts; k += blockDim.x)
+            v = v + rd.dv.partial[k];
     const double t = pa_block_sum_f64(v, sd);
-    if (threadIdx.x == 0) {
-        const double n = (double)N, r = (double)R;
+    if (threadIdx.x != 0)
+        return;
+    if (!fz) {
+        const double n = (double)rd.N, r = (double)rec->Rcur;
         rec->sumClnC = t;
         rec->e = (double)(long long)rec->sumE / (n * r);
         rec->e2 = (double)(long long)rec->sumE2 / (n * n * r);
@@ -830,23 +1030,50 @@ __global__ __launch_bounds__(kThreads) void k_obs_final(PaRecord *rec, const dou
         rec->rho_t = (double)rec->sumC2 / r;
         rec->S_f = log(r) - t / r;
     }
+    if (steprec) {
+        PaStepRecord *o = steprec + (size_t)blockIdx.x * npoints + point;
+        o->beta = rec->beta;
+        o->lnQ = point > 0 ? rec->lnQ : 0.0;
+        o->lnZ = rec->lnZ;
+        o->sv = rec->sv;
+        o->e = rec->e;
+        o->e2 = rec->e2;
+        o->abs_m = rec->abs_m;
+        o->m2 = rec->m2;
+        o->rho_t = rec->rho_t;
+        o->S_f = rec->S_f;
+        o->R = (long long)rec->Rcur;
+        o->sumE = (long long)rec->sumE;
+        o->sumE2 = (long long)rec->sumE2;
+        o->sumAbsM = (long long)rec->sumAbsM;
+        o->sumM2 = (long long)rec->sumM2;
+        o->sumC2 = (long long)rec->sumC2;
+        o->families = (long long)rec->families;
+        o->status = rec->status;
+    }
 }
 
 // ------------------------------------------------------------------ overlap
-// Pairs replica d of population a with replica d of b: per word column, the
+// Pairs replica d of run a with replica d of run b: per word column, the
 // bit-sliced count of differing sites per replica, then q-histogram entry
 // N - count.
-__global__ __launch_bounds__(kThreads) void k_overlap(const uint64_t *__restrict__ A,
-                                                      const uint64_t *__restrict__ B, int N, int64_t R,
-                                                      unsigned long long *hist)
+__global__ __launch_bounds__(kThreads) void k_overlap(const PaRunDesc *__restrict__ A,
+                                                      const PaRunDesc *__restrict__ B, unsigned long long *hist)
 {
     __shared__ uint64_t red[kThreads / 64][16];
     const uint32_t w = blockIdx.x;
+    const PaRecord *ra = A->dv.rec, *rb = B->dv.rec;
+    const int64_t R = ra->Rcur < rb->Rcur ? (int64_t)ra->Rcur : (int64_t)rb->Rcur;
+    if ((int64_t)w * 64 >= R)
+        return;
+    const int N = A->N;
+    const uint64_t *a = A->dv.spins[ra->cur] + (size_t)w * N;
+    const uint64_t *b = B->dv.spins[rb->cur] + (size_t)w * N;
     uint64_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     uint64_t c16[16];
-    // up to 255 sites per thread in 8 planes: N <= 16384 with 256 threads -> 64
+    // up to 64 sites per thread with 256 threads and N <= 16384: fits 8 planes
     for (int s = threadIdx.x; s < N; s += blockDim.x)
-        vadd8(v, A[(size_t)w * N + s] ^ B[(size_t)w * N + s]);
+        vadd8(v, a[s] ^ b[s]);
 #pragma unroll
     for (int k = 0; k < 16; ++k)
         c16[k] = k < 8 ? v[k] : 0;
@@ -867,16 +1094,98 @@ __global__ __launch_bounds__(kThreads) void k_overlap(const uint64_t *__restrict
     }
 }
 
-// Thresholds of an imported inverse temperature.
-__global__ void k_set_beta(PaRecord *rec, double beta, double lnZ)
+// Free-energy-weighted combination of runs (Eqs. (9)-(10)): for group g, the
+// runs m with group_of[m] == g in index order; l_m = ln R_i^(m) + ln Z_hat_i^(m),
+// omega_m = exp(l_m - l_max) / sum exp(l - l_max); ln Z of the pooled
+// population = l_max + ln sum exp(l - l_max) - ln sum R^(m); moments are
+// weighted averages and c, chi follow Eqs. (11)-(12).
+__global__ void k_combine(const PaStepRecord *__restrict__ steprec, int npoints, int point,
+                          const int32_t *__restrict__ group_of, int nruns, int ngroups, const int32_t *__restrict__ Ns,
+                          double *__restrict__ out /* [ngroups][10] */)
 {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ngroups)
+        return;
+    double lmax = -INFINITY, Rsum = 0.0;
+    int n = 0, N = 0;
+    for (int m = 0; m < nruns; ++m) {
+        if (group_of[m] != g)
+            continue;
+        const PaStepRecord &r = steprec[(size_t)m * npoints + point];
+        if (r.status & PA_ST_FROZEN)
+            continue;
+        const double l = log((double)r.R) + r.lnZ;
+        lmax = l > lmax ? l : lmax;
+        Rsum = Rsum + (double)r.R;
+        N = Ns[m];
+        ++n;
+    }
+    double den = 0.0, e = 0.0, e2 = 0.0, am = 0.0, m2 = 0.0, w2 = 0.0, beta = 0.0;
+    for (int m = 0; m < nruns && n > 0; ++m) {
+        if (group_of[m] != g)
+            continue;
+        const PaStepRecord &r = steprec[(size_t)m * npoints + point];
+        if (r.status & PA_ST_FROZEN)
+            continue;
+        den = den + exp(log((double)r.R) + r.lnZ - lmax);
+        beta = r.beta;
+    }
+    for (int m = 0; m < nruns && n > 0; ++m) {
+        if (group_of[m] != g)
+            continue;
+        const PaStepRecord &r = steprec[(size_t)m * npoints + point];
+        if (r.status & PA_ST_FROZEN)
+            continue;
+        const double om = exp(log((double)r.R) + r.lnZ - lmax) / den;
+        e = e + om * r.e;
+        e2 = e2 + om * r.e2;
+        am = am + om * r.abs_m;
+        m2 = m2 + om * r.m2;
+        w2 = w2 + om * om;
+    }
+    double *o = out + (size_t)g * 10;
+    o[0] = n > 0 ? lmax + log(den) - log(Rsum) : NAN;
+    o[1] = e;
+    o[2] = e2;
+    o[3] = am;
+    o[4] = m2;
+    o[5] = beta * beta * (double)N * (e2 - e * e);
+    o[6] = beta * (double)N * (m2 - am * am);
+    o[7] = n > 0 ? 1.0 / w2 : 0.0;
+    o[8] = (double)n;
+    o[9] = beta;
+}
+
+// Imported state: thresholds of its beta and the scalars.
+__global__ void k_set_beta(const PaRunDesc *__restrict__ runs, double beta, double lnZ, uint32_t step,
+                           uint32_t sweeps, uint64_t R)
+{
+    PaRecord *rec = runs[blockIdx.x].dv.rec;
     if (threadIdx.x == 0) {
         rec->T[0] = pa_threshold(beta, 4);
         rec->T[1] = pa_threshold(beta, 8);
         rec->T[2] = pa_threshold(beta, 12);
+        rec->beta = beta;
         rec->lnZ = lnZ;
+        rec->step = step;
+        rec->sweeps = sweeps;
+        rec->Rcur = R;
         rec->sv = 0.0;
+        rec->status = 0;
+        rec->skip = 0;
     }
+}
+
+hipError_t sweep_launch(const PaBatchView &v, int g, int theta, int threads)
+{
+    if (v.gncol[g] == 0)
+        return hipSuccess;
+    const size_t lds = pa_sweep_lds_bytes(v.gN[g]);
+    if (v.gd[g] == 2)
+        k_sweep<2><<<v.gncol[g], threads, lds, v.stream>>>(v.runs, v.gcol[g], theta);
+    else
+        k_sweep<3><<<v.gncol[g], threads, lds, v.stream>>>(v.runs, v.gcol[g], theta);
+    return hipGetLastError();
 }
 
 } // namespace
@@ -884,77 +1193,99 @@ __global__ void k_set_beta(PaRecord *rec, double beta, double lnZ)
 // ====================================================================== launchers
 size_t pa_sweep_lds_bytes(int N) { return ((size_t)N * 9 + 7) & ~(size_t)7; }
 
-static int sweep_threads(int N)
+hipError_t pa_query_lds(int *max_lds)
 {
-    int t = ((N / 2 + 63) / 64) * 64;
-    return t > kThreads ? kThreads : (t < 64 ? 64 : t);
+    int dev = 0, v = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e == hipSuccess)
+        *max_lds = v;
+    return e;
 }
 
-hipError_t pa_launch_init(const PaLaunch &p, const PaDev &dv, int cur)
+hipError_t pa_b_init(const PaBatchView &v)
 {
-    const int64_t W = (p.R0 + 63) / 64;
-    k_init_spins<<<grid_for(W * p.N), kThreads, 0, p.stream>>>(dv.spins[cur], p.N, W, p.seed, p.run_id);
-    k_init_labels<<<grid_for(p.R0), kThreads, 0, p.stream>>>(dv.label[cur], p.R0);
+    k_init_rec<<<v.nruns, 64, 0, v.stream>>>(v.runs);
+    k_init_spins<<<v.ncol, kThreads, 0, v.stream>>>(v.runs, v.col);
+    k_init_labels<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
     hipError_t e = hipGetLastError();
+    for (int g = 0; g < v.ngroups && e == hipSuccess; ++g)
+        e = sweep_launch(v, g, 0, v.gthreads[g]);
+    return e;
+}
+
+hipError_t pa_b_sweep_group(const PaBatchView &v, int g, int theta, int threads)
+{
+    return sweep_launch(v, g, theta, threads);
+}
+
+hipError_t pa_b_sweep(const PaBatchView &v, int theta)
+{
+    hipError_t e = hipSuccess;
+    for (int g = 0; g < v.ngroups && e == hipSuccess; ++g)
+        e = sweep_launch(v, g, theta, v.gthreads[g]);
     if (e != hipSuccess)
         return e;
-    return pa_launch_sweep(p, dv, cur, p.R0, 0u, 0u, 0);
-}
-
-hipError_t pa_launch_sweep(const PaLaunch &p, const PaDev &dv, int cur, int64_t Rcur, uint32_t step,
-                           uint32_t t0, int theta)
-{
-    const unsigned W = (unsigned)((Rcur + 63) / 64);
-    const size_t lds = pa_sweep_lds_bytes(p.N);
-    const int th = sweep_threads(p.N);
-    if (p.d == 2)
-        k_sweep<2><<<W, th, lds, p.stream>>>(dv.spins[cur], dv.jmask, p.L, p.N, dv.E[cur], dv.M[cur], Rcur,
-                                             dv.rec, p.seed, p.run_id, step, t0, theta);
-    else
-        k_sweep<3><<<W, th, lds, p.stream>>>(dv.spins[cur], dv.jmask, p.L, p.N, dv.E[cur], dv.M[cur], Rcur,
-                                             dv.rec, p.seed, p.run_id, step, t0, theta);
+    k_sweeps_add<<<v.nruns, 64, 0, v.stream>>>(v.runs, theta);
     return hipGetLastError();
 }
 
-hipError_t pa_launch_reweight(const PaLaunch &p, const PaDev &dv, int cur, int64_t Rcur, double dbeta,
-                              double beta_next)
+static hipError_t hist_launch(const PaBatchView &v)
 {
-    const int DN = p.d * p.N;
-    k_hist_prep<<<grid_for(p.H), kThreads, 0, p.stream>>>(dv.hist, p.H, dv.rec);
-    const int g = grid_for(Rcur, 4096, 1024);
-    k_hist<<<g, kThreads, (size_t)p.H * 4, p.stream>>>(dv.E[cur], Rcur, DN, p.H, dv.hist, dv.rec);
-    k_reweight<<<1, 1024, 0, p.stream>>>(dv.hist, dv.wtab, dv.rec, DN, Rcur, dbeta, beta_next);
+    k_hist_prep<<<v.nruns, kThreads, 0, v.stream>>>(v.runs);
+    k_hist<<<v.nrep, kThreads, (size_t)v.maxH * 4, v.stream>>>(v.runs, v.rep);
     return hipGetLastError();
 }
 
-hipError_t pa_launch_counts(const PaLaunch &p, const PaDev &dv, int cur, int64_t Rprev, int64_t Rt,
-                            int scheme, uint32_t step)
+hipError_t pa_b_reweight(const PaBatchView &v, double beta_next)
 {
-    const int DN = p.d * p.N;
-    const int g = grid_for(Rprev);
+    hipError_t e = hist_launch(v);
+    if (e != hipSuccess)
+        return e;
+    k_reweight<<<v.nruns, 1024, 0, v.stream>>>(v.runs, beta_next);
+    return hipGetLastError();
+}
+
+hipError_t pa_b_rule(const PaBatchView &v, double alpha_star, double dbeta_max, int iterations, int bisect)
+{
+    hipError_t e = hist_launch(v);
+    if (e != hipSuccess)
+        return e;
+    k_rule<<<v.nruns, kRuleThreads, 0, v.stream>>>(v.runs, alpha_star, dbeta_max, iterations, bisect);
+    return hipGetLastError();
+}
+
+template <typename T, bool INCL, int WHICH>
+static hipError_t scan_launch(const PaBatchView &v)
+{
+    k_scan_prep<<<v.nruns, kThreads, 0, v.stream>>>(v.runs);
+    k_fill_u32<<<1, 64, 0, v.stream>>>(v.ticket, 1, 0u);
+    k_scan<T, INCL, WHICH><<<v.ntile, PA_SCAN_THREADS, 0, v.stream>>>(v.runs, v.tile, v.ticket);
+    return hipGetLastError();
+}
+
+hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze)
+{
     hipError_t e;
+    k_resample_prep<<<v.nruns, 64, 0, v.stream>>>(v.runs);
     switch (scheme) {
     case 2:
-        k_counts_nearest<<<g, kThreads, 0, p.stream>>>(dv.E[cur], Rprev, (uint64_t)Rt, dv.wtab, dv.rec, DN, p.seed,
-                                                       p.run_id, step, dv.r);
+        k_counts_nearest<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
         break;
     case 1:
-        k_counts_poisson<<<g, kThreads, 0, p.stream>>>(dv.E[cur], Rprev, (uint64_t)Rt, dv.wtab, dv.rec, DN, p.seed,
-                                                       p.run_id, step, dv.r);
+        k_counts_poisson<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
         break;
     case 3:
     case 0:
-        k_weights<<<g, kThreads, 0, p.stream>>>(dv.E[cur], Rprev, dv.wtab, dv.rec, DN, dv.C);
-        if ((e = scan<uint64_t, true>(dv.C, dv.C, Rprev, dv, &dv.rec->Ctot, p.stream)) != hipSuccess)
+        k_weights<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
+        if ((e = scan_launch<uint64_t, true, 0>(v)) != hipSuccess)
             return e;
         if (scheme == 3) {
-            k_counts_systematic<<<g, kThreads, 0, p.stream>>>(dv.C, Rprev, (uint64_t)Rt, dv.rec, p.seed, p.run_id,
-                                                              step, dv.r);
+            k_counts_systematic<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
         } else {
-            if ((e = fill_u32(dv.r, Rprev, 0u, p.stream)) != hipSuccess)
-                return e;
-            k_counts_multinomial<<<grid_for(Rt), kThreads, 0, p.stream>>>(dv.C, Rprev, (uint64_t)Rt, dv.rec, p.seed,
-                                                                          p.run_id, step, dv.r);
+            k_clear_counts<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
+            k_counts_multinomial<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
         }
         break;
     default:
@@ -962,71 +1293,47 @@ hipError_t pa_launch_counts(const PaLaunch &p, const PaDev &dv, int cur, int64_t
     }
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
-    k_sv_partial<<<PA_RED_BLOCKS, kThreads, 0, p.stream>>>(dv.E[cur], Rprev, (uint64_t)Rt, dv.wtab, dv.rec, DN,
-                                                           dv.r, dv.partial);
-    if ((e = hipGetLastError()) != hipSuccess)
+    k_sv_partial<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
+    if ((e = scan_launch<uint32_t, false, 1>(v)) != hipSuccess)
         return e;
-    return scan<uint32_t, false>(dv.r, dv.P, Rprev, dv, reinterpret_cast<unsigned long long *>(&dv.rec->Rnew),
-                                 p.stream);
-}
-
-hipError_t pa_launch_apply(const PaLaunch &p, const PaDev &dv, int cur, int64_t Rprev, int64_t Rnew)
-{
-    const int nxt = cur ^ 1;
-    k_ancestors<<<grid_for(Rprev), kThreads, 0, p.stream>>>(dv.r, dv.P, Rprev, dv.anc);
-    k_gather_rep<<<grid_for(Rnew), kThreads, 0, p.stream>>>(dv.anc, Rnew, dv.E[cur], dv.M[cur], dv.label[cur],
-                                                            dv.E[nxt], dv.M[nxt], dv.label[nxt]);
-    const unsigned W = (unsigned)((Rnew + 63) / 64);
-    k_gather_spins<<<W, kThreads, 0, p.stream>>>(dv.spins[cur], dv.spins[nxt], dv.anc, Rnew, p.N);
-    k_commit<<<1, kThreads, 0, p.stream>>>(dv.rec, dv.partial, PA_RED_BLOCKS, Rprev, Rnew);
+    k_check<<<v.nruns, 64, 0, v.stream>>>(v.runs, freeze);
+    k_ancestors<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
+    k_gather_rep<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
+    k_gather_spins<<<v.ncol, kThreads, 0, v.stream>>>(v.runs, v.col);
+    k_commit<<<v.nruns, kThreads, 0, v.stream>>>(v.runs);
     return hipGetLastError();
 }
 
-hipError_t pa_launch_observables(const PaLaunch &p, const PaDev &dv, int cur, int64_t Rcur)
+hipError_t pa_b_observables(const PaBatchView &v, int point)
 {
-    k_obs_prep<<<grid_for(p.R0), kThreads, 0, p.stream>>>(dv.fam, p.R0, dv.rec);
-    k_obs_rep<<<grid_for(Rcur, kThreads, 1024), kThreads, 0, p.stream>>>(dv.E[cur], dv.M[cur], dv.label[cur],
-                                                                         Rcur, dv.fam, dv.rec);
-    k_obs_fam<<<PA_RED_BLOCKS, kThreads, 0, p.stream>>>(dv.fam, p.R0, dv.rec, dv.partial);
-    k_obs_final<<<1, kThreads, 0, p.stream>>>(dv.rec, dv.partial, PA_RED_BLOCKS, p.N, Rcur);
+    k_obs_prep<<<v.nruns, kThreads, 0, v.stream>>>(v.runs);
+    k_obs_rep<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
+    k_obs_fam<<<v.nfam, kThreads, 0, v.stream>>>(v.runs, v.fam);
+    k_obs_final<<<v.nruns, kThreads, 0, v.stream>>>(v.runs, point >= 0 ? v.steprec : nullptr, v.npoints,
+                                                    point);
     return hipGetLastError();
 }
 
-hipError_t pa_launch_overlap(const PaLaunch &p, const uint64_t *a, const uint64_t *b, int64_t R,
-                             unsigned long long *hist)
+hipError_t pa_b_set_beta(const PaBatchView &v, double beta, double lnZ, uint32_t step, uint32_t sweeps,
+                         uint64_t R)
 {
-    const unsigned W = (unsigned)((R + 63) / 64);
-    k_overlap<<<W, kThreads, 0, p.stream>>>(a, b, p.N, R, hist);
+    k_set_beta<<<v.nruns, 64, 0, v.stream>>>(v.runs, beta, lnZ, step, sweeps, R);
     return hipGetLastError();
 }
 
-hipError_t pa_launch_rule(const PaLaunch &p, const PaDev &dv, int cur, int64_t Rcur, double alpha_star,
-                          double dbeta_max, int iterations, int bisect)
+hipError_t pa_launch_combine(const PaBatchView &v, int point, const int32_t *group_of, int ngroups,
+                             const int32_t *Ns, double *out)
 {
-    const int DN = p.d * p.N;
-    k_hist_prep<<<grid_for(p.H), kThreads, 0, p.stream>>>(dv.hist, p.H, dv.rec);
-    k_hist<<<grid_for(Rcur, 4096, 1024), kThreads, (size_t)p.H * 4, p.stream>>>(dv.E[cur], Rcur, DN, p.H, dv.hist,
-                                                                                dv.rec);
-    k_rule<<<1, kRuleThreads, 0, p.stream>>>(dv.hist, dv.rec, DN, Rcur, alpha_star, dbeta_max, iterations, bisect);
+    k_combine<<<(ngroups + 63) / 64, 64, 0, v.stream>>>(v.steprec, v.npoints, point, group_of, (int)v.nruns,
+                                                        ngroups, Ns, out);
     return hipGetLastError();
 }
 
-hipError_t pa_launch_set_beta(const PaLaunch &p, const PaDev &dv, double beta, double lnZ)
+hipError_t pa_launch_overlap(const PaRunDesc *a, const PaRunDesc *b, int N, uint32_t ncols_a,
+                             unsigned long long *hist, hipStream_t st)
 {
-    k_set_beta<<<1, 64, 0, p.stream>>>(dv.rec, beta, lnZ);
+    k_fill_u32<<<grid_for((int64_t)(N + 1) * 2), kThreads, 0, st>>>(reinterpret_cast<uint32_t *>(hist),
+                                                                     (int64_t)(N + 1) * 2, 0u);
+    k_overlap<<<ncols_a, kThreads, 0, st>>>(a, b, hist);
     return hipGetLastError();
-}
-
-// ROCm lets a launch use dynamic LDS up to the device's per-workgroup limit
-// without a per-function attribute; only the limit is needed here.
-hipError_t pa_configure_kernels(int *max_lds)
-{
-    int dev = 0, v = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess)
-        e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    if (e != hipSuccess)
-        return e;
-    *max_lds = v;
-    return hipSuccess;
 }

@@ -46,6 +46,28 @@ class pa_counters(ctypes.Structure):
                 ("sweeps", ctypes.c_uint64)]
 
 
+class pa_step_record(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("beta", "lnQ", "lnZ", "sv", "e", "e2", "abs_m", "m2",
+                                               "rho_t", "S_f")] + \
+               [(n, ctypes.c_int64) for n in ("R", "sum_E", "sum_E2", "sum_absM", "sum_M2",
+                                              "sum_c2", "families")] + \
+               [("status", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+
+
+class pa_combined(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("lnZ", "e", "e2", "abs_m", "m2", "c", "chi", "n_eff",
+                                               "beta")] + \
+               [("runs", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+STEP_RECORD_DTYPE = np.dtype([(n, np.float64) for n in ("beta", "lnQ", "lnZ", "sv", "e", "e2",
+                                                        "abs_m", "m2", "rho_t", "S_f")] +
+                             [(n, np.int64) for n in ("R", "sum_E", "sum_E2", "sum_absM", "sum_M2",
+                                                      "sum_c2", "families")] +
+                             [("status", np.uint32), ("pad", np.uint32)])
+assert STEP_RECORD_DTYPE.itemsize == ctypes.sizeof(pa_step_record)
+
+
 class PAError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"status {status}: {msg}")
@@ -92,6 +114,25 @@ def lib():
         L.pa_step_alpha.argtypes = [v, ctypes.c_double, P(ctypes.c_double)]
         L.pa_step_rule.argtypes = [v, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                    P(ctypes.c_double)]
+        L.pa_batch_required_bytes.argtypes = [P(pa_config), ctypes.c_int32, ctypes.c_int32,
+                                              P(ctypes.c_uint64)]
+        L.pa_batch_create.argtypes = [P(pa_config), ctypes.c_int32, ctypes.c_int32, v,
+                                      ctypes.c_uint64, v, P(v)]
+        L.pa_batch_tune.argtypes = [v, ctypes.c_int32, v]
+        L.pa_batch_groups.argtypes = [v, P(ctypes.c_int32), v]
+        L.pa_batch_anneal.argtypes = [v, v, ctypes.c_int32, ctypes.c_int32, ctypes.c_int,
+                                      ctypes.c_int32]
+        L.pa_batch_records.argtypes = [v, v]
+        L.pa_batch_export_run.argtypes = [v, ctypes.c_int32, P(pa_host_state)]
+        L.pa_batch_combine.argtypes = [v, v, ctypes.c_int32, ctypes.c_int32, v]
+        L.pa_batch_destroy.argtypes = [v]
+        L.pa_batch_destroy.restype = None
+        L.pa_batch_last_error.argtypes = [v]
+        L.pa_batch_last_error.restype = ctypes.c_char_p
+        for name in ("pa_batch_required_bytes", "pa_batch_create", "pa_batch_tune",
+                     "pa_batch_groups", "pa_batch_anneal", "pa_batch_records",
+                     "pa_batch_export_run", "pa_batch_combine"):
+            getattr(L, name).restype = ctypes.c_int
         L.pa_destroy.argtypes = [v]
         L.pa_destroy.restype = None
         L.pa_last_error.argtypes = [v]
@@ -107,6 +148,12 @@ def lib():
 def _check(status, ctx):
     if status != PA_OK:
         msg = lib().pa_last_error(ctx)
+        raise _ERRORS.get(status, PAError)(status, msg.decode() if msg else "")
+
+
+def _check_b(status, b):
+    if status != PA_OK:
+        msg = lib().pa_batch_last_error(b)
         raise _ERRORS.get(status, PAError)(status, msg.decode() if msg else "")
 
 
@@ -291,6 +338,92 @@ class PARun:
         if self.ctx is not None:
             pa_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PABatch:
+    """Many independent runs annealed together (one workspace, one stream).
+
+    ``configs``: list of dicts with dim, L, R and optional seed, run_id,
+    capacity, couplings (int8[N*dim])."""
+
+    def __init__(self, configs, max_points, device=None, stream=None):
+        import torch
+        self.n = len(configs)
+        self._coup = [None if c.get("couplings") is None else
+                      np.ascontiguousarray(c["couplings"], np.int8) for c in configs]
+        arr = (pa_config * self.n)()
+        for k, c in enumerate(configs):
+            arr[k] = make_config(c["dim"], c["L"], c["R"], c.get("seed", 1), c.get("run_id", 0),
+                                 c.get("capacity", 0), self._coup[k])
+        self._cfgs = arr
+        self.N = [c["L"] ** c["dim"] for c in configs]
+        self.max_points = int(max_points)
+        nb = ctypes.c_uint64()
+        _check_b(lib().pa_batch_required_bytes(arr, self.n, self.max_points, ctypes.byref(nb)), None)
+        self.device = torch.device("cuda", 0) if device is None else torch.device(device)
+        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        # graph capture needs a stream of its own (default priority)
+        self.stream = torch.cuda.Stream(self.device) if stream is None else stream
+        torch.cuda.synchronize(self.device)
+        h = ctypes.c_void_p()
+        _check_b(lib().pa_batch_create(arr, self.n, self.max_points, self.workspace.data_ptr(),
+                                       nb.value, self.stream.cuda_stream, ctypes.byref(h)), None)
+        self.h = h
+        self.npoints = 0
+
+    def groups(self):
+        ng = ctypes.c_int32()
+        t = np.zeros(16, np.int32)
+        _check_b(lib().pa_batch_groups(self.h, ctypes.byref(ng), t.ctypes.data), self.h)
+        return t[:ng.value].tolist()
+
+    def tune(self, theta=10):
+        t = np.zeros(16, np.int32)
+        _check_b(lib().pa_batch_tune(self.h, int(theta), t.ctypes.data), self.h)
+        return self.groups()
+
+    def anneal(self, betas, theta, scheme, use_graph=True):
+        b = np.ascontiguousarray(betas, np.float64)
+        _check_b(lib().pa_batch_anneal(self.h, b.ctypes.data, len(b), int(theta),
+                                       SCHEMES.get(scheme, scheme), 1 if use_graph else 0), self.h)
+        self.npoints = len(b)
+
+    def records(self):
+        out = np.zeros((self.n, self.npoints), STEP_RECORD_DTYPE)
+        _check_b(lib().pa_batch_records(self.h, out.ctypes.data), self.h)
+        return out
+
+    def export_run(self, m):
+        st = pa_host_state()
+        _check_b(lib().pa_batch_export_run(self.h, m, ctypes.byref(st)), self.h)
+        R, N = st.R, self.N[m]
+        spins = np.zeros(((R + 63) // 64, N), np.uint64)
+        E = np.zeros(R, np.int32)
+        M = np.zeros(R, np.int32)
+        lab = np.zeros(R, np.uint32)
+        st.spins, st.energy = spins.ctypes.data, E.ctypes.data
+        st.magnetization, st.label = M.ctypes.data, lab.ctypes.data
+        _check_b(lib().pa_batch_export_run(self.h, m, ctypes.byref(st)), self.h)
+        return dict(R=R, step=st.step, sweeps=st.sweeps, beta=st.beta, lnZ=st.lnZ, spins=spins,
+                    energy=E, magnetization=M, label=lab)
+
+    def combine(self, group_of_run, ngroups, point):
+        g = np.ascontiguousarray(group_of_run, np.int32)
+        out = (pa_combined * ngroups)()
+        _check_b(lib().pa_batch_combine(self.h, g.ctypes.data, int(ngroups), int(point),
+                                        ctypes.cast(out, ctypes.c_void_p)), self.h)
+        return [{n: getattr(o, n) for n, _ in pa_combined._fields_ if n != "pad"} for o in out]
+
+    def close(self):
+        if self.h is not None:
+            lib().pa_batch_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:

@@ -1,0 +1,153 @@
+"""GPU tests of batches: a batched anneal (eager or one HIP graph, any tuned
+workgroup size) gives exactly the bits of the same runs done one by one
+through the single-run calls; the weighted combination matches its oracle."""
+import numpy as np
+import pytest
+
+from oracle import combine as OC
+from oracle import oracle as O
+from tests.paritylib import compare_state, ea_couplings, rel_ok, schedule
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(2, 8, 300, "fm"), (3, 4, 200, "ea"), (2, 6, 130, "ea"), (3, 6, 500, "ea"),
+          (2, 12, 1000, "fm"), (2, 8, 65, "ea"), (3, 4, 1, "fm"), (2, 16, 700, "ea")]
+
+
+def configs(seed=3):
+    out = []
+    for k, (d, L, R, kind) in enumerate(SHAPES):
+        J = None if kind == "fm" else ea_couplings(d, L, 100 + k)
+        out.append(dict(dim=d, L=L, R=R, seed=seed, run_id=k, couplings=J))
+    return out
+
+
+def single_records(cfg, betas, theta, scheme):
+    from paper_2401_07965_amd import pa
+    g = pa.PARun(cfg["dim"], cfg["L"], cfg["R"], seed=cfg["seed"], run_id=cfg["run_id"],
+                 couplings=cfg["couplings"])
+    rows = []
+    ob = g.observables()
+    rows.append((0.0, g.free_energy(), ob))
+    for b in betas[1:]:
+        q = g.reweight(b)
+        g.resample(scheme)
+        g.sweep(theta)
+        rows.append((q, g.free_energy(), g.observables()))
+    st = g.export()
+    g.close()
+    return rows, st
+
+
+@pytest.mark.parametrize("scheme", [O.SYSTEMATIC, O.NEAREST_INT, O.MULTINOMIAL, O.POISSON])
+def test_batch_equals_single_runs(scheme):
+    from paper_2401_07965_amd import pa
+    betas = schedule(1.5, 9)
+    cfgs = configs()
+    print(f"[batch] scheme {scheme}: {len(cfgs)} runs", flush=True)
+    B = pa.PABatch(cfgs, max_points=len(betas))
+    B.anneal(betas, 3, scheme, use_graph=False)
+    rec = B.records()
+    for m, cfg in enumerate(cfgs):
+        rows, st = single_records(cfg, betas, 3, scheme)
+        for i, (q, lz, ob) in enumerate(rows):
+            r = rec[m, i]
+            assert r["lnQ"] == q and r["lnZ"] == lz, (m, i)
+            for k in ("e", "e2", "abs_m", "m2", "rho_t", "S_f", "sv"):
+                assert r[k] == ob[k], (m, i, k)
+            for k in ("R", "sum_E", "sum_E2", "sum_absM", "sum_M2", "sum_c2", "families"):
+                assert int(r[k]) == int(ob[k]), (m, i, k)
+        bs = B.export_run(m)
+        for k in ("spins", "energy", "magnetization", "label"):
+            assert np.array_equal(bs[k], st[k]), (m, k)
+    B.close()
+
+
+def test_graph_replays_equal_eager_and_tuning_changes_nothing():
+    from paper_2401_07965_amd import pa
+    betas = schedule(2.0, 12)
+    B = pa.PABatch(configs(seed=5), max_points=len(betas))
+    B.anneal(betas, 4, O.SYSTEMATIC, use_graph=False)
+    ref = B.records().copy()
+    ref_state = [B.export_run(m) for m in range(B.n)]
+    threads = B.tune(4)
+    assert all(t in (64, 128, 192, 256, 320, 384, 448, 512) for t in threads)
+    for rep in range(3):
+        print(f"[batch] graph replay {rep}", flush=True)
+        B.anneal(betas, 4, O.SYSTEMATIC, use_graph=True)
+        got = B.records()
+        assert np.array_equal(got, ref), rep
+        for m in range(B.n):
+            s = B.export_run(m)
+            for k in ("spins", "energy", "label"):
+                assert np.array_equal(s[k], ref_state[m][k])
+        # eager work between replays
+        B.anneal(betas[:3], 1, O.NEAREST_INT, use_graph=False)
+    B.close()
+
+
+def test_batch_matches_oracle_on_small_runs():
+    from paper_2401_07965_amd import pa
+    betas = schedule(1.0, 6)
+    cfgs = configs()[:3]
+    B = pa.PABatch(cfgs, max_points=len(betas))
+    B.anneal(betas, 2, O.NEAREST_INT, use_graph=True)
+    rec = B.records()
+    for m, c in enumerate(cfgs):
+        o = O.OracleRun(c["dim"], c["L"], c["R"], seed=c["seed"], run_id=c["run_id"],
+                        J=c["couplings"])
+        for i, b in enumerate(betas[1:], 1):
+            assert rel_ok(rec[m, i]["lnQ"], o.reweight(b))
+            assert rec[m, i]["R"] == o.resample(O.NEAREST_INT)
+            o.sweep(2)
+        compare_state(_Exported(B, m), o, f"batch run {m}")
+    B.close()
+
+
+class _Exported:
+    def __init__(self, B, m):
+        self.B, self.m = B, m
+
+    def export(self):
+        return self.B.export_run(self.m)
+
+
+def test_frozen_run_does_not_disturb_the_others():
+    from paper_2401_07965_amd import pa
+    betas = [0.0, 0.5, 1.5, 3.0, 4.0]
+    cfgs = [dict(dim=2, L=8, R=200, seed=1, run_id=0, couplings=None),
+            dict(dim=2, L=4, R=64, seed=5, run_id=0, couplings=None, capacity=64),
+            dict(dim=3, L=4, R=300, seed=2, run_id=3, couplings=ea_couplings(3, 4, 1))]
+    B = pa.PABatch(cfgs, max_points=len(betas))
+    B.anneal(betas, 2, O.POISSON, use_graph=True)
+    rec = B.records()
+    assert rec[1, -1]["status"] & 16, "the tight-capacity run should freeze"
+    for m in (0, 2):
+        rows, st = single_records(cfgs[m], betas, 2, O.POISSON)
+        assert [r[1] for r in rows] == rec[m]["lnZ"].tolist()
+        assert np.array_equal(B.export_run(m)["spins"], st["spins"])
+    B.close()
+
+
+def test_weighted_combination_matches_oracle():
+    from paper_2401_07965_amd import pa
+    betas = schedule(1.0, 8)
+    J = ea_couplings(2, 8, 9)
+    cfgs = [dict(dim=2, L=8, R=int(r), seed=7, run_id=k, couplings=J)
+            for k, r in enumerate([300, 500, 800, 1000, 200, 640])]
+    B = pa.PABatch(cfgs, max_points=len(betas))
+    B.anneal(betas, 3, O.NEAREST_INT, use_graph=True)
+    rec = B.records()
+    groups = [0, 0, 0, 1, 1, -1]
+    for point in (3, 7):
+        out = B.combine(groups, 2, point)
+        for g in (0, 1):
+            rs = [dict(R=int(rec[m, point]["R"]), lnZ=rec[m, point]["lnZ"],
+                       beta=rec[m, point]["beta"], e=rec[m, point]["e"], e2=rec[m, point]["e2"],
+                       abs_m=rec[m, point]["abs_m"], m2=rec[m, point]["m2"])
+                  for m in range(len(cfgs)) if groups[m] == g]
+            ref = OC.combine(rs, 64)
+            assert out[g]["runs"] == ref["runs"]
+            for k in ("lnZ", "e", "e2", "abs_m", "m2", "c", "chi", "n_eff"):
+                assert rel_ok(out[g][k], ref[k], 1e-12), (point, g, k, out[g][k], ref[k])
+    B.close()
