@@ -173,15 +173,19 @@ pa_status pa_overlap(pa_ctx *a, pa_ctx *b, int64_t *hist_out);
 
 /* Adaptive temperature steps (Sec. 5 names them; the rule is a reading):
  * overlap of the current population with its reweighting by dbeta,
- *   alpha(dbeta) = (1/R) sum_j min(1, tau_j),  tau_j = R w_j / sum_k w_k,
- *   w_j = exp(-dbeta (E_j - E_min))  (tau of Eq. (1)),
- * i.e. one minus the total-variation distance between the population and
- * its reweighted version; alpha(0) = 1.  Synchronises the stream. */
+ *   alpha(dbeta) = (1/R) sum_j min(1, tauhat_j),  tauhat_j = R W_j / S,
+ * with the integer resampling weights W_j = floor(2^40 exp(-dbeta (E_j - E_min)))
+ * and S = sum_j W_j (tau of Eq. (1) as the resampling uses it), i.e. one minus
+ * the total-variation distance between the population and its reweighted
+ * version; alpha(0) = 1.  Evaluated exactly as sum_j min(S, R W_j) / (R S).
+ * Synchronises the stream. */
 pa_status pa_step_alpha(pa_ctx *ctx, double dbeta, double *alpha_out);
 
 /* Largest dbeta in [0, dbeta_max] with alpha(dbeta) >= alpha_star: dbeta_max
  * itself if it qualifies, else `iterations` halvings of [0, dbeta_max]
  * keeping the lower end qualified (0 < alpha_star < 1, 1 <= iterations <= 200).
+ * alpha_star counts to 2^-32 (A = nearest integer to 2^32 alpha_star, ties to
+ * even; qualifies iff 2^32 sum_j min(S, R W_j) >= A R S, exact).
  * The population is unchanged; pass beta + dbeta to pa_reweight. */
 pa_status pa_step_rule(pa_ctx *ctx, double alpha_star, double dbeta_max, int32_t iterations,
                        double *dbeta_out);

@@ -384,38 +384,66 @@ __global__ __launch_bounds__(1024) void k_reweight(const PaRunDesc *__restrict__
 }
 
 // ------------------------------------------------------------------ adaptive step
-// Overlap of the population with its reweighting by dbeta,
-// alpha = (1/R) sum_j min(1, R w_j / sum_k w_k), w_j = pa_exp(-dbeta (E_j - E_min)),
-// evaluated per energy level (fixed chunk per thread, fixed tree), and the
-// bisection for the largest dbeta in [0, dbeta_max] with alpha >= alpha_star.
-__device__ double rule_alpha(const uint32_t *__restrict__ hist, int hmin, int nlev, double R, double dbeta,
-                             double *wcache, double *sd)
+// Overlap of the population with its reweighting by dbeta, with the integer
+// weights the resampling uses: W_h = floor(2^40 pa_exp(-dbeta 4(h - hmin)))
+// per energy level, S = sum_h n_h W_h, and
+//   alpha = sum_h n_h min(S, R W_h) / (R S)
+// exactly (integer sums, so any order gives the same numbers).  The bisection
+// keeps the largest dbeta in [0, dbeta_max] with 2^32 num >= A R S, A the
+// target overlap in units of 2^-32.
+__device__ __forceinline__ pa_u128 block_sum_u128(pa_u128 v, uint64_t *su)
+{
+    pa_u128 t = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t limb = (uint64_t)(v >> (32 * k)) & 0xFFFFFFFFull;
+        t += (pa_u128)pa_block_sum_u64(limb, su) << (32 * k);
+    }
+    return t;
+}
+
+__device__ __forceinline__ double u128_to_double(pa_u128 x)
+{
+    return (double)(uint64_t)(x >> 64) * 18446744073709551616.0 + (double)(uint64_t)x;
+}
+
+struct Overlap {
+    pa_u128 num, den;
+};
+
+__device__ Overlap rule_overlap(const uint32_t *__restrict__ hist, int hmin, int nlev, uint64_t R, double dbeta,
+                                uint64_t *wcache, uint64_t *su)
 {
     const int chunk = (nlev + (int)blockDim.x - 1) / (int)blockDim.x;
     const int lo = (int)threadIdx.x * chunk;
     const int hi = lo + chunk < nlev ? lo + chunk : nlev;
-    double wsum = 0.0;
+    uint64_t s = 0;
     for (int k = lo; k < hi; ++k) {
-        const double wv = pa_exp(-(dbeta * (double)(4 * k)));
+        const uint64_t W = pa_weight(dbeta, 4 * k);
         if (k < kRuleCache)
-            wcache[k] = wv;
-        wsum = wsum + (double)hist[hmin + k] * wv;
+            wcache[k] = W;
+        s += (uint64_t)hist[hmin + k] * W;
     }
-    const double W = pa_block_sum_f64(wsum, sd);
-    double a = 0.0;
+    const uint64_t S = pa_block_sum_u64(s, su);
+    pa_u128 a = 0;
     for (int k = lo; k < hi; ++k) {
-        const double wv = k < kRuleCache ? wcache[k] : pa_exp(-(dbeta * (double)(4 * k)));
-        const double tau = (R * wv) / W;
-        a = a + (double)hist[hmin + k] * (tau < 1.0 ? tau : 1.0);
+        const uint64_t W = k < kRuleCache ? wcache[k] : pa_weight(dbeta, 4 * k);
+        const uint64_t RW = R * W;
+        a += (pa_u128)hist[hmin + k] * (RW < S ? RW : S);
     }
-    return pa_block_sum_f64(a, sd) / R;
+    Overlap o;
+    o.num = block_sum_u128(a, su);
+    o.den = (pa_u128)R * S;
+    return o;
 }
+
+__device__ __forceinline__ bool qualifies(const Overlap &o, uint64_t A) { return (o.num << 32) >= (pa_u128)A * o.den; }
 
 __global__ __launch_bounds__(kRuleThreads) void k_rule(const PaRunDesc *__restrict__ runs, double alpha_star,
                                                        double dbeta_max, int iterations, int bisect)
 {
-    __shared__ double sd[16];
-    __shared__ double wcache[kRuleCache];
+    __shared__ uint64_t su[16];
+    __shared__ uint64_t wcache[kRuleCache];
     const PaRunDesc &rd = runs[blockIdx.x];
     PaRecord *rec = rd.dv.rec;
     if (frozen(rec))
@@ -423,18 +451,20 @@ __global__ __launch_bounds__(kRuleThreads) void k_rule(const PaRunDesc *__restri
     const int DN = rd.d * rd.N;
     const int hmin = (rec->emin + DN) >> 2, hmax = (rec->emax + DN) >> 2;
     const int nlev = hmax - hmin + 1;
-    const double R = (double)rec->Rcur;
-    const double a = rule_alpha(rd.dv.hist, hmin, nlev, R, dbeta_max, wcache, sd);
-    double best = dbeta_max, abest = a;
-    if (bisect && !(a >= alpha_star)) {
+    const uint64_t R = rec->Rcur;
+    const uint64_t A = (uint64_t)rint(ldexp(alpha_star, 32));
+    const Overlap top = rule_overlap(rd.dv.hist, hmin, nlev, R, dbeta_max, wcache, su);
+    double best = dbeta_max;
+    Overlap obest = top;
+    if (bisect && !qualifies(top, A)) {
         double lo = 0.0, hi = dbeta_max;
-        abest = 1.0;
+        obest.num = obest.den = 1; // alpha(0) = 1
         for (int it = 0; it < iterations; ++it) {
             const double mid = 0.5 * (lo + hi);
-            const double am = rule_alpha(rd.dv.hist, hmin, nlev, R, mid, wcache, sd);
-            if (am >= alpha_star) {
+            const Overlap om = rule_overlap(rd.dv.hist, hmin, nlev, R, mid, wcache, su);
+            if (qualifies(om, A)) {
                 lo = mid;
-                abest = am;
+                obest = om;
             } else {
                 hi = mid;
             }
@@ -443,7 +473,7 @@ __global__ __launch_bounds__(kRuleThreads) void k_rule(const PaRunDesc *__restri
     }
     if (threadIdx.x == 0) {
         rec->rule_dbeta = best;
-        rec->rule_alpha = abest;
+        rec->rule_alpha = u128_to_double(obest.num) / u128_to_double(obest.den);
     }
 }
 

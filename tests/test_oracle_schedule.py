@@ -20,7 +20,7 @@ def test_two_level_closed_form():
         w1 = math.exp(-4 * db)
         W = n0 + n1 * w1
         ref = (n0 * min(1.0, R / W) + n1 * min(1.0, R * w1 / W)) / R
-        assert abs(S.alpha(E, db) - ref) < 1e-12
+        assert abs(S.alpha(E, db) - ref) < 1e-9
 
 
 def test_alpha_is_one_minus_total_variation():
@@ -30,13 +30,23 @@ def test_alpha_is_one_minus_total_variation():
         w = np.exp(-db * (E - E.min()).astype(np.float64))
         p = w / w.sum()
         tv = 0.5 * np.abs(p - 1.0 / len(E)).sum()
-        assert abs(S.alpha(E, db) - (1 - tv)) < 1e-12
+        assert abs(S.alpha(E, db) - (1 - tv)) < 1e-9
 
 
 def test_alpha_decreases_with_the_step():
     E = np.random.default_rng(2).normal(-5000, 60, 20000).round().astype(np.int64) * 4
     a = [S.alpha(E, db) for db in np.linspace(0, 0.05, 26)]
     assert all(x >= y - 1e-15 for x, y in zip(a, a[1:]))
+
+
+def test_exact_overlap_is_the_resampling_overlap():
+    """alpha is (1/R) sum_j min(1, tauhat_j) with the resampling's own tauhat (Eq. (3))."""
+    from oracle import oracle as O
+    E = np.random.default_rng(9).integers(-300, 0, 2000).astype(np.int32) * 4
+    for db in (0.002, 0.02):
+        _, W, Ssum = O.reweight(E, db)
+        tau = O.tau_hat(W, Ssum, len(E))
+        assert abs(S.alpha(E, db) - np.minimum(1.0, tau).mean()) < 1e-12
 
 
 def test_gaussian_energies_closed_form():
@@ -55,8 +65,9 @@ def test_step_rule_brackets_the_target(astar):
     E = np.random.default_rng(4).normal(-3000, 50, 5000).round().astype(np.int64) * 4
     dmax = 1.0
     d = S.step_rule(E, astar, dmax, iterations=60)
+    A = S.target(astar)
     assert 0.0 <= d < dmax
-    assert S.alpha(E, d) >= astar
-    assert S.alpha(E, d + 4 * dmax * 2.0 ** -60 + 1e-12) < astar or d == dmax
+    assert S.qualifies(E, d, A) and S.alpha(E, d) >= astar - 2.0 ** -32
+    assert not S.qualifies(E, d + 1e-12, A)
     # a tiny population spread admits the whole range
     assert S.step_rule(np.full(10, -40), astar, dmax) == dmax
