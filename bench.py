@@ -114,6 +114,63 @@ def resample_bytes(Rn, g):
     return g.R * (4 + 4 + 4 + 4 + 4) + Rn * (2 * N / 8 + 3 * 4 * 2 + 4)
 
 
+def batched_bench(theta=10, scheme=3, verify_runs=8):
+    """Uneven-batch workload: 256 independent +-J runs (16 disorder samples x 16
+    runs; per sample d in {2,3}, L in {8,12,16,24}; R log-uniform in [1e3, 1e5]),
+    beta_i = 3 i/150, theta = 10, systematic resampling.  Times one whole anneal
+    of all runs as one HIP graph, the same eagerly, and the same runs one after
+    the other through the single-run calls; the results are bit-identical."""
+    import numpy as np
+    import torch
+    from paper_2401_07965_amd import pa, workloads
+    cfgs, groups = workloads.uneven_batch()
+    betas = workloads.linear_schedule(3.0, 151)
+    B = pa.PABatch(cfgs, max_points=len(betas))
+    threads = B.tune(theta)
+    attempts = theta * sum(c["L"] ** c["dim"] * c["R"] for c in cfgs) * (len(betas) - 1)
+    out = {}
+    for mode, graph in (("graph", True), ("eager", False)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.anneal(betas, theta, scheme, use_graph=graph)
+        torch.cuda.synchronize()
+        out[mode] = time.perf_counter() - t0
+    rec = B.records()
+    comb = B.combine(groups, max(groups) + 1, len(betas) - 1)
+    frozen = int(np.sum(rec[:, -1]["status"] & 16 != 0))
+    # the same runs one by one (plain per-run PA through the single-run calls)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    identical = True
+    for m, c in enumerate(cfgs):
+        g = pa.PARun(c["dim"], c["L"], c["R"], seed=c["seed"], run_id=c["run_id"],
+                     couplings=c["couplings"])
+        for b in betas[1:]:
+            g.reweight(b)
+            g.resample(scheme)
+            g.sweep(theta)
+            g.observables()
+        if m < verify_runs:
+            identical &= g.free_energy() == rec[m, -1]["lnZ"]
+        g.close()
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    B.close()
+    return {
+        "workload": "256 +-J runs (16 samples x 16), d in {2,3}, L in {8,12,16,24}, "
+                    "R log-uniform [1e3,1e5], beta 0->3 in 151 points, theta=10, systematic",
+        "runs": len(cfgs), "attempts_per_anneal": attempts,
+        "graph_s": out["graph"], "eager_s": out["eager"], "sequential_s": seq,
+        "attempts_per_ns_graph": attempts / out["graph"] / 1e9,
+        "attempts_per_ns_sequential": attempts / seq / 1e9,
+        "speedup_graph_vs_sequential": seq / out["graph"],
+        "identical_to_sequential": bool(identical), "frozen_runs": frozen,
+        "tuned_threads": threads,
+        "combined_lnZ_per_spin_sample0": comb[0]["lnZ"] / (cfgs[0]["L"] ** cfgs[0]["dim"]),
+        "mean_n_eff": float(np.mean([c["n_eff"] for c in comb])),
+    }
+
+
 def cpu_baseline(budget_s=15.0):
     """The oracle as it stands, on a sample of the same workload: a population
     of R_s = 2048 replicas (same lattice, theta, schedule), whole steps."""
@@ -147,6 +204,8 @@ def main():
     ap.add_argument("--steps", type=int, default=190)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip the batched and learned-schedule measurements")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
@@ -191,6 +250,8 @@ def main():
             "traffic": None,
         },
     }
+    if not a.no_rows:
+        out["batched"] = batched_bench()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
