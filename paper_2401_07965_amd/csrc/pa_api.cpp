@@ -187,7 +187,7 @@ pa_status hip_fail(Batch *b, hipError_t e, const char *where)
 
 // Whole layout of a batch: tables first, then each run's buffers.
 struct Tables {
-    std::vector<PaBlk> rep, fam, col, tile;
+    std::vector<PaBlk> rep, hrep, fam, col, tile;
     std::vector<std::vector<PaBlk>> gcol;
     std::vector<int> gd, gN, gthreads;
 };
@@ -202,6 +202,8 @@ uint64_t layout(const std::vector<Geometry> &geo, int max_points, char *base, Ba
         const Geometry &g = geo[m];
         for (int64_t c = 0; c < (g.cap + PA_CHUNK - 1) / PA_CHUNK; ++c)
             tb.rep.push_back({(uint32_t)m, (uint32_t)c});
+        for (int64_t c = 0; c < (g.cap + PA_HCHUNK - 1) / PA_HCHUNK; ++c)
+            tb.hrep.push_back({(uint32_t)m, (uint32_t)c});
         for (int64_t c = 0; c < (g.R + PA_CHUNK - 1) / PA_CHUNK; ++c)
             tb.fam.push_back({(uint32_t)m, (uint32_t)c});
         for (int64_t w = 0; w < g.W; ++w)
@@ -228,6 +230,7 @@ uint64_t layout(const std::vector<Geometry> &geo, int max_points, char *base, Ba
     };
     char *p_desc = take(sizeof(PaRunDesc) * (uint64_t)M);
     char *p_rep = take(sizeof(PaBlk) * tb.rep.size());
+    char *p_hrep = take(sizeof(PaBlk) * tb.hrep.size());
     char *p_fam = take(sizeof(PaBlk) * tb.fam.size());
     char *p_col = take(sizeof(PaBlk) * tb.col.size());
     char *p_tile = take(sizeof(PaBlk) * tb.tile.size());
@@ -267,6 +270,8 @@ uint64_t layout(const std::vector<Geometry> &geo, int max_points, char *base, Ba
         v.nruns = (uint32_t)M;
         v.rep = (const PaBlk *)p_rep;
         v.nrep = (uint32_t)tb.rep.size();
+        v.hrep = (const PaBlk *)p_hrep;
+        v.nhrep = (uint32_t)tb.hrep.size();
         v.fam = (const PaBlk *)p_fam;
         v.nfam = (uint32_t)tb.fam.size();
         v.col = (const PaBlk *)p_col;
@@ -390,6 +395,7 @@ pa_status make_batch(const pa_config *cfgs, int32_t nruns, int32_t max_points, v
     e = hipSuccess;
     up(b->ddesc, b->hdesc.data(), sizeof(PaRunDesc) * nruns);
     up(b->v.rep, t.rep.data(), sizeof(PaBlk) * t.rep.size());
+    up(b->v.hrep, t.hrep.data(), sizeof(PaBlk) * t.hrep.size());
     up(b->v.fam, t.fam.data(), sizeof(PaBlk) * t.fam.size());
     up(b->v.col, t.col.data(), sizeof(PaBlk) * t.col.size());
     up(b->v.tile, t.tile.data(), sizeof(PaBlk) * t.tile.size());

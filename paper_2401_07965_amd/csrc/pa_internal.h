@@ -64,7 +64,8 @@ struct PaScanTile {
 #define PA_SCAN_THREADS 256
 #define PA_SCAN_ITEMS 8
 #define PA_SCAN_TILE (PA_SCAN_THREADS * PA_SCAN_ITEMS)
-#define PA_CHUNK 2048 // replicas (or families) per workgroup of the per-replica kernels
+#define PA_CHUNK 256   // replicas (or families) per workgroup of the per-replica kernels
+#define PA_HCHUNK 4096 // replicas per workgroup of the energy histogram (LDS-private counts)
 
 // Device buffers of one run, carved from the caller's workspace.
 struct PaDev {
@@ -103,6 +104,8 @@ struct PaBatchView {
     uint32_t nruns;
     const PaBlk *rep;  // chunks of PA_CHUNK replica slots (capacity)
     uint32_t nrep;
+    const PaBlk *hrep; // chunks of PA_HCHUNK replica slots (histogram)
+    uint32_t nhrep;
     const PaBlk *fam;  // chunks of PA_CHUNK families
     uint32_t nfam;
     const PaBlk *col;  // all 64-replica columns (capacity)

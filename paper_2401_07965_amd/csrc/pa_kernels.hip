@@ -23,6 +23,14 @@ constexpr int kRuleCache = 4096; // levels whose weights stay in LDS between the
 
 __device__ __forceinline__ bool frozen(const PaRecord *rec) { return (rec->status & PA_ST_FROZEN) != 0u; }
 
+// Workgroup-uniform values read from device memory, kept in scalar registers.
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uni64(uint64_t x)
+{
+    return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | (uint64_t)uni((uint32_t)x);
+}
+
 // ------------------------------------------------------------------ helpers
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
 {
@@ -138,9 +146,9 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
     const int64_t Rlive = (int64_t)rec->Rcur;
     if ((int64_t)w * 64 >= Rlive || frozen(rec))
         return;
-    const int L = rd.L, N = rd.N;
-    const int cur = rec->cur;
-    const uint32_t step = rec->step, t0 = rec->sweeps;
+    const int L = uni(rd.L), N = uni(rd.N);
+    const int cur = uni(rec->cur);
+    const uint32_t step = uni(rec->step), t0 = uni(rec->sweeps);
     uint8_t *jl = reinterpret_cast<uint8_t *>(lat + N);
     const int tid = threadIdx.x, bs = blockDim.x;
     uint64_t *g = rd.dv.spins[cur] + (size_t)w * N;
@@ -151,7 +159,7 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
     __syncthreads();
 
     const uint64_t two32 = 1ull << 32;
-    const uint64_t T4 = rec->T[0], T8 = rec->T[1], T12 = rec->T[2];
+    const uint64_t T4 = uni64(rec->T[0]), T8 = uni64(rec->T[1]), T12 = uni64(rec->T[2]);
     const uint32_t t4 = (uint32_t)T4, t8 = (uint32_t)T8, t12 = (uint32_t)T12;
     // classes whose threshold is 2^32 accept outright, those at 0 never accept
     const uint64_t sure4 = T4 >= two32 ? ~0ull : 0ull, sure8 = T8 >= two32 ? ~0ull : 0ull,
@@ -160,7 +168,7 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
                    draw8 = (T8 > 0 && T8 < two32) ? ~0ull : 0ull,
                    draw12 = (T12 > 0 && T12 < two32) ? ~0ull : 0ull;
     const int half = L >> 1, nh = N >> 1, LL = L * L;
-    const uint32_t seed = rd.seed, run_id = rd.run_id;
+    const uint32_t seed = uni(rd.seed), run_id = uni(rd.run_id);
     uint32_t calls = 0; // Philox evaluations this lane's words needed
 
     for (int tt = 0; tt < theta; ++tt) {
@@ -312,7 +320,7 @@ __global__ __launch_bounds__(kThreads) void k_hist(const PaRunDesc *__restrict__
     const PaRunDesc &rd = runs[b.run];
     PaRecord *rec = rd.dv.rec;
     const int64_t R = (int64_t)rec->Rcur;
-    const int64_t beg = (int64_t)b.idx * PA_CHUNK;
+    const int64_t beg = (int64_t)b.idx * PA_HCHUNK;
     if (beg >= R || frozen(rec))
         return;
     const int H = rd.H, DN = rd.d * rd.N;
@@ -321,7 +329,7 @@ __global__ __launch_bounds__(kThreads) void k_hist(const PaRunDesc *__restrict__
         lh[i] = 0;
     __syncthreads();
     int64_t lo = INT_MAX, hi = INT_MIN;
-    const int64_t end = beg + PA_CHUNK < R ? beg + PA_CHUNK : R;
+    const int64_t end = beg + PA_HCHUNK < R ? beg + PA_HCHUNK : R;
     for (int64_t j = beg + threadIdx.x; j < end; j += blockDim.x) {
         const int32_t e = E[j];
         atomicAdd(&lh[(e + DN) >> 2], 1u);
@@ -1264,7 +1272,7 @@ hipError_t pa_b_sweep(const PaBatchView &v, int theta)
 static hipError_t hist_launch(const PaBatchView &v)
 {
     k_hist_prep<<<v.nruns, kThreads, 0, v.stream>>>(v.runs);
-    k_hist<<<v.nrep, kThreads, (size_t)v.maxH * 4, v.stream>>>(v.runs, v.rep);
+    k_hist<<<v.nhrep, kThreads, (size_t)v.maxH * 4, v.stream>>>(v.runs, v.hrep);
     return hipGetLastError();
 }
 
