@@ -273,6 +273,51 @@ pa_status pa_batch_combine(pa_batch *b, const int32_t *group_of_run, int32_t ngr
 void pa_batch_destroy(pa_batch *b);
 const char *pa_batch_last_error(const pa_batch *b);
 
+/* ---------------------------------------------------------------------------
+ * Learned temperature steps (not in the paper; the overlap rule above stays
+ * the judge and the fallback).  A network 8 -> 64 -> 64 -> 1 with tanh hidden
+ * layers maps population statistics to a proposed ln(dbeta):
+ *   inputs  beta, <E>/N, sd(E)/sqrt(N), skewness of E, the last three ln Q
+ *           (Eq. (1)) divided by N, family entropy / ln R;
+ *   params  one float vector of PA_MLP_PARAMS: W1[64][8], b1[64], W2[64][64],
+ *           b2[64], W3[64], b3, acting on standardised inputs and target.
+ * Training runs on the GPU in float32 (loss (1/2n) sum (y_hat - y)^2, Adam
+ * with beta1 = 0.9, beta2 = 0.999, eps = 1e-8); inference in bfloat16.
+ * ------------------------------------------------------------------------- */
+#define PA_MLP_PARAMS 4801
+
+typedef struct {
+    float x_mean[8], x_std[8]; /* input standardisation: (x - mean) / std */
+    float y_mean, y_std;       /* target ln(dbeta) standardisation */
+} pa_mlp_norm;
+
+typedef struct pa_mlp pa_mlp;
+
+pa_status pa_mlp_required_bytes(int32_t max_samples, uint64_t *bytes);
+/* params: PA_MLP_PARAMS floats (host, copied). */
+pa_status pa_mlp_create(int32_t max_samples, const float *params, const pa_mlp_norm *norm,
+                        void *workspace, uint64_t workspace_bytes, void *stream, pa_mlp **out);
+/* Training set: X [n][8] raw inputs, y [n] raw targets ln(dbeta) (host, copied). */
+pa_status pa_mlp_set_data(pa_mlp *m, const float *X, const float *y, int32_t n);
+/* Gradient of the loss at the current parameters (float32, PA_MLP_PARAMS). */
+pa_status pa_mlp_gradient(pa_mlp *m, float *grad_out, double *loss_out);
+/* `epochs` full-batch Adam steps with learning rate lr; loss after them. */
+pa_status pa_mlp_train(pa_mlp *m, int32_t epochs, float lr, double *loss_out);
+pa_status pa_mlp_params(pa_mlp *m, float *out);
+/* bfloat16 inference: dbeta_out[i] = exp(ln dbeta predicted for X[i]).  Uses
+ * the training-data slot; set the data again before training further. */
+pa_status pa_mlp_predict(pa_mlp *m, const float *X, int32_t n, float *dbeta_out);
+/* The model inputs of the current population (uses the family entropy of
+ * the latest pa_observables). */
+pa_status pa_features(pa_ctx *ctx, float *out8);
+/* Learned step: the model's proposal, clamped to (0, dbeta_max], is taken if
+ * alpha(proposal) >= alpha_star (exact check as in pa_step_rule); otherwise
+ * pa_step_rule's bisection decides and *fallback_out = 1. */
+pa_status pa_step_learned(pa_ctx *ctx, pa_mlp *m, double alpha_star, double dbeta_max,
+                          int32_t iterations, double *dbeta_out, int32_t *fallback_out);
+void pa_mlp_destroy(pa_mlp *m);
+const char *pa_mlp_last_error(const pa_mlp *m);
+
 #ifdef __cplusplus
 }
 #endif

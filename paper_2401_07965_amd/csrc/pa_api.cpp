@@ -169,6 +169,14 @@ struct pa_batch {
     Batch b;
 };
 
+struct pa_mlp {
+    PaMlpDev d{};
+    int max_samples = 0;
+    int n = 0;     // samples set
+    int t = 0;     // Adam steps taken
+    std::string err;
+};
+
 namespace {
 
 pa_status fail(Batch *b, pa_status s, const std::string &msg)
@@ -1003,5 +1011,235 @@ void pa_batch_destroy(pa_batch *p)
 }
 
 const char *pa_batch_last_error(const pa_batch *p) { return p ? p->b.err.c_str() : g_init_err.c_str(); }
+
+// ====================================================================== learned step
+static uint64_t mlp_layout(int max_samples, char *base, PaMlpDev *d)
+{
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += round256(bytes);
+        return p;
+    };
+    const uint64_t n = (uint64_t)max_samples, h = PA_MLP_HIDDEN;
+    PaMlpDev m{};
+    m.P = (float *)take(4ull * PA_MLP_PARAMS);
+    m.M = (float *)take(4ull * PA_MLP_PARAMS);
+    m.V = (float *)take(4ull * PA_MLP_PARAMS);
+    m.G = (float *)take(4ull * PA_MLP_PARAMS);
+    m.norm = (PaMlpNorm *)take(sizeof(PaMlpNorm));
+    m.X = (float *)take(4 * n * 8);
+    m.Y = (float *)take(4 * n);
+    m.Xn = (float *)take(4 * n * 8);
+    m.H1 = (float *)take(4 * n * h);
+    m.H2 = (float *)take(4 * n * h);
+    m.D1 = (float *)take(4 * n * h);
+    m.D2 = (float *)take(4 * n * h);
+    m.dY = (float *)take(4 * n);
+    m.r2 = (float *)take(4 * n);
+    m.loss = (double *)take(8);
+    m.pred = (float *)take(4 * n);
+    if (d)
+        *d = m;
+    return off;
+}
+
+static pa_status mfail(pa_mlp *m, pa_status s, const std::string &msg)
+{
+    if (m)
+        m->err = msg;
+    else
+        g_init_err = msg;
+    return s;
+}
+
+pa_status pa_mlp_required_bytes(int32_t max_samples, uint64_t *bytes)
+{
+    if (max_samples < 1 || max_samples > (1 << 22) || !bytes)
+        return mfail(nullptr, PA_E_INVAL, "need 1 <= max_samples <= 2^22 and bytes");
+    *bytes = mlp_layout(max_samples, nullptr, nullptr);
+    return PA_OK;
+}
+
+pa_status pa_mlp_create(int32_t max_samples, const float *params, const pa_mlp_norm *norm, void *workspace,
+                        uint64_t bytes, void *stream, pa_mlp **out)
+{
+    if (!out)
+        return mfail(nullptr, PA_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (max_samples < 1 || max_samples > (1 << 22) || !params || !norm)
+        return mfail(nullptr, PA_E_INVAL, "need 1 <= max_samples <= 2^22, params and norm");
+    for (int k = 0; k < 8; ++k)
+        if (!(norm->x_std[k] > 0.0f) || !std::isfinite(norm->x_mean[k]))
+            return mfail(nullptr, PA_E_INVAL, "feature scales must be positive and finite");
+    if (!(norm->y_std > 0.0f) || !std::isfinite(norm->y_mean))
+        return mfail(nullptr, PA_E_INVAL, "target scale must be positive and finite");
+    if (!workspace || bytes < mlp_layout(max_samples, nullptr, nullptr) || ((uintptr_t)workspace & 255u))
+        return mfail(nullptr, PA_E_INVAL, "workspace missing, too small or not 256-byte aligned");
+    pa_mlp *m = new (std::nothrow) pa_mlp;
+    if (!m)
+        return mfail(nullptr, PA_E_NOMEM, "out of host memory");
+    mlp_layout(max_samples, (char *)workspace, &m->d);
+    m->d.stream = (hipStream_t)stream;
+    m->max_samples = max_samples;
+    static_assert(sizeof(pa_mlp_norm) == sizeof(PaMlpNorm), "norm layout");
+    std::vector<float> zeros(PA_MLP_PARAMS, 0.0f);
+    hipError_t e = hipMemcpyAsync(m->d.P, params, 4ull * PA_MLP_PARAMS, hipMemcpyHostToDevice, m->d.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(m->d.M, zeros.data(), 4ull * PA_MLP_PARAMS, hipMemcpyHostToDevice, m->d.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(m->d.V, zeros.data(), 4ull * PA_MLP_PARAMS, hipMemcpyHostToDevice, m->d.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(m->d.norm, norm, sizeof(PaMlpNorm), hipMemcpyHostToDevice, m->d.stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(m->d.stream);
+    if (e != hipSuccess) {
+        delete m;
+        return mfail(nullptr, PA_E_DEVICE, std::string("pa_mlp_create: ") + hipGetErrorString(e));
+    }
+    *out = m;
+    return PA_OK;
+}
+
+pa_status pa_mlp_set_data(pa_mlp *m, const float *X, const float *y, int32_t n)
+{
+    if (!m)
+        return mfail(nullptr, PA_E_INVAL, "model is NULL");
+    if (!X || !y || n < 1 || n > m->max_samples)
+        return mfail(m, PA_E_INVAL, "need X, y and 1 <= n <= max_samples");
+    hipError_t e = hipMemcpyAsync(m->d.X, X, 4ull * 8 * n, hipMemcpyHostToDevice, m->d.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(m->d.Y, y, 4ull * n, hipMemcpyHostToDevice, m->d.stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(m->d.stream);
+    if (e != hipSuccess)
+        return mfail(m, PA_E_DEVICE, std::string("pa_mlp_set_data: ") + hipGetErrorString(e));
+    m->n = n;
+    return PA_OK;
+}
+
+pa_status pa_mlp_gradient(pa_mlp *m, float *grad_out, double *loss_out)
+{
+    if (!m)
+        return mfail(nullptr, PA_E_INVAL, "model is NULL");
+    if (m->n == 0)
+        return mfail(m, PA_E_STATE, "no training data set");
+    hipError_t e = pa_mlp_launch_grad(m->d, m->n, 0, 1, 0.0f);
+    if (e == hipSuccess && grad_out)
+        e = hipMemcpyAsync(grad_out, m->d.G, 4ull * PA_MLP_PARAMS, hipMemcpyDeviceToHost, m->d.stream);
+    if (e == hipSuccess && loss_out)
+        e = hipMemcpyAsync(loss_out, m->d.loss, 8, hipMemcpyDeviceToHost, m->d.stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(m->d.stream);
+    if (e != hipSuccess)
+        return mfail(m, PA_E_DEVICE, std::string("pa_mlp_gradient: ") + hipGetErrorString(e));
+    return PA_OK;
+}
+
+pa_status pa_mlp_train(pa_mlp *m, int32_t epochs, float lr, double *loss_out)
+{
+    if (!m)
+        return mfail(nullptr, PA_E_INVAL, "model is NULL");
+    if (m->n == 0)
+        return mfail(m, PA_E_STATE, "no training data set");
+    if (epochs < 1 || !(lr > 0.0f))
+        return mfail(m, PA_E_INVAL, "need epochs >= 1 and lr > 0");
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < epochs && e == hipSuccess; ++k)
+        e = pa_mlp_launch_grad(m->d, m->n, 1, ++m->t, lr);
+    // the loss after the last update
+    if (e == hipSuccess && loss_out)
+        e = pa_mlp_launch_grad(m->d, m->n, 0, 1, 0.0f);
+    if (e == hipSuccess && loss_out)
+        e = hipMemcpyAsync(loss_out, m->d.loss, 8, hipMemcpyDeviceToHost, m->d.stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(m->d.stream);
+    if (e != hipSuccess)
+        return mfail(m, PA_E_DEVICE, std::string("pa_mlp_train: ") + hipGetErrorString(e));
+    return PA_OK;
+}
+
+pa_status pa_mlp_params(pa_mlp *m, float *out)
+{
+    if (!m || !out)
+        return mfail(m, PA_E_INVAL, "NULL argument");
+    hipError_t e = hipMemcpyAsync(out, m->d.P, 4ull * PA_MLP_PARAMS, hipMemcpyDeviceToHost, m->d.stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(m->d.stream);
+    if (e != hipSuccess)
+        return mfail(m, PA_E_DEVICE, std::string("pa_mlp_params: ") + hipGetErrorString(e));
+    return PA_OK;
+}
+
+pa_status pa_mlp_predict(pa_mlp *m, const float *X, int32_t n, float *dbeta_out)
+{
+    if (!m)
+        return mfail(nullptr, PA_E_INVAL, "model is NULL");
+    if (!X || !dbeta_out || n < 1 || n > m->max_samples)
+        return mfail(m, PA_E_INVAL, "need X, out and 1 <= n <= max_samples");
+    // the data slot holds the inputs; a later pa_mlp_set_data is needed to train again
+    hipError_t e = hipMemcpyAsync(m->d.X, X, 4ull * 8 * n, hipMemcpyHostToDevice, m->d.stream);
+    if (e == hipSuccess)
+        e = pa_mlp_launch_predict(m->d, m->d.X, n, m->d.pred);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dbeta_out, m->d.pred, 4ull * n, hipMemcpyDeviceToHost, m->d.stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(m->d.stream);
+    if (e != hipSuccess)
+        return mfail(m, PA_E_DEVICE, std::string("pa_mlp_predict: ") + hipGetErrorString(e));
+    m->n = 0;
+    return PA_OK;
+}
+
+pa_status pa_features(pa_ctx *c, float *out8)
+{
+    if (!c)
+        return fail(nullptr, PA_E_INVAL, "ctx is NULL");
+    Batch *b = &c->b;
+    if (!out8)
+        return fail(b, PA_E_INVAL, "out is NULL");
+    hipError_t e = pa_b_features(b->v);
+    if (e != hipSuccess)
+        return hip_fail(b, e, "pa_features");
+    pa_status s = fetch_records(b, "pa_features");
+    if (s != PA_OK)
+        return s;
+    std::memcpy(out8, b->hrec[0].feat, sizeof(float) * 8);
+    return PA_OK;
+}
+
+pa_status pa_step_learned(pa_ctx *c, pa_mlp *m, double alpha_star, double dbeta_max, int32_t iterations,
+                          double *dbeta_out, int32_t *fallback_out)
+{
+    if (!c)
+        return fail(nullptr, PA_E_INVAL, "ctx is NULL");
+    Batch *b = &c->b;
+    if (!m || !dbeta_out || !(alpha_star > 0.0 && alpha_star < 1.0) || !std::isfinite(dbeta_max) ||
+        dbeta_max <= 0.0 || iterations < 1 || iterations > 200)
+        return fail(b, PA_E_INVAL, "need a model, 0 < alpha_star < 1, dbeta_max > 0, 1 <= iterations <= 200");
+    if (m->d.stream != b->v.stream) {
+        hipError_t e = hipStreamSynchronize(m->d.stream);
+        if (e != hipSuccess)
+            return hip_fail(b, e, "pa_step_learned");
+    }
+    hipError_t e = pa_b_features(b->v);
+    if (e == hipSuccess)
+        e = pa_mlp_launch_propose(b->v, m->d, dbeta_max);
+    if (e == hipSuccess)
+        e = pa_b_check_candidate(b->v, alpha_star, dbeta_max, iterations);
+    if (e != hipSuccess)
+        return hip_fail(b, e, "pa_step_learned");
+    pa_status s = fetch_records(b, "pa_step_learned");
+    if (s != PA_OK)
+        return s;
+    *dbeta_out = b->hrec[0].rule_dbeta;
+    if (fallback_out)
+        *fallback_out = (int32_t)b->hrec[0].fallback;
+    return PA_OK;
+}
+
+void pa_mlp_destroy(pa_mlp *m) { delete m; }
+
+const char *pa_mlp_last_error(const pa_mlp *m) { return m ? m->err.c_str() : g_init_err.c_str(); }
 
 } // extern "C"

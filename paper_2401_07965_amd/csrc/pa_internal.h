@@ -45,6 +45,10 @@ struct PaRecord {
     double sumClnC;
     double e, e2, abs_m, m2, rho_t, S_f;
     double rule_dbeta, rule_alpha; // adaptive step: chosen dbeta and its overlap
+    double lnq_hist[3];            // ln Q of the last three applied steps, oldest first
+    float feat[8];                 // inputs of the learned step model
+    double cand_dbeta;             // the model's proposal
+    uint32_t fallback, pad1;       // 1: the proposal failed the overlap check
     unsigned long long philox_calls; // Philox4x32-10 evaluations of all sweeps so far
     unsigned long long site_updates; // word-site updates (64 attempts each) so far
 };
@@ -98,6 +102,27 @@ struct PaBlk {
 
 #define PA_MAX_GROUPS 16
 
+// Learned temperature-step model: 8 -> 64 -> 64 -> 1.
+#define PA_MLP_HIDDEN 64
+#ifndef PA_MLP_PARAMS
+#define PA_MLP_PARAMS 4801 // 64*8 + 64 + 64*64 + 64 + 64 + 1
+#endif
+
+struct PaMlpNorm {
+    float x_mean[8], x_std[8];
+    float y_mean, y_std;
+};
+
+struct PaMlpDev {
+    float *P, *M, *V, *G;   // parameters, Adam moments, last gradient
+    PaMlpNorm *norm;
+    float *X, *Y;           // training data [n][8], [n]
+    float *Xn, *H1, *H2, *D1, *D2, *dY, *r2; // per-sample work
+    double *loss;
+    float *pred;            // predictions [n]
+    hipStream_t stream;
+};
+
 // What the launchers need to address a batch (device pointers + counts).
 struct PaBatchView {
     const PaRunDesc *runs; // [nruns]
@@ -137,5 +162,10 @@ hipError_t pa_launch_combine(const PaBatchView &v, int point, const int32_t *gro
                              const int32_t *Ns, double *out);
 hipError_t pa_launch_overlap(const PaRunDesc *a, const PaRunDesc *b, int N, uint32_t ncols_a,
                              unsigned long long *hist, hipStream_t st);
+hipError_t pa_b_features(const PaBatchView &v);
+hipError_t pa_b_check_candidate(const PaBatchView &v, double alpha_star, double dbeta_max, int iterations);
+hipError_t pa_mlp_launch_grad(const PaMlpDev &m, int n, int adam, int t, float lr);
+hipError_t pa_mlp_launch_predict(const PaMlpDev &m, const float *X, int n, float *out);
+hipError_t pa_mlp_launch_propose(const PaBatchView &v, const PaMlpDev &m, double dbeta_max);
 hipError_t pa_query_lds(int *max_lds);
 size_t pa_sweep_lds_bytes(int N);

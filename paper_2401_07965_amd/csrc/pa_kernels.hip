@@ -69,6 +69,8 @@ __global__ void k_init_rec(const PaRunDesc *__restrict__ runs)
         rec->T[k] = rec->Tn[k] = 1ull << 32;
     rec->philox_calls = 0;
     rec->site_updates = 0;
+    rec->lnq_hist[0] = rec->lnq_hist[1] = rec->lnq_hist[2] = 0.0;
+    rec->S_f = log((double)rd.R0);
 }
 
 // Replica 64w+b, site s: bit b of x0 | x1<<32 of Philox(s, w, 0, INIT<<28).
@@ -482,6 +484,101 @@ __global__ __launch_bounds__(kRuleThreads) void k_rule(const PaRunDesc *__restri
     if (threadIdx.x == 0) {
         rec->rule_dbeta = best;
         rec->rule_alpha = u128_to_double(obest.num) / u128_to_double(obest.den);
+    }
+}
+
+// Inputs of the learned step model from the energy histogram (moments in
+// float64, fixed chunks and tree), the record's ln Q history and the family
+// entropy of the latest observables: beta, <E>/N, sd(E)/sqrt(N), skewness,
+// ln Q_{i-2..i}/N, S_f / ln R.
+__global__ __launch_bounds__(kRuleThreads) void k_features(const PaRunDesc *__restrict__ runs)
+{
+    __shared__ double sd[16];
+    const PaRunDesc &rd = runs[blockIdx.x];
+    PaRecord *rec = rd.dv.rec;
+    if (frozen(rec))
+        return;
+    const int DN = rd.d * rd.N;
+    const int32_t emin = rec->emin;
+    const int hmin = (emin + DN) >> 2, hmax = (rec->emax + DN) >> 2;
+    const int nlev = hmax - hmin + 1;
+    const double R = (double)rec->Rcur;
+    const int chunk = (nlev + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int lo = (int)threadIdx.x * chunk;
+    const int hi = lo + chunk < nlev ? lo + chunk : nlev;
+    double s1 = 0.0;
+    for (int k = lo; k < hi; ++k)
+        s1 = s1 + (double)rd.dv.hist[hmin + k] * (double)(emin + 4 * k);
+    const double mean = pa_block_sum_f64(s1, sd) / R;
+    double s2 = 0.0, s3 = 0.0;
+    for (int k = lo; k < hi; ++k) {
+        const double dx = (double)(emin + 4 * k) - mean, n = (double)rd.dv.hist[hmin + k];
+        s2 = s2 + n * dx * dx;
+        s3 = s3 + n * dx * dx * dx;
+    }
+    const double var = pa_block_sum_f64(s2, sd) / R;
+    const double m3 = pa_block_sum_f64(s3, sd) / R;
+    if (threadIdx.x == 0) {
+        const double N = (double)rd.N;
+        rec->feat[0] = (float)rec->beta;
+        rec->feat[1] = (float)(mean / N);
+        rec->feat[2] = (float)(sqrt(var) / sqrt(N));
+        rec->feat[3] = (float)(var > 0.0 ? m3 / (var * sqrt(var)) : 0.0);
+        rec->feat[4] = (float)(rec->lnq_hist[0] / N);
+        rec->feat[5] = (float)(rec->lnq_hist[1] / N);
+        rec->feat[6] = (float)(rec->lnq_hist[2] / N);
+        rec->feat[7] = (float)(R > 1.0 ? rec->S_f / log(R) : 0.0);
+    }
+}
+
+// The learned proposal is kept if it passes the exact overlap check;
+// otherwise the bisection of the rule decides (fallback).
+__global__ __launch_bounds__(kRuleThreads) void k_check_candidate(const PaRunDesc *__restrict__ runs,
+                                                                  double alpha_star, double dbeta_max, int iterations)
+{
+    __shared__ uint64_t su[16];
+    __shared__ uint64_t wcache[kRuleCache];
+    const PaRunDesc &rd = runs[blockIdx.x];
+    PaRecord *rec = rd.dv.rec;
+    if (frozen(rec))
+        return;
+    const int DN = rd.d * rd.N;
+    const int hmin = (rec->emin + DN) >> 2, hmax = (rec->emax + DN) >> 2;
+    const int nlev = hmax - hmin + 1;
+    const uint64_t R = rec->Rcur;
+    const uint64_t A = (uint64_t)rint(ldexp(alpha_star, 32));
+    const double cand = rec->cand_dbeta;
+    const Overlap oc = rule_overlap(rd.dv.hist, hmin, nlev, R, cand, wcache, su);
+    if (cand > 0.0 && qualifies(oc, A)) {
+        if (threadIdx.x == 0) {
+            rec->rule_dbeta = cand;
+            rec->rule_alpha = u128_to_double(oc.num) / u128_to_double(oc.den);
+            rec->fallback = 0;
+        }
+        return;
+    }
+    const Overlap top = rule_overlap(rd.dv.hist, hmin, nlev, R, dbeta_max, wcache, su);
+    double best = dbeta_max;
+    Overlap obest = top;
+    if (!qualifies(top, A)) {
+        double lo = 0.0, hi = dbeta_max;
+        obest.num = obest.den = 1;
+        for (int it = 0; it < iterations; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            const Overlap om = rule_overlap(rd.dv.hist, hmin, nlev, R, mid, wcache, su);
+            if (qualifies(om, A)) {
+                lo = mid;
+                obest = om;
+            } else {
+                hi = mid;
+            }
+        }
+        best = lo;
+    }
+    if (threadIdx.x == 0) {
+        rec->rule_dbeta = best;
+        rec->rule_alpha = u128_to_double(obest.num) / u128_to_double(obest.den);
+        rec->fallback = 1;
     }
 }
 
@@ -953,6 +1050,9 @@ __global__ __launch_bounds__(kThreads) void k_commit(const PaRunDesc *__restrict
     if (threadIdx.x == 0) {
         rec->sv = t / (double)Rprev;
         rec->lnZ = rec->lnZ + rec->lnQ;
+        rec->lnq_hist[0] = rec->lnq_hist[1];
+        rec->lnq_hist[1] = rec->lnq_hist[2];
+        rec->lnq_hist[2] = rec->lnQ;
         rec->T[0] = rec->Tn[0];
         rec->T[1] = rec->Tn[1];
         rec->T[2] = rec->Tn[2];
@@ -1291,6 +1391,22 @@ hipError_t pa_b_rule(const PaBatchView &v, double alpha_star, double dbeta_max, 
     if (e != hipSuccess)
         return e;
     k_rule<<<v.nruns, kRuleThreads, 0, v.stream>>>(v.runs, alpha_star, dbeta_max, iterations, bisect);
+    return hipGetLastError();
+}
+
+hipError_t pa_b_features(const PaBatchView &v)
+{
+    hipError_t e = hist_launch(v);
+    if (e != hipSuccess)
+        return e;
+    k_features<<<v.nruns, kRuleThreads, 0, v.stream>>>(v.runs);
+    return hipGetLastError();
+}
+
+// after pa_b_features and the model's proposal (the histogram is current)
+hipError_t pa_b_check_candidate(const PaBatchView &v, double alpha_star, double dbeta_max, int iterations)
+{
+    k_check_candidate<<<v.nruns, kRuleThreads, 0, v.stream>>>(v.runs, alpha_star, dbeta_max, iterations);
     return hipGetLastError();
 }
 

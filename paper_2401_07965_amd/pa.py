@@ -60,6 +60,13 @@ class pa_combined(ctypes.Structure):
                [("runs", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
+class pa_mlp_norm(ctypes.Structure):
+    _fields_ = [("x_mean", ctypes.c_float * 8), ("x_std", ctypes.c_float * 8),
+                ("y_mean", ctypes.c_float), ("y_std", ctypes.c_float)]
+
+
+MLP_PARAMS = 4801
+
 STEP_RECORD_DTYPE = np.dtype([(n, np.float64) for n in ("beta", "lnQ", "lnZ", "sv", "e", "e2",
                                                         "abs_m", "m2", "rho_t", "S_f")] +
                              [(n, np.int64) for n in ("R", "sum_E", "sum_E2", "sum_absM", "sum_M2",
@@ -133,6 +140,24 @@ def lib():
                      "pa_batch_groups", "pa_batch_anneal", "pa_batch_records",
                      "pa_batch_export_run", "pa_batch_combine"):
             getattr(L, name).restype = ctypes.c_int
+        L.pa_mlp_required_bytes.argtypes = [ctypes.c_int32, P(ctypes.c_uint64)]
+        L.pa_mlp_create.argtypes = [ctypes.c_int32, v, P(pa_mlp_norm), v, ctypes.c_uint64, v, P(v)]
+        L.pa_mlp_set_data.argtypes = [v, v, v, ctypes.c_int32]
+        L.pa_mlp_gradient.argtypes = [v, v, P(ctypes.c_double)]
+        L.pa_mlp_train.argtypes = [v, ctypes.c_int32, ctypes.c_float, P(ctypes.c_double)]
+        L.pa_mlp_params.argtypes = [v, v]
+        L.pa_mlp_predict.argtypes = [v, v, ctypes.c_int32, v]
+        L.pa_features.argtypes = [v, v]
+        L.pa_step_learned.argtypes = [v, v, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                      P(ctypes.c_double), P(ctypes.c_int32)]
+        L.pa_mlp_destroy.argtypes = [v]
+        L.pa_mlp_destroy.restype = None
+        L.pa_mlp_last_error.argtypes = [v]
+        L.pa_mlp_last_error.restype = ctypes.c_char_p
+        for name in ("pa_mlp_required_bytes", "pa_mlp_create", "pa_mlp_set_data", "pa_mlp_gradient",
+                     "pa_mlp_train", "pa_mlp_params", "pa_mlp_predict", "pa_features",
+                     "pa_step_learned"):
+            getattr(L, name).restype = ctypes.c_int
         L.pa_destroy.argtypes = [v]
         L.pa_destroy.restype = None
         L.pa_last_error.argtypes = [v]
@@ -148,6 +173,12 @@ def lib():
 def _check(status, ctx):
     if status != PA_OK:
         msg = lib().pa_last_error(ctx)
+        raise _ERRORS.get(status, PAError)(status, msg.decode() if msg else "")
+
+
+def _check_m(status, m):
+    if status != PA_OK:
+        msg = lib().pa_mlp_last_error(m)
         raise _ERRORS.get(status, PAError)(status, msg.decode() if msg else "")
 
 
@@ -334,6 +365,18 @@ class PARun:
     def counters(self):
         return pa_get_counters(self.ctx)
 
+    def features(self):
+        out = np.zeros(8, np.float32)
+        _check(lib().pa_features(self.ctx, out.ctypes.data), self.ctx)
+        return out
+
+    def step_learned(self, mlp, alpha_star, dbeta_max, iterations=60):
+        d = ctypes.c_double()
+        fb = ctypes.c_int32()
+        _check(lib().pa_step_learned(self.ctx, mlp.h, float(alpha_star), float(dbeta_max),
+                                     int(iterations), ctypes.byref(d), ctypes.byref(fb)), self.ctx)
+        return d.value, bool(fb.value)
+
     def close(self):
         if self.ctx is not None:
             pa_destroy(self.ctx)
@@ -423,6 +466,69 @@ class PABatch:
     def close(self):
         if self.h is not None:
             lib().pa_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PAMlp:
+    """The learned temperature-step model on the GPU (train, predict)."""
+
+    def __init__(self, params, x_mean, x_std, y_mean, y_std, max_samples, device=None,
+                 stream=None):
+        import torch
+        self.params0 = np.ascontiguousarray(params, np.float32)
+        assert self.params0.shape == (MLP_PARAMS,)
+        nm = pa_mlp_norm()
+        for k in range(8):
+            nm.x_mean[k], nm.x_std[k] = float(x_mean[k]), float(x_std[k])
+        nm.y_mean, nm.y_std = float(y_mean), float(y_std)
+        self.norm = nm
+        nb = ctypes.c_uint64()
+        _check_m(lib().pa_mlp_required_bytes(int(max_samples), ctypes.byref(nb)), None)
+        self.device = torch.device("cuda", 0) if device is None else torch.device(device)
+        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        h = ctypes.c_void_p()
+        _check_m(lib().pa_mlp_create(int(max_samples), self.params0.ctypes.data, ctypes.byref(nm),
+                                     self.workspace.data_ptr(), nb.value, self.stream.cuda_stream,
+                                     ctypes.byref(h)), None)
+        self.h = h
+
+    def set_data(self, X, y):
+        X = np.ascontiguousarray(X, np.float32)
+        y = np.ascontiguousarray(y, np.float32)
+        _check_m(lib().pa_mlp_set_data(self.h, X.ctypes.data, y.ctypes.data, len(y)), self.h)
+
+    def gradient(self):
+        g = np.zeros(MLP_PARAMS, np.float32)
+        loss = ctypes.c_double()
+        _check_m(lib().pa_mlp_gradient(self.h, g.ctypes.data, ctypes.byref(loss)), self.h)
+        return g, loss.value
+
+    def train(self, epochs, lr):
+        loss = ctypes.c_double()
+        _check_m(lib().pa_mlp_train(self.h, int(epochs), float(lr), ctypes.byref(loss)), self.h)
+        return loss.value
+
+    def params(self):
+        p = np.zeros(MLP_PARAMS, np.float32)
+        _check_m(lib().pa_mlp_params(self.h, p.ctypes.data), self.h)
+        return p
+
+    def predict(self, X):
+        X = np.ascontiguousarray(X, np.float32)
+        out = np.zeros(len(X), np.float32)
+        _check_m(lib().pa_mlp_predict(self.h, X.ctypes.data, len(X), out.ctypes.data), self.h)
+        return out
+
+    def close(self):
+        if self.h is not None:
+            lib().pa_mlp_destroy(self.h)
             self.h = None
 
     def __del__(self):
