@@ -171,6 +171,56 @@ def batched_bench(theta=10, scheme=3, verify_runs=8):
     }
 
 
+def learned_bench(theta=10, scheme=3, astar=0.7, dmax=0.2, beta_f=3.0):
+    """Learned-schedule workload: 3D +-J glass L = 16.  The model is trained on
+    the GPU from rule-driven anneals of 8 other disorder samples at R = 10^4;
+    then the evaluation sample is annealed at R = 10^6 (and 10^4) with the
+    rule alone and with the learned step (exact judge + rule fallback)."""
+    import numpy as np
+    import torch
+    from oracle import mlp as Mo  # parameter initialisation only (seeded uniform)
+    from paper_2401_07965_amd import pa, workloads
+    from paper_2401_07965_amd.schedule import anneal_adaptive, standardisation
+    d, L = 3, 16
+    Xs, ys = [], []
+    t0 = time.perf_counter()
+    for s in range(2, 10):
+        run = pa.PARun(d, L, 10000, seed=1, run_id=0, couplings=workloads.pm_j_couplings(d, L, s))
+        out = anneal_adaptive(run, beta_f, astar, dmax, theta, scheme, record=True)
+        Xs.append(out["X"])
+        ys.append(out["y"])
+        run.close()
+    X, y = np.concatenate(Xs), np.concatenate(ys)
+    t_data = time.perf_counter() - t0
+    xm, xs, ym, ysd = standardisation(X, y)
+    mlp = pa.PAMlp(Mo.init_params(0), xm, xs, ym, ysd, max_samples=len(y))
+    mlp.set_data(X, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = mlp.train(2000, 3e-3)
+    t_train = time.perf_counter() - t0
+    J = workloads.pm_j_couplings(d, L, 1)
+    res = {"training_steps": int(len(y)), "train_loss": loss, "data_s": t_data, "train_s": t_train}
+    for R in (1000000, 10000):
+        for name, model in (("rule", None), ("learned", mlp)):
+            run = pa.PARun(d, L, R, seed=1, run_id=0, couplings=J)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = anneal_adaptive(run, beta_f, astar, dmax, theta, scheme, mlp=model)
+            torch.cuda.synchronize()
+            res[f"R{R}_{name}"] = dict(wall_s=time.perf_counter() - t0, steps=out["steps"],
+                                       schedule_s=out["schedule_s"], fallbacks=out["fallbacks"],
+                                       lnZ_per_spin=out["lnZ"] / L ** d)
+            run.close()
+        r, l = res[f"R{R}_rule"], res[f"R{R}_learned"]
+        res[f"R{R}_wall_speedup"] = r["wall_s"] / l["wall_s"]
+        res[f"R{R}_schedule_speedup"] = r["schedule_s"] / l["schedule_s"]
+    mlp.close()
+    res["workload"] = ("3D +-J L=16, beta 0->3, alpha*=0.7, dbeta_max=0.2, theta=10, systematic; "
+                       "trained on 8 other samples at R=1e4")
+    return res
+
+
 def cpu_baseline(budget_s=15.0):
     """The oracle as it stands, on a sample of the same workload: a population
     of R_s = 2048 replicas (same lattice, theta, schedule), whole steps."""
@@ -252,6 +302,7 @@ def main():
     }
     if not a.no_rows:
         out["batched"] = batched_bench()
+        out["learned"] = learned_bench()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
