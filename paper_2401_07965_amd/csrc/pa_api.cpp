@@ -379,7 +379,8 @@ pa_status make_batch(const pa_config *cfgs, int32_t nruns, int32_t max_points, v
     if (g_max_lds == 0 && (e = pa_query_lds(&g_max_lds)) != hipSuccess)
         return hip_fail(nullptr, e, "device query");
     for (const Geometry &g : geo)
-        if (pa_sweep_lds_bytes(g.N) > (size_t)g_max_lds || (size_t)g.H * 4 > (size_t)g_max_lds)
+        if (pa_sweep_lds_bytes(g.N, default_sweep_threads(g.N, g.d)) > (size_t)g_max_lds ||
+            (size_t)g.H * 4 > (size_t)g_max_lds)
             return fail(nullptr, PA_E_INVAL, "lattice too large for the workgroup LDS of this device");
     b->jmask.resize(nruns);
     for (int m = 0; m < nruns; ++m)
@@ -825,7 +826,8 @@ pa_status pa_batch_tune(pa_batch *p, int32_t theta, int32_t *threads_out)
         float best = 1e30f;
         int best_t = b->v.gthreads[g];
         for (int t = 64; t <= 512 && e == hipSuccess; t += 64) {
-            if (!sweep_threads_ok(b->v.gN[g], b->v.gd[g], t))
+            if (!sweep_threads_ok(b->v.gN[g], b->v.gd[g], t) ||
+                pa_sweep_lds_bytes(b->v.gN[g], t) > (size_t)g_max_lds)
                 continue;
             e = pa_b_sweep_group(b->v, g, theta, t); // warm-up
             if (e == hipSuccess)

@@ -131,6 +131,93 @@ __device__ __forceinline__ void wave_vsum16(uint64_t c[16])
 
 __device__ __forceinline__ uint64_t jbit(uint32_t jb, int k) { return 0ull - (uint64_t)((jb >> k) & 1u); }
 
+// Bit-plane decision of u < T for the undecided replicas of one word: plane
+// pair q of Philox(s, w, i, METRO<<28 | t<<8 | q) gives bits 31-2q and 30-2q of
+// every replica's uniform; a replica is decided at the first bit where u and
+// its class threshold differ (accepted if u has 0 there).
+struct PlaneCtx {
+    uint32_t seed, run_id, w, step, t;
+    uint32_t t4, t8, t12;
+};
+
+__device__ __forceinline__ void plane_pair(const PlaneCtx &pc, uint32_t s, uint32_t q, uint64_t m4, uint64_t m8,
+                                           uint64_t m12, uint64_t &und, uint64_t &acc)
+{
+    const pa_philox_out o = pa_philox(pc.seed, pc.run_id, s, pc.w, pc.step, (PA_PURPOSE_METRO << 28) | (pc.t << 8) | q);
+    const uint64_t P0 = (uint64_t)o.x0 | ((uint64_t)o.x1 << 32);
+    const uint64_t P1 = (uint64_t)o.x2 | ((uint64_t)o.x3 << 32);
+    const int b0 = 31 - 2 * (int)q, b1 = b0 - 1;
+    uint64_t Tp = (m4 & (0ull - ((pc.t4 >> b0) & 1u))) | (m8 & (0ull - ((pc.t8 >> b0) & 1u))) |
+                  (m12 & (0ull - ((pc.t12 >> b0) & 1u)));
+    acc |= und & ~P0 & Tp;
+    und &= ~(P0 ^ Tp);
+    Tp = (m4 & (0ull - ((pc.t4 >> b1) & 1u))) | (m8 & (0ull - ((pc.t8 >> b1) & 1u))) |
+         (m12 & (0ull - ((pc.t12 >> b1) & 1u)));
+    acc |= und & ~P1 & Tp;
+    und &= ~(P1 ^ Tp);
+}
+
+// Per-wave queue of word-sites whose replicas are still undecided after the
+// first kInlinePairs plane pairs: they are compacted into full 64-lane
+// batches (one plane pair per batch) instead of keeping the wave waiting for
+// its slowest lane.  Results are the same: each site's planes are the same
+// Philox outputs, taken in the same order.
+constexpr int kInlinePairs = 3;
+constexpr int kQueue = 128; // per wave; never more than 127 items are live
+
+struct WaveQueue {
+    uint32_t *sq;  // site | next pair << 16
+    uint64_t *und, *m4, *m8;
+};
+
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << (threadIdx.x & 63)) - 1ull; }
+
+// Appends this lane's item if `has`; returns the new item count (wave-uniform).
+__device__ __forceinline__ uint32_t queue_push(const WaveQueue &Q, uint32_t head, uint32_t cnt, bool has,
+                                               uint32_t sq, uint64_t und, uint64_t m4, uint64_t m8)
+{
+    const uint64_t bal = __ballot(has);
+    if (has) {
+        const uint32_t slot = (head + cnt + (uint32_t)__popcll(bal & lanemask_lt())) & (kQueue - 1);
+        Q.sq[slot] = sq;
+        Q.und[slot] = und;
+        Q.m4[slot] = m4;
+        Q.m8[slot] = m8;
+    }
+    __builtin_amdgcn_wave_barrier();
+    return cnt + (uint32_t)__popcll(bal);
+}
+
+// One plane pair for up to 64 queued items; the still undecided go back.
+__device__ __forceinline__ void queue_pass(const WaveQueue &Q, const PlaneCtx &pc, uint64_t *lat, uint32_t &head,
+                                           uint32_t &cnt, uint32_t &calls)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t n = cnt < 64u ? cnt : 64u;
+    const bool act = lane < n;
+    uint32_t sq = 0;
+    uint64_t und = 0, m4 = 0, m8 = 0;
+    if (act) {
+        const uint32_t slot = (head + lane) & (kQueue - 1);
+        sq = Q.sq[slot];
+        und = Q.und[slot];
+        m4 = Q.m4[slot];
+        m8 = Q.m8[slot];
+    }
+    __builtin_amdgcn_wave_barrier();
+    head += n;
+    cnt -= n;
+    const uint32_t s = sq & 0xFFFFu, q = sq >> 16;
+    if (act) {
+        uint64_t acc = 0;
+        ++calls;
+        plane_pair(pc, s, q, m4, m8, ~(m4 | m8), und, acc);
+        lat[s] ^= acc;
+    }
+    const bool again = act && und != 0 && q + 1 < 16;
+    cnt = queue_push(Q, head, cnt, again, s | ((q + 1) << 16), und, m4, m8);
+}
+
 // One workgroup = one word column w (64 replicas) of one run; the lattice
 // stays in LDS for all theta sweeps, then each replica's unsatisfied-bond
 // count U and number of down spins are counted bit-sliced: E = 2U - dN,
@@ -139,6 +226,7 @@ template <int D>
 __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__restrict__ runs,
                                                             const PaBlk *__restrict__ map, int theta)
 {
+    // dynamic LDS: lattice [N] u64 | queues [waves][3][kQueue] u64 | queue sites [waves][kQueue] u32 | jmask [N]
     extern __shared__ uint64_t lat[];
     __shared__ uint64_t red[kSweepMaxThreads / 64][32];
     const PaBlk blk = map[blockIdx.x];
@@ -151,8 +239,10 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
     const int L = uni(rd.L), N = uni(rd.N);
     const int cur = uni(rec->cur);
     const uint32_t step = uni(rec->step), t0 = uni(rec->sweeps);
-    uint8_t *jl = reinterpret_cast<uint8_t *>(lat + N);
-    const int tid = threadIdx.x, bs = blockDim.x;
+    const int tid = threadIdx.x, bs = blockDim.x, nwaves = bs >> 6;
+    uint64_t *qbase = lat + N + (size_t)(tid >> 6) * 3 * kQueue;
+    uint32_t *qsites = reinterpret_cast<uint32_t *>(lat + N + (size_t)nwaves * 3 * kQueue);
+    uint8_t *jl = reinterpret_cast<uint8_t *>(qsites + (size_t)nwaves * kQueue);
     uint64_t *g = rd.dv.spins[cur] + (size_t)w * N;
     for (int s = tid; s < N; s += bs) {
         lat[s] = g[s];
@@ -162,7 +252,6 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
 
     const uint64_t two32 = 1ull << 32;
     const uint64_t T4 = uni64(rec->T[0]), T8 = uni64(rec->T[1]), T12 = uni64(rec->T[2]);
-    const uint32_t t4 = (uint32_t)T4, t8 = (uint32_t)T8, t12 = (uint32_t)T12;
     // classes whose threshold is 2^32 accept outright, those at 0 never accept
     const uint64_t sure4 = T4 >= two32 ? ~0ull : 0ull, sure8 = T8 >= two32 ? ~0ull : 0ull,
                    sure12 = T12 >= two32 ? ~0ull : 0ull;
@@ -170,68 +259,74 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
                    draw8 = (T8 > 0 && T8 < two32) ? ~0ull : 0ull,
                    draw12 = (T12 > 0 && T12 < two32) ? ~0ull : 0ull;
     const int half = L >> 1, nh = N >> 1, LL = L * L;
-    const uint32_t seed = uni(rd.seed), run_id = uni(rd.run_id);
-    uint32_t calls = 0; // Philox evaluations this lane's words needed
+    PlaneCtx pc;
+    pc.seed = uni(rd.seed);
+    pc.run_id = uni(rd.run_id);
+    pc.w = w;
+    pc.step = step;
+    pc.t4 = (uint32_t)T4;
+    pc.t8 = (uint32_t)T8;
+    pc.t12 = (uint32_t)T12;
+    const WaveQueue Q = {qsites + (size_t)(tid >> 6) * kQueue, qbase, qbase + kQueue, qbase + 2 * kQueue};
+    uint32_t calls = 0; // Philox evaluations this lane made
 
     for (int tt = 0; tt < theta; ++tt) {
-        const uint32_t t = t0 + (uint32_t)tt;
+        pc.t = t0 + (uint32_t)tt;
         for (int c = 0; c < 2; ++c) {
-            for (int k = tid; k < nh; k += bs) {
-                const int row = k / half, m = k - row * half; // row = y + L z
-                const int y = (D == 2) ? row : row % L;
-                const int z = (D == 2) ? 0 : row / L;
-                const int x = 2 * m + ((y + z + c) & 1);
-                const int s = x + L * row;
-                const uint32_t jb = jl[s];
-                const uint64_t S = lat[s];
-                const uint64_t a0 = S ^ lat[x == L - 1 ? s - (L - 1) : s + 1] ^ jbit(jb, 0);
-                const uint64_t a1 = S ^ lat[x == 0 ? s + (L - 1) : s - 1] ^ jbit(jb, D);
-                const uint64_t a2 = S ^ lat[y == L - 1 ? s - L * (L - 1) : s + L] ^ jbit(jb, 1);
-                const uint64_t a3 = S ^ lat[y == 0 ? s + L * (L - 1) : s - L] ^ jbit(jb, D + 1);
-                // u = number of unsatisfied bonds among 2d; dE = 4(d - u)
-                uint64_t always, m4, m8, m12;
-                if (D == 2) {
-                    const uint64_t s0 = a0 ^ a1, c0 = a0 & a1, s1 = a2 ^ a3, c1 = a2 & a3;
-                    always = c0 | c1 | (s0 & s1); // u >= 2
-                    m4 = (s0 ^ s1) & ~(c0 | c1);  // u == 1
-                    m8 = ~(s0 | s1 | c0 | c1);    // u == 0
-                    m12 = 0;
-                } else {
-                    const uint64_t a4 = S ^ lat[z == L - 1 ? s - LL * (L - 1) : s + LL] ^ jbit(jb, 2);
-                    const uint64_t a5 = S ^ lat[z == 0 ? s + LL * (L - 1) : s - LL] ^ jbit(jb, 5);
-                    const uint64_t sA = a0 ^ a1 ^ a2, cA = (a0 & a1) | (a2 & (a0 ^ a1));
-                    const uint64_t sB = a3 ^ a4 ^ a5, cB = (a3 & a4) | (a5 & (a3 ^ a4));
-                    const uint64_t ls = sA ^ sB, lc = sA & sB;
-                    // u = 2 (cA + cB + lc) + ls
-                    const uint64_t maj = (cA & cB) | (lc & (cA ^ cB));
-                    const uint64_t odd = cA ^ cB ^ lc;
-                    const uint64_t none = ~(cA | cB | lc);
-                    always = maj | (odd & ls); // u >= 3
-                    m4 = odd & ~maj & ~ls;     // u == 2
-                    m8 = none & ls;            // u == 1
-                    m12 = none & ~ls;          // u == 0
+            uint32_t head = 0, cnt = 0;
+            for (int kb = 0; kb < nh; kb += bs) {
+                const int k = kb + tid;
+                uint64_t und = 0, m4 = 0, m8 = 0;
+                uint32_t s = 0, q = 0;
+                if (k < nh) {
+                    const int row = k / half, m = k - row * half; // row = y + L z
+                    const int y = (D == 2) ? row : row % L;
+                    const int z = (D == 2) ? 0 : row / L;
+                    const int x = 2 * m + ((y + z + c) & 1);
+                    s = (uint32_t)(x + L * row);
+                    const uint32_t jb = jl[s];
+                    const uint64_t S = lat[s];
+                    const uint64_t a0 = S ^ lat[x == L - 1 ? s - (L - 1) : s + 1] ^ jbit(jb, 0);
+                    const uint64_t a1 = S ^ lat[x == 0 ? s + (L - 1) : s - 1] ^ jbit(jb, D);
+                    const uint64_t a2 = S ^ lat[y == L - 1 ? s - L * (L - 1) : s + L] ^ jbit(jb, 1);
+                    const uint64_t a3 = S ^ lat[y == 0 ? s + L * (L - 1) : s - L] ^ jbit(jb, D + 1);
+                    // u = number of unsatisfied bonds among 2d; dE = 4(d - u)
+                    uint64_t always, m12;
+                    if (D == 2) {
+                        const uint64_t s0 = a0 ^ a1, c0 = a0 & a1, s1 = a2 ^ a3, c1 = a2 & a3;
+                        always = c0 | c1 | (s0 & s1); // u >= 2
+                        m4 = (s0 ^ s1) & ~(c0 | c1);  // u == 1
+                        m8 = ~(s0 | s1 | c0 | c1);    // u == 0
+                        m12 = 0;
+                    } else {
+                        const uint64_t a4 = S ^ lat[z == L - 1 ? s - LL * (L - 1) : s + LL] ^ jbit(jb, 2);
+                        const uint64_t a5 = S ^ lat[z == 0 ? s + LL * (L - 1) : s - LL] ^ jbit(jb, 5);
+                        const uint64_t sA = a0 ^ a1 ^ a2, cA = (a0 & a1) | (a2 & (a0 ^ a1));
+                        const uint64_t sB = a3 ^ a4 ^ a5, cB = (a3 & a4) | (a5 & (a3 ^ a4));
+                        const uint64_t ls = sA ^ sB, lc = sA & sB;
+                        // u = 2 (cA + cB + lc) + ls
+                        const uint64_t maj = (cA & cB) | (lc & (cA ^ cB));
+                        const uint64_t odd = cA ^ cB ^ lc;
+                        const uint64_t none = ~(cA | cB | lc);
+                        always = maj | (odd & ls); // u >= 3
+                        m4 = odd & ~maj & ~ls;     // u == 2
+                        m8 = none & ls;            // u == 1
+                        m12 = none & ~ls;          // u == 0
+                    }
+                    uint64_t acc = always | (m4 & sure4) | (m8 & sure8) | (m12 & sure12);
+                    und = (m4 & draw4) | (m8 & draw8) | (m12 & draw12);
+                    for (; und != 0 && q < (uint32_t)kInlinePairs; ++q) {
+                        ++calls;
+                        plane_pair(pc, s, q, m4, m8, m12, und, acc);
+                    }
+                    lat[s] = S ^ acc;
                 }
-                uint64_t acc = always | (m4 & sure4) | (m8 & sure8) | (m12 & sure12);
-                uint64_t und = (m4 & draw4) | (m8 & draw8) | (m12 & draw12);
-                // u < T decided plane by plane from the most significant bit
-                for (uint32_t q = 0; und != 0 && q < 16; ++q) {
-                    ++calls;
-                    const pa_philox_out o = pa_philox(seed, run_id, (uint32_t)s, w, step,
-                                                      (PA_PURPOSE_METRO << 28) | (t << 8) | q);
-                    const uint64_t P0 = (uint64_t)o.x0 | ((uint64_t)o.x1 << 32);
-                    const uint64_t P1 = (uint64_t)o.x2 | ((uint64_t)o.x3 << 32);
-                    const int b0 = 31 - 2 * (int)q, b1 = b0 - 1;
-                    uint64_t Tp = (m4 & (0ull - ((t4 >> b0) & 1u))) | (m8 & (0ull - ((t8 >> b0) & 1u))) |
-                                  (m12 & (0ull - ((t12 >> b0) & 1u)));
-                    acc |= und & ~P0 & Tp;
-                    und &= ~(P0 ^ Tp);
-                    Tp = (m4 & (0ull - ((t4 >> b1) & 1u))) | (m8 & (0ull - ((t8 >> b1) & 1u))) |
-                         (m12 & (0ull - ((t12 >> b1) & 1u)));
-                    acc |= und & ~P1 & Tp;
-                    und &= ~(P1 ^ Tp);
-                }
-                lat[s] = S ^ acc;
+                cnt = queue_push(Q, head, cnt, und != 0, s | (q << 16), und, m4, m8);
+                while (cnt >= 64u)
+                    queue_pass(Q, pc, lat, head, cnt, calls);
             }
+            while (cnt > 0u)
+                queue_pass(Q, pc, lat, head, cnt, calls);
             __syncthreads();
         }
     }
@@ -1318,7 +1413,7 @@ hipError_t sweep_launch(const PaBatchView &v, int g, int theta, int threads)
 {
     if (v.gncol[g] == 0)
         return hipSuccess;
-    const size_t lds = pa_sweep_lds_bytes(v.gN[g]);
+    const size_t lds = pa_sweep_lds_bytes(v.gN[g], threads);
     if (v.gd[g] == 2)
         k_sweep<2><<<v.gncol[g], threads, lds, v.stream>>>(v.runs, v.gcol[g], theta);
     else
@@ -1329,7 +1424,10 @@ hipError_t sweep_launch(const PaBatchView &v, int g, int theta, int threads)
 } // namespace
 
 // ====================================================================== launchers
-size_t pa_sweep_lds_bytes(int N) { return ((size_t)N * 9 + 7) & ~(size_t)7; }
+size_t pa_sweep_lds_bytes(int N, int threads)
+{
+    return (size_t)N * 8 + (size_t)(threads / 64) * kQueue * (3 * 8 + 4) + (((size_t)N + 7) & ~(size_t)7);
+}
 
 hipError_t pa_query_lds(int *max_lds)
 {
