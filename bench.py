@@ -221,6 +221,28 @@ def learned_bench(theta=10, scheme=3, astar=0.7, dmax=0.2, beta_f=3.0):
     return res
 
 
+def profile_run():
+    """Workload for counter passes: the sweep, resample and observables kernels
+    of 3 temperature steps of one run, then torch's copy of 256 MiB (reads and
+    writes 2^28 bytes each) as the reference of known traffic."""
+    import torch
+    from paper_2401_07965_amd import pa
+    g = pa.PARun(D, L, R, seed=SEED, run_id=3)
+    sched = betas()
+    for i in range(1, 4):
+        g.reweight(sched[i])
+        g.resample(3)
+        g.sweep(THETA)
+        g.observables()
+    torch.cuda.synchronize()
+    src = torch.empty(1 << 28, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    g.close()
+    print("profile run done", flush=True)
+
+
 def cpu_baseline(budget_s=15.0):
     """The oracle as it stands, on a sample of the same workload: a population
     of R_s = 2048 replicas (same lattice, theta, schedule), whole steps."""
@@ -256,7 +278,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the batched and learned-schedule measurements")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for hardware counters: 3 steps of one run of the workload, "
+                         "then a 256 MiB device-to-device copy of known size")
     a = ap.parse_args()
+    if a.profile:
+        profile_run()
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
               "(the multi-GPU split is described in DESIGN.md, not built)", file=sys.stderr)
