@@ -44,74 +44,93 @@ def make_runs(pa):
 
 
 def gpu_bench(steps, warmup):
+    """Times `steps` temperature steps of the four runs.  Every call inside the
+    timed region is deferred (nothing waits for the device); the sweep and the
+    reweight + resample of each run are bracketed by HIP events on the run's
+    stream.  Attempts and work counters come from the device records."""
     import torch
     from paper_2401_07965_amd import pa
     pa.lib()
     sched = betas()
-    runs = make_runs(pa)
     stream = torch.cuda.current_stream()
-    state = {"i": 0, "runs": runs}
+    state = {"i": 0, "runs": make_runs(pa)}
+    keys = ("philox_calls", "site_updates", "spin_attempts")
+    done = dict.fromkeys(keys, 0)  # counters of runs closed inside the window
+    Rsum = {"start": 0, "end": 0}
 
-    def one_step(timed, acc):
+    def one_step(acc):
         i = state["i"] + 1
         if i == POINTS:  # anneal finished: start the next anneal (step 1 of the method)
             for g in state["runs"]:
+                if acc is not None:
+                    c = g.counters()
+                    for k in keys:
+                        done[k] += c[k]
+                    Rsum["end"] += g.observables()["R"]
                 g.close()
             state["runs"] = make_runs(pa)
+            if acc is not None:
+                Rsum["start"] += R * len(SCHEMES)
             i = 1
         state["i"] = i
-        attempts = 0
         for (name, rid), g in zip(SCHEMES, state["runs"]):
-            t0 = time.perf_counter()
-            g.reweight(sched[i])
-            Rn = g.resample(rid)
-            t1 = time.perf_counter()
-            if timed:
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
+            if acc is None:
+                g.reweight(sched[i], wait=False)
+                g.resample(rid, wait=False)
                 g.sweep(THETA)
-                e1.record(stream)
-                acc["sweep_events"].append((e0, e1))
-                acc["resample_s"] += t1 - t0
-                acc["resample_bytes"] += resample_bytes(Rn, g)
-            else:
-                g.sweep(THETA)
-            g.observables()
-            attempts += THETA * (L ** D) * Rn
-        return attempts
+                g.observables(wait=False)
+                continue
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record(stream)
+            g.reweight(sched[i], wait=False)
+            g.resample(rid, wait=False)
+            ev[1].record(stream)
+            g.sweep(THETA)
+            ev[2].record(stream)
+            g.observables(wait=False)
+            acc.append(ev)
 
-    acc = {"sweep_events": [], "resample_s": 0.0, "resample_bytes": 0.0}
     for _ in range(warmup):
-        one_step(False, acc)
-    c0 = [g.counters() for g in state["runs"]]
+        one_step(None)
+    base = [g.counters() for g in state["runs"]]  # synchronises; raises if a run failed
+    Rsum["start"] += sum(g.observables()["R"] for g in state["runs"])
+    acc = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    attempts = 0
     for _ in range(steps):
-        attempts += one_step(True, acc)
+        one_step(acc)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    c1 = [g.counters() for g in state["runs"]]
-    sweep_ms = [a.elapsed_time(b) for a, b in acc["sweep_events"]]
-    calls = sum(b["philox_calls"] - a["philox_calls"] for a, b in zip(c0, c1))
-    updates = sum(b["site_updates"] - a["site_updates"] for a, b in zip(c0, c1))
-    if any(b["sweeps"] < a["sweeps"] for a, b in zip(c0, c1)):
-        calls = updates = 0  # an anneal restarted inside the window: counters reset
+    tot = dict(done)
+    for g in state["runs"]:
+        c = g.counters()
+        for k in keys:
+            tot[k] += c[k]
+        Rsum["end"] += g.observables()["R"]
+    # counters of the runs alive at the window start count from their values then
+    for b in base:
+        for k in keys:
+            tot[k] -= b[k]
+    sweep_ms = [e[1].elapsed_time(e[2]) for e in acc]
+    resample_ms = [e[0].elapsed_time(e[1]) for e in acc]
     for g in state["runs"]:
         g.close()
-    return dict(elapsed=elapsed, attempts=attempts, sweep_ms=sweep_ms, calls=calls,
-                updates=updates, resample_s=acc["resample_s"],
-                resample_bytes=acc["resample_bytes"])
+    attempts = tot["spin_attempts"]
+    new_replicas = attempts // (THETA * L ** D)
+    # replicas before each resampling: the new ones, shifted by one step
+    old_replicas = new_replicas + Rsum["start"] - Rsum["end"]
+    return dict(elapsed=elapsed, attempts=attempts, sweep_ms=sweep_ms, calls=tot["philox_calls"],
+                updates=tot["site_updates"], resample_s=sum(resample_ms) / 1e3,
+                resample_bytes=resample_bytes(old_replicas, new_replicas))
 
 
-def resample_bytes(Rn, g):
-    """Algorithmic HBM bytes of one resampling: per old replica
-    the energy read and the copy number / offset writes and reads; per new
-    replica the spins read and written (2 N/8 bytes) plus energy,
+def resample_bytes(R_old, R_new):
+    """Algorithmic HBM bytes of reweighting and resampling: per
+    old replica the energy read and the copy number / offset writes and reads;
+    per new replica the spins read and written (2 N/8 bytes) plus energy,
     magnetisation and label read and written."""
     N = L ** D
-    return g.R * (4 + 4 + 4 + 4 + 4) + Rn * (2 * N / 8 + 3 * 4 * 2 + 4)
+    return R_old * (4 + 4 + 4 + 4 + 4) + R_new * (2 * N / 8 + 3 * 4 * 2 + 4)
 
 
 def batched_bench(theta=10, scheme=3, verify_runs=8):

@@ -25,6 +25,15 @@
  *    distinct streams.  Calls that return results to the host (pa_reweight,
  *    pa_resample, pa_observables, pa_free_energy, pa_export_state) synchronise
  *    the stream; pa_sweep only enqueues.
+ *  - Deferred calls: pa_reweight, pa_resample and pa_observables given a NULL
+ *    result pointer only enqueue their kernels and return at once, so that a
+ *    whole temperature step runs without waiting for the device.  A failure
+ *    that pa_resample would report (PA_E_CAPACITY, PA_E_EXTINCT,
+ *    PA_E_NONFINITE) then freezes the run instead: its population stays as it
+ *    was before that resampling, every later kernel of the run does nothing,
+ *    and every later call that synchronises returns that error.
+ *    pa_export_state still reads the frozen population; pa_import_state
+ *    replaces it and lifts the freeze.
  *
  * Spin layout in device memory (and in pa_host_state): replica r = 64 w + b is
  * bit b of word [w][s] (uint64, site-minor: word index w * N + s).  Bit 1 means
@@ -115,6 +124,8 @@ typedef struct {
     uint64_t site_updates;  /* 64-replica word-site updates (64 attempts each,
                                dead replicas of the last word included) */
     uint64_t sweeps;        /* sweeps over all sites, summed over pa_sweep calls */
+    uint64_t spin_attempts; /* Metropolis attempts: theta N R_i summed over pa_sweep
+                               calls (R_i the population at the call) */
 } pa_counters;
 
 typedef struct pa_ctx pa_ctx;
@@ -141,17 +152,20 @@ pa_status pa_sweep(pa_ctx *ctx, int32_t theta);
 /* Step 2 of Sec. 2: for beta_next >= beta, ln Q of Eq. (1) over the current
  * population, written as -dbeta E_min + ln((1/R) sum_j exp(-dbeta (E_j - E_min))).
  * Also fixes the integer resampling weights floor(2^40 exp(-dbeta (E_j - E_min))).
- * The population is unchanged; a second call replaces the first. */
+ * The population is unchanged; a second call replaces the first.
+ * lnQ_out NULL: deferred (see the conventions above). */
 pa_status pa_reweight(pa_ctx *ctx, double beta_next, double *lnQ_out);
 
 /* Step 2 of Sec. 2 with a scheme of Sec. 3: copy numbers r_j with
  * <r_j> = tauhat_j = R W_j / S (Eq. (3), R the target size), the new
  * population (r_j copies of replica j, in ascending j; spins, energies,
  * magnetisations and labels copied), then beta := beta_next, i := i + 1,
- * ln Z_hat += ln Q.  Needs a pa_reweight first.  R_new_out may be NULL. */
+ * ln Z_hat += ln Q.  Needs a pa_reweight first.  R_new_out NULL: deferred
+ * (a failure freezes the run, see the conventions above). */
 pa_status pa_resample(pa_ctx *ctx, pa_resampler scheme, int64_t *R_new_out);
 
-/* Step 4 of Sec. 2 over the current population. */
+/* Step 4 of Sec. 2 over the current population.  out NULL: deferred (the
+ * averages are still computed on the device, e.g. for pa_features). */
 pa_status pa_observables(pa_ctx *ctx, pa_obs *out);
 
 /* -beta_i F_hat_i = ln Z_{beta_0} + sum_{k<=i} ln Q_k (Eq. (7)). */

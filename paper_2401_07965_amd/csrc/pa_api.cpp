@@ -449,6 +449,18 @@ pa_status status_error(Batch *b, uint32_t st)
     return PA_OK;
 }
 
+// Records of a single run once its stream has drained.  A run frozen by a
+// deferred pa_resample reports the failure that froze it.
+pa_status ctx_records(Batch *b, const char *where)
+{
+    pa_status s = fetch_records(b, where);
+    if (s != PA_OK)
+        return s;
+    if (b->hrec[0].status & PA_ST_FROZEN)
+        return status_error(b, b->hrec[0].status);
+    return PA_OK;
+}
+
 pa_status export_run(Batch *b, int m, pa_host_state *st)
 {
     pa_status s = fetch_records(b, "export");
@@ -548,7 +560,12 @@ pa_status pa_reweight(pa_ctx *c, double beta_next, double *lnQ_out)
     hipError_t e = pa_b_reweight(b->v, beta_next);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_reweight");
-    pa_status s = fetch_records(b, "pa_reweight");
+    if (!lnQ_out) { // deferred: a non-finite ln Q is caught by the resampling
+        b->reweighted = true;
+        b->beta_next = beta_next;
+        return PA_OK;
+    }
+    pa_status s = ctx_records(b, "pa_reweight");
     if (s != PA_OK)
         return s;
     if (!std::isfinite(b->hrec[0].lnQ)) {
@@ -571,10 +588,17 @@ pa_status pa_resample(pa_ctx *c, pa_resampler scheme, int64_t *R_new_out)
         return fail(b, PA_E_INVAL, "unknown resampling scheme");
     if (!b->reweighted)
         return fail(b, PA_E_STATE, "pa_resample needs a pa_reweight first");
-    hipError_t e = pa_b_resample(b->v, (int)scheme, 0);
+    const bool deferred = R_new_out == nullptr;
+    hipError_t e = pa_b_resample(b->v, (int)scheme, deferred ? 1 : 0);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_resample");
-    pa_status s = fetch_records(b, "pa_resample");
+    if (deferred) { // a failure freezes the run; the next synchronising call reports it
+        b->beta = b->beta_next;
+        b->sweeps = 0;
+        b->reweighted = false;
+        return PA_OK;
+    }
+    pa_status s = ctx_records(b, "pa_resample");
     if (s != PA_OK)
         return s;
     if (b->hrec[0].skip)
@@ -592,12 +616,12 @@ pa_status pa_observables(pa_ctx *c, pa_obs *out)
     if (!c)
         return fail(nullptr, PA_E_INVAL, "ctx is NULL");
     Batch *b = &c->b;
-    if (!out)
-        return fail(b, PA_E_INVAL, "out is NULL");
     hipError_t e = pa_b_observables(b->v, -1);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_observables");
-    pa_status s = fetch_records(b, "pa_observables");
+    if (!out)
+        return PA_OK;
+    pa_status s = ctx_records(b, "pa_observables");
     if (s != PA_OK)
         return s;
     const PaRecord &r = b->hrec[0];
@@ -626,7 +650,7 @@ pa_status pa_free_energy(pa_ctx *c, double *lnZ_out)
     Batch *b = &c->b;
     if (!lnZ_out)
         return fail(b, PA_E_INVAL, "lnZ_out is NULL");
-    pa_status s = fetch_records(b, "pa_free_energy");
+    pa_status s = ctx_records(b, "pa_free_energy");
     if (s != PA_OK)
         return s;
     *lnZ_out = b->hrec[0].lnZ;
@@ -723,7 +747,7 @@ pa_status pa_step_alpha(pa_ctx *c, double dbeta, double *alpha_out)
     hipError_t e = pa_b_rule(b->v, 0.0, dbeta, 0, 0);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_step_alpha");
-    pa_status s = fetch_records(b, "pa_step_alpha");
+    pa_status s = ctx_records(b, "pa_step_alpha");
     if (s != PA_OK)
         return s;
     *alpha_out = b->hrec[0].rule_alpha;
@@ -741,7 +765,7 @@ pa_status pa_step_rule(pa_ctx *c, double alpha_star, double dbeta_max, int32_t i
     hipError_t e = pa_b_rule(b->v, alpha_star, dbeta_max, iterations, 1);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_step_rule");
-    pa_status s = fetch_records(b, "pa_step_rule");
+    pa_status s = ctx_records(b, "pa_step_rule");
     if (s != PA_OK)
         return s;
     *dbeta_out = b->hrec[0].rule_dbeta;
@@ -755,12 +779,13 @@ pa_status pa_get_counters(pa_ctx *c, pa_counters *out)
     Batch *b = &c->b;
     if (!out)
         return fail(b, PA_E_INVAL, "out is NULL");
-    pa_status s = fetch_records(b, "pa_get_counters");
+    pa_status s = ctx_records(b, "pa_get_counters");
     if (s != PA_OK)
         return s;
     out->philox_calls = b->hrec[0].philox_calls;
     out->site_updates = b->hrec[0].site_updates;
     out->sweeps = b->sweeps_total;
+    out->spin_attempts = b->hrec[0].attempts;
     return PA_OK;
 }
 
@@ -1203,7 +1228,7 @@ pa_status pa_features(pa_ctx *c, float *out8)
     hipError_t e = pa_b_features(b->v);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_features");
-    pa_status s = fetch_records(b, "pa_features");
+    pa_status s = ctx_records(b, "pa_features");
     if (s != PA_OK)
         return s;
     std::memcpy(out8, b->hrec[0].feat, sizeof(float) * 8);
@@ -1231,7 +1256,7 @@ pa_status pa_step_learned(pa_ctx *c, pa_mlp *m, double alpha_star, double dbeta_
         e = pa_b_check_candidate(b->v, alpha_star, dbeta_max, iterations);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_step_learned");
-    pa_status s = fetch_records(b, "pa_step_learned");
+    pa_status s = ctx_records(b, "pa_step_learned");
     if (s != PA_OK)
         return s;
     *dbeta_out = b->hrec[0].rule_dbeta;

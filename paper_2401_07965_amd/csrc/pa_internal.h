@@ -51,6 +51,7 @@ struct PaRecord {
     uint32_t fallback, pad1;       // 1: the proposal failed the overlap check
     unsigned long long philox_calls; // Philox4x32-10 evaluations of all sweeps so far
     unsigned long long site_updates; // word-site updates (64 attempts each) so far
+    unsigned long long attempts;     // spin-flip attempts so far: theta N R per sweep call
 };
 
 // One row per run and temperature point of a batched anneal.

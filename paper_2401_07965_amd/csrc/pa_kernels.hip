@@ -23,6 +23,15 @@ constexpr int kRuleCache = 4096; // levels whose weights stay in LDS between the
 
 __device__ __forceinline__ bool frozen(const PaRecord *rec) { return (rec->status & PA_ST_FROZEN) != 0u; }
 
+// Workgroups of a launch go to the 8 XCDs in turn (block b to XCD b mod 8).
+// This permutation hands each XCD one contiguous range of [0, n), so blocks
+// that read neighbouring data share that XCD's L2.
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t n)
+{
+    const uint32_t x = b & 7u, k = b >> 3, q = n >> 3, r = n & 7u;
+    return (x < r ? x * (q + 1u) : r * (q + 1u) + (x - r) * q) + k;
+}
+
 // Workgroup-uniform values read from device memory, kept in scalar registers.
 __device__ __forceinline__ uint32_t uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -69,6 +78,7 @@ __global__ void k_init_rec(const PaRunDesc *__restrict__ runs)
         rec->T[k] = rec->Tn[k] = 1ull << 32;
     rec->philox_calls = 0;
     rec->site_updates = 0;
+    rec->attempts = 0;
     rec->lnq_hist[0] = rec->lnq_hist[1] = rec->lnq_hist[2] = 0.0;
     rec->S_f = log((double)rd.R0);
 }
@@ -95,8 +105,10 @@ __global__ __launch_bounds__(kThreads) void k_init_labels(const PaRunDesc *__res
     const PaBlk b = map[blockIdx.x];
     const PaRunDesc &rd = runs[b.run];
     const int64_t beg = (int64_t)b.idx * PA_CHUNK;
-    for (int64_t j = beg + threadIdx.x; j < beg + PA_CHUNK && j < rd.R0; j += blockDim.x)
+    for (int64_t j = beg + threadIdx.x; j < beg + PA_CHUNK && j < rd.R0; j += blockDim.x) {
         rd.dv.label[0][j] = (uint32_t)j;
+        rd.dv.fam[j] = 0; // family counts start at zero; k_obs_fam returns them to zero
+    }
 }
 
 // ------------------------------------------------------------------ step 3: sweeps
@@ -390,9 +402,12 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
 // workgroup of the sweep reads a half-updated counter).
 __global__ void k_sweeps_add(const PaRunDesc *__restrict__ runs, int theta)
 {
-    PaRecord *rec = runs[blockIdx.x].dv.rec;
-    if (threadIdx.x == 0 && !frozen(rec))
+    const PaRunDesc &rd = runs[blockIdx.x];
+    PaRecord *rec = rd.dv.rec;
+    if (threadIdx.x == 0 && !frozen(rec)) {
         rec->sweeps += (uint32_t)theta;
+        rec->attempts += (unsigned long long)theta * (unsigned long long)rd.N * rec->Rcur;
+    }
 }
 
 // ------------------------------------------------------------------ step 2: Q
@@ -1075,7 +1090,9 @@ __global__ __launch_bounds__(kThreads) void k_gather_spins(const PaRunDesc *__re
     __shared__ uint32_t r_word[64];
     __shared__ uint32_t r_shift[64], r_b0[64], r_len[64];
     __shared__ int s_nruns;
-    const PaBlk blk = map[blockIdx.x];
+    // an output word takes bits of the source words its ancestors lie in, the
+    // same words as its neighbours: neighbouring words go to one XCD
+    const PaBlk blk = map[xcd_contiguous(blockIdx.x, gridDim.x)];
     const PaRunDesc &rd = runs[blk.run];
     PaRecord *rec = rd.dv.rec;
     const int64_t Rnew = (int64_t)rec->Rnew;
@@ -1108,21 +1125,38 @@ __global__ __launch_bounds__(kThreads) void k_gather_spins(const PaRunDesc *__re
             s_nruns = __popcll(sm);
     }
     __syncthreads();
-    const int nr = s_nruns;
-    for (int s = threadIdx.x; s < N; s += blockDim.x) {
-        uint64_t out = 0, v = 0;
+    const int nr = uni(s_nruns);
+    const int nt = (int)blockDim.x;
+    // kG sites per thread at a time: their loads are independent and in flight together
+    constexpr int kG = 4;
+    for (int s0 = threadIdx.x; s0 < N; s0 += kG * nt) {
+        uint64_t out[kG], v[kG];
+#pragma unroll
+        for (int k = 0; k < kG; ++k)
+            out[k] = v[k] = 0;
         uint32_t last = 0xFFFFFFFFu;
         for (int i = 0; i < nr; ++i) {
-            const uint32_t sw = r_word[i];
+            const uint32_t sw = uni(r_word[i]);
             if (sw != last) {
-                v = src[(size_t)sw * N + s];
+#pragma unroll
+                for (int k = 0; k < kG; ++k) {
+                    const int s = s0 + k * nt;
+                    v[k] = s < N ? src[(size_t)sw * N + s] : 0ull;
+                }
                 last = sw;
             }
-            const uint32_t len = r_len[i];
+            const uint32_t len = uni(r_len[i]), sh = uni(r_shift[i]), b0 = uni(r_b0[i]);
             const uint64_t mask = len >= 64 ? ~0ull : ((1ull << len) - 1ull);
-            out |= ((v >> r_shift[i]) & mask) << r_b0[i];
+#pragma unroll
+            for (int k = 0; k < kG; ++k)
+                out[k] |= ((v[k] >> sh) & mask) << b0;
         }
-        dst[(size_t)w * N + s] = out;
+#pragma unroll
+        for (int k = 0; k < kG; ++k) {
+            const int s = s0 + k * nt;
+            if (s < N)
+                dst[(size_t)w * N + s] = out[k];
+        }
     }
 }
 
@@ -1167,8 +1201,6 @@ __global__ void k_obs_prep(const PaRunDesc *__restrict__ runs)
     PaRecord *rec = rd.dv.rec;
     if (frozen(rec))
         return;
-    for (int64_t i = threadIdx.x; i < rd.R0; i += blockDim.x)
-        rd.dv.fam[i] = 0;
     if (threadIdx.x == 0)
         rec->sumE = rec->sumE2 = rec->sumAbsM = rec->sumM2 = rec->sumC2 = rec->families = 0;
 }
@@ -1183,13 +1215,29 @@ __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restric
     const PaDev &dv = c.rd->dv;
     const int cur = c.rec->cur;
     uint64_t sE = 0, sE2 = 0, sA = 0, sM2 = 0;
-    for (int64_t d = c.beg + threadIdx.x; d < c.end; d += blockDim.x) {
-        const int64_t e = dv.E[cur][d], m = dv.M[cur][d];
-        sE += (uint64_t)e;
-        sE2 += (uint64_t)(e * e);
-        sA += (uint64_t)(m < 0 ? -m : m);
-        sM2 += (uint64_t)(m * m);
-        atomicAdd(&dv.fam[dv.label[cur][d]], 1u);
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = c.beg; base < c.end; base += blockDim.x) {
+        const int64_t d = base + threadIdx.x;
+        const bool valid = d < c.end;
+        uint32_t lab = 0xFFFFFFFFu;
+        if (valid) {
+            const int64_t e = dv.E[cur][d], m = dv.M[cur][d];
+            sE += (uint64_t)e;
+            sE2 += (uint64_t)(e * e);
+            sA += (uint64_t)(m < 0 ? -m : m);
+            sM2 += (uint64_t)(m * m);
+            lab = dv.label[cur][d];
+        }
+        // family counts: one atomic per run of equal labels in the wave (the
+        // resampling keeps copies adjacent, so runs are long)
+        const uint32_t prev = (uint32_t)__shfl_up((int)lab, 1, 64);
+        const bool start = valid && (lane == 0 || lab != prev);
+        const uint64_t sm = __ballot(start), vm = __ballot(valid);
+        if (start) {
+            const uint64_t above = lane == 63 ? 0ull : ((sm | ~vm) & ~((2ull << lane) - 1ull));
+            const int stop = above ? __ffsll((long long)above) - 1 : 64;
+            atomicAdd(&dv.fam[lab], (uint32_t)(stop - lane));
+        }
     }
     sE = pa_block_sum_u64(sE, su);
     sE2 = pa_block_sum_u64(sE2, su);
@@ -1221,6 +1269,7 @@ __global__ __launch_bounds__(kThreads) void k_obs_fam(const PaRunDesc *__restric
         const uint64_t c = rd.dv.fam[f];
         c2 += c * c;
         if (c) {
+            rd.dv.fam[f] = 0;
             nf += 1;
             cl = cl + (double)c * log((double)c);
         }

@@ -43,7 +43,7 @@ class pa_host_state(ctypes.Structure):
 
 class pa_counters(ctypes.Structure):
     _fields_ = [("philox_calls", ctypes.c_uint64), ("site_updates", ctypes.c_uint64),
-                ("sweeps", ctypes.c_uint64)]
+                ("sweeps", ctypes.c_uint64), ("spin_attempts", ctypes.c_uint64)]
 
 
 class pa_step_record(ctypes.Structure):
@@ -214,19 +214,31 @@ def pa_sweep(ctx, theta):
     _check(lib().pa_sweep(ctx, int(theta)), ctx)
 
 
-def pa_reweight(ctx, beta_next):
+def pa_reweight(ctx, beta_next, wait=True):
+    """ln Q; with wait=False the call is deferred and returns None."""
+    if not wait:
+        _check(lib().pa_reweight(ctx, float(beta_next), None), ctx)
+        return None
     q = ctypes.c_double()
     _check(lib().pa_reweight(ctx, float(beta_next), ctypes.byref(q)), ctx)
     return q.value
 
 
-def pa_resample(ctx, scheme):
+def pa_resample(ctx, scheme, wait=True):
+    """New population size; with wait=False the call is deferred (a failure
+    freezes the run and is raised by the next waiting call) and returns None."""
+    if not wait:
+        _check(lib().pa_resample(ctx, int(scheme), None), ctx)
+        return None
     n = ctypes.c_int64()
     _check(lib().pa_resample(ctx, int(scheme), ctypes.byref(n)), ctx)
     return n.value
 
 
-def pa_observables(ctx):
+def pa_observables(ctx, wait=True):
+    if not wait:
+        _check(lib().pa_observables(ctx, None), ctx)
+        return None
     o = pa_obs()
     _check(lib().pa_observables(ctx, ctypes.byref(o)), ctx)
     return {name: getattr(o, name) for name, _ in pa_obs._fields_}
@@ -332,17 +344,17 @@ class PARun:
         self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
         self.ctx = pa_init(cfg, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
 
-    def reweight(self, beta_next):
-        return pa_reweight(self.ctx, beta_next)
+    def reweight(self, beta_next, wait=True):
+        return pa_reweight(self.ctx, beta_next, wait)
 
-    def resample(self, scheme):
-        return pa_resample(self.ctx, SCHEMES.get(scheme, scheme))
+    def resample(self, scheme, wait=True):
+        return pa_resample(self.ctx, SCHEMES.get(scheme, scheme), wait)
 
     def sweep(self, theta):
         pa_sweep(self.ctx, theta)
 
-    def observables(self):
-        return pa_observables(self.ctx)
+    def observables(self, wait=True):
+        return pa_observables(self.ctx, wait)
 
     def free_energy(self):
         return pa_free_energy(self.ctx)
