@@ -250,18 +250,18 @@ pa_status pa_batch_required_bytes(const pa_config *cfgs, int32_t nruns, int32_t 
                                   uint64_t *bytes);
 
 /* Lays out the batch in the caller's workspace (256-byte aligned) and draws
- * every run's initial population (step 1 of Sec. 2).  At most 16 distinct
- * lattice shapes. */
+ * every run's initial population (step 1 of Sec. 2).  Runs are grouped by
+ * (dim, L, couplings given or NULL); at most 16 groups. */
 pa_status pa_batch_create(const pa_config *cfgs, int32_t nruns, int32_t max_points, void *workspace,
                           uint64_t workspace_bytes, void *stream, pa_batch **out);
 
 /* Autotuner: times the sweep workgroup size (64..512 lanes, where the
- * lattice allows) per lattice shape with theta sweeps, keeps the fastest and
+ * lattice allows) per group with theta sweeps, keeps the fastest and
  * re-draws the initial populations.  Results do not depend on the choice.
- * threads_out (optional): one entry per shape group. */
+ * threads_out (optional): one entry per group. */
 pa_status pa_batch_tune(pa_batch *b, int32_t theta, int32_t *threads_out);
 
-/* Shape groups of the batch and their sweep workgroup sizes. */
+/* Groups of the batch (see pa_batch_create) and their sweep workgroup sizes. */
 pa_status pa_batch_groups(pa_batch *b, int32_t *ngroups, int32_t *threads);
 
 /* A whole anneal of every run from a fresh initial population: betas[0] = 0,

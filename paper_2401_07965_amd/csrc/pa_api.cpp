@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <new>
 #include <string>
 #include <utility>
@@ -39,6 +40,7 @@ int64_t default_capacity(int64_t R)
 struct Geometry {
     int d, L, N, H;
     int64_t R, cap, W;
+    int J; // 1: couplings given (+-J bonds), 0: ferromagnet
 };
 
 pa_status check_config(const pa_config *cfg, Geometry *g, std::string *msg)
@@ -73,6 +75,7 @@ pa_status check_config(const pa_config *cfg, Geometry *g, std::string *msg)
     }
     g->d = cfg->dim;
     g->L = cfg->L;
+    g->J = cfg->couplings ? 1 : 0;
     g->N = (int)N;
     g->H = cfg->dim * (int)N / 2 + 1;
     g->R = cfg->R;
@@ -197,14 +200,14 @@ pa_status hip_fail(Batch *b, hipError_t e, const char *where)
 struct Tables {
     std::vector<PaBlk> rep, hrep, fam, col, tile;
     std::vector<std::vector<PaBlk>> gcol;
-    std::vector<int> gd, gN, gthreads;
+    std::vector<int> gd, gN, gJ, gthreads;
 };
 
 uint64_t layout(const std::vector<Geometry> &geo, int max_points, char *base, Batch *b, Tables *t)
 {
     const int M = (int)geo.size();
     Tables tb;
-    std::map<std::pair<int, int>, int> group_of_shape;
+    std::map<std::tuple<int, int, int>, int> group_of_shape;
     std::vector<int> run_group(M);
     for (int m = 0; m < M; ++m) {
         const Geometry &g = geo[m];
@@ -218,13 +221,14 @@ uint64_t layout(const std::vector<Geometry> &geo, int max_points, char *base, Ba
             tb.col.push_back({(uint32_t)m, (uint32_t)w});
         for (int64_t k = 0; k < (g.cap + PA_SCAN_TILE - 1) / PA_SCAN_TILE; ++k)
             tb.tile.push_back({(uint32_t)m, (uint32_t)k});
-        const auto key = std::make_pair(g.d, g.L);
+        const auto key = std::make_tuple(g.d, g.L, g.J);
         auto it = group_of_shape.find(key);
         if (it == group_of_shape.end()) {
             it = group_of_shape.emplace(key, (int)tb.gcol.size()).first;
             tb.gcol.emplace_back();
             tb.gd.push_back(g.d);
             tb.gN.push_back(g.N);
+            tb.gJ.push_back(g.J);
             tb.gthreads.push_back(default_sweep_threads(g.N, g.d));
         }
         for (int64_t w = 0; w < g.W; ++w)
@@ -294,6 +298,7 @@ uint64_t layout(const std::vector<Geometry> &geo, int max_points, char *base, Ba
             v.gncol[g] = (uint32_t)tb.gcol[g].size();
             v.gd[g] = tb.gd[g];
             v.gN[g] = tb.gN[g];
+            v.gJ[g] = tb.gJ[g];
             v.gthreads[g] = tb.gthreads[g];
         }
         v.steprec = (PaStepRecord *)p_steprec;
@@ -320,17 +325,17 @@ pa_status check_batch(const pa_config *cfgs, int32_t nruns, int32_t max_points, 
         return PA_E_INVAL;
     }
     geo->resize(nruns);
-    std::map<std::pair<int, int>, int> shapes;
+    std::map<std::tuple<int, int, int>, int> shapes;
     for (int m = 0; m < nruns; ++m) {
         pa_status s = check_config(&cfgs[m], &(*geo)[m], msg);
         if (s != PA_OK) {
             *msg = "run " + std::to_string(m) + ": " + *msg;
             return s;
         }
-        shapes[{cfgs[m].dim, cfgs[m].L}] = 1;
+        shapes[std::make_tuple(cfgs[m].dim, cfgs[m].L, cfgs[m].couplings ? 1 : 0)] = 1;
     }
     if ((int)shapes.size() > PA_MAX_GROUPS) {
-        *msg = "at most 16 distinct lattice shapes per batch";
+        *msg = "at most 16 groups of (lattice shape, couplings given or not) per batch";
         return PA_E_INVAL;
     }
     return PA_OK;

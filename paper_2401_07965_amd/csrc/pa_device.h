@@ -28,9 +28,35 @@ struct pa_philox_out {
     uint32_t x0, x1, x2, x3;
 };
 
+// gfx950 three-input bitwise operation (v_bitop3_b32): bit i of the result is
+// bit (a_i b_i c_i) (a the most significant) of the 8-bit table.  A table is
+// written as the wanted function applied to the columns a = 0xF0, b = 0xCC,
+// c = 0xAA, e.g. PA_T3(PA_A ^ PA_B ^ PA_C) for a three-way xor.
+#define PA_A 0xF0
+#define PA_B 0xCC
+#define PA_C 0xAA
+#define PA_T3(f) ((f) & 0xFF)
+
+template <int TT>
+__device__ __forceinline__ uint32_t pa_bop3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return (uint32_t)__builtin_amdgcn_bitop3_b32((int)a, (int)b, (int)c, TT);
+}
+
+template <int TT>
+__device__ __forceinline__ uint64_t pa_bop3(uint64_t a, uint64_t b, uint64_t c)
+{
+    const uint32_t lo = pa_bop3<TT>((uint32_t)a, (uint32_t)b, (uint32_t)c);
+    const uint32_t hi = pa_bop3<TT>((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32));
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
 // Philox4x32-10: ten rounds of (x0,x1,x2,x3) -> (hi(B x2) ^ x1 ^ k0, lo(B x2),
 // hi(A x0) ^ x3 ^ k1, lo(A x0)) with A = 0xD2511F53, B = 0xCD9E8D57 and the key
-// advanced by (0x9E3779B9, 0xBB67AE85) between rounds.
+// advanced by (0x9E3779B9, 0xBB67AE85) between rounds.  From the third round
+// on every word varies per lane, and each output takes one three-way xor;
+// the first two rounds keep plain xors so that words common to a wavefront
+// stay in scalar registers.
 __device__ __forceinline__ pa_philox_out pa_philox(uint32_t k0, uint32_t k1, uint32_t x0,
                                                    uint32_t x1, uint32_t x2, uint32_t x3)
 {
@@ -38,8 +64,14 @@ __device__ __forceinline__ pa_philox_out pa_philox(uint32_t k0, uint32_t k1, uin
     for (int round = 0; round < 10; ++round) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * x0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
-        const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
-        const uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        uint32_t y0, y2;
+        if (round < 2) {
+            y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+            y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        } else {
+            y0 = pa_bop3<PA_T3(PA_A ^ PA_B ^ PA_C)>((uint32_t)(p1 >> 32), x1, k0);
+            y2 = pa_bop3<PA_T3(PA_A ^ PA_B ^ PA_C)>((uint32_t)(p0 >> 32), x3, k1);
+        }
         x1 = (uint32_t)p1;
         x3 = (uint32_t)p0;
         x0 = y0;

@@ -143,7 +143,7 @@ struct PaBatchView {
     int ngroups;       // runs grouped by lattice shape for the sweeps
     const PaBlk *gcol[PA_MAX_GROUPS];
     uint32_t gncol[PA_MAX_GROUPS];
-    int gd[PA_MAX_GROUPS], gN[PA_MAX_GROUPS], gthreads[PA_MAX_GROUPS];
+    int gd[PA_MAX_GROUPS], gN[PA_MAX_GROUPS], gJ[PA_MAX_GROUPS], gthreads[PA_MAX_GROUPS];
     PaStepRecord *steprec; // batched anneal: [nruns][npoints]
     int npoints;
     hipStream_t stream;

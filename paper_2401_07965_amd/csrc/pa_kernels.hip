@@ -143,6 +143,16 @@ __device__ __forceinline__ void wave_vsum16(uint64_t c[16])
 
 __device__ __forceinline__ uint64_t jbit(uint32_t jb, int k) { return 0ull - (uint64_t)((jb >> k) & 1u); }
 
+// Unsatisfied-bond mask of a bond between words S and n: S ^ n, inverted for
+// an antiferromagnetic coupling (bit k of jb).
+template <bool J>
+__device__ __forceinline__ uint64_t bond(uint64_t S, uint64_t n, uint32_t jb, int k)
+{
+    if (!J)
+        return S ^ n;
+    return pa_bop3<PA_T3(PA_A ^ PA_B ^ PA_C)>(S, n, jbit(jb, k));
+}
+
 // Bit-plane decision of u < T for the undecided replicas of one word: plane
 // pair q of Philox(s, w, i, METRO<<28 | t<<8 | q) gives bits 31-2q and 30-2q of
 // every replica's uniform; a replica is decided at the first bit where u and
@@ -152,21 +162,40 @@ struct PlaneCtx {
     uint32_t t4, t8, t12;
 };
 
+// All-ones if bit b of the (wave-uniform) threshold t is set.
+__device__ __forceinline__ uint64_t tbit(uint32_t t, int b) { return 0ull - (uint64_t)((t >> b) & 1u); }
+
+// The threshold bit of every replica on plane b: the classes are disjoint, so
+// Tp = m4 ? T4_b : (m8 ? T8_b : m12 & T12_b).
+template <int D>
+__device__ __forceinline__ uint64_t plane_threshold(const PlaneCtx &pc, int b, uint64_t m4, uint64_t m8,
+                                                    uint64_t m12)
+{
+    constexpr int kSel = PA_T3((PA_A & PA_B) | (~PA_A & PA_C));
+    uint64_t t = m8 & tbit(pc.t8, b);
+    if (D == 3)
+        t = pa_bop3<kSel>(m8, tbit(pc.t8, b), m12 & tbit(pc.t12, b));
+    return pa_bop3<kSel>(m4, tbit(pc.t4, b), t);
+}
+
+// One plane: accept where u has 0 and the threshold 1; stay undecided where
+// they agree.
+__device__ __forceinline__ void plane_step(uint64_t P, uint64_t Tp, uint64_t &und, uint64_t &acc)
+{
+    acc |= pa_bop3<PA_T3(PA_A & ~PA_B & PA_C)>(und, P, Tp);
+    und = pa_bop3<PA_T3(PA_A & ~(PA_B ^ PA_C))>(und, P, Tp);
+}
+
+template <int D>
 __device__ __forceinline__ void plane_pair(const PlaneCtx &pc, uint32_t s, uint32_t q, uint64_t m4, uint64_t m8,
                                            uint64_t m12, uint64_t &und, uint64_t &acc)
 {
     const pa_philox_out o = pa_philox(pc.seed, pc.run_id, s, pc.w, pc.step, (PA_PURPOSE_METRO << 28) | (pc.t << 8) | q);
     const uint64_t P0 = (uint64_t)o.x0 | ((uint64_t)o.x1 << 32);
     const uint64_t P1 = (uint64_t)o.x2 | ((uint64_t)o.x3 << 32);
-    const int b0 = 31 - 2 * (int)q, b1 = b0 - 1;
-    uint64_t Tp = (m4 & (0ull - ((pc.t4 >> b0) & 1u))) | (m8 & (0ull - ((pc.t8 >> b0) & 1u))) |
-                  (m12 & (0ull - ((pc.t12 >> b0) & 1u)));
-    acc |= und & ~P0 & Tp;
-    und &= ~(P0 ^ Tp);
-    Tp = (m4 & (0ull - ((pc.t4 >> b1) & 1u))) | (m8 & (0ull - ((pc.t8 >> b1) & 1u))) |
-         (m12 & (0ull - ((pc.t12 >> b1) & 1u)));
-    acc |= und & ~P1 & Tp;
-    und &= ~(P1 ^ Tp);
+    const int b0 = 31 - 2 * (int)q;
+    plane_step(P0, plane_threshold<D>(pc, b0, m4, m8, m12), und, acc);
+    plane_step(P1, plane_threshold<D>(pc, b0 - 1, m4, m8, m12), und, acc);
 }
 
 // Per-wave queue of word-sites whose replicas are still undecided after the
@@ -201,6 +230,7 @@ __device__ __forceinline__ uint32_t queue_push(const WaveQueue &Q, uint32_t head
 }
 
 // One plane pair for up to 64 queued items; the still undecided go back.
+template <int D>
 __device__ __forceinline__ void queue_pass(const WaveQueue &Q, const PlaneCtx &pc, uint64_t *lat, uint32_t &head,
                                            uint32_t &cnt, uint32_t &calls)
 {
@@ -223,7 +253,7 @@ __device__ __forceinline__ void queue_pass(const WaveQueue &Q, const PlaneCtx &p
     if (act) {
         uint64_t acc = 0;
         ++calls;
-        plane_pair(pc, s, q, m4, m8, ~(m4 | m8), und, acc);
+        plane_pair<D>(pc, s, q, m4, m8, D == 3 ? ~(m4 | m8) : 0ull, und, acc);
         lat[s] ^= acc;
     }
     const bool again = act && und != 0 && q + 1 < 16;
@@ -233,8 +263,9 @@ __device__ __forceinline__ void queue_pass(const WaveQueue &Q, const PlaneCtx &p
 // One workgroup = one word column w (64 replicas) of one run; the lattice
 // stays in LDS for all theta sweeps, then each replica's unsatisfied-bond
 // count U and number of down spins are counted bit-sliced: E = 2U - dN,
-// M = N - 2 n_down.  theta = 0 only measures.
-template <int D>
+// M = N - 2 n_down.  theta = 0 only measures.  J: the run has +-J couplings
+// (per-site bond masks in LDS); without, every bond is ferromagnetic.
+template <int D, bool J>
 __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__restrict__ runs,
                                                             const PaBlk *__restrict__ map, int theta)
 {
@@ -258,7 +289,8 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
     uint64_t *g = rd.dv.spins[cur] + (size_t)w * N;
     for (int s = tid; s < N; s += bs) {
         lat[s] = g[s];
-        jl[s] = rd.dv.jmask[s];
+        if (J)
+            jl[s] = rd.dv.jmask[s];
     }
     __syncthreads();
 
@@ -271,6 +303,10 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
                    draw8 = (T8 > 0 && T8 < two32) ? ~0ull : 0ull,
                    draw12 = (T12 > 0 && T12 < two32) ? ~0ull : 0ull;
     const int half = L >> 1, nh = N >> 1, LL = L * L;
+    // floor(n / half) and floor(n / L) as one high multiply by ceil(2^32 / d):
+    // exact for n d < 2^32, and here n < 2^14, d <= 2^13
+    const uint32_t mhalf = half > 1 ? uni((uint32_t)(((1ull << 32) + (uint64_t)half - 1) / (uint64_t)half)) : 0u;
+    const uint32_t mL = uni((uint32_t)(((1ull << 32) + (uint64_t)L - 1) / (uint64_t)L));
     PlaneCtx pc;
     pc.seed = uni(rd.seed);
     pc.run_id = uni(rd.run_id);
@@ -291,17 +327,19 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
                 uint64_t und = 0, m4 = 0, m8 = 0;
                 uint32_t s = 0, q = 0;
                 if (k < nh) {
-                    const int row = k / half, m = k - row * half; // row = y + L z
-                    const int y = (D == 2) ? row : row % L;
-                    const int z = (D == 2) ? 0 : row / L;
+                    const int row = half > 1 ? (int)__umulhi((uint32_t)k, mhalf) : k; // row = y + L z
+                    const int m = k - row * half;
+                    const int z = (D == 2) ? 0 : (int)__umulhi((uint32_t)row, mL);
+                    const int y = row - z * L;
                     const int x = 2 * m + ((y + z + c) & 1);
                     s = (uint32_t)(x + L * row);
-                    const uint32_t jb = jl[s];
+                    const uint32_t jb = J ? (uint32_t)jl[s] : 0u;
                     const uint64_t S = lat[s];
-                    const uint64_t a0 = S ^ lat[x == L - 1 ? s - (L - 1) : s + 1] ^ jbit(jb, 0);
-                    const uint64_t a1 = S ^ lat[x == 0 ? s + (L - 1) : s - 1] ^ jbit(jb, D);
-                    const uint64_t a2 = S ^ lat[y == L - 1 ? s - L * (L - 1) : s + L] ^ jbit(jb, 1);
-                    const uint64_t a3 = S ^ lat[y == 0 ? s + L * (L - 1) : s - L] ^ jbit(jb, D + 1);
+                    // a_k: bond k unsatisfied (S ^ neighbour ^ [J = -1])
+                    const uint64_t a0 = bond<J>(S, lat[x == L - 1 ? s - (L - 1) : s + 1], jb, 0);
+                    const uint64_t a1 = bond<J>(S, lat[x == 0 ? s + (L - 1) : s - 1], jb, D);
+                    const uint64_t a2 = bond<J>(S, lat[y == L - 1 ? s - L * (L - 1) : s + L], jb, 1);
+                    const uint64_t a3 = bond<J>(S, lat[y == 0 ? s + L * (L - 1) : s - L], jb, D + 1);
                     // u = number of unsatisfied bonds among 2d; dE = 4(d - u)
                     uint64_t always, m12;
                     if (D == 2) {
@@ -311,8 +349,8 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
                         m8 = ~(s0 | s1 | c0 | c1);    // u == 0
                         m12 = 0;
                     } else {
-                        const uint64_t a4 = S ^ lat[z == L - 1 ? s - LL * (L - 1) : s + LL] ^ jbit(jb, 2);
-                        const uint64_t a5 = S ^ lat[z == 0 ? s + LL * (L - 1) : s - LL] ^ jbit(jb, 5);
+                        const uint64_t a4 = bond<J>(S, lat[z == L - 1 ? s - LL * (L - 1) : s + LL], jb, 2);
+                        const uint64_t a5 = bond<J>(S, lat[z == 0 ? s + LL * (L - 1) : s - LL], jb, 5);
                         const uint64_t sA = a0 ^ a1 ^ a2, cA = (a0 & a1) | (a2 & (a0 ^ a1));
                         const uint64_t sB = a3 ^ a4 ^ a5, cB = (a3 & a4) | (a5 & (a3 ^ a4));
                         const uint64_t ls = sA ^ sB, lc = sA & sB;
@@ -329,16 +367,16 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
                     und = (m4 & draw4) | (m8 & draw8) | (m12 & draw12);
                     for (; und != 0 && q < (uint32_t)kInlinePairs; ++q) {
                         ++calls;
-                        plane_pair(pc, s, q, m4, m8, m12, und, acc);
+                        plane_pair<D>(pc, s, q, m4, m8, m12, und, acc);
                     }
                     lat[s] = S ^ acc;
                 }
                 cnt = queue_push(Q, head, cnt, und != 0, s | (q << 16), und, m4, m8);
                 while (cnt >= 64u)
-                    queue_pass(Q, pc, lat, head, cnt, calls);
+                    queue_pass<D>(Q, pc, lat, head, cnt, calls);
             }
             while (cnt > 0u)
-                queue_pass(Q, pc, lat, head, cnt, calls);
+                queue_pass<D>(Q, pc, lat, head, cnt, calls);
             __syncthreads();
         }
     }
@@ -346,16 +384,16 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
     // measure: forward bonds once each, plus the down-spin count
     uint64_t ve[8] = {0, 0, 0, 0, 0, 0, 0, 0}, vm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int s = tid; s < N; s += bs) {
-        const int x = s % L;
-        const int row = s / L;
-        const int y = (D == 2) ? row : row % L;
-        const int z = (D == 2) ? 0 : row / L;
-        const uint32_t jb = jl[s];
+        const int row = (int)__umulhi((uint32_t)s, mL);
+        const int x = s - row * L;
+        const int z = (D == 2) ? 0 : (int)__umulhi((uint32_t)row, mL);
+        const int y = row - z * L;
+        const uint32_t jb = J ? (uint32_t)jl[s] : 0u;
         const uint64_t S = lat[s];
-        vadd8(ve, S ^ lat[x == L - 1 ? s - (L - 1) : s + 1] ^ jbit(jb, 0));
-        vadd8(ve, S ^ lat[y == L - 1 ? s - L * (L - 1) : s + L] ^ jbit(jb, 1));
+        vadd8(ve, bond<J>(S, lat[x == L - 1 ? s - (L - 1) : s + 1], jb, 0));
+        vadd8(ve, bond<J>(S, lat[y == L - 1 ? s - L * (L - 1) : s + L], jb, 1));
         if (D == 3)
-            vadd8(ve, S ^ lat[z == L - 1 ? s - LL * (L - 1) : s + LL] ^ jbit(jb, 2));
+            vadd8(ve, bond<J>(S, lat[z == L - 1 ? s - LL * (L - 1) : s + LL], jb, 2));
         vadd8(vm, S);
         g[s] = S;
     }
@@ -1463,10 +1501,14 @@ hipError_t sweep_launch(const PaBatchView &v, int g, int theta, int threads)
     if (v.gncol[g] == 0)
         return hipSuccess;
     const size_t lds = pa_sweep_lds_bytes(v.gN[g], threads);
-    if (v.gd[g] == 2)
-        k_sweep<2><<<v.gncol[g], threads, lds, v.stream>>>(v.runs, v.gcol[g], theta);
+    if (v.gd[g] == 2 && v.gJ[g])
+        k_sweep<2, true><<<v.gncol[g], threads, lds, v.stream>>>(v.runs, v.gcol[g], theta);
+    else if (v.gd[g] == 2)
+        k_sweep<2, false><<<v.gncol[g], threads, lds, v.stream>>>(v.runs, v.gcol[g], theta);
+    else if (v.gJ[g])
+        k_sweep<3, true><<<v.gncol[g], threads, lds, v.stream>>>(v.runs, v.gcol[g], theta);
     else
-        k_sweep<3><<<v.gncol[g], threads, lds, v.stream>>>(v.runs, v.gcol[g], theta);
+        k_sweep<3, false><<<v.gncol[g], threads, lds, v.stream>>>(v.runs, v.gcol[g], theta);
     return hipGetLastError();
 }
 
