@@ -28,11 +28,17 @@ if ROOT not in sys.path:
 D, L, R, THETA, BETA_F, POINTS, SEED = 2, 64, 100000, 10, 0.6, 201, 1
 SCHEMES = (("multinomial", 0), ("poisson", 1), ("nearest", 2), ("systematic", 3))
 
-# Roofline of the sweep kernel (integer VALU bound):
-# peak = 256 CUs x 64 int32 lanes/clock x 2.4 GHz.
+# Roofline of the sweep kernel (integer VALU bound).
+# peak = 256 CUs x 64 int32 lanes/clock x 2.4 GHz.  The achieved rate counts
+# the algorithmic 32-bit lane operations of the 2D ferromagnet sweep on gfx950:
+# each Philox4x32-10 call is 10 rounds of two 32x32->64 multiplies and two
+# three-input xors (40); consuming its two bit planes for a 64-replica word is
+# 2 planes x 2 halves x (threshold select 2 + accept 2 + undecided 1) = 20;
+# a word-site update is 4 bond xors x 2 halves (8), the three energy-change
+# classes (20), the initial accept/undecided masks (8) and the flip (2) = 38.
 PEAK_INT_OPS = 256 * 64 * 2.4e9
-OPS_PER_PHILOX = 120      # 80 for Philox4x32-10 + 40 to consume its two bit planes
-OPS_PER_SITE_UPDATE = 60  # 2D neighbour bonds, dE classes, accept mask, store (64 replicas)
+OPS_PER_PHILOX = 40 + 20   # generate a plane pair and decide 64 replicas on it
+OPS_PER_SITE_UPDATE = 38   # 2D, no couplings
 
 
 def betas():

@@ -132,7 +132,8 @@ uint64_t carve_run(const Geometry &g, char *base, PaDev *dv)
     d.anc = (uint32_t *)take(slots * 4);
     d.C = (uint64_t *)take(slots * 8);
     d.qhist = (unsigned long long *)take((uint64_t)(g.N + 1) * 8);
-    d.tiles = (PaScanTile *)take((uint64_t)((g.cap + PA_SCAN_TILE - 1) / PA_SCAN_TILE) * sizeof(PaScanTile));
+    // tile flags of the two prefix sums of a resampling (weights, copy numbers)
+    d.tiles = (PaScanTile *)take((uint64_t)((g.cap + PA_SCAN_TILE - 1) / PA_SCAN_TILE) * 2 * sizeof(PaScanTile));
     d.partial = (double *)take(chunks * 8);
     d.fam = (uint32_t *)take((uint64_t)g.R * 4);
     d.rec = (PaRecord *)take(sizeof(PaRecord));
@@ -249,7 +250,7 @@ uint64_t layout(const std::vector<Geometry> &geo, int max_points, char *base, Ba
     std::vector<char *> p_g;
     for (auto &gc : tb.gcol)
         p_g.push_back(take(sizeof(PaBlk) * gc.size()));
-    char *p_ticket = take(4);
+    char *p_ticket = take(8);
     char *p_steprec = take(sizeof(PaStepRecord) * (uint64_t)M * (uint64_t)(max_points > 0 ? max_points : 0));
     char *p_group = take(4ull * M);
     char *p_Ns = take(4ull * M);
@@ -547,7 +548,7 @@ pa_status pa_sweep(pa_ctx *c, int32_t theta)
         return fail(b, PA_E_INVAL, "more than 2^20 sweeps at one temperature");
     if (theta == 0)
         return PA_OK;
-    hipError_t e = pa_b_sweep(b->v, theta);
+    hipError_t e = pa_b_sweep(b->v, theta, b->sweeps);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_sweep");
     b->sweeps += (uint32_t)theta;
@@ -935,7 +936,7 @@ pa_status pa_batch_anneal(pa_batch *p, const double *betas, int32_t npoints, int
         if (e == hipSuccess)
             e = pa_b_resample(v, (int)scheme, 1);
         if (e == hipSuccess && theta > 0)
-            e = pa_b_sweep(v, theta);
+            e = pa_b_sweep(v, theta, 0u); // every run was just resampled
         if (e == hipSuccess)
             e = pa_b_observables(v, i);
     }

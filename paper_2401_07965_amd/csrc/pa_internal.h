@@ -42,6 +42,9 @@ struct PaRecord {
     double lnZ; // ln Z_0 + sum_k ln Q_k, Eq. (7)
     // observables (exact integer sums, then the finalised averages)
     unsigned long long sumE, sumE2, sumAbsM, sumM2, sumC2, families;
+    // accumulators of the observables pass; k_obs_final publishes them into
+    // the sums above and returns them to zero for the next pass
+    unsigned long long accE, accE2, accAbsM, accM2, accC2, accFam;
     double sumClnC;
     double e, e2, abs_m, m2, rho_t, S_f;
     double rule_dbeta, rule_alpha; // adaptive step: chosen dbeta and its overlap
@@ -138,7 +141,7 @@ struct PaBatchView {
     uint32_t ncol;
     const PaBlk *tile; // scan tiles, run-major
     uint32_t ntile;
-    uint32_t *ticket;  // scan tile ticket
+    uint32_t *ticket;  // tile tickets of the two prefix sums of a resampling
     int maxH;
     int ngroups;       // runs grouped by lattice shape for the sweeps
     const PaBlk *gcol[PA_MAX_GROUPS];
@@ -151,7 +154,7 @@ struct PaBatchView {
 
 // launchers (pa_kernels.hip); each returns the first launch error
 hipError_t pa_b_init(const PaBatchView &v);
-hipError_t pa_b_sweep(const PaBatchView &v, int theta);
+hipError_t pa_b_sweep(const PaBatchView &v, int theta, uint32_t t0); // t0: sweeps already done at this beta
 hipError_t pa_b_sweep_group(const PaBatchView &v, int g, int theta, int threads);
 hipError_t pa_b_reweight(const PaBatchView &v, double beta_next);
 hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze);

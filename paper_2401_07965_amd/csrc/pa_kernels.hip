@@ -79,6 +79,7 @@ __global__ void k_init_rec(const PaRunDesc *__restrict__ runs)
     rec->philox_calls = 0;
     rec->site_updates = 0;
     rec->attempts = 0;
+    rec->accE = rec->accE2 = rec->accAbsM = rec->accM2 = rec->accC2 = rec->accFam = 0;
     rec->lnq_hist[0] = rec->lnq_hist[1] = rec->lnq_hist[2] = 0.0;
     rec->S_f = log((double)rd.R0);
 }
@@ -186,16 +187,27 @@ __device__ __forceinline__ void plane_step(uint64_t P, uint64_t Tp, uint64_t &un
     und = pa_bop3<PA_T3(PA_A & ~(PA_B ^ PA_C))>(und, P, Tp);
 }
 
-template <int D>
-__device__ __forceinline__ void plane_pair(const PlaneCtx &pc, uint32_t s, uint32_t q, uint64_t m4, uint64_t m8,
-                                           uint64_t m12, uint64_t &und, uint64_t &acc)
+__device__ __forceinline__ pa_philox_out metro_philox(const PlaneCtx &pc, uint32_t s, uint32_t q)
 {
-    const pa_philox_out o = pa_philox(pc.seed, pc.run_id, s, pc.w, pc.step, (PA_PURPOSE_METRO << 28) | (pc.t << 8) | q);
+    return pa_philox(pc.seed, pc.run_id, s, pc.w, pc.step, (PA_PURPOSE_METRO << 28) | (pc.t << 8) | q);
+}
+
+template <int D>
+__device__ __forceinline__ void apply_pair(const PlaneCtx &pc, const pa_philox_out &o, uint32_t q, uint64_t m4,
+                                           uint64_t m8, uint64_t m12, uint64_t &und, uint64_t &acc)
+{
     const uint64_t P0 = (uint64_t)o.x0 | ((uint64_t)o.x1 << 32);
     const uint64_t P1 = (uint64_t)o.x2 | ((uint64_t)o.x3 << 32);
     const int b0 = 31 - 2 * (int)q;
     plane_step(P0, plane_threshold<D>(pc, b0, m4, m8, m12), und, acc);
     plane_step(P1, plane_threshold<D>(pc, b0 - 1, m4, m8, m12), und, acc);
+}
+
+template <int D>
+__device__ __forceinline__ void plane_pair(const PlaneCtx &pc, uint32_t s, uint32_t q, uint64_t m4, uint64_t m8,
+                                           uint64_t m12, uint64_t &und, uint64_t &acc)
+{
+    apply_pair<D>(pc, metro_philox(pc, s, q), q, m4, m8, m12, und, acc);
 }
 
 // Per-wave queue of word-sites whose replicas are still undecided after the
@@ -267,7 +279,7 @@ __device__ __forceinline__ void queue_pass(const WaveQueue &Q, const PlaneCtx &p
 // (per-site bond masks in LDS); without, every bond is ferromagnetic.
 template <int D, bool J>
 __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__restrict__ runs,
-                                                            const PaBlk *__restrict__ map, int theta)
+                                                            const PaBlk *__restrict__ map, int theta, uint32_t t0)
 {
     // dynamic LDS: lattice [N] u64 | queues [waves][3][kQueue] u64 | queue sites [waves][kQueue] u32 | jmask [N]
     extern __shared__ uint64_t lat[];
@@ -281,7 +293,7 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
         return;
     const int L = uni(rd.L), N = uni(rd.N);
     const int cur = uni(rec->cur);
-    const uint32_t step = uni(rec->step), t0 = uni(rec->sweeps);
+    const uint32_t step = uni(rec->step);
     const int tid = threadIdx.x, bs = blockDim.x, nwaves = bs >> 6;
     uint64_t *qbase = lat + N + (size_t)(tid >> 6) * 3 * kQueue;
     uint32_t *qsites = reinterpret_cast<uint32_t *>(lat + N + (size_t)nwaves * 3 * kQueue);
@@ -365,9 +377,20 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
                     }
                     uint64_t acc = always | (m4 & sure4) | (m8 & sure8) | (m12 & sure12);
                     und = (m4 & draw4) | (m8 & draw8) | (m12 & draw12);
-                    for (; und != 0 && q < (uint32_t)kInlinePairs; ++q) {
-                        ++calls;
-                        plane_pair<D>(pc, s, q, m4, m8, m12, und, acc);
+                    if (und != 0) {
+                        // nearly every site needs the first kInlinePairs pairs:
+                        // their Philox outputs are independent and computed together
+                        pa_philox_out o[kInlinePairs];
+#pragma unroll
+                        for (int k = 0; k < kInlinePairs; ++k)
+                            o[k] = metro_philox(pc, s, (uint32_t)k);
+#pragma unroll
+                        for (int k = 0; k < kInlinePairs; ++k)
+                            if (und != 0) {
+                                ++calls;
+                                apply_pair<D>(pc, o[k], (uint32_t)k, m4, m8, m12, und, acc);
+                                q = (uint32_t)k + 1;
+                            }
                     }
                     lat[s] = S ^ acc;
                 }
@@ -403,6 +426,10 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
             atomicAdd(&rec->philox_calls, (unsigned long long)tot);
         if (tid == 0)
             atomicAdd(&rec->site_updates, (unsigned long long)theta * (unsigned long long)N);
+        if (tid == 0 && w == 0) { // once per run; no block reads these during the launch
+            rec->sweeps = t0 + (uint32_t)theta;
+            rec->attempts += (unsigned long long)theta * (unsigned long long)N * (unsigned long long)Rlive;
+        }
     }
     uint64_t ce[16], cm[16];
 #pragma unroll
@@ -438,16 +465,6 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
 
 // The sweep counter advances after the sweeps (a separate launch, so that no
 // workgroup of the sweep reads a half-updated counter).
-__global__ void k_sweeps_add(const PaRunDesc *__restrict__ runs, int theta)
-{
-    const PaRunDesc &rd = runs[blockIdx.x];
-    PaRecord *rec = rd.dv.rec;
-    if (threadIdx.x == 0 && !frozen(rec)) {
-        rec->sweeps += (uint32_t)theta;
-        rec->attempts += (unsigned long long)theta * (unsigned long long)rd.N * rec->Rcur;
-    }
-}
-
 // ------------------------------------------------------------------ step 2: Q
 // Energy levels h = (E + dN) / 4: all energies of a run share E mod 4, since a
 // flip changes E by a multiple of 4.
@@ -757,6 +774,23 @@ __device__ __forceinline__ bool rep_ctx(const PaRunDesc *runs, const PaBlk *map,
 
 // Nearest integer: floor(tauhat) + [u S < (R W mod S) 2^32], u = x0 of
 // Philox(j, 0, i, RS_NI<<28).
+// Sampling variance, Eq. (5): each chunk sums (r_j - tauhat_j)^2 over its
+// replicas with a fixed per-thread stride and the block's fixed tree into
+// partial[chunk]; k_commit adds the partials in chunk order.
+__device__ __forceinline__ double sv_term(uint32_t r, uint64_t W, double S, double Rt)
+{
+    const double tau = ((double)W / S) * Rt;
+    const double dlt = (double)r - tau;
+    return dlt * dlt;
+}
+
+__device__ __forceinline__ void sv_store(const RepCtx &c, double acc, double *sd)
+{
+    const double t = pa_block_sum_f64(acc, sd);
+    if (threadIdx.x == 0)
+        c.rd->dv.partial[c.beg / PA_CHUNK] = t;
+}
+
 __global__ __launch_bounds__(kThreads) void k_counts_nearest(const PaRunDesc *__restrict__ runs,
                                                              const PaBlk *__restrict__ map)
 {
@@ -769,6 +803,8 @@ __global__ __launch_bounds__(kThreads) void k_counts_nearest(const PaRunDesc *__
     const uint64_t S = c.rec->S, Rt = (uint64_t)rd.R0;
     const uint32_t step = c.rec->step + 1;
     const int32_t *E = rd.dv.E[c.rec->cur];
+    __shared__ double sd[16];
+    double sv = 0.0;
     for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x) {
         const uint64_t W = weight_of(E[j], DN, hmin, rd.dv.wtab);
         const uint64_t a = Rt * W;
@@ -776,8 +812,11 @@ __global__ __launch_bounds__(kThreads) void k_counts_nearest(const PaRunDesc *__
         const uint64_t rho = a - qt * S;
         const pa_philox_out o = pa_philox(rd.seed, rd.run_id, (uint32_t)j, 0u, step, PA_PURPOSE_RS_NI << 28);
         const bool extra = ((pa_u128)o.x0 * S) < ((pa_u128)rho << 32);
-        rd.dv.r[j] = (uint32_t)qt + (extra ? 1u : 0u);
+        const uint32_t r = (uint32_t)qt + (extra ? 1u : 0u);
+        rd.dv.r[j] = r;
+        sv = sv + sv_term(r, W, (double)S, (double)Rt);
     }
+    sv_store(c, sv, sd);
 }
 
 // Poisson by inversion; tauhat > 32 is cut into ceil(tauhat/32) equal pieces,
@@ -794,6 +833,8 @@ __global__ __launch_bounds__(kThreads) void k_counts_poisson(const PaRunDesc *__
     const uint64_t S = c.rec->S, Rt = (uint64_t)rd.R0;
     const uint32_t step = c.rec->step + 1;
     const int32_t *E = rd.dv.E[c.rec->cur];
+    __shared__ double sd[16];
+    double sv = 0.0;
     for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x) {
         const uint64_t W = weight_of(E[j], DN, hmin, rd.dv.wtab);
         const double tau = ((double)W / (double)S) * (double)Rt;
@@ -820,7 +861,9 @@ __global__ __launch_bounds__(kThreads) void k_counts_poisson(const PaRunDesc *__
             tot += k;
         }
         rd.dv.r[j] = tot;
+        sv = sv + sv_term(tot, W, (double)S, (double)Rt);
     }
+    sv_store(c, sv, sd);
 }
 
 __global__ __launch_bounds__(kThreads) void k_weights(const PaRunDesc *__restrict__ runs,
@@ -864,11 +907,17 @@ __global__ __launch_bounds__(kThreads) void k_counts_systematic(const PaRunDesc 
     const uint64_t S = c.rec->S, Rt = (uint64_t)rd.R0;
     const uint32_t U = pa_philox(rd.seed, rd.run_id, 0u, 0u, c.rec->step + 1, PA_PURPOSE_RS_SYS << 28).x0;
     const uint64_t *C = rd.dv.C;
+    __shared__ double sd[16];
+    double sv = 0.0;
     for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x) {
-        const uint64_t hi = sys_below(C[j], Rt, S, U);
-        const uint64_t lo = j > 0 ? sys_below(C[j - 1], Rt, S, U) : 0;
-        rd.dv.r[j] = (uint32_t)(hi - lo);
+        const uint64_t cj = C[j], cp = j > 0 ? C[j - 1] : 0ull;
+        const uint64_t hi = sys_below(cj, Rt, S, U);
+        const uint64_t lo = j > 0 ? sys_below(cp, Rt, S, U) : 0;
+        const uint32_t r = (uint32_t)(hi - lo);
+        rd.dv.r[j] = r;
+        sv = sv + sv_term(r, cj - cp, (double)S, (double)Rt); // C is the inclusive sum of W
     }
+    sv_store(c, sv, sd);
 }
 
 __global__ __launch_bounds__(kThreads) void k_clear_counts(const PaRunDesc *__restrict__ runs,
@@ -916,8 +965,8 @@ __global__ __launch_bounds__(kThreads) void k_counts_multinomial(const PaRunDesc
     }
 }
 
-// Sampling variance, Eq. (5): chunk c of the run sums its replicas with a
-// fixed per-thread stride and the block's fixed tree into partial[c].
+// Sampling variance of the multinomial scheme (its copy numbers are complete
+// only after k_counts_multinomial).
 __global__ __launch_bounds__(kThreads) void k_sv_partial(const PaRunDesc *__restrict__ runs,
                                                           const PaBlk *__restrict__ map)
 {
@@ -931,20 +980,18 @@ __global__ __launch_bounds__(kThreads) void k_sv_partial(const PaRunDesc *__rest
     const double S = (double)c.rec->S, Rt = (double)rd.R0;
     const int32_t *E = rd.dv.E[c.rec->cur];
     double acc = 0.0;
-    for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x) {
-        const double tau = ((double)weight_of(E[j], DN, hmin, rd.dv.wtab) / S) * Rt;
-        const double dlt = (double)rd.dv.r[j] - tau;
-        acc = acc + dlt * dlt;
-    }
-    const double t = pa_block_sum_f64(acc, sd);
-    if (threadIdx.x == 0)
-        rd.dv.partial[c.beg / PA_CHUNK] = t;
+    for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x)
+        acc = acc + sv_term(rd.dv.r[j], weight_of(E[j], DN, hmin, rd.dv.wtab), S, Rt);
+    sv_store(c, acc, sd);
 }
 
 // Decoupled look-back scan (Merrill & Garland 2016) of each run's first
 // Rcur entries: tiles take their order from an atomic ticket over a
 // run-major tile map, so every tile a tile waits on (same run, lower index)
-// is already running.  Entries past Rcur count as 0.
+// is already running.  Entries past Rcur count as 0.  WHICH = 0: inclusive
+// sums of the weights C in place; WHICH = 1: exclusive sums P of the copy
+// numbers r, and with them the ancestor map anc[P_j + k] = j, k < r_j (kept
+// below the capacity; a resampling that overflows is not applied).
 template <typename T, bool INCLUSIVE, int WHICH>
 __global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const PaRunDesc *__restrict__ runs,
                                                           const PaBlk *__restrict__ map, uint32_t *ticket)
@@ -953,7 +1000,7 @@ __global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const PaRunDesc *__res
     __shared__ unsigned long long s_wave[PA_SCAN_THREADS / 64];
     __shared__ unsigned long long s_excl;
     if (threadIdx.x == 0)
-        s_tile = atomicAdd(ticket, 1u);
+        s_tile = atomicAdd(ticket + WHICH, 1u);
     __syncthreads();
     const PaBlk b = map[s_tile];
     const PaRunDesc &rd = runs[b.run];
@@ -966,7 +1013,7 @@ __global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const PaRunDesc *__res
     const T *in = WHICH == 0 ? (const T *)rd.dv.C : (const T *)rd.dv.r;
     T *out = WHICH == 0 ? (T *)rd.dv.C : (T *)rd.dv.P;
     unsigned long long *total = WHICH == 0 ? &rec->Ctot : &rec->Rnew;
-    PaScanTile *tiles = rd.dv.tiles;
+    PaScanTile *tiles = rd.dv.tiles + (WHICH ? ntiles : 0);
     const int64_t base = (int64_t)tile * PA_SCAN_TILE + (int64_t)threadIdx.x * PA_SCAN_ITEMS;
     unsigned long long v[PA_SCAN_ITEMS];
     unsigned long long run = 0;
@@ -1037,87 +1084,54 @@ __global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const PaRunDesc *__res
         const int64_t i = base + k;
         if (INCLUSIVE)
             acc += v[k];
-        if (i < n)
+        if (i < n) {
             out[i] = (T)acc;
+            if (WHICH == 1)
+                for (unsigned long long d = acc; d < acc + v[k] && d < (unsigned long long)rd.cap; ++d)
+                    rd.dv.anc[d] = (uint32_t)i;
+        }
         if (!INCLUSIVE)
             acc += v[k];
     }
 }
 
-__global__ void k_scan_prep(const PaRunDesc *__restrict__ runs)
+// A new resampling starts with a clean status (a frozen run stays frozen),
+// cleared tile flags for both prefix sums (weights, copy numbers) and their
+// tile tickets.
+__global__ void k_resample_prep(const PaRunDesc *__restrict__ runs, uint32_t *tickets)
 {
     const PaRunDesc &rd = runs[blockIdx.x];
+    PaRecord *rec = rd.dv.rec;
     const int64_t ntiles = (rd.cap + PA_SCAN_TILE - 1) / PA_SCAN_TILE;
-    for (int64_t t = threadIdx.x; t < ntiles; t += blockDim.x)
+    for (int64_t t = threadIdx.x; t < 2 * ntiles; t += blockDim.x)
         rd.dv.tiles[t].flag = 0u;
-}
-
-// A new resampling starts with a clean status (a frozen run stays frozen).
-__global__ void k_resample_prep(const PaRunDesc *__restrict__ runs)
-{
-    PaRecord *rec = runs[blockIdx.x].dv.rec;
     if (threadIdx.x == 0 && !frozen(rec)) {
         rec->status = 0;
         rec->skip = 0;
     }
+    if (blockIdx.x == 0 && threadIdx.x < 2)
+        tickets[threadIdx.x] = 0u;
 }
 
 // Capacity and extinction: a resampling that would not fit (or leave no
-// replica) is not applied; in batch mode the run is frozen from then on.
-__global__ void k_check(const PaRunDesc *__restrict__ runs, int freeze)
+// replica), a non-finite ln Q or an unfinished prefix sum is not applied.
+// Every kernel after the copy-number scan evaluates this from the same record
+// fields, so they agree without a separate pass; k_commit records it.
+__device__ __forceinline__ uint32_t resample_status(const PaRecord *rec, int64_t cap)
 {
-    const PaRunDesc &rd = runs[blockIdx.x];
-    PaRecord *rec = rd.dv.rec;
-    if (threadIdx.x != 0 || frozen(rec))
-        return;
     const uint64_t Rn = rec->Rnew;
     uint32_t st = rec->status & PA_ST_SCAN_TIMEOUT;
-    if (Rn > (uint64_t)rd.cap)
+    if (Rn > (uint64_t)cap)
         st |= PA_ST_CAPACITY;
     if (Rn == 0)
         st |= PA_ST_EXTINCT;
-    if (!(rec->lnQ == rec->lnQ) || rec->lnQ - rec->lnQ != 0.0)
+    const double q = rec->lnQ;
+    if (!(q == q) || q - q != 0.0)
         st |= PA_ST_NONFINITE;
-    rec->skip = st != 0u;
-    rec->status = (st != 0u && freeze) ? (st | PA_ST_FROZEN) : st;
+    return st;
 }
 
 // ------------------------------------------------------------------ apply
-__global__ __launch_bounds__(kThreads) void k_ancestors(const PaRunDesc *__restrict__ runs,
-                                                        const PaBlk *__restrict__ map)
-{
-    RepCtx c;
-    if (!rep_ctx(runs, map, &c) || c.rec->skip)
-        return;
-    const PaDev &dv = c.rd->dv;
-    for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x) {
-        const uint32_t n = dv.r[j], p = dv.P[j];
-        for (uint32_t k = 0; k < n; ++k)
-            dv.anc[p + k] = (uint32_t)j;
-    }
-}
-
-// New replica d takes energy, magnetisation and label of its ancestor.
-__global__ __launch_bounds__(kThreads) void k_gather_rep(const PaRunDesc *__restrict__ runs,
-                                                         const PaBlk *__restrict__ map)
-{
-    const PaBlk b = map[blockIdx.x];
-    const PaRunDesc &rd = runs[b.run];
-    PaRecord *rec = rd.dv.rec;
-    const int64_t Rn = (int64_t)rec->Rnew;
-    const int64_t beg = (int64_t)b.idx * PA_CHUNK;
-    if (frozen(rec) || rec->skip || beg >= Rn)
-        return;
-    const int64_t end = beg + PA_CHUNK < Rn ? beg + PA_CHUNK : Rn;
-    const int cur = rec->cur, nxt = cur ^ 1;
-    const PaDev &dv = rd.dv;
-    for (int64_t d = beg + threadIdx.x; d < end; d += blockDim.x) {
-        const uint32_t a = dv.anc[d];
-        dv.E[nxt][d] = dv.E[cur][a];
-        dv.M[nxt][d] = dv.M[cur][a];
-        dv.label[nxt][d] = dv.label[cur][a];
-    }
-}
 
 // Destination word column w takes the bits of its 64 ancestors.  Ancestors are
 // non-decreasing, so the column splits into runs of consecutive source bits
@@ -1135,7 +1149,7 @@ __global__ __launch_bounds__(kThreads) void k_gather_spins(const PaRunDesc *__re
     PaRecord *rec = rd.dv.rec;
     const int64_t Rnew = (int64_t)rec->Rnew;
     const uint32_t w = blk.idx;
-    if (frozen(rec) || rec->skip || (int64_t)w * 64 >= Rnew)
+    if (frozen(rec) || resample_status(rec, rd.cap) != 0u || (int64_t)w * 64 >= Rnew)
         return;
     const int N = rd.N;
     const int cur = rec->cur;
@@ -1146,6 +1160,11 @@ __global__ __launch_bounds__(kThreads) void k_gather_spins(const PaRunDesc *__re
         const int64_t d = 64 * (int64_t)w + b;
         const bool valid = d < Rnew;
         const uint32_t a = valid ? rd.dv.anc[d] : 0u;
+        if (valid) { // the replica's energy, magnetisation and label
+            rd.dv.E[cur ^ 1][d] = rd.dv.E[cur][a];
+            rd.dv.M[cur ^ 1][d] = rd.dv.M[cur][a];
+            rd.dv.label[cur ^ 1][d] = rd.dv.label[cur][a];
+        }
         const uint32_t ap = (uint32_t)__shfl_up((int)a, 1, 64);
         const bool start = valid && (b == 0 || a != ap + 1u || (a & 63u) == 0u);
         const uint64_t sm = __ballot(start);
@@ -1166,7 +1185,7 @@ __global__ __launch_bounds__(kThreads) void k_gather_spins(const PaRunDesc *__re
     const int nr = uni(s_nruns);
     const int nt = (int)blockDim.x;
     // kG sites per thread at a time: their loads are independent and in flight together
-    constexpr int kG = 4;
+    constexpr int kG = 8;
     for (int s0 = threadIdx.x; s0 < N; s0 += kG * nt) {
         uint64_t out[kG], v[kG];
 #pragma unroll
@@ -1184,10 +1203,10 @@ __global__ __launch_bounds__(kThreads) void k_gather_spins(const PaRunDesc *__re
                 last = sw;
             }
             const uint32_t len = uni(r_len[i]), sh = uni(r_shift[i]), b0 = uni(r_b0[i]);
-            const uint64_t mask = len >= 64 ? ~0ull : ((1ull << len) - 1ull);
+            const uint64_t mask = (len >= 64 ? ~0ull : ((1ull << len) - 1ull)) << b0;
 #pragma unroll
             for (int k = 0; k < kG; ++k)
-                out[k] |= ((v[k] >> sh) & mask) << b0;
+                out[k] = pa_bop3<PA_T3((PA_A & PA_B) | PA_C)>((v[k] >> sh) << b0, mask, out[k]);
         }
 #pragma unroll
         for (int k = 0; k < kG; ++k) {
@@ -1201,13 +1220,22 @@ __global__ __launch_bounds__(kThreads) void k_gather_spins(const PaRunDesc *__re
 // Completes an applied resampling: SV (Eq. (5)) from the partials in fixed
 // order, ln Z_hat += ln Q (Eq. (7)), the new beta and its thresholds, the
 // buffer swap and the step count.
-__global__ __launch_bounds__(kThreads) void k_commit(const PaRunDesc *__restrict__ runs)
+__global__ __launch_bounds__(kThreads) void k_commit(const PaRunDesc *__restrict__ runs, int freeze)
 {
     __shared__ double sd[16];
     const PaRunDesc &rd = runs[blockIdx.x];
     PaRecord *rec = rd.dv.rec;
-    if (frozen(rec) || rec->skip)
+    if (frozen(rec))
         return;
+    const uint32_t st = resample_status(rec, rd.cap);
+    __syncthreads(); // every thread has read the status before thread 0 writes it
+    if (st != 0u) {
+        if (threadIdx.x == 0) {
+            rec->skip = 1;
+            rec->status = freeze ? (st | PA_ST_FROZEN) : st;
+        }
+        return;
+    }
     const int64_t Rprev = (int64_t)rec->Rcur;
     const int nlive = (int)((Rprev + PA_CHUNK - 1) / PA_CHUNK);
     double v = 0.0;
@@ -1233,16 +1261,6 @@ __global__ __launch_bounds__(kThreads) void k_commit(const PaRunDesc *__restrict
 }
 
 // ------------------------------------------------------------------ step 4: observables
-__global__ void k_obs_prep(const PaRunDesc *__restrict__ runs)
-{
-    const PaRunDesc &rd = runs[blockIdx.x];
-    PaRecord *rec = rd.dv.rec;
-    if (frozen(rec))
-        return;
-    if (threadIdx.x == 0)
-        rec->sumE = rec->sumE2 = rec->sumAbsM = rec->sumM2 = rec->sumC2 = rec->families = 0;
-}
-
 __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restrict__ runs,
                                                       const PaBlk *__restrict__ map)
 {
@@ -1282,10 +1300,10 @@ __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restric
     sA = pa_block_sum_u64(sA, su);
     sM2 = pa_block_sum_u64(sM2, su);
     if (threadIdx.x == 0) {
-        atomicAdd(&c.rec->sumE, (unsigned long long)sE);
-        atomicAdd(&c.rec->sumE2, (unsigned long long)sE2);
-        atomicAdd(&c.rec->sumAbsM, (unsigned long long)sA);
-        atomicAdd(&c.rec->sumM2, (unsigned long long)sM2);
+        atomicAdd(&c.rec->accE, (unsigned long long)sE);
+        atomicAdd(&c.rec->accE2, (unsigned long long)sE2);
+        atomicAdd(&c.rec->accAbsM, (unsigned long long)sA);
+        atomicAdd(&c.rec->accM2, (unsigned long long)sM2);
     }
 }
 
@@ -1316,8 +1334,8 @@ __global__ __launch_bounds__(kThreads) void k_obs_fam(const PaRunDesc *__restric
     nf = pa_block_sum_u64(nf, su);
     cl = pa_block_sum_f64(cl, sd);
     if (threadIdx.x == 0) {
-        atomicAdd(&rec->sumC2, (unsigned long long)c2);
-        atomicAdd(&rec->families, (unsigned long long)nf);
+        atomicAdd(&rec->accC2, (unsigned long long)c2);
+        atomicAdd(&rec->accFam, (unsigned long long)nf);
         rd.dv.partial[b.idx] = cl;
     }
 }
@@ -1341,6 +1359,13 @@ __global__ __launch_bounds__(kThreads) void k_obs_final(const PaRunDesc *__restr
     if (threadIdx.x != 0)
         return;
     if (!fz) {
+        rec->sumE = rec->accE;
+        rec->sumE2 = rec->accE2;
+        rec->sumAbsM = rec->accAbsM;
+        rec->sumM2 = rec->accM2;
+        rec->sumC2 = rec->accC2;
+        rec->families = rec->accFam;
+        rec->accE = rec->accE2 = rec->accAbsM = rec->accM2 = rec->accC2 = rec->accFam = 0;
         const double n = (double)rd.N, r = (double)rec->Rcur;
         rec->sumClnC = t;
         rec->e = (double)(long long)rec->sumE / (n * r);
@@ -1496,19 +1521,19 @@ __global__ void k_set_beta(const PaRunDesc *__restrict__ runs, double beta, doub
     }
 }
 
-hipError_t sweep_launch(const PaBatchView &v, int g, int theta, int threads)
+hipError_t sweep_launch(const PaBatchView &v, int g, int theta, int threads, uint32_t t0)
 {
     if (v.gncol[g] == 0)
         return hipSuccess;
     const size_t lds = pa_sweep_lds_bytes(v.gN[g], threads);
     if (v.gd[g] == 2 && v.gJ[g])
-        k_sweep<2, true><<<v.gncol[g], threads, lds, v.stream>>>(v.runs, v.gcol[g], theta);
+        k_sweep<2, true><<<v.gncol[g], threads, lds, v.stream>>>(v.runs, v.gcol[g], theta, t0);
     else if (v.gd[g] == 2)
-        k_sweep<2, false><<<v.gncol[g], threads, lds, v.stream>>>(v.runs, v.gcol[g], theta);
+        k_sweep<2, false><<<v.gncol[g], threads, lds, v.stream>>>(v.runs, v.gcol[g], theta, t0);
     else if (v.gJ[g])
-        k_sweep<3, true><<<v.gncol[g], threads, lds, v.stream>>>(v.runs, v.gcol[g], theta);
+        k_sweep<3, true><<<v.gncol[g], threads, lds, v.stream>>>(v.runs, v.gcol[g], theta, t0);
     else
-        k_sweep<3, false><<<v.gncol[g], threads, lds, v.stream>>>(v.runs, v.gcol[g], theta);
+        k_sweep<3, false><<<v.gncol[g], threads, lds, v.stream>>>(v.runs, v.gcol[g], theta, t0);
     return hipGetLastError();
 }
 
@@ -1538,24 +1563,21 @@ hipError_t pa_b_init(const PaBatchView &v)
     k_init_labels<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
     hipError_t e = hipGetLastError();
     for (int g = 0; g < v.ngroups && e == hipSuccess; ++g)
-        e = sweep_launch(v, g, 0, v.gthreads[g]);
+        e = sweep_launch(v, g, 0, v.gthreads[g], 0u);
     return e;
 }
 
 hipError_t pa_b_sweep_group(const PaBatchView &v, int g, int theta, int threads)
 {
-    return sweep_launch(v, g, theta, threads);
+    return sweep_launch(v, g, theta, threads, 0u);
 }
 
-hipError_t pa_b_sweep(const PaBatchView &v, int theta)
+hipError_t pa_b_sweep(const PaBatchView &v, int theta, uint32_t t0)
 {
     hipError_t e = hipSuccess;
     for (int g = 0; g < v.ngroups && e == hipSuccess; ++g)
-        e = sweep_launch(v, g, theta, v.gthreads[g]);
-    if (e != hipSuccess)
-        return e;
-    k_sweeps_add<<<v.nruns, 64, 0, v.stream>>>(v.runs, theta);
-    return hipGetLastError();
+        e = sweep_launch(v, g, theta, v.gthreads[g], t0);
+    return e;
 }
 
 static hipError_t hist_launch(const PaBatchView &v)
@@ -1602,8 +1624,6 @@ hipError_t pa_b_check_candidate(const PaBatchView &v, double alpha_star, double 
 template <typename T, bool INCL, int WHICH>
 static hipError_t scan_launch(const PaBatchView &v)
 {
-    k_scan_prep<<<v.nruns, kThreads, 0, v.stream>>>(v.runs);
-    k_fill_u32<<<1, 64, 0, v.stream>>>(v.ticket, 1, 0u);
     k_scan<T, INCL, WHICH><<<v.ntile, PA_SCAN_THREADS, 0, v.stream>>>(v.runs, v.tile, v.ticket);
     return hipGetLastError();
 }
@@ -1611,7 +1631,7 @@ static hipError_t scan_launch(const PaBatchView &v)
 hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze)
 {
     hipError_t e;
-    k_resample_prep<<<v.nruns, 64, 0, v.stream>>>(v.runs);
+    k_resample_prep<<<v.nruns, kThreads, 0, v.stream>>>(v.runs, v.ticket);
     switch (scheme) {
     case 2:
         k_counts_nearest<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
@@ -1629,6 +1649,7 @@ hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze)
         } else {
             k_clear_counts<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
             k_counts_multinomial<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
+            k_sv_partial<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
         }
         break;
     default:
@@ -1636,20 +1657,15 @@ hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze)
     }
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
-    k_sv_partial<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
     if ((e = scan_launch<uint32_t, false, 1>(v)) != hipSuccess)
         return e;
-    k_check<<<v.nruns, 64, 0, v.stream>>>(v.runs, freeze);
-    k_ancestors<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
-    k_gather_rep<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
     k_gather_spins<<<v.ncol, kThreads, 0, v.stream>>>(v.runs, v.col);
-    k_commit<<<v.nruns, kThreads, 0, v.stream>>>(v.runs);
+    k_commit<<<v.nruns, kThreads, 0, v.stream>>>(v.runs, freeze);
     return hipGetLastError();
 }
 
 hipError_t pa_b_observables(const PaBatchView &v, int point)
 {
-    k_obs_prep<<<v.nruns, kThreads, 0, v.stream>>>(v.runs);
     k_obs_rep<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
     k_obs_fam<<<v.nfam, kThreads, 0, v.stream>>>(v.runs, v.fam);
     k_obs_final<<<v.nruns, kThreads, 0, v.stream>>>(v.runs, point >= 0 ? v.steprec : nullptr, v.npoints,
