@@ -41,6 +41,35 @@ OPS_PER_PHILOX = 40 + 20   # generate a plane pair and decide 64 replicas on it
 OPS_PER_SITE_UPDATE = 38   # 2D, no couplings
 
 
+COUNTER_PROFILE = os.path.join(ROOT, "profiles", "k_sweep_2d_L64_R1e5_counters.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2401_07965_amd", "csrc", f)
+                  for f in ("pa_kernels.hip", "pa_device.h", "pa_internal.h")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_counters():
+    """HBM traffic and VALU figures of the sweep from the committed counter
+    profile, or None when the kernel sources changed since it was taken."""
+    import re
+    try:
+        with open(COUNTER_PROFILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    vals = dict(re.findall(r"^- (\w+): (\S+)\s*$", text, re.M))
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return vals
+
+
 def betas():
     return [i * BETA_F / (POINTS - 1) for i in range(POINTS)]
 
@@ -353,6 +382,12 @@ def main():
             "traffic": None,
         },
     }
+    prof = profiled_counters()
+    if prof:
+        # HBM bytes per sweep launch (FETCH_SIZE, WRITE_SIZE scaled by a copy of known size)
+        out["roofline"]["traffic"] = float(prof["traffic_bytes_per_launch"])
+        out["roofline"]["traffic_unit"] = "bytes/launch"
+        out["roofline"]["valu_busy"] = float(prof["valu_busy"])
     if not a.no_rows:
         out["batched"] = batched_bench()
         out["learned"] = learned_bench()
