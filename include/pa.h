@@ -99,6 +99,9 @@ typedef struct {
     double rho_t;         /* Eq. (6): R sum_k n_k^2 = sum_k c_k^2 / R_i */
     double S_f;           /* family entropy -sum_k n_k ln n_k */
     double sv;            /* Eq. (5) of the latest resampling, over R_{i-1} */
+    int64_t sum_E3_hi;    /* sum of E^3 over replicas, exact: the signed 128-bit */
+    uint64_t sum_E3_lo;   /*   integer sum_E3_hi * 2^64 + sum_E3_lo */
+    double e3;            /* <E^3>/N^3 */
 } pa_obs;
 
 /* Host copy of a run's state (pa_export_state / pa_import_state).  Array

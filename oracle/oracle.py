@@ -284,7 +284,7 @@ def default_capacity(R):
 def population_observables(N, E, M, label, R0, sv):
     """Plain population averages (step 4 of Sec. 2) and the family statistics.
 
-    Exact integer sums, then: e = <E>/N, e2 = <E^2>/N^2, |m|, m^2, the family
+    Exact integer sums, then: e = <E>/N, e2 = <E^2>/N^2, e3 = <E^3>/N^3, |m|, m^2, the family
     measure rho_t = R sum_k n_k^2 of Eq. (6) with n_k = c_k / R (so
     rho_t = sum_k c_k^2 / R), the family entropy S_f = -sum_k n_k ln n_k and
     the sampling variance of the last resampling, Eq. (5).
@@ -294,6 +294,9 @@ def population_observables(N, E, M, label, R0, sv):
     M = np.asarray(M, np.int64)
     sumE = int(E.sum())
     sumE2 = int((E * E).sum())
+    # |E^3| < 2^47; chunks of 2^15 keep every partial sum inside int64
+    E3 = E * E * E
+    sumE3 = sum(int(E3[k:k + 32768].sum()) for k in range(0, R, 32768))
     sumAbsM = int(np.abs(M).sum())
     sumM2 = int((M * M).sum())
     c = np.bincount(np.asarray(label, np.int64), minlength=R0).astype(np.int64)
@@ -306,7 +309,8 @@ def population_observables(N, E, M, label, R0, sv):
     var = sumE2 / R - mean * mean
     m3 = float(np.mean((Ef - mean) ** 3))
     skew = m3 / var ** 1.5 if var > 0 else 0.0
-    return dict(R=R, sumE=sumE, sumE2=sumE2, sumAbsM=sumAbsM, sumM2=sumM2, sumC2=sumC2,
+    return dict(R=R, sumE=sumE, sumE2=sumE2, sumE3=sumE3, sumAbsM=sumAbsM, sumM2=sumM2, sumC2=sumC2,
                 families=int((c > 0).sum()), e=sumE / (N * R), e2=sumE2 / (N * N * R),
+                e3=sumE3 / (N * N * N * R),
                 abs_m=sumAbsM / (N * R), m2=sumM2 / (N * N * R), rho_t=rho_t, S_f=S_f, sv=sv,
                 E_mean=mean, E_var=var, E_skew=skew)

@@ -646,6 +646,9 @@ pa_status pa_observables(pa_ctx *c, pa_obs *out)
     out->rho_t = r.rho_t;
     out->S_f = r.S_f;
     out->sv = r.sv;
+    out->sum_E3_hi = (int64_t)r.sumE3[1];
+    out->sum_E3_lo = (uint64_t)r.sumE3[0];
+    out->e3 = r.e3;
     return PA_OK;
 }
 

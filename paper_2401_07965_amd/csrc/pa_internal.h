@@ -45,6 +45,9 @@ struct PaRecord {
     // accumulators of the observables pass; k_obs_final publishes them into
     // the sums above and returns them to zero for the next pass
     unsigned long long accE, accE2, accAbsM, accM2, accC2, accFam;
+    // sum of E^3 as a signed 128-bit integer (two's complement, low word first)
+    unsigned long long sumE3[2], accE3[2];
+    double e3;
     double sumClnC;
     double e, e2, abs_m, m2, rho_t, S_f;
     double rule_dbeta, rule_alpha; // adaptive step: chosen dbeta and its overlap

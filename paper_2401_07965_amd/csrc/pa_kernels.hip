@@ -80,6 +80,7 @@ __global__ void k_init_rec(const PaRunDesc *__restrict__ runs)
     rec->site_updates = 0;
     rec->attempts = 0;
     rec->accE = rec->accE2 = rec->accAbsM = rec->accM2 = rec->accC2 = rec->accFam = 0;
+    rec->accE3[0] = rec->accE3[1] = 0;
     rec->lnq_hist[0] = rec->lnq_hist[1] = rec->lnq_hist[2] = 0.0;
     rec->S_f = log((double)rd.R0);
 }
@@ -1270,7 +1271,7 @@ __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restric
         return;
     const PaDev &dv = c.rd->dv;
     const int cur = c.rec->cur;
-    uint64_t sE = 0, sE2 = 0, sA = 0, sM2 = 0;
+    uint64_t sE = 0, sE2 = 0, sA = 0, sM2 = 0, sE3 = 0; // sE3: int64 bits (|sum| < 2^63 per block)
     const int lane = threadIdx.x & 63;
     for (int64_t base = c.beg; base < c.end; base += blockDim.x) {
         const int64_t d = base + threadIdx.x;
@@ -1280,6 +1281,7 @@ __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restric
             const int64_t e = dv.E[cur][d], m = dv.M[cur][d];
             sE += (uint64_t)e;
             sE2 += (uint64_t)(e * e);
+            sE3 += (uint64_t)(e * e * e);
             sA += (uint64_t)(m < 0 ? -m : m);
             sM2 += (uint64_t)(m * m);
             lab = dv.label[cur][d];
@@ -1299,7 +1301,13 @@ __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restric
     sE2 = pa_block_sum_u64(sE2, su);
     sA = pa_block_sum_u64(sA, su);
     sM2 = pa_block_sum_u64(sM2, su);
+    sE3 = pa_block_sum_u64(sE3, su);
     if (threadIdx.x == 0) {
+        // 128-bit add of the block's signed sum: low word, then the high word
+        // with the carry out of the low word (order-free, hence exact)
+        const unsigned long long lo = sE3, hi = (long long)sE3 < 0 ? ~0ull : 0ull;
+        const unsigned long long old = atomicAdd(&c.rec->accE3[0], lo);
+        atomicAdd(&c.rec->accE3[1], hi + (old + lo < old ? 1ull : 0ull));
         atomicAdd(&c.rec->accE, (unsigned long long)sE);
         atomicAdd(&c.rec->accE2, (unsigned long long)sE2);
         atomicAdd(&c.rec->accAbsM, (unsigned long long)sA);
@@ -1340,6 +1348,19 @@ __global__ __launch_bounds__(kThreads) void k_obs_fam(const PaRunDesc *__restric
     }
 }
 
+// A signed 128-bit integer (two's complement words) to double: magnitude
+// from its two non-negative words, so no cancellation between them.
+__device__ __forceinline__ double i128_to_double(unsigned long long lo, unsigned long long hi)
+{
+    const bool neg = (long long)hi < 0;
+    if (neg) {
+        lo = ~lo + 1ull;
+        hi = ~hi + (lo == 0ull ? 1ull : 0ull);
+    }
+    const double m = (double)hi * 18446744073709551616.0 + (double)lo;
+    return neg ? -m : m;
+}
+
 // Averages of step 4 and the family statistics: rho_t = sum_k c_k^2 / R
 // (Eq. (6) with n_k = c_k / R), S_f = ln R - (1/R) sum_k c_k ln c_k.  In a
 // batched anneal the row of temperature point `point` is written too.
@@ -1366,7 +1387,11 @@ __global__ __launch_bounds__(kThreads) void k_obs_final(const PaRunDesc *__restr
         rec->sumC2 = rec->accC2;
         rec->families = rec->accFam;
         rec->accE = rec->accE2 = rec->accAbsM = rec->accM2 = rec->accC2 = rec->accFam = 0;
+        rec->sumE3[0] = rec->accE3[0];
+        rec->sumE3[1] = rec->accE3[1];
+        rec->accE3[0] = rec->accE3[1] = 0;
         const double n = (double)rd.N, r = (double)rec->Rcur;
+        rec->e3 = i128_to_double(rec->sumE3[0], rec->sumE3[1]) / (n * n * n * r);
         rec->sumClnC = t;
         rec->e = (double)(long long)rec->sumE / (n * r);
         rec->e2 = (double)(long long)rec->sumE2 / (n * n * r);

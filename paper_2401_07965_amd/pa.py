@@ -31,7 +31,8 @@ class pa_obs(ctypes.Structure):
                 ("sum_M2", ctypes.c_int64), ("sum_c2", ctypes.c_int64),
                 ("families", ctypes.c_int64), ("e", ctypes.c_double), ("e2", ctypes.c_double),
                 ("abs_m", ctypes.c_double), ("m2", ctypes.c_double), ("rho_t", ctypes.c_double),
-                ("S_f", ctypes.c_double), ("sv", ctypes.c_double)]
+                ("S_f", ctypes.c_double), ("sv", ctypes.c_double),
+                ("sum_E3_hi", ctypes.c_int64), ("sum_E3_lo", ctypes.c_uint64), ("e3", ctypes.c_double)]
 
 
 class pa_host_state(ctypes.Structure):
@@ -241,7 +242,9 @@ def pa_observables(ctx, wait=True):
         return None
     o = pa_obs()
     _check(lib().pa_observables(ctx, ctypes.byref(o)), ctx)
-    return {name: getattr(o, name) for name, _ in pa_obs._fields_}
+    out = {name: getattr(o, name) for name, _ in pa_obs._fields_}
+    out["sum_E3"] = (out.pop("sum_E3_hi") << 64) + out.pop("sum_E3_lo")
+    return out
 
 
 def pa_free_energy(ctx):

@@ -41,9 +41,10 @@ def compare_observables(g, o, where=""):
     b = o.observables()
     assert a["R"] == b["R"], where
     assert a["sum_E"] == b["sumE"] and a["sum_E2"] == b["sumE2"], where
+    assert a["sum_E3"] == b["sumE3"], (a["sum_E3"], b["sumE3"], where)
     assert a["sum_absM"] == b["sumAbsM"] and a["sum_M2"] == b["sumM2"], where
     assert a["sum_c2"] == b["sumC2"] and a["families"] == b["families"], where
-    for k in ("e", "e2", "abs_m", "m2", "rho_t", "S_f"):
+    for k in ("e", "e2", "e3", "abs_m", "m2", "rho_t", "S_f"):
         assert rel_ok(a[k], b[k]), (k, a[k], b[k], where)
     assert rel_ok(a["sv"], b["sv"], 1e-9) or abs(a["sv"] - b["sv"]) < 1e-14, (a["sv"], b["sv"])
     return a

@@ -45,6 +45,18 @@ def test_shapes_and_edge_sizes(d, L, R):
         g.close()
 
 
+@pytest.mark.parametrize("d,L,kind,R,scheme", [(2, 128, "fm", 130, O.NEAREST_INT),
+                                                (2, 128, "ea", 65, O.POISSON),
+                                                (3, 24, "ea", 70, O.SYSTEMATIC),
+                                                (3, 24, "fm", 64, O.MULTINOMIAL)])
+def test_largest_lattices(d, L, kind, R, scheme):
+    """The largest lattices one workgroup holds in LDS: N = 16384 (2D L = 128)
+    and 13824 (3D L = 24), with and without couplings."""
+    J = ea_couplings(d, L, 17) if kind == "ea" else None
+    g, _ = run_pair(d, L, R, scheme, schedule(1.0, 4), 2, seed=4, run_id=scheme, J=J)
+    g.close()
+
+
 def test_large_steps_and_poisson_pieces():
     # few, large steps: broad weights, tauhat > 32 for the lowest energies
     for scheme in SCHEMES:

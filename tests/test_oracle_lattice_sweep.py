@@ -153,3 +153,26 @@ def test_sweeps_sample_boltzmann(d, L, kind, beta):
     dof = int(keep.sum()) - 1
     # chi^2 with dof degrees of freedom: mean dof, sd sqrt(2 dof)
     assert chi2 < dof + 6 * math.sqrt(2 * dof) + 10, (chi2, dof)
+
+
+@pytest.mark.parametrize("d,L,kind,beta", [(2, 4, "fm", 0.4), (2, 4, "ea", 0.8)])
+def test_population_energy_moments_match_exact(d, L, kind, beta):
+    """The observables' <E>, <E^2>, <E^3> of an equilibrated population agree with
+    the exact canonical moments from the density of states (brute force) within
+    six standard errors; a dropped term or a wrong power fails this."""
+    J = O.ferromagnet(d, L) if kind == "fm" else ea_couplings(d, L, 21)
+    R = 8192
+    N = L ** d
+    rows = np.arange(R)
+    spins, E, _ = O.init_rows(d, L, rows, 9, 0, J)
+    O.sweep_rows(d, L, J, rows, spins, E, 9, 0, 1, 0, 60, beta)
+    M = spins.astype(np.int64).sum(axis=1)
+    obs = O.population_observables(N, E, M, np.arange(R, dtype=np.uint32), R, 0.0)
+    dos = exact.brute_force(d, L, J)
+    lz = exact.lnZ_from_dos(dos, beta)
+    mom = {k: sum(g * e ** k * math.exp(-beta * e - lz) for e, g in dos.items()) for k in range(7)}
+    for k, key, scale in ((1, "e", N), (2, "e2", N ** 2), (3, "e3", N ** 3)):
+        sd = math.sqrt((mom[2 * k] - mom[k] ** 2) / R)
+        assert abs(obs[key] * scale - mom[k]) < 6 * sd + 1e-9, (k, obs[key] * scale, mom[k], sd)
+    # the exact integer sums behind them
+    assert obs["sumE3"] == sum(int(e) ** 3 for e in E.tolist())
