@@ -9,8 +9,9 @@ systematic; run_id = scheme index, seed 1).  Synthetic lattices, seeded.
 
 One step = one temperature step of all four runs: reweight (Q of Eq. (1)),
 resample (copy numbers, prefix sums, gather), theta sweeps, observables.
-``value`` = spin-flip attempts (theta N R_i summed over the runs) per ns of
-wall time over the timed steps, inputs resident in HBM throughout.
+The runs are independent and each has its own stream, so their kernels
+overlap.  ``value`` = spin-flip attempts (theta N R_i summed over the runs)
+per ns of wall time over the timed steps, inputs resident in HBM throughout.
 
 Prints one JSON line.  Only one GPU is used; --gpus above 1 is refused.
 """
@@ -74,21 +75,27 @@ def betas():
     return [i * BETA_F / (POINTS - 1) for i in range(POINTS)]
 
 
-def make_runs(pa):
-    return [pa.PARun(D, L, R, seed=SEED, run_id=rid) for _, rid in SCHEMES]
+def make_runs(pa, streams=None):
+    """The four runs; each on its own stream when streams are given (the runs are
+    independent, so one run's small resampling kernels overlap another's sweep)."""
+    streams = streams or [None] * len(SCHEMES)
+    return [pa.PARun(D, L, R, seed=SEED, run_id=rid, stream=st) for (_, rid), st in zip(SCHEMES, streams)]
 
 
 def gpu_bench(steps, warmup):
-    """Times `steps` temperature steps of the four runs.  Every call inside the
-    timed region is deferred (nothing waits for the device); the sweep and the
-    reweight + resample of each run are bracketed by HIP events on the run's
-    stream.  Attempts and work counters come from the device records."""
+    """Times `steps` temperature steps of the four runs, each run on its own
+    stream.  Every call inside the timed region is deferred (nothing waits for
+    the device); the sweep and the reweight + resample of each run are
+    bracketed by HIP events on the run's stream.  Launches of different runs
+    overlap, so kernel time is the union of those intervals over the four
+    streams (the time during which that kernel was running).  Attempts and
+    work counters come from the device records."""
     import torch
     from paper_2401_07965_amd import pa
     pa.lib()
     sched = betas()
-    stream = torch.cuda.current_stream()
-    state = {"i": 0, "runs": make_runs(pa)}
+    streams = [torch.cuda.Stream() for _ in SCHEMES]  # default priority
+    state = {"i": 0, "runs": make_runs(pa, streams)}
     keys = ("philox_calls", "site_updates", "spin_attempts")
     done = dict.fromkeys(keys, 0)  # counters of runs closed inside the window
     Rsum = {"start": 0, "end": 0}
@@ -103,12 +110,12 @@ def gpu_bench(steps, warmup):
                         done[k] += c[k]
                     Rsum["end"] += g.observables()["R"]
                 g.close()
-            state["runs"] = make_runs(pa)
+            state["runs"] = make_runs(pa, streams)
             if acc is not None:
                 Rsum["start"] += R * len(SCHEMES)
             i = 1
         state["i"] = i
-        for (name, rid), g in zip(SCHEMES, state["runs"]):
+        for (name, rid), g, stream in zip(SCHEMES, state["runs"], streams):
             if acc is None:
                 g.reweight(sched[i], wait=False)
                 g.resample(rid, wait=False)
@@ -131,6 +138,8 @@ def gpu_bench(steps, warmup):
     Rsum["start"] += sum(g.observables()["R"] for g in state["runs"])
     acc = []
     torch.cuda.synchronize()
+    ref = torch.cuda.Event(enable_timing=True)
+    ref.record(streams[0])
     t0 = time.perf_counter()
     for _ in range(steps):
         one_step(acc)
@@ -146,17 +155,71 @@ def gpu_bench(steps, warmup):
     for b in base:
         for k in keys:
             tot[k] -= b[k]
-    sweep_ms = [e[1].elapsed_time(e[2]) for e in acc]
-    resample_ms = [e[0].elapsed_time(e[1]) for e in acc]
+    sweep_iv = [(ref.elapsed_time(e[1]), ref.elapsed_time(e[2])) for e in acc]
+    resample_iv = [(ref.elapsed_time(e[0]), ref.elapsed_time(e[1])) for e in acc]
+    iso = isolated_steps(state, streams, sched, ISO_STEPS)
     for g in state["runs"]:
         g.close()
     attempts = tot["spin_attempts"]
     new_replicas = attempts // (THETA * L ** D)
     # replicas before each resampling: the new ones, shifted by one step
     old_replicas = new_replicas + Rsum["start"] - Rsum["end"]
-    return dict(elapsed=elapsed, attempts=attempts, sweep_ms=sweep_ms, calls=tot["philox_calls"],
-                updates=tot["site_updates"], resample_s=sum(resample_ms) / 1e3,
+    return dict(elapsed=elapsed, attempts=attempts, sweep_ms=[b - a for a, b in sweep_iv], iso=iso,
+                sweep_union_s=union_length(sweep_iv) / 1e3, calls=tot["philox_calls"],
+                updates=tot["site_updates"], resample_s=union_length(resample_iv) / 1e3,
                 resample_bytes=resample_bytes(old_replicas, new_replicas))
+
+
+ISO_STEPS = 6
+
+
+def isolated_steps(state, streams, sched, nsteps):
+    """After the timed region (untimed): `nsteps` more steps with one run at a
+    time on the device, HIP events around its reweight + resample and its
+    sweep.  Gives the per-launch sweep time and the resampling rate without
+    the other runs' kernels alongside."""
+    import torch
+    sweep_ms, res_ms, res_bytes, attempts = [], [], 0.0, 0
+    i = state["i"]
+    for _ in range(nsteps):
+        i += 1
+        if i == POINTS:
+            break
+        for (name, rid), g, stream in zip(SCHEMES, state["runs"], streams):
+            R_old = g.observables()["R"]
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record(stream)
+            g.reweight(sched[i], wait=False)
+            g.resample(rid, wait=False)
+            ev[1].record(stream)
+            g.sweep(THETA)
+            ev[2].record(stream)
+            R_new = g.observables()["R"]  # waits for the stream
+            res_ms.append(ev[0].elapsed_time(ev[1]))
+            sweep_ms.append(ev[1].elapsed_time(ev[2]))
+            res_bytes += resample_bytes(R_old, R_new)
+            attempts += THETA * L ** D * R_new
+    if not sweep_ms:
+        return None
+    return {"steps": len(sweep_ms) // len(SCHEMES),
+            "sweep_attempts_per_ns": attempts / (sum(sweep_ms) * 1e-3) / 1e9,
+            "sweep_avg_launch_ms": sum(sweep_ms) / len(sweep_ms),
+            "resample_GB_per_s": res_bytes / (sum(res_ms) * 1e-3) / 1e9}
+
+
+def union_length(intervals):
+    """Total length of the union of (start, end) intervals."""
+    tot, cur_a, cur_b = 0.0, None, None
+    for a, b in sorted(intervals):
+        if cur_b is None or a > cur_b:
+            if cur_b is not None:
+                tot += cur_b - cur_a
+            cur_a, cur_b = a, b
+        else:
+            cur_b = max(cur_b, b)
+    if cur_b is not None:
+        tot += cur_b - cur_a
+    return tot
 
 
 def resample_bytes(R_old, R_new):
@@ -345,7 +408,8 @@ def main():
         sys.exit(2)
     r = gpu_bench(a.steps, a.warmup)
     value = r["attempts"] / r["elapsed"] / 1e9
-    sweep_s = sum(r["sweep_ms"]) / 1e3
+    # the sweep kernel's time: union of its launches on the four streams
+    sweep_s = r["sweep_union_s"]
     avg_launch = sweep_s / len(r["sweep_ms"])
     ops = OPS_PER_PHILOX * r["calls"] + OPS_PER_SITE_UPDATE * r["updates"]
     achieved = ops / sweep_s if r["calls"] else None
@@ -369,7 +433,10 @@ def main():
             "dim": D, "L": L, "R": R, "theta": THETA, "runs_per_step": len(SCHEMES),
         },
         "sweep_attempts_per_ns": r["attempts"] / sweep_s / 1e9,
-        "resample_GB_per_s": r["resample_bytes"] / r["resample_s"] / 1e9,
+        # reweight + resample rate with one run on the device at a time (the
+        # concurrent runs' sweeps stretch its intervals inside the timed region)
+        "resample_GB_per_s": r["iso"]["resample_GB_per_s"] if r["iso"] else None,
+        "isolated": r["iso"],
         "philox_calls_per_attempt": (r["calls"] / (64.0 * r["updates"])) if r["updates"] else None,
         "roofline": {
             "kernel": "k_sweep<2>",
@@ -379,6 +446,8 @@ def main():
             "unit": "Tops/s (int32)",
             "frac": achieved / PEAK_INT_OPS if achieved else None,
             "avg_launch_ms": avg_launch * 1e3,
+            "concurrent_streams": len(SCHEMES),
+            "launch_span_ms": sum(r["sweep_ms"]) / len(r["sweep_ms"]),
             "traffic": None,
         },
     }

@@ -72,8 +72,8 @@ struct PaScanTile {
     uint32_t flag, pad;
 };
 
-#define PA_SCAN_THREADS 256
-#define PA_SCAN_ITEMS 8
+#define PA_SCAN_THREADS 512
+#define PA_SCAN_ITEMS 16
 #define PA_SCAN_TILE (PA_SCAN_THREADS * PA_SCAN_ITEMS)
 #define PA_CHUNK 256   // replicas (or families) per workgroup of the per-replica kernels
 #define PA_HCHUNK 4096 // replicas per workgroup of the energy histogram (LDS-private counts)
