@@ -29,7 +29,7 @@ if ROOT not in sys.path:
 D, L, R, THETA, BETA_F, POINTS, SEED = 2, 64, 100000, 10, 0.6, 201, 1
 SCHEMES = (("multinomial", 0), ("poisson", 1), ("nearest", 2), ("systematic", 3))
 
-# Roofline of the sweep kernel (integer VALU bound, see DESIGN.md).
+# Roofline of the sweep kernel (integer VALU bound).
 # peak = 256 CUs x 64 int32 lanes/clock x 2.4 GHz.  The achieved rate counts
 # the algorithmic 32-bit lane operations of the 2D ferromagnet sweep on gfx950:
 # each Philox4x32-10 call is 10 rounds of two 32x32->64 multiplies and two
@@ -223,7 +223,7 @@ def union_length(intervals):
 
 
 def resample_bytes(R_old, R_new):
-    """Algorithmic HBM bytes of reweighting and resampling (see DESIGN.md): per
+    """Algorithmic HBM bytes of reweighting and resampling: per
     old replica the energy read and the copy number / offset writes and reads;
     per new replica the spins read and written (2 N/8 bytes) plus energy,
     magnetisation and label read and written."""
@@ -292,7 +292,7 @@ def learned_bench(theta=10, scheme=3, astar=0.7, dmax=0.2, beta_f=3.0):
     """Learned-schedule workload: 3D +-J glass L = 16.  The model is trained on
     the GPU from rule-driven anneals of 8 other disorder samples at R = 10^4;
     then the evaluation sample is annealed at R = 10^6 (and 10^4) with the
-    rule alone and with the learned step (exact judge + rule fallback)."""
+    rule alone and with the learned step (exact overlap check + rule fallback)."""
     import numpy as np
     import torch
     from oracle import mlp as Mo  # parameter initialisation only (seeded uniform)
@@ -404,7 +404,7 @@ def main():
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
-              "(the multi-GPU split is described in DESIGN.md, not built)", file=sys.stderr)
+              "(this library runs one GPU; sharding across GPUs is not built)", file=sys.stderr)
         sys.exit(2)
     r = gpu_bench(a.steps, a.warmup)
     value = r["attempts"] / r["elapsed"] / 1e9

@@ -292,7 +292,7 @@ const char *pa_batch_last_error(const pa_batch *b);
 
 /* ---------------------------------------------------------------------------
  * Learned temperature steps (not in the paper; the overlap rule above stays
- * the judge and the fallback).  A network 8 -> 64 -> 64 -> 1 with tanh hidden
+ * the arbiter and the fallback).  A network 8 -> 64 -> 64 -> 1 with tanh hidden
  * layers maps population statistics to a proposed ln(dbeta):
  *   inputs  beta, <E>/N, sd(E)/sqrt(N), skewness of E, the last three ln Q
  *           (Eq. (1)) divided by N, family entropy / ln R;

@@ -2,7 +2,7 @@
 
 Not part of the paper: a small network proposes the next inverse-temperature
 step from population statistics; the exact overlap rule (oracle/schedule.py)
-stays as its judge and fallback.  This module is the plain float64 version
+stays as its arbiter and fallback.  This module is the plain float64 version
 of everything the GPU computes for it, pinned by finite differences:
 
 * features of a population (8 numbers): beta, <E>/N, sd(E)/sqrt(N),

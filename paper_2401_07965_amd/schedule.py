@@ -2,7 +2,7 @@
 
 ``anneal_adaptive`` runs one population-annealing anneal whose temperature
 steps come either from the exact overlap rule (pa_step_rule) or from the
-learned model with the rule as judge and fallback (pa_step_learned); it can
+learned model with the rule as arbiter and fallback (pa_step_learned); it can
 record (features, ln dbeta_rule) pairs for training the model.  Every step
 runs in the library's kernels; this module only sequences the calls.
 """

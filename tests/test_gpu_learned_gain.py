@@ -4,7 +4,7 @@
 trained on the GPU from plain rule-driven anneals of six other disorder
 samples; on the evaluation sample, 8 independent anneals per schedule.  Both
 schedules keep the overlap alpha >= alpha* at every step (the learned one
-through the exact judge), so their free-energy errors must agree within the
+through the exact overlap check), so their free-energy errors must agree within the
 run-to-run spread, while the learned one spends less time choosing steps."""
 import math
 

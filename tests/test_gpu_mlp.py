@@ -1,7 +1,7 @@
 """GPU tests of the learned temperature-step model: gradients and Adam steps
 of the float32 training kernels against the float64 oracle, bfloat16
 inference against the oracle's bfloat16 emulation, the model inputs of a
-population, and the exact judge of a proposal."""
+population, and the exact check of a proposal."""
 import math
 
 import numpy as np
@@ -82,7 +82,7 @@ def test_bf16_inference_matches_emulation():
     m.close()
 
 
-def test_features_and_learned_judge():
+def test_features_and_learned_check():
     from paper_2401_07965_amd import pa
     betas = schedule(0.6, 7)
     g, o = run_pair(2, 8, 1000, O.NEAREST_INT, betas, 4, observables=True)
