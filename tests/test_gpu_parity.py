@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 SCHEMES = [O.MULTINOMIAL, O.POISSON, O.NEAREST_INT, O.SYSTEMATIC]
 
 
-def test_config1_every_step():
+def test_2d_L8_R1000_every_step():
     """2D Ising FM, L = 8, R = 1000, beta 0 -> 1 in 101 points, theta = 10, nearest integer."""
     g, o = run_pair(2, 8, 1000, O.NEAREST_INT, schedule(1.0, 101), 10, seed=1, run_id=0)
     assert rel_ok(g.free_energy(), o.free_energy())
@@ -197,7 +197,7 @@ def test_overlap_distribution():
     gb.close()
 
 
-def test_config2_sampled_full_size():
+def test_2d_L64_R1e5_sampled_full_size():
     """2D Ising FM, L = 64, R = 10^5, theta = 10, beta_i = 0.6 i/200: sampled steps, all schemes."""
     from paper_2401_07965_amd import pa
     betas = schedule(0.6, 201)
@@ -215,7 +215,7 @@ def test_config2_sampled_full_size():
         g.close()
 
 
-def test_config3_sampled_full_size():
+def test_3d_L10_R5e5_sampled_full_size():
     """3D +-J glass, L = 10, R = 5 10^5, systematic, theta = 10, beta_i = 3 i/300: sampled step."""
     from paper_2401_07965_amd import pa
     J = ea_couplings(3, 10, 1)
