@@ -143,7 +143,12 @@ __device__ __forceinline__ void wave_vsum16(uint64_t c[16])
     }
 }
 
-__device__ __forceinline__ uint64_t jbit(uint32_t jb, int k) { return 0ull - (uint64_t)((jb >> k) & 1u); }
+// All-ones if bit k of jb is set (one signed bit-field extract; both halves alike).
+__device__ __forceinline__ uint64_t jbit(uint32_t jb, int k)
+{
+    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)jb, (uint32_t)k, 1u);
+    return ((uint64_t)m << 32) | m;
+}
 
 // Unsatisfied-bond mask of a bond between words S and n: S ^ n, inverted for
 // an antiferromagnetic coupling (bit k of jb).
@@ -273,6 +278,109 @@ __device__ __forceinline__ void queue_pass(const WaveQueue &Q, const PlaneCtx &p
     cnt = queue_push(Q, head, cnt, again, s | ((q + 1) << 16), und, m4, m8);
 }
 
+// The theta sweeps of one column in LDS.  ALL: every energy-change class has
+// a threshold strictly between 0 and 2^32 (the usual case), so no class is
+// decided without random bits.  Returns the Philox evaluations this lane made.
+struct SweepGeom {
+    int L, N, half, nh, LL;
+    uint32_t mhalf, mL; // ceil(2^32 / half), ceil(2^32 / L)
+};
+
+template <int D, bool J, bool ALL>
+__device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *jl, const SweepGeom &G, PlaneCtx pc,
+                                                  const WaveQueue &Q, int theta, uint32_t t0, uint64_t sure4,
+                                                  uint64_t sure8, uint64_t sure12, uint64_t draw4, uint64_t draw8,
+                                                  uint64_t draw12)
+{
+    const int L = G.L, half = G.half, nh = G.nh, LL = G.LL;
+    const uint32_t mhalf = G.mhalf, mL = G.mL;
+    const int tid = threadIdx.x, bs = blockDim.x;
+    uint32_t calls = 0;
+    for (int tt = 0; tt < theta; ++tt) {
+        pc.t = t0 + (uint32_t)tt;
+        for (int c = 0; c < 2; ++c) {
+            uint32_t head = 0, cnt = 0;
+            for (int kb = 0; kb < nh; kb += bs) {
+                const int k = kb + tid;
+                uint64_t und = 0, m4 = 0, m8 = 0;
+                uint32_t s = 0, q = 0;
+                if (k < nh) {
+                    const int row = half > 1 ? (int)__umulhi((uint32_t)k, mhalf) : k; // row = y + L z
+                    const int m = k - row * half;
+                    const int z = (D == 2) ? 0 : (int)__umulhi((uint32_t)row, mL);
+                    const int y = row - z * L;
+                    const int x = 2 * m + ((y + z + c) & 1);
+                    s = (uint32_t)(x + L * row);
+                    const uint32_t jb = J ? (uint32_t)jl[s] : 0u;
+                    const uint64_t S = lat[s];
+                    // a_k: bond k unsatisfied (S ^ neighbour ^ [J = -1])
+                    const uint64_t a0 = bond<J>(S, lat[x == L - 1 ? s - (L - 1) : s + 1], jb, 0);
+                    const uint64_t a1 = bond<J>(S, lat[x == 0 ? s + (L - 1) : s - 1], jb, D);
+                    const uint64_t a2 = bond<J>(S, lat[y == L - 1 ? s - L * (L - 1) : s + L], jb, 1);
+                    const uint64_t a3 = bond<J>(S, lat[y == 0 ? s + L * (L - 1) : s - L], jb, D + 1);
+                    // u = number of unsatisfied bonds among 2d; dE = 4(d - u)
+                    uint64_t always, m12;
+                    if (D == 2) {
+                        const uint64_t s0 = a0 ^ a1, c0 = a0 & a1, s1 = a2 ^ a3, c1 = a2 & a3;
+                        always = c0 | c1 | (s0 & s1); // u >= 2
+                        m4 = (s0 ^ s1) & ~(c0 | c1);  // u == 1
+                        m8 = ~(s0 | s1 | c0 | c1);    // u == 0
+                        m12 = 0;
+                    } else {
+                        const uint64_t a4 = bond<J>(S, lat[z == L - 1 ? s - LL * (L - 1) : s + LL], jb, 2);
+                        const uint64_t a5 = bond<J>(S, lat[z == 0 ? s + LL * (L - 1) : s - LL], jb, 5);
+                        constexpr int kXor3 = PA_T3(PA_A ^ PA_B ^ PA_C);
+                        constexpr int kMaj = PA_T3((PA_A & PA_B) | (PA_A & PA_C) | (PA_B & PA_C));
+                        // three-bond sums and carries, then u = 2 (cA + cB + lc) + ls
+                        const uint64_t sA = pa_bop3<kXor3>(a0, a1, a2), cA = pa_bop3<kMaj>(a0, a1, a2);
+                        const uint64_t sB = pa_bop3<kXor3>(a3, a4, a5), cB = pa_bop3<kMaj>(a3, a4, a5);
+                        const uint64_t ls = sA ^ sB, lc = sA & sB;
+                        const uint64_t maj = pa_bop3<kMaj>(cA, cB, lc);  // cA + cB + lc >= 2
+                        const uint64_t odd = pa_bop3<kXor3>(cA, cB, lc); // ... is odd
+                        const uint64_t none = pa_bop3<PA_T3(~(PA_A | PA_B | PA_C))>(cA, cB, lc);
+                        always = pa_bop3<PA_T3(PA_A | (PA_B & PA_C))>(maj, odd, ls); // u >= 3
+                        m4 = pa_bop3<PA_T3(~PA_A & PA_B & ~PA_C)>(maj, odd, ls);     // u == 2
+                        m8 = none & ls;                                               // u == 1
+                        m12 = none & ~ls;                                             // u == 0
+                    }
+                    uint64_t acc;
+                    if (ALL) { // every class draws: the rest of the word is undecided
+                        acc = always;
+                        und = ~always;
+                    } else {
+                        acc = always | (m4 & sure4) | (m8 & sure8) | (m12 & sure12);
+                        und = (m4 & draw4) | (m8 & draw8) | (m12 & draw12);
+                    }
+                    if (und != 0) {
+                        // nearly every site needs the first kInlinePairs pairs:
+                        // their Philox outputs are independent and computed together
+                        pa_philox_out o[kInlinePairs];
+#pragma unroll
+                        for (int k = 0; k < kInlinePairs; ++k)
+                            o[k] = metro_philox(pc, s, (uint32_t)k);
+#pragma unroll
+                        for (int k = 0; k < kInlinePairs; ++k)
+                            if (und != 0) {
+                                ++calls;
+                                apply_pair<D>(pc, o[k], (uint32_t)k, m4, m8, m12, und, acc);
+                                q = (uint32_t)k + 1;
+                            }
+                    }
+                    lat[s] = S ^ acc;
+                }
+                cnt = queue_push(Q, head, cnt, und != 0, s | (q << 16), und, m4, m8);
+                while (cnt >= 64u)
+                    queue_pass<D>(Q, pc, lat, head, cnt, calls);
+            }
+            while (cnt > 0u)
+                queue_pass<D>(Q, pc, lat, head, cnt, calls);
+            __syncthreads();
+        }
+    }
+
+    return calls;
+}
+
 // One workgroup = one word column w (64 replicas) of one run; the lattice
 // stays in LDS for all theta sweeps, then each replica's unsatisfied-bond
 // count U and number of down spins are counted bit-sliced: E = 2U - dN,
@@ -329,81 +437,11 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
     pc.t8 = (uint32_t)T8;
     pc.t12 = (uint32_t)T12;
     const WaveQueue Q = {qsites + (size_t)(tid >> 6) * kQueue, qbase, qbase + kQueue, qbase + 2 * kQueue};
-    uint32_t calls = 0; // Philox evaluations this lane made
-
-    for (int tt = 0; tt < theta; ++tt) {
-        pc.t = t0 + (uint32_t)tt;
-        for (int c = 0; c < 2; ++c) {
-            uint32_t head = 0, cnt = 0;
-            for (int kb = 0; kb < nh; kb += bs) {
-                const int k = kb + tid;
-                uint64_t und = 0, m4 = 0, m8 = 0;
-                uint32_t s = 0, q = 0;
-                if (k < nh) {
-                    const int row = half > 1 ? (int)__umulhi((uint32_t)k, mhalf) : k; // row = y + L z
-                    const int m = k - row * half;
-                    const int z = (D == 2) ? 0 : (int)__umulhi((uint32_t)row, mL);
-                    const int y = row - z * L;
-                    const int x = 2 * m + ((y + z + c) & 1);
-                    s = (uint32_t)(x + L * row);
-                    const uint32_t jb = J ? (uint32_t)jl[s] : 0u;
-                    const uint64_t S = lat[s];
-                    // a_k: bond k unsatisfied (S ^ neighbour ^ [J = -1])
-                    const uint64_t a0 = bond<J>(S, lat[x == L - 1 ? s - (L - 1) : s + 1], jb, 0);
-                    const uint64_t a1 = bond<J>(S, lat[x == 0 ? s + (L - 1) : s - 1], jb, D);
-                    const uint64_t a2 = bond<J>(S, lat[y == L - 1 ? s - L * (L - 1) : s + L], jb, 1);
-                    const uint64_t a3 = bond<J>(S, lat[y == 0 ? s + L * (L - 1) : s - L], jb, D + 1);
-                    // u = number of unsatisfied bonds among 2d; dE = 4(d - u)
-                    uint64_t always, m12;
-                    if (D == 2) {
-                        const uint64_t s0 = a0 ^ a1, c0 = a0 & a1, s1 = a2 ^ a3, c1 = a2 & a3;
-                        always = c0 | c1 | (s0 & s1); // u >= 2
-                        m4 = (s0 ^ s1) & ~(c0 | c1);  // u == 1
-                        m8 = ~(s0 | s1 | c0 | c1);    // u == 0
-                        m12 = 0;
-                    } else {
-                        const uint64_t a4 = bond<J>(S, lat[z == L - 1 ? s - LL * (L - 1) : s + LL], jb, 2);
-                        const uint64_t a5 = bond<J>(S, lat[z == 0 ? s + LL * (L - 1) : s - LL], jb, 5);
-                        const uint64_t sA = a0 ^ a1 ^ a2, cA = (a0 & a1) | (a2 & (a0 ^ a1));
-                        const uint64_t sB = a3 ^ a4 ^ a5, cB = (a3 & a4) | (a5 & (a3 ^ a4));
-                        const uint64_t ls = sA ^ sB, lc = sA & sB;
-                        // u = 2 (cA + cB + lc) + ls
-                        const uint64_t maj = (cA & cB) | (lc & (cA ^ cB));
-                        const uint64_t odd = cA ^ cB ^ lc;
-                        const uint64_t none = ~(cA | cB | lc);
-                        always = maj | (odd & ls); // u >= 3
-                        m4 = odd & ~maj & ~ls;     // u == 2
-                        m8 = none & ls;            // u == 1
-                        m12 = none & ~ls;          // u == 0
-                    }
-                    uint64_t acc = always | (m4 & sure4) | (m8 & sure8) | (m12 & sure12);
-                    und = (m4 & draw4) | (m8 & draw8) | (m12 & draw12);
-                    if (und != 0) {
-                        // nearly every site needs the first kInlinePairs pairs:
-                        // their Philox outputs are independent and computed together
-                        pa_philox_out o[kInlinePairs];
-#pragma unroll
-                        for (int k = 0; k < kInlinePairs; ++k)
-                            o[k] = metro_philox(pc, s, (uint32_t)k);
-#pragma unroll
-                        for (int k = 0; k < kInlinePairs; ++k)
-                            if (und != 0) {
-                                ++calls;
-                                apply_pair<D>(pc, o[k], (uint32_t)k, m4, m8, m12, und, acc);
-                                q = (uint32_t)k + 1;
-                            }
-                    }
-                    lat[s] = S ^ acc;
-                }
-                cnt = queue_push(Q, head, cnt, und != 0, s | (q << 16), und, m4, m8);
-                while (cnt >= 64u)
-                    queue_pass<D>(Q, pc, lat, head, cnt, calls);
-            }
-            while (cnt > 0u)
-                queue_pass<D>(Q, pc, lat, head, cnt, calls);
-            __syncthreads();
-        }
-    }
+    const SweepGeom G = {L, N, half, nh, LL, mhalf, mL};
+    const bool all_draw = draw4 != 0 && draw8 != 0 && (D == 2 || draw12 != 0);
+    const uint32_t calls =
+        all_draw ? sweep_columns<D, J, true>(lat, jl, G, pc, Q, theta, t0, sure4, sure8, sure12, draw4, draw8, draw12)
+                 : sweep_columns<D, J, false>(lat, jl, G, pc, Q, theta, t0, sure4, sure8, sure12, draw4, draw8, draw12);
 
     // measure: forward bonds once each, plus the down-spin count
     uint64_t ve[8] = {0, 0, 0, 0, 0, 0, 0, 0}, vm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
