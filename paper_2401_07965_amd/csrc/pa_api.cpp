@@ -250,7 +250,6 @@ uint64_t layout(const std::vector<Geometry> &geo, int max_points, char *base, Ba
     std::vector<char *> p_g;
     for (auto &gc : tb.gcol)
         p_g.push_back(take(sizeof(PaBlk) * gc.size()));
-    char *p_ticket = take(8);
     char *p_steprec = take(sizeof(PaStepRecord) * (uint64_t)M * (uint64_t)(max_points > 0 ? max_points : 0));
     char *p_group = take(4ull * M);
     char *p_Ns = take(4ull * M);
@@ -291,7 +290,6 @@ uint64_t layout(const std::vector<Geometry> &geo, int max_points, char *base, Ba
         v.ncol = (uint32_t)tb.col.size();
         v.tile = (const PaBlk *)p_tile;
         v.ntile = (uint32_t)tb.tile.size();
-        v.ticket = (uint32_t *)p_ticket;
         v.maxH = maxH;
         v.ngroups = (int)tb.gcol.size();
         for (int g = 0; g < v.ngroups; ++g) {

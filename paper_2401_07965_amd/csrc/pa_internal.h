@@ -58,6 +58,7 @@ struct PaRecord {
     unsigned long long philox_calls; // Philox4x32-10 evaluations of all sweeps so far
     unsigned long long site_updates; // word-site updates (64 attempts each) so far
     unsigned long long attempts;     // spin-flip attempts so far: theta N R per sweep call
+    uint32_t ticket[2];              // tile tickets of the two prefix sums of a resampling
 };
 
 // One row per run and temperature point of a batched anneal.
@@ -144,7 +145,6 @@ struct PaBatchView {
     uint32_t ncol;
     const PaBlk *tile; // scan tiles, run-major
     uint32_t ntile;
-    uint32_t *ticket;  // tile tickets of the two prefix sums of a resampling
     int maxH;
     int ngroups;       // runs grouped by lattice shape for the sweeps
     const PaBlk *gcol[PA_MAX_GROUPS];

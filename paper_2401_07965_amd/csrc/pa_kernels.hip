@@ -1025,28 +1025,28 @@ __global__ __launch_bounds__(kThreads) void k_sv_partial(const PaRunDesc *__rest
 }
 
 // Decoupled look-back scan (Merrill & Garland 2016) of each run's first
-// Rcur entries: tiles take their order from an atomic ticket over a
-// run-major tile map, so every tile a tile waits on (same run, lower index)
-// is already running.  Entries past Rcur count as 0.  WHICH = 0: inclusive
+// Rcur entries: the workgroups of a run (from the tile map) take their tile
+// index from the run's own atomic ticket, so every tile a tile waits on (same
+// run, lower index) belongs to a workgroup that is already running.  Entries past Rcur count as 0.  WHICH = 0: inclusive
 // sums of the weights C in place; WHICH = 1: exclusive sums P of the copy
 // numbers r, and with them the ancestor map anc[P_j + k] = j, k < r_j (kept
 // below the capacity; a resampling that overflows is not applied).
 template <typename T, bool INCLUSIVE, int WHICH>
 __global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const PaRunDesc *__restrict__ runs,
-                                                          const PaBlk *__restrict__ map, uint32_t *ticket)
+                                                          const PaBlk *__restrict__ map)
 {
     __shared__ uint32_t s_tile;
     __shared__ unsigned long long s_wave[PA_SCAN_THREADS / 64];
     __shared__ unsigned long long s_excl;
-    if (threadIdx.x == 0)
-        s_tile = atomicAdd(ticket + WHICH, 1u);
-    __syncthreads();
-    const PaBlk b = map[s_tile];
+    const PaBlk b = map[blockIdx.x];
     const PaRunDesc &rd = runs[b.run];
     PaRecord *rec = rd.dv.rec;
     if (frozen(rec))
         return; // every tile of a frozen run returns: none waits
-    const uint32_t tile = b.idx;
+    if (threadIdx.x == 0)
+        s_tile = atomicAdd(&rec->ticket[WHICH], 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
     const int64_t n = (int64_t)rec->Rcur;
     const int64_t ntiles = (rd.cap + PA_SCAN_TILE - 1) / PA_SCAN_TILE;
     const T *in = WHICH == 0 ? (const T *)rd.dv.C : (const T *)rd.dv.r;
@@ -1137,19 +1137,20 @@ __global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const PaRunDesc *__res
 // A new resampling starts with a clean status (a frozen run stays frozen),
 // cleared tile flags for both prefix sums (weights, copy numbers) and their
 // tile tickets.
-__global__ void k_resample_prep(const PaRunDesc *__restrict__ runs, uint32_t *tickets)
+__global__ void k_resample_prep(const PaRunDesc *__restrict__ runs)
 {
     const PaRunDesc &rd = runs[blockIdx.x];
     PaRecord *rec = rd.dv.rec;
     const int64_t ntiles = (rd.cap + PA_SCAN_TILE - 1) / PA_SCAN_TILE;
     for (int64_t t = threadIdx.x; t < 2 * ntiles; t += blockDim.x)
         rd.dv.tiles[t].flag = 0u;
-    if (threadIdx.x == 0 && !frozen(rec)) {
-        rec->status = 0;
-        rec->skip = 0;
+    if (threadIdx.x == 0) {
+        rec->ticket[0] = rec->ticket[1] = 0u;
+        if (!frozen(rec)) {
+            rec->status = 0;
+            rec->skip = 0;
+        }
     }
-    if (blockIdx.x == 0 && threadIdx.x < 2)
-        tickets[threadIdx.x] = 0u;
 }
 
 // Capacity and extinction: a resampling that would not fit (or leave no
@@ -1687,14 +1688,14 @@ hipError_t pa_b_check_candidate(const PaBatchView &v, double alpha_star, double 
 template <typename T, bool INCL, int WHICH>
 static hipError_t scan_launch(const PaBatchView &v)
 {
-    k_scan<T, INCL, WHICH><<<v.ntile, PA_SCAN_THREADS, 0, v.stream>>>(v.runs, v.tile, v.ticket);
+    k_scan<T, INCL, WHICH><<<v.ntile, PA_SCAN_THREADS, 0, v.stream>>>(v.runs, v.tile);
     return hipGetLastError();
 }
 
 hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze)
 {
     hipError_t e;
-    k_resample_prep<<<v.nruns, kThreads, 0, v.stream>>>(v.runs, v.ticket);
+    k_resample_prep<<<v.nruns, kThreads, 0, v.stream>>>(v.runs);
     switch (scheme) {
     case 2:
         k_counts_nearest<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
