@@ -76,7 +76,7 @@ struct PaScanTile {
 #define PA_SCAN_THREADS 512
 #define PA_SCAN_ITEMS 16
 #define PA_SCAN_TILE (PA_SCAN_THREADS * PA_SCAN_ITEMS)
-#define PA_CHUNK 256   // replicas (or families) per workgroup of the per-replica kernels
+#define PA_CHUNK 1024  // replicas (or families) per workgroup of the per-replica kernels
 #define PA_HCHUNK 4096 // replicas per workgroup of the energy histogram (LDS-private counts)
 
 // Device buffers of one run, carved from the caller's workspace.
