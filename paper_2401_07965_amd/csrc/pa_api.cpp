@@ -366,6 +366,8 @@ pa_status coupling_masks(const pa_config &cfg, const Geometry &g, std::vector<ui
     return PA_OK;
 }
 
+void free_batch(Batch *b);
+
 pa_status make_batch(const pa_config *cfgs, int32_t nruns, int32_t max_points, void *workspace, uint64_t bytes,
                      void *stream, Batch *b)
 {
@@ -400,6 +402,18 @@ pa_status make_batch(const pa_config *cfgs, int32_t nruns, int32_t max_points, v
     if ((e = hipHostMalloc((void **)&b->hrec, sizeof(PaRecord) * (size_t)nruns, hipHostMallocDefault)) !=
         hipSuccess)
         return hip_fail(nullptr, e, "pinned records");
+    if (b->v.ngroups > 1) { // side streams (default priority) and events for the groups' sweeps
+        e = hipEventCreateWithFlags(&b->v.fork, hipEventDisableTiming);
+        for (int g = 0; g < b->v.ngroups && e == hipSuccess; ++g) {
+            e = hipStreamCreateWithFlags(&b->v.gstream[g], hipStreamNonBlocking);
+            if (e == hipSuccess)
+                e = hipEventCreateWithFlags(&b->v.join[g], hipEventDisableTiming);
+        }
+        if (e != hipSuccess) {
+            free_batch(b);
+            return hip_fail(nullptr, e, "group streams");
+        }
+    }
     const hipStream_t st = b->v.stream;
     auto up = [&](const void *dst, const void *src, size_t n) {
         if (e == hipSuccess && n)
@@ -421,8 +435,7 @@ pa_status make_batch(const pa_config *cfgs, int32_t nruns, int32_t max_points, v
     if (e == hipSuccess)
         e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
-        (void)hipHostFree(b->hrec);
-        b->hrec = nullptr;
+        free_batch(b);
         return hip_fail(nullptr, e, "batch set-up");
     }
     return PA_OK;
@@ -498,6 +511,17 @@ void free_batch(Batch *b)
     if (b->hrec)
         (void)hipHostFree(b->hrec);
     b->hrec = nullptr;
+    for (int g = 0; g < PA_MAX_GROUPS; ++g) {
+        if (b->v.gstream[g])
+            (void)hipStreamDestroy(b->v.gstream[g]);
+        if (b->v.join[g])
+            (void)hipEventDestroy(b->v.join[g]);
+        b->v.gstream[g] = nullptr;
+        b->v.join[g] = nullptr;
+    }
+    if (b->v.fork)
+        (void)hipEventDestroy(b->v.fork);
+    b->v.fork = nullptr;
 }
 
 } // namespace

@@ -153,6 +153,10 @@ struct PaBatchView {
     PaStepRecord *steprec; // batched anneal: [nruns][npoints]
     int npoints;
     hipStream_t stream;
+    // with several groups: one side stream per group, so that the groups'
+    // sweeps run side by side (fork on `stream`, join back into it)
+    hipStream_t gstream[PA_MAX_GROUPS];
+    hipEvent_t fork, join[PA_MAX_GROUPS];
 };
 
 // launchers (pa_kernels.hip); each returns the first launch error

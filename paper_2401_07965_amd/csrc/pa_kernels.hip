@@ -1585,19 +1585,19 @@ __global__ void k_set_beta(const PaRunDesc *__restrict__ runs, double beta, doub
     }
 }
 
-hipError_t sweep_launch(const PaBatchView &v, int g, int theta, int threads, uint32_t t0)
+hipError_t sweep_launch(const PaBatchView &v, int g, int theta, int threads, uint32_t t0, hipStream_t st)
 {
     if (v.gncol[g] == 0)
         return hipSuccess;
     const size_t lds = pa_sweep_lds_bytes(v.gN[g], threads);
     if (v.gd[g] == 2 && v.gJ[g])
-        k_sweep<2, true><<<v.gncol[g], threads, lds, v.stream>>>(v.runs, v.gcol[g], theta, t0);
+        k_sweep<2, true><<<v.gncol[g], threads, lds, st>>>(v.runs, v.gcol[g], theta, t0);
     else if (v.gd[g] == 2)
-        k_sweep<2, false><<<v.gncol[g], threads, lds, v.stream>>>(v.runs, v.gcol[g], theta, t0);
+        k_sweep<2, false><<<v.gncol[g], threads, lds, st>>>(v.runs, v.gcol[g], theta, t0);
     else if (v.gJ[g])
-        k_sweep<3, true><<<v.gncol[g], threads, lds, v.stream>>>(v.runs, v.gcol[g], theta, t0);
+        k_sweep<3, true><<<v.gncol[g], threads, lds, st>>>(v.runs, v.gcol[g], theta, t0);
     else
-        k_sweep<3, false><<<v.gncol[g], threads, lds, v.stream>>>(v.runs, v.gcol[g], theta, t0);
+        k_sweep<3, false><<<v.gncol[g], threads, lds, st>>>(v.runs, v.gcol[g], theta, t0);
     return hipGetLastError();
 }
 
@@ -1627,20 +1627,35 @@ hipError_t pa_b_init(const PaBatchView &v)
     k_init_labels<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
     hipError_t e = hipGetLastError();
     for (int g = 0; g < v.ngroups && e == hipSuccess; ++g)
-        e = sweep_launch(v, g, 0, v.gthreads[g], 0u);
+        e = sweep_launch(v, g, 0, v.gthreads[g], 0u, v.stream);
     return e;
 }
 
 hipError_t pa_b_sweep_group(const PaBatchView &v, int g, int theta, int threads)
 {
-    return sweep_launch(v, g, theta, threads, 0u);
+    return sweep_launch(v, g, theta, threads, 0u, v.stream);
 }
 
 hipError_t pa_b_sweep(const PaBatchView &v, int theta, uint32_t t0)
 {
     hipError_t e = hipSuccess;
+    if (v.ngroups < 2 || !v.fork) {
+        for (int g = 0; g < v.ngroups && e == hipSuccess; ++g)
+            e = sweep_launch(v, g, theta, v.gthreads[g], t0, v.stream);
+        return e;
+    }
+    // the groups are independent: each on its own stream, so that one group's
+    // last partly filled round of workgroups overlaps the others' work
+    e = hipEventRecord(v.fork, v.stream);
+    for (int g = 0; g < v.ngroups && e == hipSuccess; ++g) {
+        e = hipStreamWaitEvent(v.gstream[g], v.fork, 0);
+        if (e == hipSuccess)
+            e = sweep_launch(v, g, theta, v.gthreads[g], t0, v.gstream[g]);
+        if (e == hipSuccess)
+            e = hipEventRecord(v.join[g], v.gstream[g]);
+    }
     for (int g = 0; g < v.ngroups && e == hipSuccess; ++g)
-        e = sweep_launch(v, g, theta, v.gthreads[g], t0);
+        e = hipStreamWaitEvent(v.stream, v.join[g], 0);
     return e;
 }
 
