@@ -207,6 +207,27 @@ def isolated_steps(state, streams, sched, nsteps):
             "resample_GB_per_s": res_bytes / (sum(res_ms) * 1e-3) / 1e9}
 
 
+def philox_rate():
+    """Device Philox4x32-10 evaluations per second (the library's probe: three
+    independent chains per thread, 2^20 threads), best of three timed launches."""
+    import torch
+    from paper_2401_07965_amd import pa
+    out = torch.empty(1 << 20, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    iters = 64
+    pa.philox_probe(out, iters, stream)  # warm-up
+    best = None
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        pa.philox_probe(out, iters, stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    return out.numel() * 3 * iters / (best * 1e-3)
+
+
 def union_length(intervals):
     """Total length of the union of (start, end) intervals."""
     tot, cur_a, cur_b = 0.0, None, None
@@ -407,6 +428,7 @@ def main():
               "(this library runs one GPU; sharding across GPUs is not built)", file=sys.stderr)
         sys.exit(2)
     r = gpu_bench(a.steps, a.warmup)
+    rate = philox_rate()
     value = r["attempts"] / r["elapsed"] / 1e9
     # the sweep kernel's time: union of its launches on the four streams
     sweep_s = r["sweep_union_s"]
@@ -438,6 +460,10 @@ def main():
         "resample_GB_per_s": r["iso"]["resample_GB_per_s"] if r["iso"] else None,
         "isolated": r["iso"],
         "philox_calls_per_attempt": (r["calls"] / (64.0 * r["updates"])) if r["updates"] else None,
+        "philox_calls_per_ns": rate / 1e9,
+        # the sweep's rate if generating its random bits were all it did
+        "philox_bound_attempts_per_ns": (rate / (r["calls"] / (64.0 * r["updates"])) / 1e9)
+                                        if r["updates"] else None,
         "roofline": {
             "kernel": "k_sweep<2>",
             "bound": "alu",

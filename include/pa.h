@@ -188,6 +188,15 @@ pa_status pa_import_state(pa_ctx *ctx, const pa_host_state *st);
  * (i.e. k = N - popcount). */
 pa_status pa_overlap(pa_ctx *a, pa_ctx *b, int64_t *hist_out);
 
+/* Throughput probe of the generator the sweeps draw from (no step of the
+ * method): each of nthreads threads (a multiple of 256, <= 2^24) evaluates
+ * 3 * iters Philox4x32-10 calls as three independent chains (the sweep's
+ * first plane pairs) and writes the xor of all outputs to out[thread]
+ * (device memory, uint32[nthreads], caller-owned).  Enqueued on `stream`;
+ * returns without waiting.  Timing it gives the device's Philox rate, the
+ * ceiling of any sweep that decides u < T from these bits. */
+pa_status pa_philox_probe(void *out, int64_t nthreads, int32_t iters, void *stream);
+
 /* Adaptive temperature steps (Sec. 5 names them; the rule is a reading):
  * overlap of the current population with its reweighting by dbeta,
  *   alpha(dbeta) = (1/R) sum_j min(1, tauhat_j),  tauhat_j = R W_j / S,

@@ -743,6 +743,16 @@ pa_status pa_import_state(pa_ctx *c, const pa_host_state *st)
     return PA_OK;
 }
 
+pa_status pa_philox_probe(void *out, int64_t nthreads, int32_t iters, void *stream)
+{
+    if (!out || nthreads < 256 || nthreads % 256 || nthreads > (1 << 24) || iters < 1)
+        return fail(nullptr, PA_E_INVAL, "need out, nthreads a multiple of 256 in [256, 2^24], iters >= 1");
+    const hipError_t e = pa_launch_philox_probe((uint32_t *)out, nthreads, iters, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(nullptr, e, "pa_philox_probe");
+    return PA_OK;
+}
+
 pa_status pa_overlap(pa_ctx *a, pa_ctx *c2, int64_t *hist_out)
 {
     if (!a || !c2)

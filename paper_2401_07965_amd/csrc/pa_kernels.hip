@@ -1585,6 +1585,24 @@ __global__ void k_set_beta(const PaRunDesc *__restrict__ runs, double beta, doub
     }
 }
 
+// Generator throughput probe: Metropolis-purpose counters as the sweep forms
+// them, three independent chains per thread, outputs folded into one word.
+__global__ __launch_bounds__(kThreads) void k_philox_probe(uint32_t *__restrict__ out, int iters)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t acc = 0;
+    for (int i = 0; i < iters; ++i) {
+        pa_philox_out o[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            o[q] = pa_philox(1u, 2u, t, (uint32_t)i, 7u, (PA_PURPOSE_METRO << 28) | (uint32_t)q);
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            acc ^= o[q].x0 ^ o[q].x1 ^ o[q].x2 ^ o[q].x3;
+    }
+    out[t] = acc;
+}
+
 hipError_t sweep_launch(const PaBatchView &v, int g, int theta, int threads, uint32_t t0, hipStream_t st)
 {
     if (v.gncol[g] == 0)
@@ -1764,6 +1782,12 @@ hipError_t pa_launch_combine(const PaBatchView &v, int point, const int32_t *gro
 {
     k_combine<<<(ngroups + 63) / 64, 64, 0, v.stream>>>(v.steprec, v.npoints, point, group_of, (int)v.nruns,
                                                         ngroups, Ns, out);
+    return hipGetLastError();
+}
+
+hipError_t pa_launch_philox_probe(uint32_t *out, int64_t nthreads, int iters, hipStream_t st)
+{
+    k_philox_probe<<<(unsigned)(nthreads / kThreads), kThreads, 0, st>>>(out, iters);
     return hipGetLastError();
 }
 

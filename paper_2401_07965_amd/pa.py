@@ -118,6 +118,7 @@ def lib():
         L.pa_export_state.argtypes = [v, P(pa_host_state)]
         L.pa_import_state.argtypes = [v, P(pa_host_state)]
         L.pa_overlap.argtypes = [v, v, v]
+        L.pa_philox_probe.argtypes = [v, ctypes.c_int64, ctypes.c_int32, v]
         L.pa_get_counters.argtypes = [v, P(pa_counters)]
         L.pa_step_alpha.argtypes = [v, ctypes.c_double, P(ctypes.c_double)]
         L.pa_step_rule.argtypes = [v, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
@@ -165,7 +166,8 @@ def lib():
         L.pa_last_error.restype = ctypes.c_char_p
         for name in ("pa_required_bytes", "pa_init", "pa_sweep", "pa_reweight", "pa_resample",
                      "pa_observables", "pa_free_energy", "pa_export_state", "pa_import_state",
-                     "pa_overlap", "pa_get_counters", "pa_step_alpha", "pa_step_rule"):
+                     "pa_overlap", "pa_get_counters", "pa_step_alpha", "pa_step_rule",
+                     "pa_philox_probe"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -278,6 +280,13 @@ def pa_import_state(ctx, R, step, sweeps, beta, lnZ, spins, energy, magnetizatio
     st = pa_host_state(int(R), int(step), int(sweeps), float(beta), float(lnZ), spins.ctypes.data,
                        energy.ctypes.data, magnetization.ctypes.data, label.ctypes.data)
     _check(lib().pa_import_state(ctx, ctypes.byref(st)), ctx)
+
+
+def philox_probe(out, iters, stream):
+    """Enqueue the generator throughput probe: out is a device uint32 tensor
+    (one word per thread, a multiple of 256 threads); 3 * iters Philox calls per
+    thread."""
+    _check(lib().pa_philox_probe(out.data_ptr(), out.numel(), int(iters), stream.cuda_stream), None)
 
 
 def pa_overlap(a, b, N):

@@ -65,3 +65,9 @@ def test_spin_packing_roundtrip(libpa):
         # replica r is bit r % 64 of word r // 64; bit 1 means sigma = -1
         r = R - 1
         assert ((int(w[r // 64, 0]) >> (r % 64)) & 1) == (1 if s[r, 0] < 0 else 0)
+
+
+def test_philox_probe_checks_arguments_without_gpu(libpa):
+    L = libpa.lib()
+    for n, iters in ((100, 1), (0, 1), (256, 0), ((1 << 24) + 256, 1)):
+        assert L.pa_philox_probe(None, n, iters, None) == 1  # PA_E_INVAL, nothing launched

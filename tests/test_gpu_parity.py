@@ -229,3 +229,19 @@ def test_3d_L10_R5e5_sampled_full_size():
                            np.random.default_rng(1).integers(0, 499000, 64)])
     sampled_step(g, 3, 10, J, O.SYSTEMATIC, betas[3], 10, rows, 1, 0, 500000)
     g.close()
+
+
+def test_philox_probe_matches_the_oracle_generator():
+    """The throughput probe evaluates the same generator as the sweeps."""
+    import torch
+    from paper_2401_07965_amd import pa
+    out = torch.empty(1024, dtype=torch.int32, device="cuda")
+    pa.philox_probe(out, 3, torch.cuda.current_stream())
+    got = out.cpu().numpy().view(np.uint32)
+    for t in (0, 1, 255, 700, 1023):
+        acc = 0
+        for i in range(3):
+            for q in range(3):
+                x = O.philox(1, 2, [t, i, 7, (2 << 28) | q])
+                acc ^= int(x[0]) ^ int(x[1]) ^ int(x[2]) ^ int(x[3])
+        assert int(got[t]) == acc, t
