@@ -245,3 +245,32 @@ def test_philox_probe_matches_the_oracle_generator():
                 x = O.philox(1, 2, [t, i, 7, (2 << 28) | q])
                 acc ^= int(x[0]) ^ int(x[1]) ^ int(x[2]) ^ int(x[3])
         assert int(got[t]) == acc, t
+
+
+def test_extinction_matches_oracle_and_leaves_the_state():
+    """One replica, Poisson resampling: the step that would empty the
+    population fails on both sides at the same step, state unchanged."""
+    from paper_2401_07965_amd import pa
+    g = pa.PARun(2, 4, 1, seed=2, run_id=1)
+    o = O.OracleRun(2, 4, 1, seed=2, run_id=1)
+    for s in range(40):
+        b = 0.01 * (s + 1)
+        assert rel_ok(g.reweight(b), o.reweight(b))
+        before = g.export()
+        try:
+            o.resample(O.POISSON)
+        except O.ExtinctError:
+            with pytest.raises(pa.ExtinctError):
+                g.resample(O.POISSON)
+            after = g.export()
+            for k in ("spins", "energy", "label", "magnetization"):
+                assert np.array_equal(before[k], after[k])
+            assert before["lnZ"] == after["lnZ"] and before["R"] == after["R"] == 1
+            break
+        assert g.resample(O.POISSON) == o.Rcur
+        g.sweep(1)
+        o.sweep(1)
+        compare_state(g, o, f"step {s}")
+    else:
+        raise AssertionError("no extinction in 40 steps")
+    g.close()

@@ -123,3 +123,23 @@ def test_resample_before_reweight_is_rejected():
     run = O.OracleRun(2, 4, 10, seed=1)
     with pytest.raises(O.PAError):
         run.resample(O.SYSTEMATIC)
+
+
+def test_extinction_is_an_error_that_leaves_the_state():
+    """A single replica under Poisson resampling dies with probability e^-1 per
+    step (tauhat = 1); the resampling that would empty the population is
+    refused and the replica stays."""
+    run = O.OracleRun(2, 4, 1, seed=2, run_id=1)
+    died = False
+    for s in range(40):
+        run.reweight(0.01 * (s + 1))
+        spins, E, lnZ = run.spins.copy(), run.E.copy(), run.free_energy()
+        try:
+            assert run.resample(O.POISSON) >= 1
+        except O.ExtinctError:
+            died = True
+            assert run.Rcur == 1 and np.array_equal(run.spins, spins) and np.array_equal(run.E, E)
+            assert run.free_energy() == lnZ
+            break
+        run.sweep(1)
+    assert died  # (1 - e^-1)^40 < 1e-7
