@@ -316,7 +316,6 @@ def learned_bench(theta=10, scheme=3, astar=0.7, dmax=0.2, beta_f=3.0):
     rule alone and with the learned step (exact overlap check + rule fallback)."""
     import numpy as np
     import torch
-    from oracle import mlp as Mo  # parameter initialisation only (seeded uniform)
     from paper_2401_07965_amd import pa, workloads
     from paper_2401_07965_amd.schedule import anneal_adaptive, standardisation
     d, L = 3, 16
@@ -331,7 +330,7 @@ def learned_bench(theta=10, scheme=3, astar=0.7, dmax=0.2, beta_f=3.0):
     X, y = np.concatenate(Xs), np.concatenate(ys)
     t_data = time.perf_counter() - t0
     xm, xs, ym, ysd = standardisation(X, y)
-    mlp = pa.PAMlp(Mo.init_params(0), xm, xs, ym, ysd, max_samples=len(y))
+    mlp = pa.PAMlp(workloads.mlp_initial_parameters(0), xm, xs, ym, ysd, max_samples=len(y))
     mlp.set_data(X, y)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -39,3 +39,14 @@ def uneven_batch(samples=16, runs_per_sample=16, seed0=1000, R_lo=1e3, R_hi=1e5,
             groups.append(s)
             k += 1
     return cfgs, groups
+
+
+def mlp_initial_parameters(seed, hidden=64, inputs=8):
+    """Seeded starting point of the step model's training: float32 vector in
+    the layout W1[h][8], b1[h], W2[h][h], b2[h], W3[h], b3, weights uniform in
+    +-1/sqrt(fan in), biases zero."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.uniform(-1, 1, (hidden, inputs)) / np.sqrt(inputs), np.zeros(hidden),
+             rng.uniform(-1, 1, (hidden, hidden)) / np.sqrt(hidden), np.zeros(hidden),
+             rng.uniform(-1, 1, hidden) / np.sqrt(hidden), np.zeros(1)]
+    return np.concatenate([p.reshape(-1) for p in parts]).astype(np.float32)
