@@ -267,7 +267,7 @@ pa_status pa_batch_required_bytes(const pa_config *cfgs, int32_t nruns, int32_t 
 pa_status pa_batch_create(const pa_config *cfgs, int32_t nruns, int32_t max_points, void *workspace,
                           uint64_t workspace_bytes, void *stream, pa_batch **out);
 
-/* Autotuner: times the sweep workgroup size (64..512 lanes, where the
+/* Autotuner: times the sweep workgroup size (64..768 lanes, where the
  * lattice allows) per group with theta sweeps, keeps the fastest and
  * re-draws the initial populations.  Results do not depend on the choice.
  * threads_out (optional): one entry per group. */

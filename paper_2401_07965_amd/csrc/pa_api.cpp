@@ -84,23 +84,37 @@ pa_status check_config(const pa_config *cfg, Geometry *g, std::string *msg)
     return PA_OK;
 }
 
-// Sweep workgroup size: enough lanes for a colour's sites, and at most 255
-// unsatisfied bonds per lane for its 8-plane counters.
-int default_sweep_threads(int N, int d)
-{
-    int t = ((N / 2 + 63) / 64) * 64;
-    if (t > 256)
-        t = 256;
-    if (t < 64)
-        t = 64;
-    while (t < 512 && (int64_t)((N + t - 1) / t) * d > 255)
-        t += 64;
-    return t;
-}
-
+// Sweep workgroup sizes: 64..768 lanes, at most 255 unsatisfied bonds per
+// lane for the measurement's 8-plane counters.
 bool sweep_threads_ok(int N, int d, int t)
 {
-    return t >= 64 && t <= 512 && t % 64 == 0 && (int64_t)((N + t - 1) / t) * d <= 255;
+    return t >= 64 && t <= 768 && t % 64 == 0 && (int64_t)((N + t - 1) / t) * d <= 255;
+}
+
+constexpr int kLdsPerCu = 163840;  // gfx950: 160 KiB of LDS per CU
+constexpr int kSweepWavesPerSimd = 3; // the sweep kernel's register use allows 3 waves per SIMD
+
+// Default sweep workgroup size: the one that keeps the most sweep waves
+// resident per CU (LDS of the lattice and queues, registers), the smaller on
+// ties (more sites per lane, fewer waits per site).
+int default_sweep_threads(int N, int d, bool J)
+{
+    const int lds_max = g_max_lds ? g_max_lds : kLdsPerCu;
+    int best = 0, best_waves = -1;
+    for (int t = 64; t <= 768; t += 64) {
+        const size_t lds = pa_sweep_lds_bytes(N, t, J);
+        if (!sweep_threads_ok(N, d, t) || lds > (size_t)lds_max)
+            continue;
+        const int w = t / 64;
+        int blocks = (int)(kLdsPerCu / lds);
+        if (blocks > 4 * kSweepWavesPerSimd / w)
+            blocks = 4 * kSweepWavesPerSimd / w;
+        if (blocks * w > best_waves) {
+            best_waves = blocks * w;
+            best = t;
+        }
+    }
+    return best ? best : 768; // none fits: rejected by the LDS check of the batch set-up
 }
 
 uint64_t round256(uint64_t b) { return (b + 255) / 256 * 256; }
@@ -230,7 +244,7 @@ uint64_t layout(const std::vector<Geometry> &geo, int max_points, char *base, Ba
             tb.gd.push_back(g.d);
             tb.gN.push_back(g.N);
             tb.gJ.push_back(g.J);
-            tb.gthreads.push_back(default_sweep_threads(g.N, g.d));
+            tb.gthreads.push_back(default_sweep_threads(g.N, g.d, g.J != 0));
         }
         for (int64_t w = 0; w < g.W; ++w)
             tb.gcol[it->second].push_back({(uint32_t)m, (uint32_t)w});
@@ -385,7 +399,7 @@ pa_status make_batch(const pa_config *cfgs, int32_t nruns, int32_t max_points, v
     if (g_max_lds == 0 && (e = pa_query_lds(&g_max_lds)) != hipSuccess)
         return hip_fail(nullptr, e, "device query");
     for (const Geometry &g : geo)
-        if (pa_sweep_lds_bytes(g.N, default_sweep_threads(g.N, g.d)) > (size_t)g_max_lds ||
+        if (pa_sweep_lds_bytes(g.N, default_sweep_threads(g.N, g.d, g.J != 0), g.J != 0) > (size_t)g_max_lds ||
             (size_t)g.H * 4 > (size_t)g_max_lds)
             return fail(nullptr, PA_E_INVAL, "lattice too large for the workgroup LDS of this device");
     b->jmask.resize(nruns);
@@ -891,9 +905,9 @@ pa_status pa_batch_tune(pa_batch *p, int32_t theta, int32_t *threads_out)
     for (int g = 0; g < b->v.ngroups && e == hipSuccess; ++g) {
         float best = 1e30f;
         int best_t = b->v.gthreads[g];
-        for (int t = 64; t <= 512 && e == hipSuccess; t += 64) {
+        for (int t = 64; t <= 768 && e == hipSuccess; t += 64) {
             if (!sweep_threads_ok(b->v.gN[g], b->v.gd[g], t) ||
-                pa_sweep_lds_bytes(b->v.gN[g], t) > (size_t)g_max_lds)
+                pa_sweep_lds_bytes(b->v.gN[g], t, b->v.gJ[g] != 0) > (size_t)g_max_lds)
                 continue;
             e = pa_b_sweep_group(b->v, g, theta, t); // warm-up
             if (e == hipSuccess)

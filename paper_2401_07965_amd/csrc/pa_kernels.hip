@@ -17,7 +17,7 @@
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kSweepMaxThreads = 512;
+constexpr int kSweepMaxThreads = 768;
 constexpr int kRuleThreads = 1024;
 constexpr int kRuleCache = 4096; // levels whose weights stay in LDS between the two sums
 
@@ -392,7 +392,6 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
 {
     // dynamic LDS: lattice [N] u64 | queues [waves][3][kQueue] u64 | queue sites [waves][kQueue] u32 | jmask [N]
     extern __shared__ uint64_t lat[];
-    __shared__ uint64_t red[kSweepMaxThreads / 64][32];
     const PaBlk blk = map[blockIdx.x];
     const PaRunDesc &rd = runs[blk.run];
     PaRecord *rec = rd.dv.rec;
@@ -443,6 +442,8 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
         all_draw ? sweep_columns<D, J, true>(lat, jl, G, pc, Q, theta, t0, sure4, sure8, sure12, draw4, draw8, draw12)
                  : sweep_columns<D, J, false>(lat, jl, G, pc, Q, theta, t0, sure4, sure8, sure12, draw4, draw8, draw12);
 
+    // after the sweeps the queue region is free: per-wave partial counts of the measurement
+    uint64_t *red = lat + N;
     // measure: forward bonds once each, plus the down-spin count
     uint64_t ve[8] = {0, 0, 0, 0, 0, 0, 0, 0}, vm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int s = tid; s < N; s += bs) {
@@ -482,8 +483,8 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
     if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            red[wave][k] = ce[k];
-            red[wave][16 + k] = cm[k];
+            red[wave * 32 + k] = ce[k];
+            red[wave * 32 + 16 + k] = cm[k];
         }
     }
     __syncthreads();
@@ -491,8 +492,8 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
         uint32_t U = 0, nd = 0;
         for (int v = 0; v < nw; ++v)
             for (int k = 0; k < 16; ++k) {
-                U += (uint32_t)((red[v][k] >> lane) & 1u) << k;
-                nd += (uint32_t)((red[v][16 + k] >> lane) & 1u) << k;
+                U += (uint32_t)((red[v * 32 + k] >> lane) & 1u) << k;
+                nd += (uint32_t)((red[v * 32 + 16 + k] >> lane) & 1u) << k;
             }
         const int64_t r = 64 * (int64_t)w + lane;
         if (r < Rlive) {
@@ -1607,7 +1608,7 @@ hipError_t sweep_launch(const PaBatchView &v, int g, int theta, int threads, uin
 {
     if (v.gncol[g] == 0)
         return hipSuccess;
-    const size_t lds = pa_sweep_lds_bytes(v.gN[g], threads);
+    const size_t lds = pa_sweep_lds_bytes(v.gN[g], threads, v.gJ[g] != 0);
     if (v.gd[g] == 2 && v.gJ[g])
         k_sweep<2, true><<<v.gncol[g], threads, lds, st>>>(v.runs, v.gcol[g], theta, t0);
     else if (v.gd[g] == 2)
@@ -1622,9 +1623,9 @@ hipError_t sweep_launch(const PaBatchView &v, int g, int theta, int threads, uin
 } // namespace
 
 // ====================================================================== launchers
-size_t pa_sweep_lds_bytes(int N, int threads)
+size_t pa_sweep_lds_bytes(int N, int threads, bool J)
 {
-    return (size_t)N * 8 + (size_t)(threads / 64) * kQueue * (3 * 8 + 4) + (((size_t)N + 7) & ~(size_t)7);
+    return (size_t)N * 8 + (size_t)(threads / 64) * kQueue * (3 * 8 + 4) + (J ? (((size_t)N + 7) & ~(size_t)7) : 0);
 }
 
 hipError_t pa_query_lds(int *max_lds)
