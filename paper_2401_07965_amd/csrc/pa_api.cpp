@@ -92,15 +92,19 @@ bool sweep_threads_ok(int N, int d, int t)
 }
 
 constexpr int kLdsPerCu = 163840;  // gfx950: 160 KiB of LDS per CU
-constexpr int kSweepWavesPerSimd = 3; // the sweep kernel's register use allows 3 waves per SIMD
+constexpr int kSweepWavesPerSimd = 3; // the sweep kernel's register use allows at least 3 waves per SIMD
 
-// Default sweep workgroup size: the one that keeps the most sweep waves
-// resident per CU (LDS of the lattice and queues, registers), the smaller on
-// ties (more sites per lane, fewer waits per site).
+// Default sweep workgroup size, by a score: resident sweep waves per CU
+// (limited by the LDS of the lattice and queues and by registers; counted up
+// to 3 per SIMD, beyond which more waves hide no more latency) times the
+// fraction of lanes busy over a colour's sites (N/2 sites in rounds of t
+// lanes).  The smaller size wins ties.  Autotuning refines it for batches.
 int default_sweep_threads(int N, int d, bool J)
 {
     const int lds_max = g_max_lds ? g_max_lds : kLdsPerCu;
-    int best = 0, best_waves = -1;
+    const int nh = N / 2;
+    int best = 0;
+    double best_score = -1.0;
     for (int t = 64; t <= 768; t += 64) {
         const size_t lds = pa_sweep_lds_bytes(N, t, J);
         if (!sweep_threads_ok(N, d, t) || lds > (size_t)lds_max)
@@ -109,8 +113,13 @@ int default_sweep_threads(int N, int d, bool J)
         int blocks = (int)(kLdsPerCu / lds);
         if (blocks > 4 * kSweepWavesPerSimd / w)
             blocks = 4 * kSweepWavesPerSimd / w;
-        if (blocks * w > best_waves) {
-            best_waves = blocks * w;
+        int waves = blocks * w;
+        if (waves > 4 * kSweepWavesPerSimd)
+            waves = 4 * kSweepWavesPerSimd;
+        const int rounds = (nh + t - 1) / t;
+        const double score = waves * ((double)nh / ((double)rounds * t));
+        if (score > best_score + 1e-9) {
+            best_score = score;
             best = t;
         }
     }
