@@ -309,6 +309,39 @@ def batched_bench(theta=10, scheme=3, verify_runs=8):
     }
 
 
+def combination_study(L=16, R=100, theta=1, runs=1024, points=21, beta_f=0.44):
+    """Weighted combination of M runs (Sec. 4): 1024 seeded 2D ferromagnet runs
+    far from equilibrium (R = 100, theta = 1, 21 temperature points to beta
+    0.44), one batched anneal; then for M in 1, 4, 16, 64, 256 the runs are
+    combined in groups of M and each estimator is averaged over the groups.
+    The reference is the weighted combination of all runs (the most accurate
+    estimate available here; the tests compare with the exact values)."""
+    import numpy as np
+    import torch
+    from paper_2401_07965_amd import pa, workloads
+    betas = workloads.linear_schedule(beta_f, points)
+    cfgs = [dict(dim=2, L=L, R=R, seed=11, run_id=k, couplings=None) for k in range(runs)]
+    B = pa.PABatch(cfgs, max_points=len(betas))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.anneal(betas, theta, 3, use_graph=True)
+    torch.cuda.synchronize()
+    anneal_s = time.perf_counter() - t0
+    point = len(betas) - 1
+    ref = B.combine([0] * runs, 1, point)[0]
+    table = {}
+    for M in (1, 4, 16, 64, 256):
+        out = B.combine([k // M for k in range(runs)], runs // M, point)
+        table[M] = {key: float(np.mean([o[key] for o in out]) - ref[ref_key])
+                    for key, ref_key in (("e", "e"), ("e_plain", "e"), ("c", "c"), ("c_naive", "c"),
+                                         ("c_plain", "c"))}
+    B.close()
+    return {"workload": f"{runs} runs 2D Ising FM L={L}, R={R}, theta={theta}, beta 0->{beta_f} in "
+                        f"{points} points, systematic; groups of M combined",
+            "anneal_s": anneal_s, "reference_e": ref["e"], "reference_c": ref["c"],
+            "deviation_from_reference": table}
+
+
 def learned_bench(theta=10, scheme=3, astar=0.7, dmax=0.2, beta_f=3.0):
     """Learned-schedule workload: 3D +-J glass L = 16.  The model is trained on
     the GPU from rule-driven anneals of 8 other disorder samples at R = 10^4;
@@ -485,6 +518,7 @@ def main():
     if not a.no_rows:
         out["batched"] = batched_bench()
         out["learned"] = learned_bench()
+        out["combination"] = combination_study()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

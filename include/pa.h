@@ -253,6 +253,10 @@ typedef struct {
     double chi;          /* W_var of the susceptibility, Eq. (12), with |m| */
     double n_eff;        /* 1 / sum_m omega_m^2 */
     double beta;
+    /* for comparison (Fig. 5 left, Fig. 8): the naive weighted averages
+       sum_m omega_m c_m, sum_m omega_m chi_m of each run's own c_m, chi_m, and
+       the plain means over the runs of e, c_m and chi_m */
+    double c_naive, chi_naive, e_plain, c_plain, chi_plain;
     int32_t runs, pad;
 } pa_combined;
 

@@ -276,7 +276,7 @@ uint64_t layout(const std::vector<Geometry> &geo, int max_points, char *base, Ba
     char *p_steprec = take(sizeof(PaStepRecord) * (uint64_t)M * (uint64_t)(max_points > 0 ? max_points : 0));
     char *p_group = take(4ull * M);
     char *p_Ns = take(4ull * M);
-    char *p_comb = take(80ull * M);
+    char *p_comb = take(8ull * PA_COMBINE_FIELDS * M);
     std::vector<PaDev> devs(M);
     for (int m = 0; m < M; ++m) {
         char *rb = take(0); // current offset
@@ -1070,7 +1070,7 @@ pa_status pa_batch_combine(pa_batch *p, const int32_t *group_of_run, int32_t ngr
         e = hipMemcpyAsync(b->dNs, Ns.data(), 4ull * b->M, hipMemcpyHostToDevice, v.stream);
     if (e == hipSuccess)
         e = pa_launch_combine(v, point, b->dgroup, ngroups, b->dNs, b->dcomb);
-    std::vector<double> h((size_t)ngroups * 10);
+    std::vector<double> h((size_t)ngroups * PA_COMBINE_FIELDS);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h.data(), b->dcomb, h.size() * 8, hipMemcpyDeviceToHost, v.stream);
     if (e == hipSuccess)
@@ -1078,7 +1078,7 @@ pa_status pa_batch_combine(pa_batch *p, const int32_t *group_of_run, int32_t ngr
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_batch_combine");
     for (int g = 0; g < ngroups; ++g) {
-        const double *o = h.data() + (size_t)g * 10;
+        const double *o = h.data() + (size_t)g * PA_COMBINE_FIELDS;
         out[g].lnZ = o[0];
         out[g].e = o[1];
         out[g].e2 = o[2];
@@ -1089,6 +1089,11 @@ pa_status pa_batch_combine(pa_batch *p, const int32_t *group_of_run, int32_t ngr
         out[g].n_eff = o[7];
         out[g].runs = (int32_t)o[8];
         out[g].beta = o[9];
+        out[g].c_naive = o[10];
+        out[g].chi_naive = o[11];
+        out[g].e_plain = o[12];
+        out[g].c_plain = o[13];
+        out[g].chi_plain = o[14];
     }
     return PA_OK;
 }

@@ -109,6 +109,7 @@ struct PaBlk {
 };
 
 #define PA_MAX_GROUPS 16
+#define PA_COMBINE_FIELDS 15 // doubles per group written by the combination kernel
 
 // Learned temperature-step model: 8 -> 64 -> 64 -> 1.
 #define PA_MLP_HIDDEN 64

@@ -1511,7 +1511,7 @@ __global__ __launch_bounds__(kThreads) void k_overlap(const PaRunDesc *__restric
 // weighted averages and c, chi follow Eqs. (11)-(12).
 __global__ void k_combine(const PaStepRecord *__restrict__ steprec, int npoints, int point,
                           const int32_t *__restrict__ group_of, int nruns, int ngroups, const int32_t *__restrict__ Ns,
-                          double *__restrict__ out /* [ngroups][10] */)
+                          double *__restrict__ out /* [ngroups][PA_COMBINE_FIELDS] */)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ngroups)
@@ -1531,6 +1531,7 @@ __global__ void k_combine(const PaStepRecord *__restrict__ steprec, int npoints,
         ++n;
     }
     double den = 0.0, e = 0.0, e2 = 0.0, am = 0.0, m2 = 0.0, w2 = 0.0, beta = 0.0;
+    double cn = 0.0, chn = 0.0, ep = 0.0, cp = 0.0, chp = 0.0; // naive weighted and plain means
     for (int m = 0; m < nruns && n > 0; ++m) {
         if (group_of[m] != g)
             continue;
@@ -1552,8 +1553,15 @@ __global__ void k_combine(const PaStepRecord *__restrict__ steprec, int npoints,
         am = am + om * r.abs_m;
         m2 = m2 + om * r.m2;
         w2 = w2 + om * om;
+        const double c_m = beta * beta * (double)N * (r.e2 - r.e * r.e); // the run's own c and chi
+        const double chi_m = beta * (double)N * (r.m2 - r.abs_m * r.abs_m);
+        cn = cn + om * c_m;
+        chn = chn + om * chi_m;
+        ep = ep + r.e;
+        cp = cp + c_m;
+        chp = chp + chi_m;
     }
-    double *o = out + (size_t)g * 10;
+    double *o = out + (size_t)g * PA_COMBINE_FIELDS;
     o[0] = n > 0 ? lmax + log(den) - log(Rsum) : NAN;
     o[1] = e;
     o[2] = e2;
@@ -1564,6 +1572,11 @@ __global__ void k_combine(const PaStepRecord *__restrict__ steprec, int npoints,
     o[7] = n > 0 ? 1.0 / w2 : 0.0;
     o[8] = (double)n;
     o[9] = beta;
+    o[10] = cn;
+    o[11] = chn;
+    o[12] = n > 0 ? ep / (double)n : NAN;
+    o[13] = n > 0 ? cp / (double)n : NAN;
+    o[14] = n > 0 ? chp / (double)n : NAN;
 }
 
 // Imported state: thresholds of its beta and the scalars.

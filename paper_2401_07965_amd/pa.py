@@ -57,7 +57,8 @@ class pa_step_record(ctypes.Structure):
 
 class pa_combined(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in ("lnZ", "e", "e2", "abs_m", "m2", "c", "chi", "n_eff",
-                                               "beta")] + \
+                                               "beta", "c_naive", "chi_naive", "e_plain", "c_plain",
+                                               "chi_plain")] + \
                [("runs", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 

@@ -151,6 +151,7 @@ def test_weighted_combination_matches_oracle():
                   for m in range(len(cfgs)) if groups[m] == g]
             ref = OC.combine(rs, 64)
             assert out[g]["runs"] == ref["runs"]
-            for k in ("lnZ", "e", "e2", "abs_m", "m2", "c", "chi", "n_eff"):
+            for k in ("lnZ", "e", "e2", "abs_m", "m2", "c", "chi", "n_eff", "c_naive", "chi_naive",
+                      "e_plain", "c_plain", "chi_plain"):
                 assert rel_ok(out[g][k], ref[k], 1e-12), (point, g, k, out[g][k], ref[k])
     B.close()

@@ -1,0 +1,55 @@
+"""Weighted combination of M runs (Sec. 4, Eqs. (9)-(12), Fig. 5): on runs far
+from equilibrium, the free-energy-weighted average removes the bias of the
+plain average as M grows, and for the specific heat only the weighting of the
+non-central moments (W_var, Eq. (11)) does, while the naive weighted average of
+each run's own c does not.  2D Ising ferromagnet L = 16 against the exact
+finite-lattice values (Kaufman); 1024 seeded runs in one batch, so the numbers
+are fixed by the seeds."""
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+from oracle import exact
+
+pytestmark = pytest.mark.gpu
+
+
+def exact_e_c(L, beta):
+    """Energy and specific heat per spin from the 60-digit ln Z."""
+    N = L * L
+    with mp.workdps(60):
+        b, h = mp.mpf(beta), mp.mpf("1e-15")
+        l0, lp, lm = (exact.kaufman_lnZ_mp(L, x) for x in (b, b + h, b - h))
+        return float(-(lp - lm) / (2 * h)) / N, float(b * b * (lp - 2 * l0 + lm) / (h * h)) / N
+
+
+def test_weighted_averages_remove_the_bias_of_m_runs():
+    from paper_2401_07965_amd import pa, workloads
+    L, R, theta, K = 16, 100, 1, 1024
+    betas = workloads.linear_schedule(0.44, 21)  # few, large steps and theta = 1: far from equilibrium
+    print(f"[mrun] 2D FM L={L} R={R} theta={theta} runs={K}", flush=True)
+    cfgs = [dict(dim=2, L=L, R=R, seed=11, run_id=k, couplings=None) for k in range(K)]
+    B = pa.PABatch(cfgs, max_points=len(betas))
+    B.anneal(betas, theta, 3, use_graph=True)
+    point = len(betas) - 1
+    e_ex, c_ex = exact_e_c(L, betas[point])
+    bias, sd = {}, {}
+    for M in (1, 64, 256):
+        out = B.combine([k // M for k in range(K)], K // M, point)
+        for key, ex in (("e", e_ex), ("e_plain", e_ex), ("c", c_ex), ("c_naive", c_ex),
+                        ("c_plain", c_ex)):
+            v = np.array([o[key] for o in out])
+            bias[key, M] = float(v.mean() - ex)
+            sd[key, M] = float(v.std() / math.sqrt(len(v) - 1))
+    B.close()
+    print("[mrun] bias", {f"{k}@{M}": round(b, 4) for (k, M), b in bias.items()}, flush=True)
+    plain_e, plain_c = bias["e_plain", 1], bias["c_plain", 1]
+    assert abs(plain_e) > 10 * sd["e_plain", 1]       # the runs are biased
+    assert abs(plain_c) > 10 * sd["c_plain", 1]
+    assert abs(bias["e_plain", 256] - plain_e) < 1e-9  # a plain mean does not change with M
+    assert abs(bias["e", 256]) < 0.3 * abs(plain_e)    # the weighted mean removes the bias
+    assert abs(bias["e", 64]) < 0.3 * abs(plain_e)
+    assert abs(bias["c", 64]) < 0.5 * abs(plain_c)     # W_var of Eq. (11) removes most of it
+    assert abs(bias["c_naive", 64]) > 0.8 * abs(plain_c)  # the naive weighting does not

@@ -41,3 +41,24 @@ def test_variance_estimators_eq11_eq12():
     c = combine([run(10, 0.0, e=-1.2, e2=1.5, am=0.4, m2=0.2, beta=0.7)], 100)
     assert abs(c["c"] - 0.49 * 100 * (1.5 - 1.44)) < 1e-12
     assert abs(c["chi"] - 0.7 * 100 * (0.2 - 0.16)) < 1e-12
+
+
+def test_naive_and_plain_schemes():
+    """W_var c exceeds the naive weighted c by exactly beta^2 N times the weighted
+    variance of the runs' energies (and likewise for chi with |m|); identical
+    runs make all schemes agree; equal weights make plain = weighted."""
+    rs = [run(1000, 10.0, e=-1.0, e2=1.10, am=0.50, m2=0.30),
+          run(2000, 11.0, e=-1.2, e2=1.50, am=0.40, m2=0.20),
+          run(500, 9.5, e=-0.9, e2=0.85, am=0.60, m2=0.40)]
+    N, b = 16, 0.5
+    c = combine(rs, N)
+    om = c["omega"]
+    var_e = sum(o * (r["e"] - c["e"]) ** 2 for o, r in zip(om, rs))
+    var_m = sum(o * (r["abs_m"] - c["abs_m"]) ** 2 for o, r in zip(om, rs))
+    assert abs((c["c"] - c["c_naive"]) - b * b * N * var_e) < 1e-12
+    assert abs((c["chi"] - c["chi_naive"]) - b * N * var_m) < 1e-12
+    assert c["c"] >= c["c_naive"] and c["chi"] >= c["chi_naive"]
+    same = combine([run(1000, 5.0 + k, e=-1.1, e2=1.3) for k in range(4)], N)
+    assert abs(same["c"] - same["c_naive"]) < 1e-12 and abs(same["c_plain"] - same["c"]) < 1e-12
+    eq = combine([run(700, 3.0, e=-1 - 0.1 * k, e2=1.2 + 0.05 * k) for k in range(5)], N)
+    assert abs(eq["e_plain"] - eq["e"]) < 1e-15 and abs(eq["c_plain"] - eq["c_naive"]) < 1e-12
