@@ -342,6 +342,44 @@ def combination_study(L=16, R=100, theta=1, runs=1024, points=21, beta_f=0.44):
             "deviation_from_reference": table}
 
 
+def resampling_study():
+    """Resampling diagnostics per scheme (Sec. 3): the sampling variance of
+    Eq. (5) along beta_i = i/300 (2D FM L = 64, R = 2 10^4, theta = 5, up to
+    beta = 0.6), and the resampling cost d rho_t / d beta over beta 0 -> 0.3
+    for temperature steps from 0.0005 to 0.03 (2D FM L = 32, R = 2 10^4,
+    theta = 5)."""
+    import numpy as np
+    from paper_2401_07965_amd import pa
+    t0 = time.perf_counter()
+    sv = {}
+    for name, sc in SCHEMES:
+        g = pa.PARun(2, 64, 20000, seed=3, run_id=sc)
+        vals = []
+        for i in range(1, 181):
+            g.reweight(i / 300.0, wait=False)
+            g.resample(sc, wait=False)
+            g.sweep(5)
+            o = g.observables()
+            vals.append((i / 300.0, o["sv"]))
+        g.close()
+        a = np.array(vals)
+        near = a[(a[:, 0] > 0.40) & (a[:, 0] < 0.48)]
+        sv[name] = {"mean": float(a[:, 1].mean()), "near_beta_c": float(near[:, 1].mean())}
+    cost = {}
+    for name, sc in SCHEMES:
+        cost[name] = {}
+        for db in (0.0005, 0.001, 0.002, 0.005, 0.01, 0.03):
+            n = int(round(0.3 / db))
+            g = pa.PARun(2, 32, 20000, seed=5, run_id=100 + sc)
+            for i in range(1, n + 1):
+                g.reweight(i * db, wait=False)
+                g.resample(sc, wait=False)
+                g.sweep(5)
+            cost[name][str(db)] = (g.observables()["rho_t"] - 1.0) / 0.3
+            g.close()
+    return {"sampling_variance": sv, "resampling_cost_drho_dbeta": cost, "wall_s": time.perf_counter() - t0}
+
+
 def learned_bench(theta=10, scheme=3, astar=0.7, dmax=0.2, beta_f=3.0):
     """Learned-schedule workload: 3D +-J glass L = 16.  The model is trained on
     the GPU from rule-driven anneals of 8 other disorder samples at R = 10^4;
@@ -519,6 +557,7 @@ def main():
         out["batched"] = batched_bench()
         out["learned"] = learned_bench()
         out["combination"] = combination_study()
+        out["resampling"] = resampling_study()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
