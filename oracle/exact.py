@@ -26,18 +26,25 @@ def neighbor_index(d, L, mu):
     return np.roll(g, -1, axis=d - 1 - mu).reshape(-1)
 
 
-def brute_force(d, L, J):
-    """Density of states {E: count} over all 2^N spin states (N <= 20)."""
+def enumerate_states(d, L, J):
+    """All 2^N spin states (N <= 20) as int8 rows, state c having sigma_s = -1
+    where bit s of c is set, with their energies (Eq. (4), bond-wise J)."""
     N = L ** d
     if N > 20:
         raise ValueError("too many states")
     J = np.asarray(J, np.int64).reshape(N, d)
     c = np.arange(2 ** N, dtype=np.int64)[:, None]
-    sigma = 1 - 2 * ((c >> np.arange(N)[None, :]) & 1)  # bit s set -> sigma_s = -1
+    sigma = 1 - 2 * ((c >> np.arange(N)[None, :]) & 1)
     E = np.zeros(2 ** N, np.int64)
     for mu in range(d):
         nb = neighbor_index(d, L, mu)
         E -= (J[:, mu][None, :] * sigma * sigma[:, nb]).sum(axis=1)
+    return sigma.astype(np.int8), E
+
+
+def brute_force(d, L, J):
+    """Density of states {E: count} over all 2^N spin states (N <= 20)."""
+    _, E = enumerate_states(d, L, J)
     vals, cnt = np.unique(E, return_counts=True)
     return dict(zip(vals.tolist(), cnt.tolist()))
 

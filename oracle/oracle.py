@@ -9,7 +9,10 @@ sampling variance of Eq. (5) and the free energy of Eq. (7).
 
 The step cycle follows the enumerated algorithm of Sec. 2: ``reweight`` to the
 next inverse temperature (step 2, Q of Eq. (1)), ``resample`` (step 2, Sec. 3),
-``sweep`` (step 3), ``observables`` (step 4).
+``sweep`` (step 3), ``observables`` (step 4).  ``resample_conditional``
+resamples only when the weights' effective sample size is small (the remark
+of Sec. 3 that resampling need not happen at every step); a kept population
+carries importance weights, which reweighting and the averages then use.
 """
 import ctypes
 import math
@@ -177,6 +180,63 @@ def tau_hat(W, S, R_target):
     return (W.astype(np.float64) / float(S)) * float(R_target)
 
 
+# --------------------------------------------------------------------------- weighted populations
+# Sec. 3 notes that resampling need not happen at every temperature step: the
+# population can be kept, with importance weights, until their variance grows
+# too large.  A kept replica j carries a log-weight lw_j <= 0 (largest 0); its
+# weight at the next inverse temperature is exp(lw_j - dbeta E_j), so Q of
+# Eq. (1) becomes the ratio of weighted sums and the resampling draws with
+# tauhat_j proportional to that weight.
+
+def weighted_reweight(E, lw, dbeta):
+    """Reweighting of a population with log-weights ``lw`` (zeros: uniform).
+
+    With x_j = lw_j + (-(dbeta (E_j - E_min))) and m = min_j |x_j| (every x_j is
+    <= 0, so max_j x_j = -m):
+      lnQ = ln sum_j exp(lw_j - dbeta E_j) - ln sum_j exp(lw_j)
+          = -dbeta E_min - m + ln sum_j exp(x_j + m) - ln sum_j exp(lw_j),
+      W_j = floor(2^40 pa_exp(x_j + m)),  S = sum_j W_j,
+    and the log-weights the population keeps if it is not resampled are
+    x_j + m.  With lw = 0 the integer weights are those of ``reweight``.
+    """
+    E = np.asarray(E, np.int64)
+    lw = np.asarray(lw, np.float64)
+    emin = int(E.min())
+    x = lw + (-(float(dbeta) * (E - emin).astype(np.float64)))
+    m = float(np.abs(x).min())
+    y = x + m
+    W = np.floor(np.ldexp(pa_exp_array(y), 40)).astype(np.uint64)
+    lnQ = (-float(dbeta) * emin - m + math.log(float(np.sum(np.exp(y))))
+           - math.log(float(np.sum(np.exp(lw)))))
+    return dict(lnQ=lnQ, W=W, S=int(W.sum(dtype=np.uint64)), lw_next=y)
+
+
+KAPPA_ONE = 65536  # the ESS fraction kappa in units of 2^-16
+
+
+def kappa_units(kappa):
+    """kappa in [0, 1] as an integer count of 2^-16 (nearest, halves up)."""
+    if not 0.0 <= kappa <= 1.0:
+        raise ValueError("kappa must lie in [0, 1]")
+    return int(math.floor(kappa * KAPPA_ONE + 0.5))
+
+
+def ess_resamples(W, kq):
+    """Whether the population resamples: its effective sample size
+    ESS = (sum_j W_j)^2 / sum_j W_j^2 lies below kappa R, decided exactly in
+    integers as 2^16 S^2 < kq R sum_j W_j^2 (R = len(W), kq = kappa 2^16)."""
+    S = sum(int(w) for w in W)
+    Q2 = sum(int(w) * int(w) for w in W)
+    return KAPPA_ONE * S * S < int(kq) * len(W) * Q2, S, Q2
+
+
+def ess(W):
+    """ESS = S^2 / sum W^2 as a double."""
+    S = sum(int(w) for w in W)
+    Q2 = sum(int(w) * int(w) for w in W)
+    return S * S / Q2
+
+
 # --------------------------------------------------------------------------- one PA run
 class PAError(Exception):
     pass
@@ -195,7 +255,9 @@ class OracleRun:
 
     State: replicas' int8 spins (row = replica), energies, family labels, the
     current inverse temperature, the step index i, the sweep counter t within
-    the step and ln Z_hat = ln Z_0 + sum_k ln Q_k (Eq. (7)).
+    the step and ln Z_hat = ln Z_0 + sum_k ln Q_k (Eq. (7)).  After a step that
+    kept its population (``resample_conditional``) the replicas carry
+    log-weights ``lw`` (None: uniform).
     """
 
     def __init__(self, d, L, R, seed=1, run_id=0, J=None, capacity=None):
@@ -216,6 +278,8 @@ class OracleRun:
         self.pending = None
         self.last_sv = 0.0
         self.last_counts = None
+        self.lw = None
+        self.resamplings = 0
 
     @property
     def Rcur(self):
@@ -225,14 +289,51 @@ class OracleRun:
         self.spins = np.ascontiguousarray(spins, np.int8).copy()
         self.E = np.ascontiguousarray(E, np.int32).copy()
         self.label = np.ascontiguousarray(label, np.uint32).copy()
+        self.lw = None
+
+    def log_weights(self):
+        """Per-replica log-weights (zeros for a uniform population)."""
+        return np.zeros(self.Rcur) if self.lw is None else self.lw.copy()
 
     def reweight(self, beta_next):
         if beta_next < self.beta:
             raise ValueError("beta must not decrease")
         dbeta = float(beta_next) - self.beta
-        lnQ, W, S = reweight(self.E, dbeta)
-        self.pending = dict(beta=float(beta_next), lnQ=lnQ, W=W, S=S)
+        if self.lw is None:
+            lnQ, W, S = reweight(self.E, dbeta)
+            self.pending = dict(beta=float(beta_next), lnQ=lnQ, W=W, S=S, dbeta=dbeta)
+        else:
+            p = weighted_reweight(self.E, self.lw, dbeta)
+            lnQ = p["lnQ"]
+            self.pending = dict(beta=float(beta_next), lnQ=lnQ, W=p["W"], S=p["S"], dbeta=dbeta,
+                                lw_next=p["lw_next"])
         return lnQ
+
+    def resample_conditional(self, scheme, kappa):
+        """Resample (as ``resample``) only if the effective sample size of the
+        step's weights is below kappa R_cur; otherwise keep the population with
+        its new log-weights, and advance beta, the step and ln Z_hat as a
+        resampling would.  Returns (R, resampled)."""
+        if self.pending is None:
+            raise PAError("resample before reweight")
+        go, _, _ = ess_resamples(self.pending["W"], kappa_units(kappa))
+        if go:
+            return self.resample(scheme), True
+        p = self.pending
+        lw_next = p.get("lw_next")
+        if lw_next is None:
+            lw_next = weighted_reweight(self.E, np.zeros(self.Rcur), p["dbeta"])["lw_next"]
+        if not math.isfinite(p["lnQ"]):
+            raise PAError("ln Q is not finite")
+        self.lw = lw_next
+        self.last_sv = 0.0
+        self.last_counts = None
+        self.lnZ += p["lnQ"]
+        self.beta = p["beta"]
+        self.step += 1
+        self.t = 0
+        self.pending = None
+        return self.Rcur, False
 
     def resample(self, scheme):
         if self.pending is None:
@@ -249,6 +350,8 @@ class OracleRun:
         self.last_sv = float(np.mean((r.astype(np.float64) - tau) ** 2))
         self.last_counts = r
         self.spins, self.E, self.label = apply_counts(self.N, r, self.spins, self.E, self.label)
+        self.lw = None
+        self.resamplings += 1
         self.lnZ += p["lnQ"]
         self.beta = p["beta"]
         self.step = step
@@ -266,7 +369,7 @@ class OracleRun:
 
     def observables(self):
         return population_observables(self.N, self.E, self.magnetization(), self.label, self.R0,
-                                      self.last_sv)
+                                      self.last_sv, self.lw)
 
     def free_energy(self):
         """ln Z_hat = -beta_i F_hat_i, Eq. (7)."""
@@ -281,13 +384,18 @@ def default_capacity(R):
     return (c + 63) // 64 * 64
 
 
-def population_observables(N, E, M, label, R0, sv):
+def population_observables(N, E, M, label, R0, sv, lw=None):
     """Plain population averages (step 4 of Sec. 2) and the family statistics.
 
     Exact integer sums, then: e = <E>/N, e2 = <E^2>/N^2, e3 = <E^3>/N^3, |m|, m^2, the family
     measure rho_t = R sum_k n_k^2 of Eq. (6) with n_k = c_k / R (so
     rho_t = sum_k c_k^2 / R), the family entropy S_f = -sum_k n_k ln n_k and
     the sampling variance of the last resampling, Eq. (5).
+
+    A weighted population (log-weights ``lw``) reports the weighted averages
+    sum_j w_j O_j / sum_j w_j, w_j = exp(lw_j), in e, e2, e3, abs_m and m2, and
+    its effective size ess = (sum w)^2 / sum w^2; the integer sums and the
+    family statistics stay those of the members.
     """
     R = len(E)
     E = np.asarray(E, np.int64)
@@ -309,8 +417,19 @@ def population_observables(N, E, M, label, R0, sv):
     var = sumE2 / R - mean * mean
     m3 = float(np.mean((Ef - mean) ** 3))
     skew = m3 / var ** 1.5 if var > 0 else 0.0
-    return dict(R=R, sumE=sumE, sumE2=sumE2, sumE3=sumE3, sumAbsM=sumAbsM, sumM2=sumM2, sumC2=sumC2,
-                families=int((c > 0).sum()), e=sumE / (N * R), e2=sumE2 / (N * N * R),
-                e3=sumE3 / (N * N * N * R),
-                abs_m=sumAbsM / (N * R), m2=sumM2 / (N * N * R), rho_t=rho_t, S_f=S_f, sv=sv,
-                E_mean=mean, E_var=var, E_skew=skew)
+    out = dict(R=R, sumE=sumE, sumE2=sumE2, sumE3=sumE3, sumAbsM=sumAbsM, sumM2=sumM2, sumC2=sumC2,
+               families=int((c > 0).sum()), e=sumE / (N * R), e2=sumE2 / (N * N * R),
+               e3=sumE3 / (N * N * N * R),
+               abs_m=sumAbsM / (N * R), m2=sumM2 / (N * N * R), rho_t=rho_t, S_f=S_f, sv=sv,
+               E_mean=mean, E_var=var, E_skew=skew, weighted=False, ess=float(R))
+    if lw is not None:
+        w = np.exp(np.asarray(lw, np.float64))
+        sw = float(w.sum())
+        Mf = M.astype(np.float64)
+
+        def avg(v):
+            return float(np.sum(w * v)) / sw
+        out.update(e=avg(Ef) / N, e2=avg(Ef * Ef) / (N * N), e3=avg(Ef * Ef * Ef) / (N * N * N),
+                   abs_m=avg(np.abs(Mf)) / N, m2=avg(Mf * Mf) / (N * N), weighted=True,
+                   ess=sw * sw / float(np.sum(w * w)))
+    return out
