@@ -12,6 +12,9 @@
  *   pa_observables step 4: plain population averages, family statistics
  *                  (Eq. (6)) and the sampling variance (Eq. (5))
  *   pa_free_energy ln Z_hat = ln Z_{beta_0} + sum_k ln Q_k, Eq. (7)
+ *   pa_resample_conditional
+ *                  Sec. 3 remark: resample only when the weights' variance is
+ *                  large; otherwise keep the population with importance weights
  *
  * Conventions (every call):
  *  - The return value is a pa_status; nothing aborts or throws across the ABI.
@@ -25,8 +28,9 @@
  *    distinct streams.  Calls that return results to the host (pa_reweight,
  *    pa_resample, pa_observables, pa_free_energy, pa_export_state) synchronise
  *    the stream; pa_sweep only enqueues.
- *  - Deferred calls: pa_reweight, pa_resample and pa_observables given a NULL
- *    result pointer only enqueue their kernels and return at once, so that a
+ *  - Deferred calls: pa_reweight, pa_resample, pa_resample_conditional and
+ *    pa_observables given NULL result pointers only enqueue their kernels and
+ *    return at once, so that a
  *    whole temperature step runs without waiting for the device.  A failure
  *    that pa_resample would report (PA_E_CAPACITY, PA_E_EXTINCT,
  *    PA_E_NONFINITE) then freezes the run instead: its population stays as it
@@ -102,6 +106,14 @@ typedef struct {
     int64_t sum_E3_hi;    /* sum of E^3 over replicas, exact: the signed 128-bit */
     uint64_t sum_E3_lo;   /*   integer sum_E3_hi * 2^64 + sum_E3_lo */
     double e3;            /* <E^3>/N^3 */
+    double ess;           /* (sum w)^2 / sum w^2 of the importance weights (R if uniform) */
+    int32_t weighted;     /* 1: the population carries importance weights (a step
+                             kept it, pa_resample_conditional); e, e2, e3, abs_m
+                             and m2 are then the weighted averages
+                             sum_j w_j O_j / sum_j w_j, w_j = exp(lw_j), while
+                             the sums, rho_t, S_f and families stay those of the
+                             members */
+    int32_t pad;
 } pa_obs;
 
 /* Host copy of a run's state (pa_export_state / pa_import_state).  Array
@@ -129,6 +141,7 @@ typedef struct {
     uint64_t sweeps;        /* sweeps over all sites, summed over pa_sweep calls */
     uint64_t spin_attempts; /* Metropolis attempts: theta N R_i summed over pa_sweep
                                calls (R_i the population at the call) */
+    uint64_t resamplings;   /* resamplings applied (a kept step is not one) */
 } pa_counters;
 
 typedef struct pa_ctx pa_ctx;
@@ -155,6 +168,11 @@ pa_status pa_sweep(pa_ctx *ctx, int32_t theta);
 /* Step 2 of Sec. 2: for beta_next >= beta, ln Q of Eq. (1) over the current
  * population, written as -dbeta E_min + ln((1/R) sum_j exp(-dbeta (E_j - E_min))).
  * Also fixes the integer resampling weights floor(2^40 exp(-dbeta (E_j - E_min))).
+ * A weighted population (log-weights lw_j <= 0, largest 0, left by
+ * pa_resample_conditional) uses x_j = lw_j + (-(dbeta (E_j - E_min))) and
+ * m = min_j |x_j|: W_j = floor(2^40 exp(x_j + m)) and
+ * ln Q = -dbeta E_min - m + ln sum_j exp(x_j + m) - ln sum_j exp(lw_j)
+ * (every operation IEEE-754 rounded on its own; exp is the library's own).
  * The population is unchanged; a second call replaces the first.
  * lnQ_out NULL: deferred (see the conventions above). */
 pa_status pa_reweight(pa_ctx *ctx, double beta_next, double *lnQ_out);
@@ -167,8 +185,30 @@ pa_status pa_reweight(pa_ctx *ctx, double beta_next, double *lnQ_out);
  * (a failure freezes the run, see the conventions above). */
 pa_status pa_resample(pa_ctx *ctx, pa_resampler scheme, int64_t *R_new_out);
 
+/* Conditional resampling (Sec. 3: resampling need not happen at every step;
+ * population control once the variance of the importance weights is too large
+ * can be enough).  After pa_reweight, with the step's integer weights W_j:
+ *   ESS = S^2 / sum_j W_j^2 < kappa R_i  ->  resample exactly as pa_resample;
+ *   otherwise keep the population: every member stays, replica j's log-weight
+ *   becomes lw_j := x_j + m (see pa_reweight), and beta := beta_next,
+ *   i := i + 1, ln Z_hat += ln Q as after a resampling, SV := 0.
+ * kappa in [0, 1] counts in units of 2^-16 (kq = floor(kappa 2^16 + 1/2)); the
+ * test is exact: 2^16 S^2 < kq R_i sum_j W_j^2.  kappa = 0 never resamples,
+ * kappa = 1 resamples unless all weights are equal.  A resampled population is
+ * uniform again.  Outputs: R_new_out (population after the step), resampled_out
+ * (1 resampled, 0 kept); both NULL: deferred (a failure freezes the run, see the
+ * conventions above).  Failures as pa_resample (PA_E_NONFINITE also when kept). */
+pa_status pa_resample_conditional(pa_ctx *ctx, pa_resampler scheme, double kappa, int64_t *R_new_out,
+                                  int32_t *resampled_out);
+
+/* Importance log-weights of the current population: out (host, double[R_i])
+ * gets lw_j (all 0 for a uniform population); weighted_out (optional) 1 if a
+ * kept step left weights.  Synchronises the stream. */
+pa_status pa_log_weights(pa_ctx *ctx, double *out, int32_t *weighted_out);
+
 /* Step 4 of Sec. 2 over the current population.  out NULL: deferred (the
- * averages are still computed on the device, e.g. for pa_features). */
+ * averages are still computed on the device, e.g. for pa_features).  For a
+ * weighted population see pa_obs.weighted. */
 pa_status pa_observables(pa_ctx *ctx, pa_obs *out);
 
 /* -beta_i F_hat_i = ln Z_{beta_0} + sum_{k<=i} ln Q_k (Eq. (7)). */
@@ -212,7 +252,9 @@ pa_status pa_step_alpha(pa_ctx *ctx, double dbeta, double *alpha_out);
  * keeping the lower end qualified (0 < alpha_star < 1, 1 <= iterations <= 200).
  * alpha_star counts to 2^-32 (A = nearest integer to 2^32 alpha_star, ties to
  * even; qualifies iff 2^32 sum_j min(S, R W_j) >= A R S, exact).
- * The population is unchanged; pass beta + dbeta to pa_reweight. */
+ * The population is unchanged; pass beta + dbeta to pa_reweight.
+ * The rule (and pa_step_alpha, pa_features, pa_step_learned) needs a uniform
+ * population: PA_E_STATE after a kept step until the next resampling. */
 pa_status pa_step_rule(pa_ctx *ctx, double alpha_star, double dbeta_max, int32_t iterations,
                        double *dbeta_out);
 

@@ -6,6 +6,7 @@
 #include "pa.h"
 #include "pa_internal.h"
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -159,6 +160,9 @@ uint64_t carve_run(const Geometry &g, char *base, PaDev *dv)
     d.tiles = (PaScanTile *)take((uint64_t)((g.cap + PA_SCAN_TILE - 1) / PA_SCAN_TILE) * 2 * sizeof(PaScanTile));
     d.partial = (double *)take(chunks * 8);
     d.fam = (uint32_t *)take((uint64_t)g.R * 4);
+    d.lw = (double *)take(slots * 8);
+    d.Wj = (uint64_t *)take(slots * 8);
+    d.wpart = (double *)take(chunks * PA_WPARTS * 8);
     d.rec = (PaRecord *)take(sizeof(PaRecord));
     if (dv)
         *dv = d;
@@ -501,6 +505,21 @@ pa_status ctx_records(Batch *b, const char *where)
     return PA_OK;
 }
 
+// The overlap rule and the learned step read the energy histogram, which
+// describes a uniform population only.
+pa_status need_uniform(Batch *b, const char *where)
+{
+    if (!b->v.weights)
+        return PA_OK;
+    pa_status s = ctx_records(b, where);
+    if (s != PA_OK)
+        return s;
+    if (b->hrec[0].weighted)
+        return fail(b, PA_E_STATE,
+                    std::string(where) + " needs a uniform population: a kept step left weights (resample first)");
+    return PA_OK;
+}
+
 pa_status export_run(Batch *b, int m, pa_host_state *st)
 {
     pa_status s = fetch_records(b, "export");
@@ -640,7 +659,7 @@ pa_status pa_resample(pa_ctx *c, pa_resampler scheme, int64_t *R_new_out)
     if (!b->reweighted)
         return fail(b, PA_E_STATE, "pa_resample needs a pa_reweight first");
     const bool deferred = R_new_out == nullptr;
-    hipError_t e = pa_b_resample(b->v, (int)scheme, deferred ? 1 : 0);
+    hipError_t e = pa_b_resample(b->v, (int)scheme, deferred ? 1 : 0, -1);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_resample");
     if (deferred) { // a failure freezes the run; the next synchronising call reports it
@@ -659,6 +678,72 @@ pa_status pa_resample(pa_ctx *c, pa_resampler scheme, int64_t *R_new_out)
     b->reweighted = false;
     if (R_new_out)
         *R_new_out = (int64_t)b->hrec[0].Rcur;
+    return PA_OK;
+}
+
+pa_status pa_resample_conditional(pa_ctx *c, pa_resampler scheme, double kappa, int64_t *R_new_out,
+                                  int32_t *resampled_out)
+{
+    if (!c)
+        return fail(nullptr, PA_E_INVAL, "ctx is NULL");
+    Batch *b = &c->b;
+    if ((int)scheme < 0 || (int)scheme > 3)
+        return fail(b, PA_E_INVAL, "unknown resampling scheme");
+    if (!(kappa >= 0.0 && kappa <= 1.0))
+        return fail(b, PA_E_INVAL, "kappa must lie in [0, 1]");
+    if (!b->reweighted)
+        return fail(b, PA_E_STATE, "pa_resample_conditional needs a pa_reweight first");
+    // From now on the reweighting runs the per-replica passes a weighted
+    // population needs.  This step's population is still uniform (only a step
+    // of this call can keep one), so its reweighting is complete already.
+    b->v.weights = true;
+    const int kq = (int)std::floor(kappa * 65536.0 + 0.5);
+    const bool deferred = R_new_out == nullptr && resampled_out == nullptr;
+    hipError_t e = pa_b_resample(b->v, (int)scheme, deferred ? 1 : 0, kq);
+    if (e != hipSuccess)
+        return hip_fail(b, e, "pa_resample_conditional");
+    if (deferred) {
+        b->beta = b->beta_next;
+        b->sweeps = 0;
+        b->reweighted = false;
+        return PA_OK;
+    }
+    pa_status s = ctx_records(b, "pa_resample_conditional");
+    if (s != PA_OK)
+        return s;
+    if (b->hrec[0].skip)
+        return status_error(b, b->hrec[0].status);
+    b->beta = b->beta_next;
+    b->sweeps = 0;
+    b->reweighted = false;
+    if (R_new_out)
+        *R_new_out = (int64_t)b->hrec[0].Rcur;
+    if (resampled_out)
+        *resampled_out = b->hrec[0].keep ? 0 : 1;
+    return PA_OK;
+}
+
+pa_status pa_log_weights(pa_ctx *c, double *out, int32_t *weighted_out)
+{
+    if (!c)
+        return fail(nullptr, PA_E_INVAL, "ctx is NULL");
+    Batch *b = &c->b;
+    if (!out)
+        return fail(b, PA_E_INVAL, "out is NULL");
+    pa_status s = fetch_records(b, "pa_log_weights");
+    if (s != PA_OK)
+        return s;
+    const PaRecord &r = b->hrec[0];
+    const int64_t R = (int64_t)r.Rcur;
+    if (r.weighted) {
+        hipError_t e = hipMemcpy(out, b->hdesc[0].dv.lw, (size_t)R * 8, hipMemcpyDeviceToHost);
+        if (e != hipSuccess)
+            return hip_fail(b, e, "pa_log_weights");
+    } else {
+        std::fill(out, out + R, 0.0);
+    }
+    if (weighted_out)
+        *weighted_out = r.weighted ? 1 : 0;
     return PA_OK;
 }
 
@@ -694,6 +779,9 @@ pa_status pa_observables(pa_ctx *c, pa_obs *out)
     out->sum_E3_hi = (int64_t)r.sumE3[1];
     out->sum_E3_lo = (uint64_t)r.sumE3[0];
     out->e3 = r.e3;
+    out->ess = r.ess;
+    out->weighted = r.weighted ? 1 : 0;
+    out->pad = 0;
     return PA_OK;
 }
 
@@ -808,6 +896,9 @@ pa_status pa_step_alpha(pa_ctx *c, double dbeta, double *alpha_out)
     Batch *b = &c->b;
     if (!alpha_out || !std::isfinite(dbeta) || dbeta < 0.0)
         return fail(b, PA_E_INVAL, "dbeta must be finite and >= 0; alpha_out non-NULL");
+    pa_status u = need_uniform(b, "pa_step_alpha");
+    if (u != PA_OK)
+        return u;
     hipError_t e = pa_b_rule(b->v, 0.0, dbeta, 0, 0);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_step_alpha");
@@ -826,6 +917,9 @@ pa_status pa_step_rule(pa_ctx *c, double alpha_star, double dbeta_max, int32_t i
     if (!dbeta_out || !(alpha_star > 0.0 && alpha_star < 1.0) || !std::isfinite(dbeta_max) || dbeta_max <= 0.0 ||
         iterations < 1 || iterations > 200)
         return fail(b, PA_E_INVAL, "need 0 < alpha_star < 1, dbeta_max > 0, 1 <= iterations <= 200");
+    pa_status u = need_uniform(b, "pa_step_rule");
+    if (u != PA_OK)
+        return u;
     hipError_t e = pa_b_rule(b->v, alpha_star, dbeta_max, iterations, 1);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_step_rule");
@@ -850,6 +944,7 @@ pa_status pa_get_counters(pa_ctx *c, pa_counters *out)
     out->site_updates = b->hrec[0].site_updates;
     out->sweeps = b->sweeps_total;
     out->spin_attempts = b->hrec[0].attempts;
+    out->resamplings = b->hrec[0].resamplings;
     return PA_OK;
 }
 
@@ -992,7 +1087,7 @@ pa_status pa_batch_anneal(pa_batch *p, const double *betas, int32_t npoints, int
     for (int i = 1; i < npoints && e == hipSuccess; ++i) {
         e = pa_b_reweight(v, betas[i]);
         if (e == hipSuccess)
-            e = pa_b_resample(v, (int)scheme, 1);
+            e = pa_b_resample(v, (int)scheme, 1, -1);
         if (e == hipSuccess && theta > 0)
             e = pa_b_sweep(v, theta, 0u); // every run was just resampled
         if (e == hipSuccess)
@@ -1294,6 +1389,9 @@ pa_status pa_features(pa_ctx *c, float *out8)
     Batch *b = &c->b;
     if (!out8)
         return fail(b, PA_E_INVAL, "out is NULL");
+    pa_status u = need_uniform(b, "pa_features");
+    if (u != PA_OK)
+        return u;
     hipError_t e = pa_b_features(b->v);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_features");
@@ -1313,6 +1411,9 @@ pa_status pa_step_learned(pa_ctx *c, pa_mlp *m, double alpha_star, double dbeta_
     if (!m || !dbeta_out || !(alpha_star > 0.0 && alpha_star < 1.0) || !std::isfinite(dbeta_max) ||
         dbeta_max <= 0.0 || iterations < 1 || iterations > 200)
         return fail(b, PA_E_INVAL, "need a model, 0 < alpha_star < 1, dbeta_max > 0, 1 <= iterations <= 200");
+    pa_status u = need_uniform(b, "pa_step_learned");
+    if (u != PA_OK)
+        return u;
     if (m->d.stream != b->v.stream) {
         hipError_t e = hipStreamSynchronize(m->d.stream);
         if (e != hipSuccess)

@@ -59,6 +59,14 @@ struct PaRecord {
     unsigned long long site_updates; // word-site updates (64 attempts each) so far
     unsigned long long attempts;     // spin-flip attempts so far: theta N R per sweep call
     uint32_t ticket[2];              // tile tickets of the two prefix sums of a resampling
+    // Weighted populations (conditional resampling): after a step that kept
+    // its population, replica j carries the log-weight lw[j] <= 0 (largest 0).
+    uint32_t weighted;              // 1: lw holds the population's log-weights; 0: uniform
+    uint32_t keep;                  // the latest conditional resampling kept the population
+    unsigned long long xmag;        // min_j |x_j| as IEEE bits, x_j = lw_j - dbeta (E_j - E_min) <= 0
+    unsigned long long Q2[2];       // sum_j W_j^2 of the step's integer weights, 128-bit, low word first
+    unsigned long long resamplings; // resamplings applied so far
+    double ess;                     // (sum w)^2 / sum w^2 of the population's weights (observables)
 };
 
 // One row per run and temperature point of a batched anneal.
@@ -93,8 +101,13 @@ struct PaDev {
     PaScanTile *tiles;
     double *partial; // fixed-order partial sums, one per chunk
     uint32_t *fam;   // [R0] replicas per family
+    double *lw;      // [slots] log-weights of a weighted population
+    uint64_t *Wj;    // [slots] integer weights of a weighted population's reweighting
+    double *wpart;   // [PA_WPARTS][chunks] fixed-order partial sums of the weighted passes
     PaRecord *rec;
 };
+
+#define PA_WPARTS 7 // weighted partial sums per chunk: w, wE, wE^2, wE^3, w|M|, wM^2, w^2
 
 struct PaRunDesc {
     int d, L, N, H;
@@ -151,6 +164,7 @@ struct PaBatchView {
     const PaBlk *gcol[PA_MAX_GROUPS];
     uint32_t gncol[PA_MAX_GROUPS];
     int gd[PA_MAX_GROUPS], gN[PA_MAX_GROUPS], gJ[PA_MAX_GROUPS], gthreads[PA_MAX_GROUPS];
+    bool weights;          // some run may hold a weighted population (conditional resampling)
     PaStepRecord *steprec; // batched anneal: [nruns][npoints]
     int npoints;
     hipStream_t stream;
@@ -165,7 +179,8 @@ hipError_t pa_b_init(const PaBatchView &v);
 hipError_t pa_b_sweep(const PaBatchView &v, int theta, uint32_t t0); // t0: sweeps already done at this beta
 hipError_t pa_b_sweep_group(const PaBatchView &v, int g, int theta, int threads);
 hipError_t pa_b_reweight(const PaBatchView &v, double beta_next);
-hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze);
+// kq >= 0: conditional, resample only when ESS < kq 2^-16 R_cur (else keep the population)
+hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze, int kq);
 hipError_t pa_b_observables(const PaBatchView &v, int point);
 hipError_t pa_b_rule(const PaBatchView &v, double alpha_star, double dbeta_max, int iterations, int bisect);
 hipError_t pa_b_set_beta(const PaBatchView &v, double beta, double lnZ, uint32_t step, uint32_t sweeps,

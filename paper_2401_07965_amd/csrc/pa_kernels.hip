@@ -83,6 +83,10 @@ __global__ void k_init_rec(const PaRunDesc *__restrict__ runs)
     rec->accE3[0] = rec->accE3[1] = 0;
     rec->lnq_hist[0] = rec->lnq_hist[1] = rec->lnq_hist[2] = 0.0;
     rec->S_f = log((double)rd.R0);
+    rec->weighted = 0;
+    rec->keep = 0;
+    rec->resamplings = 0;
+    rec->ess = (double)rd.R0;
 }
 
 // Replica 64w+b, site s: bit b of x0 | x1<<32 of Philox(s, w, 0, INIT<<28).
@@ -555,9 +559,22 @@ __global__ __launch_bounds__(kThreads) void k_hist(const PaRunDesc *__restrict__
     }
 }
 
+__device__ __forceinline__ pa_u128 block_sum_u128(pa_u128 v, uint64_t *su)
+{
+    pa_u128 t = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t limb = (uint64_t)(v >> (32 * k)) & 0xFFFFFFFFull;
+        t += (pa_u128)pa_block_sum_u64(limb, su) << (32 * k);
+    }
+    return t;
+}
+
 // One workgroup per run: weights per level above the lowest, the Q sum in a
 // fixed order (contiguous chunk per thread, then the block's fixed tree), S
-// exactly, ln Q and the Metropolis thresholds of the next beta.
+// and sum_h n_h W_h^2 exactly, ln Q and the Metropolis thresholds of the next
+// beta.  A weighted population only gets dbeta and the thresholds here; its
+// per-replica passes (k_rw_max, k_rw_sum, k_rw_final) do the rest.
 __global__ __launch_bounds__(1024) void k_reweight(const PaRunDesc *__restrict__ runs, double beta_next)
 {
     __shared__ double sd[16];
@@ -569,6 +586,20 @@ __global__ __launch_bounds__(1024) void k_reweight(const PaRunDesc *__restrict__
     const int DN = rd.d * rd.N;
     const double dbeta = beta_next - rec->beta;
     const int32_t emin = rec->emin, emax = rec->emax;
+    if (rec->weighted) {
+        __syncthreads(); // every thread has read the record before thread 0 writes it
+        if (threadIdx.x == 0) {
+            rec->dbeta = dbeta;
+            rec->beta_next = beta_next;
+            rec->S = 0;
+            rec->Q2[0] = rec->Q2[1] = 0;
+            rec->xmag = ~0ull;
+            rec->Tn[0] = pa_threshold(beta_next, 4);
+            rec->Tn[1] = pa_threshold(beta_next, 8);
+            rec->Tn[2] = pa_threshold(beta_next, 12);
+        }
+        return;
+    }
     const int hmin = (emin + DN) >> 2, hmax = (emax + DN) >> 2;
     const int nlev = hmax - hmin + 1;
     const int chunk = (nlev + (int)blockDim.x - 1) / (int)blockDim.x;
@@ -576,6 +607,7 @@ __global__ __launch_bounds__(1024) void k_reweight(const PaRunDesc *__restrict__
     const int hi = lo + chunk < nlev ? lo + chunk : nlev;
     double q = 0.0;
     uint64_t s = 0;
+    pa_u128 s2 = 0;
     for (int k = lo; k < hi; ++k) {
         const uint32_t n = rd.dv.hist[hmin + k];
         const double wv = pa_exp(-(dbeta * (double)(4 * k)));
@@ -583,12 +615,16 @@ __global__ __launch_bounds__(1024) void k_reweight(const PaRunDesc *__restrict__
         rd.dv.wtab[k] = W;
         q = q + (double)n * wv;
         s += (uint64_t)n * W;
+        s2 += (pa_u128)((uint64_t)n * W) * W;
     }
     const double Q = pa_block_sum_f64(q, sd);
     const uint64_t S = pa_block_sum_u64(s, su);
+    const pa_u128 S2 = block_sum_u128(s2, su);
     if (threadIdx.x == 0) {
         rec->qsum = Q;
         rec->S = S;
+        rec->Q2[0] = (uint64_t)S2;
+        rec->Q2[1] = (uint64_t)(S2 >> 64);
         rec->dbeta = dbeta;
         rec->beta_next = beta_next;
         rec->lnQ = -dbeta * (double)emin + log(Q / (double)rec->Rcur);
@@ -606,17 +642,6 @@ __global__ __launch_bounds__(1024) void k_reweight(const PaRunDesc *__restrict__
 // exactly (integer sums, so any order gives the same numbers).  The bisection
 // keeps the largest dbeta in [0, dbeta_max] with 2^32 num >= A R S, A the
 // target overlap in units of 2^-32.
-__device__ __forceinline__ pa_u128 block_sum_u128(pa_u128 v, uint64_t *su)
-{
-    pa_u128 t = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint64_t limb = (uint64_t)(v >> (32 * k)) & 0xFFFFFFFFull;
-        t += (pa_u128)pa_block_sum_u64(limb, su) << (32 * k);
-    }
-    return t;
-}
-
 __device__ __forceinline__ double u128_to_double(pa_u128 x)
 {
     return (double)(uint64_t)(x >> 64) * 18446744073709551616.0 + (double)(uint64_t)x;
@@ -812,6 +837,146 @@ __device__ __forceinline__ bool rep_ctx(const PaRunDesc *runs, const PaBlk *map,
     return c->beg < R && !frozen(c->rec);
 }
 
+// The kernels of a resampling proper: idle when a conditional resampling
+// decided to keep the population.
+__device__ __forceinline__ bool rs_ctx(const PaRunDesc *runs, const PaBlk *map, RepCtx *c)
+{
+    return rep_ctx(runs, map, c) && !c->rec->keep;
+}
+
+// Integer weight of replica j for the resampling: per energy level for a
+// uniform population, per replica (k_rw_sum) for a weighted one.
+__device__ __forceinline__ uint64_t rep_weight(const RepCtx &c, bool wt, const int32_t *E, int64_t j, int DN,
+                                               int hmin)
+{
+    return wt ? c.rd->dv.Wj[j] : weight_of(E[j], DN, hmin, c.rd->dv.wtab);
+}
+
+// ------------------------------------------------------------------ weighted populations
+// Sec. 3 allows keeping the population, with importance weights, while their
+// variance is small.  Replica j then carries a log-weight lw_j <= 0 (largest
+// 0) and weighs exp(lw_j - dbeta E_j) at the next beta.  With
+//   x_j = lw_j + (-(dbeta (E_j - E_min)))   (every x_j <= 0)
+// and m = min_j |x_j| (so max_j x_j = -m), the integer weights are
+// W_j = floor(2^40 pa_exp(x_j + m)) and
+//   ln Q = -dbeta E_min - m + ln sum_j exp(x_j + m) - ln sum_j exp(lw_j),
+// Eq. (1) for weighted replicas.  A uniform population is the case lw = 0
+// (x_j is then the argument of its per-level weights and m = 0).
+__device__ __forceinline__ double wx(const PaDev &dv, const PaRecord *rec, int cur, bool wt, int64_t j)
+{
+    const double g = (double)(dv.E[cur][j] - rec->emin);
+    const double lw = wt ? dv.lw[j] : 0.0;
+    return lw + (-(rec->dbeta * g));
+}
+
+__device__ __forceinline__ double xmag_value(const PaRecord *rec) { return __longlong_as_double((long long)rec->xmag); }
+
+// m: the smallest |x_j| (IEEE bits of non-negative doubles order as integers).
+__global__ __launch_bounds__(kThreads) void k_rw_max(const PaRunDesc *__restrict__ runs,
+                                                     const PaBlk *__restrict__ map)
+{
+    RepCtx c;
+    if (!rep_ctx(runs, map, &c) || !c.rec->weighted)
+        return;
+    const PaDev &dv = c.rd->dv;
+    const int cur = c.rec->cur;
+    int64_t mag = INT64_MAX;
+    for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x) {
+        const int64_t b = __double_as_longlong(wx(dv, c.rec, cur, true, j)) & INT64_MAX;
+        mag = b < mag ? b : mag;
+    }
+    mag = pa_wave_min_i64(mag);
+    if ((threadIdx.x & 63) == 0)
+        atomicMin(&c.rec->xmag, (unsigned long long)mag);
+}
+
+// Per-replica integer weights, S and sum W^2 exactly (order-free atomics),
+// and per chunk the fixed-order sums of pa_exp(x_j + m) and pa_exp(lw_j).
+__global__ __launch_bounds__(kThreads) void k_rw_sum(const PaRunDesc *__restrict__ runs,
+                                                     const PaBlk *__restrict__ map)
+{
+    __shared__ double sd[16];
+    __shared__ uint64_t su[16];
+    RepCtx c;
+    if (!rep_ctx(runs, map, &c) || !c.rec->weighted)
+        return;
+    const PaDev &dv = c.rd->dv;
+    const int cur = c.rec->cur;
+    const double m = xmag_value(c.rec);
+    uint64_t s = 0;
+    pa_u128 s2 = 0;
+    double q = 0.0, l = 0.0;
+    for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x) {
+        const double wv = pa_exp(wx(dv, c.rec, cur, true, j) + m);
+        const uint64_t W = (uint64_t)floor(ldexp(wv, 40));
+        dv.Wj[j] = W;
+        s += W;
+        s2 += (pa_u128)W * W;
+        q = q + wv;
+        l = l + pa_exp(dv.lw[j]);
+    }
+    s = pa_block_sum_u64(s, su);
+    s2 = block_sum_u128(s2, su);
+    q = pa_block_sum_f64(q, sd);
+    l = pa_block_sum_f64(l, sd);
+    if (threadIdx.x == 0) {
+        atomicAdd((unsigned long long *)&c.rec->S, (unsigned long long)s);
+        const unsigned long long lo = (uint64_t)s2, hi = (uint64_t)(s2 >> 64);
+        const unsigned long long old = atomicAdd(&c.rec->Q2[0], lo);
+        atomicAdd(&c.rec->Q2[1], hi + (old + lo < old ? 1ull : 0ull));
+        const int64_t chunks = (c.rd->cap + PA_CHUNK - 1) / PA_CHUNK, k = c.beg / PA_CHUNK;
+        dv.wpart[k] = q;
+        dv.wpart[chunks + k] = l;
+    }
+}
+
+// ln Q of a weighted population from the chunk sums in chunk order.
+__global__ __launch_bounds__(kThreads) void k_rw_final(const PaRunDesc *__restrict__ runs)
+{
+    __shared__ double sd[16];
+    const PaRunDesc &rd = runs[blockIdx.x];
+    PaRecord *rec = rd.dv.rec;
+    if (frozen(rec) || !rec->weighted)
+        return;
+    const int64_t chunks = (rd.cap + PA_CHUNK - 1) / PA_CHUNK;
+    const int nlive = (int)(((int64_t)rec->Rcur + PA_CHUNK - 1) / PA_CHUNK);
+    double q = 0.0, l = 0.0;
+    for (int k = threadIdx.x; k < nlive; k += blockDim.x) {
+        q = q + rd.dv.wpart[k];
+        l = l + rd.dv.wpart[chunks + k];
+    }
+    q = pa_block_sum_f64(q, sd);
+    l = pa_block_sum_f64(l, sd);
+    if (threadIdx.x == 0) {
+        rec->qsum = q;
+        rec->lnQ = ((-rec->dbeta * (double)rec->emin - xmag_value(rec)) + log(q)) - log(l);
+    }
+}
+
+// Conditional resampling: resample only if the effective sample size of the
+// step's weights, ESS = S^2 / sum_j W_j^2, is below kappa R_cur.  Decided
+// exactly as 2^16 S^2 < kq R_cur sum_j W_j^2 (kq = kappa 2^16) on 192-bit
+// integers: S^2 < 2^128, sum W^2 < 2^104, kq R_cur < 2^41.
+__global__ void k_cond_decide(const PaRunDesc *__restrict__ runs, uint32_t kq)
+{
+    const PaRunDesc &rd = runs[blockIdx.x];
+    PaRecord *rec = rd.dv.rec;
+    if (threadIdx.x != 0 || frozen(rec))
+        return;
+    const uint64_t S = rec->S;
+    const pa_u128 S2 = (pa_u128)S * S;
+    const uint64_t a0 = (uint64_t)(S2 << 16), a1 = (uint64_t)((S2 << 16) >> 64), a2 = (uint64_t)(S2 >> 112);
+    const uint64_t f = (uint64_t)kq * rec->Rcur;
+    const pa_u128 p0 = (pa_u128)rec->Q2[0] * f, p1 = (pa_u128)rec->Q2[1] * f;
+    const pa_u128 mid = (p0 >> 64) + (pa_u128)(uint64_t)p1;
+    const uint64_t r0 = (uint64_t)p0, r1 = (uint64_t)mid, r2 = (uint64_t)(p1 >> 64) + (uint64_t)(mid >> 64);
+    const bool resample = a2 != r2 ? a2 < r2 : (a1 != r1 ? a1 < r1 : a0 < r0);
+    rec->keep = resample ? 0u : 1u;
+    if (!resample)
+        rec->Rnew = rec->Rcur; // the capacity and extinction checks see the kept size
+}
+
+
 // Nearest integer: floor(tauhat) + [u S < (R W mod S) 2^32], u = x0 of
 // Philox(j, 0, i, RS_NI<<28).
 // Sampling variance, Eq. (5): each chunk sums (r_j - tauhat_j)^2 over its
@@ -835,8 +1000,9 @@ __global__ __launch_bounds__(kThreads) void k_counts_nearest(const PaRunDesc *__
                                                              const PaBlk *__restrict__ map)
 {
     RepCtx c;
-    if (!rep_ctx(runs, map, &c))
+    if (!rs_ctx(runs, map, &c))
         return;
+    const bool wt = c.rec->weighted != 0u;
     const PaRunDesc &rd = *c.rd;
     const int DN = rd.d * rd.N;
     const int hmin = (c.rec->emin + DN) >> 2;
@@ -846,7 +1012,7 @@ __global__ __launch_bounds__(kThreads) void k_counts_nearest(const PaRunDesc *__
     __shared__ double sd[16];
     double sv = 0.0;
     for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x) {
-        const uint64_t W = weight_of(E[j], DN, hmin, rd.dv.wtab);
+        const uint64_t W = rep_weight(c, wt, E, j, DN, hmin);
         const uint64_t a = Rt * W;
         const uint64_t qt = a / S;
         const uint64_t rho = a - qt * S;
@@ -865,8 +1031,9 @@ __global__ __launch_bounds__(kThreads) void k_counts_poisson(const PaRunDesc *__
                                                              const PaBlk *__restrict__ map)
 {
     RepCtx c;
-    if (!rep_ctx(runs, map, &c))
+    if (!rs_ctx(runs, map, &c))
         return;
+    const bool wt = c.rec->weighted != 0u;
     const PaRunDesc &rd = *c.rd;
     const int DN = rd.d * rd.N;
     const int hmin = (c.rec->emin + DN) >> 2;
@@ -876,7 +1043,7 @@ __global__ __launch_bounds__(kThreads) void k_counts_poisson(const PaRunDesc *__
     __shared__ double sd[16];
     double sv = 0.0;
     for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x) {
-        const uint64_t W = weight_of(E[j], DN, hmin, rd.dv.wtab);
+        const uint64_t W = rep_weight(c, wt, E, j, DN, hmin);
         const double tau = ((double)W / (double)S) * (double)Rt;
         uint32_t m = 1;
         if (tau > 32.0)
@@ -910,14 +1077,15 @@ __global__ __launch_bounds__(kThreads) void k_weights(const PaRunDesc *__restric
                                                       const PaBlk *__restrict__ map)
 {
     RepCtx c;
-    if (!rep_ctx(runs, map, &c))
+    if (!rs_ctx(runs, map, &c))
         return;
     const PaRunDesc &rd = *c.rd;
+    const bool wt = c.rec->weighted != 0u;
     const int DN = rd.d * rd.N;
     const int hmin = (c.rec->emin + DN) >> 2;
     const int32_t *E = rd.dv.E[c.rec->cur];
     for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x)
-        rd.dv.C[j] = weight_of(E[j], DN, hmin, rd.dv.wtab);
+        rd.dv.C[j] = rep_weight(c, wt, E, j, DN, hmin);
 }
 
 // Systematic: #points (k + U/2^32) S/R below c, k < R, is
@@ -941,7 +1109,7 @@ __global__ __launch_bounds__(kThreads) void k_counts_systematic(const PaRunDesc 
                                                                 const PaBlk *__restrict__ map)
 {
     RepCtx c;
-    if (!rep_ctx(runs, map, &c))
+    if (!rs_ctx(runs, map, &c))
         return;
     const PaRunDesc &rd = *c.rd;
     const uint64_t S = c.rec->S, Rt = (uint64_t)rd.R0;
@@ -964,7 +1132,7 @@ __global__ __launch_bounds__(kThreads) void k_clear_counts(const PaRunDesc *__re
                                                            const PaBlk *__restrict__ map)
 {
     RepCtx c;
-    if (!rep_ctx(runs, map, &c))
+    if (!rs_ctx(runs, map, &c))
         return;
     for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x)
         c.rd->dv.r[j] = 0;
@@ -981,7 +1149,7 @@ __global__ __launch_bounds__(kThreads) void k_counts_multinomial(const PaRunDesc
     PaRecord *rec = rd.dv.rec;
     const int64_t Rt = rd.R0, Rprev = (int64_t)rec->Rcur;
     const int64_t beg = (int64_t)b.idx * PA_CHUNK;
-    if (beg >= Rt || frozen(rec))
+    if (beg >= Rt || frozen(rec) || rec->keep)
         return;
     const int64_t end = beg + PA_CHUNK < Rt ? beg + PA_CHUNK : Rt;
     const uint64_t S = rec->S;
@@ -1012,16 +1180,17 @@ __global__ __launch_bounds__(kThreads) void k_sv_partial(const PaRunDesc *__rest
 {
     __shared__ double sd[16];
     RepCtx c;
-    if (!rep_ctx(runs, map, &c))
+    if (!rs_ctx(runs, map, &c))
         return;
     const PaRunDesc &rd = *c.rd;
+    const bool wt = c.rec->weighted != 0u;
     const int DN = rd.d * rd.N;
     const int hmin = (c.rec->emin + DN) >> 2;
     const double S = (double)c.rec->S, Rt = (double)rd.R0;
     const int32_t *E = rd.dv.E[c.rec->cur];
     double acc = 0.0;
     for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x)
-        acc = acc + sv_term(rd.dv.r[j], weight_of(E[j], DN, hmin, rd.dv.wtab), S, Rt);
+        acc = acc + sv_term(rd.dv.r[j], rep_weight(c, wt, E, j, DN, hmin), S, Rt);
     sv_store(c, acc, sd);
 }
 
@@ -1042,8 +1211,8 @@ __global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const PaRunDesc *__res
     const PaBlk b = map[blockIdx.x];
     const PaRunDesc &rd = runs[b.run];
     PaRecord *rec = rd.dv.rec;
-    if (frozen(rec))
-        return; // every tile of a frozen run returns: none waits
+    if (frozen(rec) || rec->keep)
+        return; // every tile of a frozen (or kept) run returns: none waits
     if (threadIdx.x == 0)
         s_tile = atomicAdd(&rec->ticket[WHICH], 1u);
     __syncthreads();
@@ -1150,6 +1319,7 @@ __global__ void k_resample_prep(const PaRunDesc *__restrict__ runs)
         if (!frozen(rec)) {
             rec->status = 0;
             rec->skip = 0;
+            rec->keep = 0;
         }
     }
 }
@@ -1190,7 +1360,7 @@ __global__ __launch_bounds__(kThreads) void k_gather_spins(const PaRunDesc *__re
     PaRecord *rec = rd.dv.rec;
     const int64_t Rnew = (int64_t)rec->Rnew;
     const uint32_t w = blk.idx;
-    if (frozen(rec) || resample_status(rec, rd.cap) != 0u || (int64_t)w * 64 >= Rnew)
+    if (frozen(rec) || rec->keep || resample_status(rec, rd.cap) != 0u || (int64_t)w * 64 >= Rnew)
         return;
     const int N = rd.N;
     const int cur = rec->cur;
@@ -1258,9 +1428,25 @@ __global__ __launch_bounds__(kThreads) void k_gather_spins(const PaRunDesc *__re
     }
 }
 
+// A kept population takes its new log-weights x_j + m (m = 0 if it was uniform).
+__global__ __launch_bounds__(kThreads) void k_keep(const PaRunDesc *__restrict__ runs,
+                                                   const PaBlk *__restrict__ map)
+{
+    RepCtx c;
+    if (!rep_ctx(runs, map, &c) || !c.rec->keep || resample_status(c.rec, c.rd->cap) != 0u)
+        return;
+    const PaDev &dv = c.rd->dv;
+    const int cur = c.rec->cur;
+    const bool wt = c.rec->weighted != 0u;
+    const double m = wt ? xmag_value(c.rec) : 0.0;
+    for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x)
+        dv.lw[j] = wx(dv, c.rec, cur, wt, j) + m;
+}
+
 // Completes an applied resampling: SV (Eq. (5)) from the partials in fixed
 // order, ln Z_hat += ln Q (Eq. (7)), the new beta and its thresholds, the
-// buffer swap and the step count.
+// buffer swap and the step count.  A kept population advances the same way
+// with its members in place, its new log-weights and SV = 0 (nothing drawn).
 __global__ __launch_bounds__(kThreads) void k_commit(const PaRunDesc *__restrict__ runs, int freeze)
 {
     __shared__ double sd[16];
@@ -1274,6 +1460,24 @@ __global__ __launch_bounds__(kThreads) void k_commit(const PaRunDesc *__restrict
         if (threadIdx.x == 0) {
             rec->skip = 1;
             rec->status = freeze ? (st | PA_ST_FROZEN) : st;
+        }
+        return;
+    }
+    if (rec->keep) {
+        if (threadIdx.x == 0) {
+            rec->sv = 0.0;
+            rec->lnZ = rec->lnZ + rec->lnQ;
+            rec->lnq_hist[0] = rec->lnq_hist[1];
+            rec->lnq_hist[1] = rec->lnq_hist[2];
+            rec->lnq_hist[2] = rec->lnQ;
+            rec->T[0] = rec->Tn[0];
+            rec->T[1] = rec->Tn[1];
+            rec->T[2] = rec->Tn[2];
+            rec->Rprev = rec->Rcur;
+            rec->beta = rec->beta_next;
+            rec->step += 1;
+            rec->sweeps = 0;
+            rec->weighted = 1;
         }
         return;
     }
@@ -1298,6 +1502,8 @@ __global__ __launch_bounds__(kThreads) void k_commit(const PaRunDesc *__restrict
         rec->beta = rec->beta_next;
         rec->step += 1;
         rec->sweeps = 0;
+        rec->weighted = 0;
+        rec->resamplings += 1;
     }
 }
 
@@ -1306,6 +1512,7 @@ __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restric
                                                       const PaBlk *__restrict__ map)
 {
     __shared__ uint64_t su[16];
+    __shared__ double sd[16];
     RepCtx c;
     if (!rep_ctx(runs, map, &c))
         return;
@@ -1313,6 +1520,9 @@ __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restric
     const int cur = c.rec->cur;
     uint64_t sE = 0, sE2 = 0, sA = 0, sM2 = 0, sE3 = 0; // sE3: int64 bits (|sum| < 2^63 per block)
     const int lane = threadIdx.x & 63;
+    // a weighted population: sums of w, wE, wE^2, wE^3, w|M|, wM^2, w^2 with w = pa_exp(lw)
+    const bool wt = c.rec->weighted != 0u;
+    double ws[PA_WPARTS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int64_t base = c.beg; base < c.end; base += blockDim.x) {
         const int64_t d = base + threadIdx.x;
         const bool valid = d < c.end;
@@ -1325,6 +1535,16 @@ __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restric
             sA += (uint64_t)(m < 0 ? -m : m);
             sM2 += (uint64_t)(m * m);
             lab = dv.label[cur][d];
+            if (wt) {
+                const double w = pa_exp(dv.lw[d]), ef = (double)e, mf = (double)(m < 0 ? -m : m);
+                ws[0] = ws[0] + w;
+                ws[1] = ws[1] + w * ef;
+                ws[2] = ws[2] + w * (ef * ef);
+                ws[3] = ws[3] + w * (ef * ef * ef);
+                ws[4] = ws[4] + w * mf;
+                ws[5] = ws[5] + w * (mf * mf);
+                ws[6] = ws[6] + w * w;
+            }
         }
         // family counts: one atomic per run of equal labels in the wave (the
         // resampling keeps copies adjacent, so runs are long)
@@ -1342,6 +1562,15 @@ __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restric
     sA = pa_block_sum_u64(sA, su);
     sM2 = pa_block_sum_u64(sM2, su);
     sE3 = pa_block_sum_u64(sE3, su);
+    if (wt) {
+        const int64_t chunks = (c.rd->cap + PA_CHUNK - 1) / PA_CHUNK, k = c.beg / PA_CHUNK;
+#pragma unroll
+        for (int f = 0; f < PA_WPARTS; ++f) {
+            const double t = pa_block_sum_f64(ws[f], sd);
+            if (threadIdx.x == 0)
+                dv.wpart[f * chunks + k] = t;
+        }
+    }
     if (threadIdx.x == 0) {
         // 128-bit add of the block's signed sum: low word, then the high word
         // with the carry out of the low word (order-free, hence exact)
@@ -1402,8 +1631,11 @@ __device__ __forceinline__ double i128_to_double(unsigned long long lo, unsigned
 }
 
 // Averages of step 4 and the family statistics: rho_t = sum_k c_k^2 / R
-// (Eq. (6) with n_k = c_k / R), S_f = ln R - (1/R) sum_k c_k ln c_k.  In a
-// batched anneal the row of temperature point `point` is written too.
+// (Eq. (6) with n_k = c_k / R), S_f = ln R - (1/R) sum_k c_k ln c_k.  A
+// weighted population reports weighted averages sum_j w_j O_j / sum_j w_j and
+// ESS = (sum w)^2 / sum w^2 (the integer sums and family statistics stay
+// those of the members).  In a batched anneal the row of temperature point
+// `point` is written too.
 __global__ __launch_bounds__(kThreads) void k_obs_final(const PaRunDesc *__restrict__ runs, PaStepRecord *steprec,
                                                         int npoints, int point)
 {
@@ -1411,12 +1643,24 @@ __global__ __launch_bounds__(kThreads) void k_obs_final(const PaRunDesc *__restr
     const PaRunDesc &rd = runs[blockIdx.x];
     PaRecord *rec = rd.dv.rec;
     const bool fz = frozen(rec);
+    const bool wt = !fz && rec->weighted != 0u;
     const int nparts = (int)((rd.R0 + PA_CHUNK - 1) / PA_CHUNK);
     double v = 0.0;
     if (!fz)
         for (int k = threadIdx.x; k < nparts; k += blockDim.x)
             v = v + rd.dv.partial[k];
     const double t = pa_block_sum_f64(v, sd);
+    double ws[PA_WPARTS];
+    if (wt) {
+        const int64_t chunks = (rd.cap + PA_CHUNK - 1) / PA_CHUNK;
+        const int nlive = (int)(((int64_t)rec->Rcur + PA_CHUNK - 1) / PA_CHUNK);
+        for (int f = 0; f < PA_WPARTS; ++f) {
+            double a = 0.0;
+            for (int k = threadIdx.x; k < nlive; k += blockDim.x)
+                a = a + rd.dv.wpart[f * chunks + k];
+            ws[f] = pa_block_sum_f64(a, sd);
+        }
+    }
     if (threadIdx.x != 0)
         return;
     if (!fz) {
@@ -1439,6 +1683,15 @@ __global__ __launch_bounds__(kThreads) void k_obs_final(const PaRunDesc *__restr
         rec->m2 = (double)(long long)rec->sumM2 / (n * n * r);
         rec->rho_t = (double)rec->sumC2 / r;
         rec->S_f = log(r) - t / r;
+        rec->ess = r;
+        if (wt) {
+            rec->e = ws[1] / ws[0] / n;
+            rec->e2 = ws[2] / ws[0] / (n * n);
+            rec->e3 = ws[3] / ws[0] / (n * n * n);
+            rec->abs_m = ws[4] / ws[0] / n;
+            rec->m2 = ws[5] / ws[0] / (n * n);
+            rec->ess = ws[0] * ws[0] / ws[6];
+        }
     }
     if (steprec) {
         PaStepRecord *o = steprec + (size_t)blockIdx.x * npoints + point;
@@ -1596,6 +1849,8 @@ __global__ void k_set_beta(const PaRunDesc *__restrict__ runs, double beta, doub
         rec->sv = 0.0;
         rec->status = 0;
         rec->skip = 0;
+        rec->weighted = 0;
+        rec->keep = 0;
     }
 }
 
@@ -1704,6 +1959,11 @@ hipError_t pa_b_reweight(const PaBatchView &v, double beta_next)
     if (e != hipSuccess)
         return e;
     k_reweight<<<v.nruns, 1024, 0, v.stream>>>(v.runs, beta_next);
+    if (v.weights) { // runs that may hold a weighted population
+        k_rw_max<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
+        k_rw_sum<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
+        k_rw_final<<<v.nruns, kThreads, 0, v.stream>>>(v.runs);
+    }
     return hipGetLastError();
 }
 
@@ -1739,10 +1999,12 @@ static hipError_t scan_launch(const PaBatchView &v)
     return hipGetLastError();
 }
 
-hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze)
+hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze, int kq)
 {
     hipError_t e;
     k_resample_prep<<<v.nruns, kThreads, 0, v.stream>>>(v.runs);
+    if (kq >= 0)
+        k_cond_decide<<<v.nruns, 64, 0, v.stream>>>(v.runs, (uint32_t)kq);
     switch (scheme) {
     case 2:
         k_counts_nearest<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
@@ -1771,6 +2033,8 @@ hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze)
     if ((e = scan_launch<uint32_t, false, 1>(v)) != hipSuccess)
         return e;
     k_gather_spins<<<v.ncol, kThreads, 0, v.stream>>>(v.runs, v.col);
+    if (kq >= 0)
+        k_keep<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
     k_commit<<<v.nruns, kThreads, 0, v.stream>>>(v.runs, freeze);
     return hipGetLastError();
 }

@@ -32,7 +32,8 @@ class pa_obs(ctypes.Structure):
                 ("families", ctypes.c_int64), ("e", ctypes.c_double), ("e2", ctypes.c_double),
                 ("abs_m", ctypes.c_double), ("m2", ctypes.c_double), ("rho_t", ctypes.c_double),
                 ("S_f", ctypes.c_double), ("sv", ctypes.c_double),
-                ("sum_E3_hi", ctypes.c_int64), ("sum_E3_lo", ctypes.c_uint64), ("e3", ctypes.c_double)]
+                ("sum_E3_hi", ctypes.c_int64), ("sum_E3_lo", ctypes.c_uint64), ("e3", ctypes.c_double),
+                ("ess", ctypes.c_double), ("weighted", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class pa_host_state(ctypes.Structure):
@@ -44,7 +45,8 @@ class pa_host_state(ctypes.Structure):
 
 class pa_counters(ctypes.Structure):
     _fields_ = [("philox_calls", ctypes.c_uint64), ("site_updates", ctypes.c_uint64),
-                ("sweeps", ctypes.c_uint64), ("spin_attempts", ctypes.c_uint64)]
+                ("sweeps", ctypes.c_uint64), ("spin_attempts", ctypes.c_uint64),
+                ("resamplings", ctypes.c_uint64)]
 
 
 class pa_step_record(ctypes.Structure):
@@ -114,6 +116,9 @@ def lib():
         L.pa_sweep.argtypes = [v, ctypes.c_int32]
         L.pa_reweight.argtypes = [v, ctypes.c_double, P(ctypes.c_double)]
         L.pa_resample.argtypes = [v, ctypes.c_int, P(ctypes.c_int64)]
+        L.pa_resample_conditional.argtypes = [v, ctypes.c_int, ctypes.c_double, P(ctypes.c_int64),
+                                              P(ctypes.c_int32)]
+        L.pa_log_weights.argtypes = [v, v, P(ctypes.c_int32)]
         L.pa_observables.argtypes = [v, P(pa_obs)]
         L.pa_free_energy.argtypes = [v, P(ctypes.c_double)]
         L.pa_export_state.argtypes = [v, P(pa_host_state)]
@@ -239,14 +244,35 @@ def pa_resample(ctx, scheme, wait=True):
     return n.value
 
 
+def pa_resample_conditional(ctx, scheme, kappa, wait=True):
+    """(new population size, resampled?); with wait=False deferred, returns None."""
+    if not wait:
+        _check(lib().pa_resample_conditional(ctx, int(scheme), float(kappa), None, None), ctx)
+        return None
+    n = ctypes.c_int64()
+    r = ctypes.c_int32()
+    _check(lib().pa_resample_conditional(ctx, int(scheme), float(kappa), ctypes.byref(n),
+                                         ctypes.byref(r)), ctx)
+    return n.value, bool(r.value)
+
+
+def pa_log_weights(ctx, R):
+    """Log-weights of the R current replicas (zeros if uniform) and the weighted flag."""
+    out = np.zeros(R, np.float64)
+    w = ctypes.c_int32()
+    _check(lib().pa_log_weights(ctx, out.ctypes.data, ctypes.byref(w)), ctx)
+    return out, bool(w.value)
+
+
 def pa_observables(ctx, wait=True):
     if not wait:
         _check(lib().pa_observables(ctx, None), ctx)
         return None
     o = pa_obs()
     _check(lib().pa_observables(ctx, ctypes.byref(o)), ctx)
-    out = {name: getattr(o, name) for name, _ in pa_obs._fields_}
+    out = {name: getattr(o, name) for name, _ in pa_obs._fields_ if name != "pad"}
     out["sum_E3"] = (out.pop("sum_E3_hi") << 64) + out.pop("sum_E3_lo")
+    out["weighted"] = bool(out["weighted"])
     return out
 
 
@@ -362,6 +388,14 @@ class PARun:
 
     def resample(self, scheme, wait=True):
         return pa_resample(self.ctx, SCHEMES.get(scheme, scheme), wait)
+
+    def resample_conditional(self, scheme, kappa, wait=True):
+        return pa_resample_conditional(self.ctx, SCHEMES.get(scheme, scheme), kappa, wait)
+
+    def log_weights(self):
+        """(log-weights of the current replicas, weighted flag)."""
+        R = pa_export_state(self.ctx, self.N, arrays=False)["R"]
+        return pa_log_weights(self.ctx, R)
 
     def sweep(self, theta):
         pa_sweep(self.ctx, theta)

@@ -3,6 +3,7 @@ include/pa.h declares, and the argument checks that need no GPU."""
 import ctypes
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -71,3 +72,37 @@ def test_philox_probe_checks_arguments_without_gpu(libpa):
     L = libpa.lib()
     for n, iters in ((100, 1), (0, 1), (256, 0), ((1 << 24) + 256, 1)):
         assert L.pa_philox_probe(None, n, iters, None) == 1  # PA_E_INVAL, nothing launched
+
+
+def test_conditional_resampling_calls_check_arguments_without_gpu(libpa):
+    L = libpa.lib()
+    n = ctypes.c_int64()
+    r = ctypes.c_int32()
+    # no context: PA_E_INVAL before anything else
+    assert L.pa_resample_conditional(None, 2, 0.5, ctypes.byref(n), ctypes.byref(r)) == 1
+    assert L.pa_log_weights(None, None, None) == 1
+
+
+def test_binding_structures_match_the_header(libpa, tmp_path):
+    """Sizes and field offsets of every struct the binding mirrors, from the
+    header compiled by the C compiler."""
+    structs = ("pa_config", "pa_obs", "pa_host_state", "pa_counters", "pa_step_record",
+               "pa_combined", "pa_mlp_norm")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pa.h"', 'int main(void) {']
+    for s in structs:
+        lines.append(f'printf("{s} %zu\\n", sizeof({s}));')
+        for name, _ in getattr(libpa, s)._fields_:
+            lines.append(f'printf("{s}.{name} %zu\\n", offsetof({s}, {name}));')
+    lines += ['return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                       text=True).stdout.splitlines())
+    for s in structs:
+        cls = getattr(libpa, s)
+        assert int(got[s]) == ctypes.sizeof(cls), s
+        for name, _ in cls._fields_:
+            assert int(got[f"{s}.{name}"]) == getattr(cls, name).offset, (s, name)
