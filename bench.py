@@ -413,6 +413,75 @@ def conditional_study(L=32, R=20000, theta=10, points=101, beta_f=0.44, seeds=8)
                         f"points, systematic, {seeds} seeds per kappa", "by_kappa": table}
 
 
+def scheme_error_study(L=64, R=20000, theta=5, runs=128):
+    """Fig. 3's workload: specific heat per resampling scheme, 2D FM L = 64,
+    R = 2 10^4, theta = 5, beta_i = i/300 to 0.6, 128 seeded runs per scheme
+    (one batched anneal each).  Reported: the relative spread of c over the
+    runs (statistical error of one run) averaged over beta 0.40..0.47, and the
+    anneal time.  The tests compare with the exact c."""
+    import numpy as np
+    import torch
+    from paper_2401_07965_amd import pa
+    betas = [i / 300 for i in range(181)]
+    N = L * L
+    out = {}
+    for name, sc in SCHEMES:
+        cfgs = [dict(dim=2, L=L, R=R, seed=41, run_id=100 * sc + k, couplings=None) for k in range(runs)]
+        B = pa.PABatch(cfgs, max_points=len(betas))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.anneal(betas, theta, sc, use_graph=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rec = B.records()
+        B.close()
+        rel = []
+        for i in range(120, 142):
+            r = rec[:, i]
+            Rr = r["R"].astype(np.float64)
+            m1 = r["sum_E"] / Rr
+            c = betas[i] ** 2 * (r["sum_E2"] / Rr - m1 * m1) / N
+            rel.append(float(c.std() / c.mean()))
+        out[name] = {"relative_sd_c_near_beta_c": float(np.mean(rel)), "anneal_s": dt}
+    return {"workload": f"{runs} runs per scheme, 2D Ising FM L={L}, R={R}, theta={theta}, "
+                        f"beta_i = i/300 to 0.6", "by_scheme": out}
+
+
+def rmsd_study(L=64, R=20000, theta=2, runs=500):
+    """Fig. 8's workload: 500 seeded runs of the 2D FM L = 64, R = 2 10^4,
+    theta = 2, beta_i = i/300 to 0.6, systematic, one batched anneal; groups of
+    M runs combined plainly and by weight.  The reference here is the weighted
+    combination of all runs (the tests use the exact values); reported: RMSD of
+    u and c at beta = 0.44 and 0.46 for M = 1, 10, 50."""
+    import math
+    import numpy as np
+    import torch
+    from paper_2401_07965_amd import pa
+    betas = [i / 300 for i in range(181)]
+    cfgs = [dict(dim=2, L=L, R=R, seed=43, run_id=k, couplings=None) for k in range(runs)]
+    B = pa.PABatch(cfgs, max_points=len(betas))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.anneal(betas, theta, 3, use_graph=True)
+    torch.cuda.synchronize()
+    anneal_s = time.perf_counter() - t0
+    table = {}
+    for i in (132, 138):
+        ref = B.combine([0] * runs, 1, i)[0]
+        row = {}
+        for M in (1, 10, 50):
+            out = B.combine([k // M for k in range(runs)], runs // M, i)
+
+            def rm(key, rkey):
+                return math.sqrt(float(np.mean([(o[key] - ref[rkey]) ** 2 for o in out])))
+            row[M] = {"u_plain": rm("e_plain", "e"), "u_weighted": rm("e", "e"),
+                      "c_plain": rm("c_plain", "c"), "c_weighted": rm("c", "c")}
+        table[f"beta={betas[i]:.3f}"] = row
+    B.close()
+    return {"workload": f"{runs} runs 2D Ising FM L={L}, R={R}, theta={theta}, beta_i = i/300, "
+                        "systematic; groups of M", "anneal_s": anneal_s, "rmsd_vs_all_runs_weighted": table}
+
+
 def learned_bench(theta=10, scheme=3, astar=0.7, dmax=0.2, beta_f=3.0):
     """Learned-schedule workload: 3D +-J glass L = 16.  The model is trained on
     the GPU from rule-driven anneals of 8 other disorder samples at R = 10^4;
@@ -592,6 +661,8 @@ def main():
         out["combination"] = combination_study()
         out["resampling"] = resampling_study()
         out["conditional"] = conditional_study()
+        out["scheme_errors"] = scheme_error_study()
+        out["rmsd"] = rmsd_study()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

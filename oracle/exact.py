@@ -129,3 +129,23 @@ def transfer_matrix_lnZ(L, J, beta):
 def beta_c():
     """Critical coupling of the 2D square-lattice Ising model, (1/2) ln(1 + sqrt 2)."""
     return 0.5 * math.log(1.0 + math.sqrt(2.0))
+
+
+def kaufman_e_c(L, beta):
+    """Energy and specific heat per spin, e = <E>/N and c = beta^2 Var(E)/N, from
+    central differences (step 1e-15) of the 60-digit Kaufman ln Z."""
+    N = L * L
+    with mp.workdps(60):
+        b, h = mp.mpf(beta), mp.mpf("1e-15")
+        l0, lp, lm = (kaufman_lnZ_mp(L, x) for x in (b, b + h, b - h))
+        return float(-(lp - lm) / (2 * h)) / N, float(b * b * (lp - 2 * l0 + lm) / (h * h)) / N
+
+
+def moments_from_dos(dos, beta):
+    """<E> and Var(E) at beta from a density of states, in mpmath."""
+    b = mp.mpf(beta)
+    w = {E: mp.mpf(g) * mp.exp(-b * E) for E, g in dos.items()}
+    Z = mp.fsum(w.values())
+    m1 = mp.fsum(E * x for E, x in w.items()) / Z
+    m2 = mp.fsum(E * E * x for E, x in w.items()) / Z
+    return float(m1), float(m2 - m1 * m1)

@@ -7,22 +7,12 @@ finite-lattice values (Kaufman); 1024 seeded runs in one batch, so the numbers
 are fixed by the seeds."""
 import math
 
-import mpmath as mp
 import numpy as np
 import pytest
 
 from oracle import exact
 
 pytestmark = pytest.mark.gpu
-
-
-def exact_e_c(L, beta):
-    """Energy and specific heat per spin from the 60-digit ln Z."""
-    N = L * L
-    with mp.workdps(60):
-        b, h = mp.mpf(beta), mp.mpf("1e-15")
-        l0, lp, lm = (exact.kaufman_lnZ_mp(L, x) for x in (b, b + h, b - h))
-        return float(-(lp - lm) / (2 * h)) / N, float(b * b * (lp - 2 * l0 + lm) / (h * h)) / N
 
 
 def test_weighted_averages_remove_the_bias_of_m_runs():
@@ -34,7 +24,7 @@ def test_weighted_averages_remove_the_bias_of_m_runs():
     B = pa.PABatch(cfgs, max_points=len(betas))
     B.anneal(betas, theta, 3, use_graph=True)
     point = len(betas) - 1
-    e_ex, c_ex = exact_e_c(L, betas[point])
+    e_ex, c_ex = exact.kaufman_e_c(L, betas[point])
     bias, sd = {}, {}
     for M in (1, 64, 256):
         out = B.combine([k // M for k in range(K)], K // M, point)

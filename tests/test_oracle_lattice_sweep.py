@@ -52,6 +52,17 @@ def test_brute_force_matches_kaufman_and_transfer_matrix():
                        exact.transfer_matrix_lnZ(L, O.ferromagnet(2, L), beta)) < 1e-10
 
 
+def test_kaufman_energy_and_specific_heat_match_brute_force():
+    """e and c from central differences of Kaufman's ln Z equal the moments of the
+    enumerated 4x4 density of states."""
+    dos = exact.brute_force(2, 4, O.ferromagnet(2, 4))
+    for beta in (0.1, 0.3, 0.44068, 0.7):
+        e, c = exact.kaufman_e_c(4, beta)
+        m1, var = exact.moments_from_dos(dos, beta)
+        assert abs(e - m1 / 16) < 1e-12
+        assert abs(c - beta * beta * var / 16) < 1e-10
+
+
 def test_paper_critical_point(golden):
     """The exact specific heat peak approaches the beta_c the paper prints (Sec. 3)."""
     bc = golden["beta_c_2d_ising"]["value"]
