@@ -1344,15 +1344,20 @@ __device__ __forceinline__ uint32_t resample_status(const PaRecord *rec, int64_t
 
 // ------------------------------------------------------------------ apply
 
-// Destination word column w takes the bits of its 64 ancestors.  Ancestors are
-// non-decreasing, so the column splits into runs of consecutive source bits
-// within one source word; each run is one shift-and-mask per site.
+// Destination word column w takes the bits of its 64 ancestors.  Bit b comes
+// from bit (a_b & 63) of source word a_b >> 6, i.e. from that word shifted by
+// delta_b = (a_b & 63) - b.  Bits sharing (source word, delta) form one group:
+// one shift, mask and or per group per site.  Ancestors are non-decreasing, so
+// delta moves by one per dropped or repeated replica and a column has few
+// groups (fewer than its runs of consecutive ancestors), listed in order of
+// source word.
 __global__ __launch_bounds__(kThreads) void k_gather_spins(const PaRunDesc *__restrict__ runs,
                                                            const PaBlk *__restrict__ map)
 {
-    __shared__ uint32_t r_word[64];
-    __shared__ uint32_t r_shift[64], r_b0[64], r_len[64];
-    __shared__ int s_nruns;
+    __shared__ uint64_t g_mask[64];
+    __shared__ uint32_t g_word[64];
+    __shared__ int g_shift[64];
+    __shared__ int s_ngroups;
     // an output word takes bits of the source words its ancestors lie in, the
     // same words as its neighbours: neighbouring words go to one XCD
     const PaBlk blk = map[xcd_contiguous(blockIdx.x, gridDim.x)];
@@ -1376,24 +1381,28 @@ __global__ __launch_bounds__(kThreads) void k_gather_spins(const PaRunDesc *__re
             rd.dv.M[cur ^ 1][d] = rd.dv.M[cur][a];
             rd.dv.label[cur ^ 1][d] = rd.dv.label[cur][a];
         }
-        const uint32_t ap = (uint32_t)__shfl_up((int)a, 1, 64);
-        const bool start = valid && (b == 0 || a != ap + 1u || (a & 63u) == 0u);
-        const uint64_t sm = __ballot(start);
-        const uint64_t vm = __ballot(valid);
-        if (start) {
-            const int idx = __popcll(sm & ((1ull << b) - 1ull));
-            const uint64_t above = b == 63 ? 0ull : ((sm | ~vm) & ~((2ull << b) - 1ull));
-            const int end = above ? __ffsll((long long)above) - 1 : 64;
-            r_word[idx] = a >> 6;
-            r_shift[idx] = a & 63u;
-            r_b0[idx] = (uint32_t)b;
-            r_len[idx] = (uint32_t)(end - b);
+        const uint32_t q = a >> 6;
+        const int dl = (int)(a & 63u) - b;
+        uint64_t rem = __ballot(valid);
+        int ng = 0;
+        while (rem) { // wave-uniform: one group per pass, led by the lowest remaining lane
+            const int l = __ffsll((long long)rem) - 1;
+            const uint32_t ql = (uint32_t)__shfl((int)q, l, 64);
+            const int dll = __shfl(dl, l, 64);
+            const uint64_t m = __ballot(valid && q == ql && dl == dll);
+            if (b == 0) {
+                g_word[ng] = ql;
+                g_shift[ng] = dll;
+                g_mask[ng] = m;
+            }
+            rem &= ~m;
+            ++ng;
         }
         if (b == 0)
-            s_nruns = __popcll(sm);
+            s_ngroups = ng;
     }
     __syncthreads();
-    const int nr = uni(s_nruns);
+    const int ng = uni(s_ngroups);
     const int nt = (int)blockDim.x;
     // kG sites per thread at a time: their loads are independent and in flight together
     constexpr int kG = 8;
@@ -1403,8 +1412,8 @@ __global__ __launch_bounds__(kThreads) void k_gather_spins(const PaRunDesc *__re
         for (int k = 0; k < kG; ++k)
             out[k] = v[k] = 0;
         uint32_t last = 0xFFFFFFFFu;
-        for (int i = 0; i < nr; ++i) {
-            const uint32_t sw = uni(r_word[i]);
+        for (int i = 0; i < ng; ++i) {
+            const uint32_t sw = uni(g_word[i]);
             if (sw != last) {
 #pragma unroll
                 for (int k = 0; k < kG; ++k) {
@@ -1413,11 +1422,17 @@ __global__ __launch_bounds__(kThreads) void k_gather_spins(const PaRunDesc *__re
                 }
                 last = sw;
             }
-            const uint32_t len = uni(r_len[i]), sh = uni(r_shift[i]), b0 = uni(r_b0[i]);
-            const uint64_t mask = (len >= 64 ? ~0ull : ((1ull << len) - 1ull)) << b0;
+            const int sh = uni(g_shift[i]);
+            const uint64_t mask = uni64(g_mask[i]);
+            if (sh >= 0) {
 #pragma unroll
-            for (int k = 0; k < kG; ++k)
-                out[k] = pa_bop3<PA_T3((PA_A & PA_B) | PA_C)>((v[k] >> sh) << b0, mask, out[k]);
+                for (int k = 0; k < kG; ++k)
+                    out[k] = pa_bop3<PA_T3((PA_A & PA_B) | PA_C)>(v[k] >> sh, mask, out[k]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < kG; ++k)
+                    out[k] = pa_bop3<PA_T3((PA_A & PA_B) | PA_C)>(v[k] << -sh, mask, out[k]);
+            }
         }
 #pragma unroll
         for (int k = 0; k < kG; ++k) {
