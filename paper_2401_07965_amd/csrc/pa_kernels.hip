@@ -1197,14 +1197,20 @@ __global__ __launch_bounds__(kThreads) void k_sv_partial(const PaRunDesc *__rest
 // Decoupled look-back scan (Merrill & Garland 2016) of each run's first
 // Rcur entries: the workgroups of a run (from the tile map) take their tile
 // index from the run's own atomic ticket, so every tile a tile waits on (same
-// run, lower index) belongs to a workgroup that is already running.  Entries past Rcur count as 0.  WHICH = 0: inclusive
-// sums of the weights C in place; WHICH = 1: exclusive sums P of the copy
-// numbers r, and with them the ancestor map anc[P_j + k] = j, k < r_j (kept
-// below the capacity; a resampling that overflows is not applied).
+// run, lower index) belongs to a workgroup that is already running.  Entries
+// past Rcur count as 0.  The first wave looks back over up to 64 preceding
+// tiles at once (one flag per lane): the nearest tile with an inclusive
+// prefix ends the look-back, the aggregates of the tiles after it add up.
+// WHICH = 0: inclusive sums of the weights C in place; WHICH = 1: exclusive
+// sums P of the copy numbers r, and with them the ancestor map
+// anc[P_j + k] = j, k < r_j (kept below the capacity; a resampling that
+// overflows is not applied).
 template <typename T, bool INCLUSIVE, int WHICH>
 __global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const PaRunDesc *__restrict__ runs,
                                                           const PaBlk *__restrict__ map)
 {
+    static_assert(PA_SCAN_ITEMS * sizeof(T) % 16 == 0, "items of a thread are whole 16-byte vectors");
+    constexpr int kVec = PA_SCAN_ITEMS * (int)sizeof(T) / 16;
     __shared__ uint32_t s_tile;
     __shared__ unsigned long long s_wave[PA_SCAN_THREADS / 64];
     __shared__ unsigned long long s_excl;
@@ -1224,14 +1230,23 @@ __global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const PaRunDesc *__res
     unsigned long long *total = WHICH == 0 ? &rec->Ctot : &rec->Rnew;
     PaScanTile *tiles = rd.dv.tiles + (WHICH ? ntiles : 0);
     const int64_t base = (int64_t)tile * PA_SCAN_TILE + (int64_t)threadIdx.x * PA_SCAN_ITEMS;
-    unsigned long long v[PA_SCAN_ITEMS];
+    const bool whole = base + PA_SCAN_ITEMS <= n; // the thread's items are all live
+    alignas(16) T v[PA_SCAN_ITEMS];
+    if (whole) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(in + base);
+        uint4 *dv = reinterpret_cast<uint4 *>(v);
+#pragma unroll
+        for (int k = 0; k < kVec; ++k)
+            dv[k] = src[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < PA_SCAN_ITEMS; ++k)
+            v[k] = base + k < n ? in[base + k] : (T)0;
+    }
     unsigned long long run = 0;
 #pragma unroll
-    for (int k = 0; k < PA_SCAN_ITEMS; ++k) {
-        const int64_t i = base + k;
-        v[k] = i < n ? (unsigned long long)in[i] : 0ull;
-        run += v[k];
-    }
+    for (int k = 0; k < PA_SCAN_ITEMS; ++k)
+        run += (unsigned long long)v[k];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     unsigned long long incl = run;
 #pragma unroll
@@ -1250,57 +1265,85 @@ __global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const PaRunDesc *__res
         agg += s_wave[k];
     }
     const unsigned long long thread_excl = wave_off + incl - run;
-    if (threadIdx.x == 0) {
+    if (wave == 0) {
         PaScanTile *me = tiles + tile;
         unsigned long long excl = 0;
-        if (tile == 0) {
-            me->incl = agg;
-            pa_store_release(&me->flag, 2u);
-        } else {
-            me->agg = agg;
-            pa_store_release(&me->flag, 1u);
-            int64_t p = (int64_t)tile - 1;
-            while (p >= 0) {
-                uint32_t f;
-                uint32_t spins = 0;
-                while ((f = pa_load_acquire(&tiles[p].flag)) == 0u) {
+        if (lane == 0) {
+            if (tile == 0) {
+                me->incl = agg;
+                pa_store_release(&me->flag, 2u);
+            } else {
+                me->agg = agg;
+                pa_store_release(&me->flag, 1u);
+            }
+        }
+        if (tile > 0) {
+            int64_t top = (int64_t)tile - 1; // the window: tiles top - lane
+            uint32_t spins = 0;
+            for (;;) {
+                const int64_t p = top - lane;
+                uint32_t f = 2u; // before tile 0: an inclusive prefix of 0
+                unsigned long long val = 0;
+                if (p >= 0) {
+                    f = pa_load_acquire(&tiles[p].flag);
+                    if (f == 2u)
+                        val = tiles[p].incl;
+                    else if (f == 1u)
+                        val = tiles[p].agg;
+                }
+                const uint64_t inc = __ballot(f == 2u), pending = __ballot(f == 0u);
+                const int first = inc ? __ffsll((long long)inc) - 1 : 64;
+                const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1ull); // lanes 0..first
+                if (pending & need) { // a tile the prefix needs has not published yet
                     if (++spins > (1u << 26)) {
-                        atomicOr(&rec->status, PA_ST_SCAN_TIMEOUT);
-                        break;
+                        if (lane == 0)
+                            atomicOr(&rec->status, PA_ST_SCAN_TIMEOUT);
+                        break; // gave up; the status bit is set
                     }
                     __builtin_amdgcn_s_sleep(1);
+                    continue;
                 }
-                if (f == 2u) {
-                    excl += tiles[p].incl;
+                excl += pa_wave_sum_u64(((need >> lane) & 1ull) ? val : 0ull);
+                if (first < 64)
                     break;
-                }
-                if (f == 0u)
-                    break; // gave up; the status bit is set
-                excl += tiles[p].agg;
-                --p;
+                top -= 64;
             }
-            me->incl = excl + agg;
-            pa_store_release(&me->flag, 2u);
+            if (lane == 0) {
+                me->incl = excl + agg;
+                pa_store_release(&me->flag, 2u);
+            }
         }
-        s_excl = excl;
-        if ((int64_t)tile == ntiles - 1)
-            *total = excl + agg;
+        if (lane == 0) {
+            s_excl = excl;
+            if ((int64_t)tile == ntiles - 1)
+                *total = excl + agg;
+        }
     }
     __syncthreads();
     unsigned long long acc = s_excl + thread_excl;
+    alignas(16) T o[PA_SCAN_ITEMS];
 #pragma unroll
     for (int k = 0; k < PA_SCAN_ITEMS; ++k) {
-        const int64_t i = base + k;
         if (INCLUSIVE)
-            acc += v[k];
-        if (i < n) {
-            out[i] = (T)acc;
-            if (WHICH == 1)
-                for (unsigned long long d = acc; d < acc + v[k] && d < (unsigned long long)rd.cap; ++d)
-                    rd.dv.anc[d] = (uint32_t)i;
-        }
+            acc += (unsigned long long)v[k];
+        o[k] = (T)acc;
+        if (WHICH == 1 && base + k < n)
+            for (unsigned long long d = acc; d < acc + v[k] && d < (unsigned long long)rd.cap; ++d)
+                rd.dv.anc[d] = (uint32_t)(base + k);
         if (!INCLUSIVE)
-            acc += v[k];
+            acc += (unsigned long long)v[k];
+    }
+    if (whole) {
+        uint4 *dst = reinterpret_cast<uint4 *>(out + base);
+        const uint4 *so = reinterpret_cast<const uint4 *>(o);
+#pragma unroll
+        for (int k = 0; k < kVec; ++k)
+            dst[k] = so[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < PA_SCAN_ITEMS; ++k)
+            if (base + k < n)
+                out[base + k] = o[k];
     }
 }
 
