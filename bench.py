@@ -177,17 +177,27 @@ def isolated_steps(state, streams, sched, nsteps):
     """After the timed region (untimed): `nsteps` more steps with one run at a
     time on the device, HIP events around its reweight + resample and its
     sweep.  Gives the per-launch sweep time and the resampling rate without
-    the other runs' kernels alongside."""
+    the other runs' kernels alongside.  On every other step a gate kernel
+    (the generator probe, a few hundred us) runs first on the stream, so that
+    the whole reweight + resample is queued before its first kernel starts:
+    the rate of the kernels themselves ("pre-queued"); on the others the host
+    issues the launches while the device runs them ("host-paced")."""
     import torch
-    sweep_ms, res_ms, res_bytes, attempts = [], [], 0.0, 0
+    from paper_2401_07965_amd import pa
+    gate = torch.empty(1 << 20, dtype=torch.int32, device="cuda")
+    sweep_ms, attempts = [], 0
+    res = {True: [0.0, 0.0], False: [0.0, 0.0]}  # pre-queued?: [ms, bytes]
     i = state["i"]
-    for _ in range(nsteps):
+    for k in range(nsteps):
         i += 1
         if i == POINTS:
             break
+        queued = k % 2 == 0
         for (name, rid), g, stream in zip(SCHEMES, state["runs"], streams):
             R_old = g.observables()["R"]
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            if queued:
+                pa.philox_probe(gate, 128, stream)
             ev[0].record(stream)
             g.reweight(sched[i], wait=False)
             g.resample(rid, wait=False)
@@ -195,16 +205,20 @@ def isolated_steps(state, streams, sched, nsteps):
             g.sweep(THETA)
             ev[2].record(stream)
             R_new = g.observables()["R"]  # waits for the stream
-            res_ms.append(ev[0].elapsed_time(ev[1]))
+            res[queued][0] += ev[0].elapsed_time(ev[1])
+            res[queued][1] += resample_bytes(R_old, R_new)
             sweep_ms.append(ev[1].elapsed_time(ev[2]))
-            res_bytes += resample_bytes(R_old, R_new)
             attempts += THETA * L ** D * R_new
     if not sweep_ms:
         return None
+
+    def rate(q):
+        return res[q][1] / (res[q][0] * 1e-3) / 1e9 if res[q][0] > 0 else None
     return {"steps": len(sweep_ms) // len(SCHEMES),
             "sweep_attempts_per_ns": attempts / (sum(sweep_ms) * 1e-3) / 1e9,
             "sweep_avg_launch_ms": sum(sweep_ms) / len(sweep_ms),
-            "resample_GB_per_s": res_bytes / (sum(res_ms) * 1e-3) / 1e9}
+            "resample_GB_per_s": rate(True),
+            "resample_GB_per_s_host_paced": rate(False)}
 
 
 def philox_rate():

@@ -190,7 +190,55 @@ struct Batch {
     uint32_t sweeps = 0;
     bool reweighted = false;
     int anneal_points = 0;
+    // launch bookkeeping: the level histogram is zero (init or observables
+    // ran since it was last built); the latest launch was a reweighting, which
+    // also prepared the resampling's flags and status
+    bool hist_clean = false;
+    bool rs_prepped = false;
 };
+
+namespace {
+
+// Launch wrappers that keep the bookkeeping above.
+hipError_t launch_init(Batch *b)
+{
+    hipError_t e = pa_b_init(b->v);
+    b->hist_clean = true;
+    b->rs_prepped = false;
+    return e;
+}
+
+hipError_t launch_reweight(Batch *b, double beta_next)
+{
+    hipError_t e = pa_b_reweight(b->v, beta_next, b->hist_clean);
+    b->hist_clean = false;
+    b->rs_prepped = true;
+    return e;
+}
+
+hipError_t launch_resample(Batch *b, int scheme, int freeze, int kq)
+{
+    hipError_t e = pa_b_resample(b->v, scheme, freeze, kq, b->rs_prepped);
+    b->rs_prepped = false;
+    return e;
+}
+
+hipError_t launch_observables(Batch *b, int point)
+{
+    hipError_t e = pa_b_observables(b->v, point);
+    b->hist_clean = true;
+    b->rs_prepped = false;
+    return e;
+}
+
+// Kernels that build the histogram themselves, or replace the population.
+void touched_histogram(Batch *b)
+{
+    b->hist_clean = false;
+    b->rs_prepped = false;
+}
+
+} // namespace
 
 struct pa_ctx {
     Batch b;
@@ -458,7 +506,7 @@ pa_status make_batch(const pa_config *cfgs, int32_t nruns, int32_t max_points, v
     for (int m = 0; m < nruns; ++m)
         up(b->hdesc[m].dv.jmask, b->jmask[m].data(), b->jmask[m].size());
     if (e == hipSuccess)
-        e = pa_b_init(b->v);
+        e = launch_init(b);
     if (e == hipSuccess)
         e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
@@ -627,7 +675,7 @@ pa_status pa_reweight(pa_ctx *c, double beta_next, double *lnQ_out)
     Batch *b = &c->b;
     if (!std::isfinite(beta_next) || beta_next < b->beta)
         return fail(b, PA_E_INVAL, "beta_next must be finite and >= the current beta");
-    hipError_t e = pa_b_reweight(b->v, beta_next);
+    hipError_t e = launch_reweight(b, beta_next);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_reweight");
     if (!lnQ_out) { // deferred: a non-finite ln Q is caught by the resampling
@@ -659,7 +707,7 @@ pa_status pa_resample(pa_ctx *c, pa_resampler scheme, int64_t *R_new_out)
     if (!b->reweighted)
         return fail(b, PA_E_STATE, "pa_resample needs a pa_reweight first");
     const bool deferred = R_new_out == nullptr;
-    hipError_t e = pa_b_resample(b->v, (int)scheme, deferred ? 1 : 0, -1);
+    hipError_t e = launch_resample(b, (int)scheme, deferred ? 1 : 0, -1);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_resample");
     if (deferred) { // a failure freezes the run; the next synchronising call reports it
@@ -699,7 +747,7 @@ pa_status pa_resample_conditional(pa_ctx *c, pa_resampler scheme, double kappa, 
     b->v.weights = true;
     const int kq = (int)std::floor(kappa * 65536.0 + 0.5);
     const bool deferred = R_new_out == nullptr && resampled_out == nullptr;
-    hipError_t e = pa_b_resample(b->v, (int)scheme, deferred ? 1 : 0, kq);
+    hipError_t e = launch_resample(b, (int)scheme, deferred ? 1 : 0, kq);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_resample_conditional");
     if (deferred) {
@@ -752,7 +800,7 @@ pa_status pa_observables(pa_ctx *c, pa_obs *out)
     if (!c)
         return fail(nullptr, PA_E_INVAL, "ctx is NULL");
     Batch *b = &c->b;
-    hipError_t e = pa_b_observables(b->v, -1);
+    hipError_t e = launch_observables(b, -1);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_observables");
     if (!out)
@@ -844,6 +892,7 @@ pa_status pa_import_state(pa_ctx *c, const pa_host_state *st)
         e = hipMemcpy(d.dv.label[k], st->label, (size_t)R * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = pa_b_set_beta(b->v, st->beta, st->lnZ, st->step, st->sweeps, (uint64_t)R);
+    touched_histogram(b);
     if (e == hipSuccess)
         e = hipStreamSynchronize(b->v.stream);
     if (e != hipSuccess)
@@ -899,6 +948,7 @@ pa_status pa_step_alpha(pa_ctx *c, double dbeta, double *alpha_out)
     pa_status u = need_uniform(b, "pa_step_alpha");
     if (u != PA_OK)
         return u;
+    touched_histogram(b);
     hipError_t e = pa_b_rule(b->v, 0.0, dbeta, 0, 0);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_step_alpha");
@@ -920,6 +970,7 @@ pa_status pa_step_rule(pa_ctx *c, double alpha_star, double dbeta_max, int32_t i
     pa_status u = need_uniform(b, "pa_step_rule");
     if (u != PA_OK)
         return u;
+    touched_histogram(b);
     hipError_t e = pa_b_rule(b->v, alpha_star, dbeta_max, iterations, 1);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_step_rule");
@@ -1035,7 +1086,7 @@ pa_status pa_batch_tune(pa_batch *p, int32_t theta, int32_t *threads_out)
             threads_out[g] = best_t;
     }
     if (e == hipSuccess)
-        e = pa_b_init(b->v);
+        e = launch_init(b);
     if (e == hipSuccess)
         e = hipStreamSynchronize(b->v.stream);
     (void)hipEventDestroy(e0);
@@ -1081,17 +1132,17 @@ pa_status pa_batch_anneal(pa_batch *p, const double *betas, int32_t npoints, int
         e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     const PaBatchView &v = b->v; // record rows keep the stride max_points
     if (e == hipSuccess)
-        e = pa_b_init(v);
+        e = launch_init(b);
     if (e == hipSuccess)
-        e = pa_b_observables(v, 0);
+        e = launch_observables(b, 0);
     for (int i = 1; i < npoints && e == hipSuccess; ++i) {
-        e = pa_b_reweight(v, betas[i]);
+        e = launch_reweight(b, betas[i]);
         if (e == hipSuccess)
-            e = pa_b_resample(v, (int)scheme, 1, -1);
+            e = launch_resample(b, (int)scheme, 1, -1);
         if (e == hipSuccess && theta > 0)
             e = pa_b_sweep(v, theta, 0u); // every run was just resampled
         if (e == hipSuccess)
-            e = pa_b_observables(v, i);
+            e = launch_observables(b, i);
     }
     if (use_graph) {
         hipError_t e2 = hipStreamEndCapture(st, &graph);
@@ -1392,6 +1443,7 @@ pa_status pa_features(pa_ctx *c, float *out8)
     pa_status u = need_uniform(b, "pa_features");
     if (u != PA_OK)
         return u;
+    touched_histogram(b);
     hipError_t e = pa_b_features(b->v);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_features");
@@ -1419,6 +1471,7 @@ pa_status pa_step_learned(pa_ctx *c, pa_mlp *m, double alpha_star, double dbeta_
         if (e != hipSuccess)
             return hip_fail(b, e, "pa_step_learned");
     }
+    touched_histogram(b);
     hipError_t e = pa_b_features(b->v);
     if (e == hipSuccess)
         e = pa_mlp_launch_propose(b->v, m->d, dbeta_max);

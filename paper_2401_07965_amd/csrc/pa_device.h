@@ -221,6 +221,30 @@ __device__ __forceinline__ uint64_t pa_block_sum_u64(uint64_t v, uint64_t *lds /
     return t;
 }
 
+// K block-wide uint64 sums with one exchange through LDS (exact, so any order).
+template <int K>
+__device__ __forceinline__ void pa_block_sum_u64x(uint64_t (&v)[K], uint64_t *lds /* >= 16 K */)
+{
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        v[i] = pa_wave_sum_u64(v[i]);
+    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            lds[wave * K + i] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        uint64_t t = 0;
+        for (int k = 0; k < nwaves; ++k)
+            t += lds[k * K + i];
+        v[i] = t;
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------- agent-scope flags
 __device__ __forceinline__ void pa_store_release(uint32_t *p, uint32_t v)
 {

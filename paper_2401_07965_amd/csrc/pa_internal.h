@@ -30,6 +30,7 @@ struct PaRecord {
     double beta;      // current inverse temperature
     // histogram of the current population (reweight, adaptive step)
     int32_t emin, emax;
+    int32_t wemin, pad2; // E_min of the latest reweighting (its weights are per level above it)
     // Q(beta_cur, beta_next): Eq. (1) with the shift by E_min
     double qsum, lnQ, dbeta, beta_next;
     uint64_t S;     // sum of integer weights
@@ -178,9 +179,11 @@ struct PaBatchView {
 hipError_t pa_b_init(const PaBatchView &v);
 hipError_t pa_b_sweep(const PaBatchView &v, int theta, uint32_t t0); // t0: sweeps already done at this beta
 hipError_t pa_b_sweep_group(const PaBatchView &v, int g, int theta, int threads);
-hipError_t pa_b_reweight(const PaBatchView &v, double beta_next);
+// hist_clean: the level histogram is zero (observables or init ran since it was last built)
+hipError_t pa_b_reweight(const PaBatchView &v, double beta_next, bool hist_clean);
 // kq >= 0: conditional, resample only when ESS < kq 2^-16 R_cur (else keep the population)
-hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze, int kq);
+// prepped: a pa_b_reweight came right before (it clears the resampling's flags and status)
+hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze, int kq, bool prepped);
 hipError_t pa_b_observables(const PaBatchView &v, int point);
 hipError_t pa_b_rule(const PaBatchView &v, double alpha_star, double dbeta_max, int iterations, int bisect);
 hipError_t pa_b_set_beta(const PaBatchView &v, double beta, double lnZ, uint32_t step, uint32_t sweeps,

@@ -551,9 +551,20 @@ __global__ __launch_bounds__(kThreads) void k_hist(const PaRunDesc *__restrict__
     for (int i = threadIdx.x; i < H; i += blockDim.x)
         if (lh[i])
             atomicAdd(&rd.dv.hist[i], lh[i]);
+    // one atomic per workgroup: the wave extremes meet in LDS first
+    __shared__ int64_t s_lo[16], s_hi[16];
     lo = pa_wave_min_i64(lo);
     hi = pa_wave_max_i64(hi);
     if ((threadIdx.x & 63) == 0) {
+        s_lo[threadIdx.x >> 6] = lo;
+        s_hi[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+            lo = s_lo[k] < lo ? s_lo[k] : lo;
+            hi = s_hi[k] > hi ? s_hi[k] : hi;
+        }
         atomicMin(&rec->emin, (int)lo);
         atomicMax(&rec->emax, (int)hi);
     }
@@ -578,7 +589,7 @@ __device__ __forceinline__ pa_u128 block_sum_u128(pa_u128 v, uint64_t *su)
 __global__ __launch_bounds__(1024) void k_reweight(const PaRunDesc *__restrict__ runs, double beta_next)
 {
     __shared__ double sd[16];
-    __shared__ uint64_t su[16];
+    __shared__ uint64_t su[16 * 5];
     const PaRunDesc &rd = runs[blockIdx.x];
     PaRecord *rec = rd.dv.rec;
     if (frozen(rec))
@@ -586,9 +597,18 @@ __global__ __launch_bounds__(1024) void k_reweight(const PaRunDesc *__restrict__
     const int DN = rd.d * rd.N;
     const double dbeta = beta_next - rec->beta;
     const int32_t emin = rec->emin, emax = rec->emax;
+    // the resampling that follows starts with clean tile flags, tickets and status
+    const int64_t ntiles = (rd.cap + PA_SCAN_TILE - 1) / PA_SCAN_TILE;
+    for (int64_t t = threadIdx.x; t < 2 * ntiles; t += blockDim.x)
+        rd.dv.tiles[t].flag = 0u;
     if (rec->weighted) {
         __syncthreads(); // every thread has read the record before thread 0 writes it
         if (threadIdx.x == 0) {
+            rec->ticket[0] = rec->ticket[1] = 0u;
+            rec->status = 0;
+            rec->skip = 0;
+            rec->keep = 0;
+            rec->wemin = emin;
             rec->dbeta = dbeta;
             rec->beta_next = beta_next;
             rec->S = 0;
@@ -618,9 +638,18 @@ __global__ __launch_bounds__(1024) void k_reweight(const PaRunDesc *__restrict__
         s2 += (pa_u128)((uint64_t)n * W) * W;
     }
     const double Q = pa_block_sum_f64(q, sd);
-    const uint64_t S = pa_block_sum_u64(s, su);
-    const pa_u128 S2 = block_sum_u128(s2, su);
+    // S and the four 32-bit limbs of sum n W^2 (a limb's block total stays below 2^42)
+    uint64_t x[5] = {s, (uint64_t)s2 & 0xFFFFFFFFull, (uint64_t)(s2 >> 32) & 0xFFFFFFFFull,
+                     (uint64_t)(s2 >> 64) & 0xFFFFFFFFull, (uint64_t)(s2 >> 96)};
+    pa_block_sum_u64x<5>(x, su);
+    const uint64_t S = x[0];
+    const pa_u128 S2 = (pa_u128)x[1] + ((pa_u128)x[2] << 32) + ((pa_u128)x[3] << 64) + ((pa_u128)x[4] << 96);
     if (threadIdx.x == 0) {
+        rec->ticket[0] = rec->ticket[1] = 0u;
+        rec->status = 0;
+        rec->skip = 0;
+        rec->keep = 0;
+        rec->wemin = emin;
         rec->qsum = Q;
         rec->S = S;
         rec->Q2[0] = (uint64_t)S2;
@@ -864,7 +893,7 @@ __device__ __forceinline__ uint64_t rep_weight(const RepCtx &c, bool wt, const i
 // (x_j is then the argument of its per-level weights and m = 0).
 __device__ __forceinline__ double wx(const PaDev &dv, const PaRecord *rec, int cur, bool wt, int64_t j)
 {
-    const double g = (double)(dv.E[cur][j] - rec->emin);
+    const double g = (double)(dv.E[cur][j] - rec->wemin);
     const double lw = wt ? dv.lw[j] : 0.0;
     return lw + (-(rec->dbeta * g));
 }
@@ -949,7 +978,7 @@ __global__ __launch_bounds__(kThreads) void k_rw_final(const PaRunDesc *__restri
     l = pa_block_sum_f64(l, sd);
     if (threadIdx.x == 0) {
         rec->qsum = q;
-        rec->lnQ = ((-rec->dbeta * (double)rec->emin - xmag_value(rec)) + log(q)) - log(l);
+        rec->lnQ = ((-rec->dbeta * (double)rec->wemin - xmag_value(rec)) + log(q)) - log(l);
     }
 }
 
@@ -1005,7 +1034,7 @@ __global__ __launch_bounds__(kThreads) void k_counts_nearest(const PaRunDesc *__
     const bool wt = c.rec->weighted != 0u;
     const PaRunDesc &rd = *c.rd;
     const int DN = rd.d * rd.N;
-    const int hmin = (c.rec->emin + DN) >> 2;
+    const int hmin = (c.rec->wemin + DN) >> 2;
     const uint64_t S = c.rec->S, Rt = (uint64_t)rd.R0;
     const uint32_t step = c.rec->step + 1;
     const int32_t *E = rd.dv.E[c.rec->cur];
@@ -1036,7 +1065,7 @@ __global__ __launch_bounds__(kThreads) void k_counts_poisson(const PaRunDesc *__
     const bool wt = c.rec->weighted != 0u;
     const PaRunDesc &rd = *c.rd;
     const int DN = rd.d * rd.N;
-    const int hmin = (c.rec->emin + DN) >> 2;
+    const int hmin = (c.rec->wemin + DN) >> 2;
     const uint64_t S = c.rec->S, Rt = (uint64_t)rd.R0;
     const uint32_t step = c.rec->step + 1;
     const int32_t *E = rd.dv.E[c.rec->cur];
@@ -1082,10 +1111,12 @@ __global__ __launch_bounds__(kThreads) void k_weights(const PaRunDesc *__restric
     const PaRunDesc &rd = *c.rd;
     const bool wt = c.rec->weighted != 0u;
     const int DN = rd.d * rd.N;
-    const int hmin = (c.rec->emin + DN) >> 2;
+    const int hmin = (c.rec->wemin + DN) >> 2;
     const int32_t *E = rd.dv.E[c.rec->cur];
-    for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x)
+    for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x) {
         rd.dv.C[j] = rep_weight(c, wt, E, j, DN, hmin);
+        rd.dv.r[j] = 0; // the multinomial draws add to it; the systematic counts overwrite it
+    }
 }
 
 // Systematic: #points (k + U/2^32) S/R below c, k < R, is
@@ -1126,16 +1157,6 @@ __global__ __launch_bounds__(kThreads) void k_counts_systematic(const PaRunDesc 
         sv = sv + sv_term(r, cj - cp, (double)S, (double)Rt); // C is the inclusive sum of W
     }
     sv_store(c, sv, sd);
-}
-
-__global__ __launch_bounds__(kThreads) void k_clear_counts(const PaRunDesc *__restrict__ runs,
-                                                           const PaBlk *__restrict__ map)
-{
-    RepCtx c;
-    if (!rs_ctx(runs, map, &c))
-        return;
-    for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x)
-        c.rd->dv.r[j] = 0;
 }
 
 // Multinomial: U_k = floor(r S / 2^128), r = 128 bits of Philox(k, 0, i,
@@ -1185,7 +1206,7 @@ __global__ __launch_bounds__(kThreads) void k_sv_partial(const PaRunDesc *__rest
     const PaRunDesc &rd = *c.rd;
     const bool wt = c.rec->weighted != 0u;
     const int DN = rd.d * rd.N;
-    const int hmin = (c.rec->emin + DN) >> 2;
+    const int hmin = (c.rec->wemin + DN) >> 2;
     const double S = (double)c.rec->S, Rt = (double)rd.R0;
     const int32_t *E = rd.dv.E[c.rec->cur];
     double acc = 0.0;
@@ -1708,6 +1729,13 @@ __global__ __launch_bounds__(kThreads) void k_obs_final(const PaRunDesc *__restr
         for (int k = threadIdx.x; k < nparts; k += blockDim.x)
             v = v + rd.dv.partial[k];
     const double t = pa_block_sum_f64(v, sd);
+    // the level histogram starts from zero at the next reweighting
+    for (int i = threadIdx.x; i < rd.H; i += blockDim.x)
+        rd.dv.hist[i] = 0;
+    if (threadIdx.x == 0) {
+        rec->emin = INT_MAX;
+        rec->emax = INT_MIN;
+    }
     double ws[PA_WPARTS];
     if (wt) {
         const int64_t chunks = (rd.cap + PA_CHUNK - 1) / PA_CHUNK;
@@ -1968,6 +1996,7 @@ hipError_t pa_query_lds(int *max_lds)
 hipError_t pa_b_init(const PaBatchView &v)
 {
     k_init_rec<<<v.nruns, 64, 0, v.stream>>>(v.runs);
+    k_hist_prep<<<v.nruns, kThreads, 0, v.stream>>>(v.runs);
     k_init_spins<<<v.ncol, kThreads, 0, v.stream>>>(v.runs, v.col);
     k_init_labels<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
     hipError_t e = hipGetLastError();
@@ -2011,9 +2040,12 @@ static hipError_t hist_launch(const PaBatchView &v)
     return hipGetLastError();
 }
 
-hipError_t pa_b_reweight(const PaBatchView &v, double beta_next)
+hipError_t pa_b_reweight(const PaBatchView &v, double beta_next, bool hist_clean)
 {
-    hipError_t e = hist_launch(v);
+    if (!hist_clean)
+        k_hist_prep<<<v.nruns, kThreads, 0, v.stream>>>(v.runs);
+    k_hist<<<v.nhrep, kThreads, (size_t)v.maxH * 4, v.stream>>>(v.runs, v.hrep);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
     k_reweight<<<v.nruns, 1024, 0, v.stream>>>(v.runs, beta_next);
@@ -2057,10 +2089,11 @@ static hipError_t scan_launch(const PaBatchView &v)
     return hipGetLastError();
 }
 
-hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze, int kq)
+hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze, int kq, bool prepped)
 {
     hipError_t e;
-    k_resample_prep<<<v.nruns, kThreads, 0, v.stream>>>(v.runs);
+    if (!prepped)
+        k_resample_prep<<<v.nruns, kThreads, 0, v.stream>>>(v.runs);
     if (kq >= 0)
         k_cond_decide<<<v.nruns, 64, 0, v.stream>>>(v.runs, (uint32_t)kq);
     switch (scheme) {
@@ -2078,7 +2111,6 @@ hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze, int kq)
         if (scheme == 3) {
             k_counts_systematic<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
         } else {
-            k_clear_counts<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
             k_counts_multinomial<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
             k_sv_partial<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
         }
