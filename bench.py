@@ -266,6 +266,46 @@ def resample_bytes(R_old, R_new):
     return R_old * (4 + 4 + 4 + 4 + 4) + R_new * (2 * N / 8 + 3 * 4 * 2 + 4)
 
 
+def resample_scaling(sizes=(100000, 1000000, 4000000), steps=4):
+    """Reweight + resample rate against the population size: one run of the
+    2D ferromagnet L = 64 per size, theta = 10 sweeps between steps (beta_i =
+    0.6 i/200 from i = 100), nearest-integer and systematic resampling, each
+    step queued whole behind a gate kernel; HIP events on the run's stream."""
+    import torch
+    from paper_2401_07965_amd import pa
+    gate = torch.empty(1 << 20, dtype=torch.int32, device="cuda")
+    sched = betas()
+    out = {}
+    for R in sizes:
+        row = {}
+        for name, rid in (("nearest", 2), ("systematic", 3)):
+            stream = torch.cuda.Stream()
+            g = pa.PARun(D, L, R, seed=1, run_id=rid, stream=stream)
+            i0 = 100
+            for i in range(1, i0):  # reach the schedule point untimed (one sweep per step)
+                g.reweight(sched[i], wait=False)
+                g.resample(rid, wait=False)
+                g.sweep(1)
+            ms, nbytes = 0.0, 0.0
+            for i in range(i0, i0 + steps):
+                R_old = g.observables()["R"]
+                pa.philox_probe(gate, 128, stream)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                g.reweight(sched[i], wait=False)
+                g.resample(rid, wait=False)
+                e1.record(stream)
+                g.sweep(THETA)
+                R_new = g.observables()["R"]
+                ms += e0.elapsed_time(e1)
+                nbytes += resample_bytes(R_old, R_new)
+            g.close()
+            row[name] = {"GB_per_s": nbytes / (ms * 1e-3) / 1e9, "us_per_resampling": ms * 1e3 / steps}
+        out[str(R)] = row
+    return {"workload": "2D Ising FM L=64, one run per size, steps at beta_i = 0.6 i/200 from i = 100, "
+                        "theta=10, each reweight + resample queued whole", "by_R": out}
+
+
 def batched_bench(theta=10, scheme=3, verify_runs=8):
     """Uneven-batch workload: 256 independent +-J runs (16 disorder samples x 16
     runs; per sample d in {2,3}, L in {8,12,16,24}; R log-uniform in [1e3, 1e5]),
@@ -670,6 +710,7 @@ def main():
         out["roofline"]["traffic_unit"] = "bytes/launch"
         out["roofline"]["valu_busy"] = float(prof["valu_busy"])
     if not a.no_rows:
+        out["resample_scaling"] = resample_scaling()
         out["batched"] = batched_bench()
         out["learned"] = learned_bench()
         out["combination"] = combination_study()

@@ -244,14 +244,3 @@ __device__ __forceinline__ void pa_block_sum_u64x(uint64_t (&v)[K], uint64_t *ld
     }
     __syncthreads();
 }
-
-// ---------------------------------------------------------------- agent-scope flags
-__device__ __forceinline__ void pa_store_release(uint32_t *p, uint32_t v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ uint32_t pa_load_acquire(const uint32_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}

@@ -77,10 +77,15 @@ struct PaStepRecord {
     uint32_t status, pad;
 };
 
+// Published state of a scan tile in one 64-bit word, so that a single atomic
+// store makes the status and its value visible together: bits 63..62 are the
+// status (0 none, 1 aggregate, 2 inclusive prefix), bits 61..0 the value.
 struct PaScanTile {
-    unsigned long long agg, incl;
-    uint32_t flag, pad;
+    unsigned long long word;
 };
+#define PA_TILE_AGG (1ull << 62)
+#define PA_TILE_INCL (2ull << 62)
+#define PA_TILE_VALUE ((1ull << 62) - 1ull)
 
 #define PA_SCAN_THREADS 512
 #define PA_SCAN_ITEMS 16

@@ -600,7 +600,7 @@ __global__ __launch_bounds__(1024) void k_reweight(const PaRunDesc *__restrict__
     // the resampling that follows starts with clean tile flags, tickets and status
     const int64_t ntiles = (rd.cap + PA_SCAN_TILE - 1) / PA_SCAN_TILE;
     for (int64_t t = threadIdx.x; t < 2 * ntiles; t += blockDim.x)
-        rd.dv.tiles[t].flag = 0u;
+        rd.dv.tiles[t].word = 0ull;
     if (rec->weighted) {
         __syncthreads(); // every thread has read the record before thread 0 writes it
         if (threadIdx.x == 0) {
@@ -1287,31 +1287,21 @@ __global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const PaRunDesc *__res
     }
     const unsigned long long thread_excl = wave_off + incl - run;
     if (wave == 0) {
-        PaScanTile *me = tiles + tile;
+        unsigned long long *me = &tiles[tile].word;
         unsigned long long excl = 0;
-        if (lane == 0) {
-            if (tile == 0) {
-                me->incl = agg;
-                pa_store_release(&me->flag, 2u);
-            } else {
-                me->agg = agg;
-                pa_store_release(&me->flag, 1u);
-            }
-        }
+        if (lane == 0) // tile 0's aggregate is its inclusive prefix
+            __hip_atomic_store(me, (tile == 0 ? PA_TILE_INCL : PA_TILE_AGG) | agg, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         if (tile > 0) {
             int64_t top = (int64_t)tile - 1; // the window: tiles top - lane
             uint32_t spins = 0;
             for (;;) {
                 const int64_t p = top - lane;
-                uint32_t f = 2u; // before tile 0: an inclusive prefix of 0
-                unsigned long long val = 0;
-                if (p >= 0) {
-                    f = pa_load_acquire(&tiles[p].flag);
-                    if (f == 2u)
-                        val = tiles[p].incl;
-                    else if (f == 1u)
-                        val = tiles[p].agg;
-                }
+                unsigned long long word = PA_TILE_INCL; // before tile 0: an inclusive prefix of 0
+                if (p >= 0)
+                    word = __hip_atomic_load(&tiles[p].word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t f = (uint32_t)(word >> 62);
+                const unsigned long long val = word & PA_TILE_VALUE;
                 const uint64_t inc = __ballot(f == 2u), pending = __ballot(f == 0u);
                 const int first = inc ? __ffsll((long long)inc) - 1 : 64;
                 const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1ull); // lanes 0..first
@@ -1329,10 +1319,10 @@ __global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const PaRunDesc *__res
                     break;
                 top -= 64;
             }
-            if (lane == 0) {
-                me->incl = excl + agg;
-                pa_store_release(&me->flag, 2u);
-            }
+            // a prefix too wide for the word stays unpublished: later tiles then
+            // add this tile's aggregate themselves
+            if (lane == 0 && excl + agg <= PA_TILE_VALUE)
+                __hip_atomic_store(me, PA_TILE_INCL | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (lane == 0) {
             s_excl = excl;
@@ -1377,7 +1367,7 @@ __global__ void k_resample_prep(const PaRunDesc *__restrict__ runs)
     PaRecord *rec = rd.dv.rec;
     const int64_t ntiles = (rd.cap + PA_SCAN_TILE - 1) / PA_SCAN_TILE;
     for (int64_t t = threadIdx.x; t < 2 * ntiles; t += blockDim.x)
-        rd.dv.tiles[t].flag = 0u;
+        rd.dv.tiles[t].word = 0ull;
     if (threadIdx.x == 0) {
         rec->ticket[0] = rec->ticket[1] = 0u;
         if (!frozen(rec)) {
