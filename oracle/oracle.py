@@ -58,7 +58,7 @@ def lib():
         L.orc_init.restype = None
         L.orc_sweep.argtypes = [_c.c_int, _c.c_int, _i8p, _c.c_int64, _i64p, _i8p, _i32p,
                                 _c.c_uint32, _c.c_uint32, _c.c_uint32, _c.c_uint32, _c.c_int32,
-                                _c.c_double]
+                                _c.c_double, _c.POINTER(_c.c_uint64)]
         L.orc_sweep.restype = None
         L.orc_reweight.argtypes = [_c.c_int64, _i32p, _c.c_double, _c.POINTER(_c.c_double), _u64p,
                                    _c.POINTER(_c.c_uint64)]
@@ -137,12 +137,16 @@ def init_rows(d, L, rows, seed, run_id, J):
 
 
 def sweep_rows(d, L, J, rows, spins, E, seed, run_id, step, t0, theta, beta):
-    """theta Metropolis sweeps (in place) of the replicas listed in ``rows``."""
+    """theta Metropolis sweeps (in place) of the replicas listed in ``rows``.
+    Returns the plane pairs (Philox evaluations) deciding them needed: per
+    word-site, pairs up to the one where its slowest drawing replica decides."""
     rows = np.ascontiguousarray(rows, np.int64)
     assert np.all(np.diff(rows) > 0) if len(rows) > 1 else True
     assert spins.dtype == np.int8 and spins.flags.c_contiguous and E.dtype == np.int32
+    calls = ctypes.c_uint64()
     lib().orc_sweep(d, L, np.ascontiguousarray(J, np.int8), len(rows), rows, spins, E, seed,
-                    run_id, step, t0, theta, float(beta))
+                    run_id, step, t0, theta, float(beta), ctypes.byref(calls))
+    return calls.value
 
 
 def reweight(E, dbeta):
@@ -280,6 +284,7 @@ class OracleRun:
         self.last_counts = None
         self.lw = None
         self.resamplings = 0
+        self.philox_calls = 0  # plane pairs the sweeps needed (work count)
 
     @property
     def Rcur(self):
@@ -360,8 +365,8 @@ class OracleRun:
         return Rn
 
     def sweep(self, theta):
-        sweep_rows(self.d, self.L, self.J, np.arange(self.Rcur), self.spins, self.E, self.seed,
-                   self.run_id, self.step, self.t, theta, self.beta)
+        self.philox_calls += sweep_rows(self.d, self.L, self.J, np.arange(self.Rcur), self.spins, self.E,
+                                        self.seed, self.run_id, self.step, self.t, theta, self.beta)
         self.t += theta
 
     def magnetization(self):

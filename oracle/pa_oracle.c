@@ -200,6 +200,13 @@ void orc_init(int d, int L, int64_t nrows, const int64_t *rep, uint32_t seed, ui
 /* rows[n] holds replica index rep[n] (ascending); E is updated with each   */
 /* accepted dE.  Replicas are independent chains, so they are visited one   */
 /* word (64 replicas) at a time to reuse the planes of that word.           */
+/*                                                                          */
+/* Work count (accounting, not part of the method): u < T is decided at the */
+/* first plane k where bit 31-k of u and of T differ (k = 32 if u = T).  A  */
+/* word-site needs plane pairs 0..k/2 of its slowest drawing replica (dE > 0 */
+/* and 0 < T < 2^32), at most 16; *calls (if not NULL) gets the sum of the  */
+/* pairs over the word-sites visited, i.e. the Philox evaluations that      */
+/* deciding replica by replica in plane order needs.                        */
 /* ------------------------------------------------------------------------ */
 uint64_t orc_threshold(double beta, int dE)
 {
@@ -230,10 +237,21 @@ static uint32_t uniform_of(const uint64_t planes[32], uint32_t b)
     return u;
 }
 
+static int decision_plane(uint32_t u, uint64_t T)
+{
+    for (int k = 0; k < 32; ++k) {
+        uint32_t ub = (u >> (31 - k)) & 1u, tb = (uint32_t)(T >> (31 - k)) & 1u;
+        if (ub != tb)
+            return k;
+    }
+    return 32;
+}
+
 void orc_sweep(int d, int L, const int8_t *J, int64_t nrows, const int64_t *rep, int8_t *spins,
                int32_t *E, uint32_t seed, uint32_t run_id, uint32_t step, uint32_t t0,
-               int32_t theta, double beta)
+               int32_t theta, double beta, uint64_t *calls)
 {
+    uint64_t total_calls = 0;
     int64_t N = n_sites(d, L);
     uint64_t T[4 * 3 + 1];
     for (int dE = 0; dE <= 12; ++dE)
@@ -247,7 +265,7 @@ void orc_sweep(int d, int L, const int8_t *J, int64_t nrows, const int64_t *rep,
             gstart[ng++] = n;
     gstart[ng] = nrows;
 
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : total_calls)
     for (int64_t g = 0; g < ng; ++g) {
         uint32_t w = (uint32_t)(rep[gstart[g]] >> 6);
         uint64_t planes[32];
@@ -258,6 +276,7 @@ void orc_sweep(int d, int L, const int8_t *J, int64_t nrows, const int64_t *rep,
                     if (color_of(s, d, L) != color)
                         continue;
                     metro_planes(seed, run_id, (uint32_t)s, w, step, t, planes);
+                    int pairs = 0;
                     for (int64_t n = gstart[g]; n < gstart[g + 1]; ++n) {
                         int8_t *sp = spins + n * N;
                         int field = 0;
@@ -273,17 +292,26 @@ void orc_sweep(int d, int L, const int8_t *J, int64_t nrows, const int64_t *rep,
                         } else {
                             uint32_t u = uniform_of(planes, (uint32_t)(rep[n] & 63));
                             accept = (uint64_t)u < T[dE];
+                            if (T[dE] > 0 && T[dE] < ((uint64_t)1 << 32)) {
+                                int k = decision_plane(u, T[dE]);
+                                int need = (k < 32 ? k : 31) / 2 + 1;
+                                if (need > pairs)
+                                    pairs = need;
+                            }
                         }
                         if (accept) {
                             sp[s] = (int8_t)-sp[s];
                             E[n] += dE;
                         }
                     }
+                    total_calls += (uint64_t)pairs;
                 }
             }
         }
     }
     free(gstart);
+    if (calls)
+        *calls = total_calls;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -274,3 +274,29 @@ def test_extinction_matches_oracle_and_leaves_the_state():
     else:
         raise AssertionError("no extinction in 40 steps")
     g.close()
+
+
+@pytest.mark.parametrize("d,L,R,scheme,J", [(2, 8, 640, O.SYSTEMATIC, None),
+                                            (3, 4, 256, O.MULTINOMIAL, "glass")])
+def test_work_counters_match_the_oracle_count(d, L, R, scheme, J):
+    """The sweeps' Philox count (the roofline's work figure) equals the oracle's
+    count of plane pairs the decisions need, and the site and attempt counts
+    their closed forms (full 64-replica words, fixed-size resampling)."""
+    from paper_2401_07965_amd import pa
+    Jc = ea_couplings(d, L, 3) if J else None
+    print(f"[parity] work counters d={d} L={L} R={R} scheme={scheme}", flush=True)
+    g = pa.PARun(d, L, R, seed=6, run_id=1, couplings=Jc)
+    o = O.OracleRun(d, L, R, seed=6, run_id=1, J=Jc)
+    theta, steps = 4, 12
+    for beta in schedule(1.2, steps + 1)[1:]:
+        g.reweight(beta)
+        o.reweight(beta)
+        g.resample(scheme)
+        o.resample(scheme)
+        g.sweep(theta)
+        o.sweep(theta)
+    c = g.counters()
+    assert c["philox_calls"] == o.philox_calls > 0
+    assert c["site_updates"] == steps * theta * L ** d * (R // 64)
+    assert c["spin_attempts"] == steps * theta * L ** d * R
+    g.close()

@@ -187,3 +187,25 @@ def test_population_energy_moments_match_exact(d, L, kind, beta):
         assert abs(obs[key] * scale - mom[k]) < 6 * sd + 1e-9, (k, obs[key] * scale, mom[k], sd)
     # the exact integer sums behind them
     assert obs["sumE3"] == sum(int(e) ** 3 for e in E.tolist())
+
+
+def test_plane_pair_count_of_all_drawing_words():
+    """Work count of the sweeps: a word-site whose 64 replicas all draw needs
+    plane pairs up to its slowest replica's deciding plane; each plane decides
+    a replica with probability 1/2, so E[pairs] = sum_{p=1..16} P(max_b k_b >=
+    2(p-1)) = sum_p 1 - (1 - 2^(-2(p-1)))^64.  A ferromagnet's ordered state
+    at beta = 0.5 keeps (nearly) every replica drawing."""
+    d, L, R = 2, 16, 64
+    J = O.ferromagnet(d, L)
+    spins = np.ones((R, L * L), np.int8)
+    E = np.full(R, -2 * L * L, np.int32)
+    theta = 40
+    calls = O.sweep_rows(d, L, J, np.arange(R), spins, E, 21, 0, 1, 0, theta, 0.5)
+    expect = sum(1.0 - (1.0 - 2.0 ** (-2 * (p - 1))) ** 64 for p in range(1, 17))
+    per_site = calls / (theta * L * L)
+    assert abs(per_site - expect) < 0.05, (per_site, expect)
+    # nothing draws at beta = 0 (every move accepted) or when no move can be accepted
+    spins = np.ones((R, L * L), np.int8)
+    assert O.sweep_rows(d, L, J, np.arange(R), spins, E.copy(), 21, 0, 1, 0, 2, 0.0) == 0
+    spins = np.ones((R, L * L), np.int8)
+    assert O.sweep_rows(d, L, J, np.arange(R), spins, E.copy(), 21, 0, 1, 0, 2, 1e4) == 0
