@@ -77,7 +77,7 @@ typedef struct {
     int32_t dim;       /* 2 or 3 */
     int32_t L;         /* even, >= 2; N = L^dim <= 16384 */
     int64_t R;         /* target population size, >= 1 */
-    int64_t capacity;  /* max replicas after a resampling (>= R, < 2^24);
+    int64_t capacity;  /* max replicas after a resampling (>= R, <= 2^24 - 64);
                           0 = R + 8 ceil(sqrt R) + 64 rounded up to 64 */
     uint32_t seed;     /* Philox key word 0 */
     uint32_t run_id;   /* Philox key word 1: independent runs differ here */

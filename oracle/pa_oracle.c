@@ -329,9 +329,19 @@ void orc_reweight(int64_t R, const int32_t *E, double dbeta, double *lnQ, uint64
     for (int64_t j = 1; j < R; ++j)
         if (E[j] < emin)
             emin = E[j];
-    double sum = 0.0;
-    for (int64_t j = 0; j < R; ++j)
-        sum += exp(-dbeta * (double)(E[j] - emin));
+    /* compensated (Neumaier) sum, so that its rounding error does not grow */
+    /* with R: ln Q is small where the two terms below nearly cancel        */
+    double sum = 0.0, comp = 0.0;
+    for (int64_t j = 0; j < R; ++j) {
+        double x = exp(-dbeta * (double)(E[j] - emin));
+        double t = sum + x;
+        if (fabs(sum) >= fabs(x))
+            comp += (sum - t) + x;
+        else
+            comp += (x - t) + sum;
+        sum = t;
+    }
+    sum += comp;
     *lnQ = -dbeta * (double)emin + log(sum / (double)R);
     uint64_t tot = 0;
     for (int64_t j = 0; j < R; ++j) {

@@ -71,7 +71,7 @@ pa_status check_config(const pa_config *cfg, Geometry *g, std::string *msg)
     }
     const int64_t cap = cfg->capacity ? cfg->capacity : default_capacity(cfg->R);
     if (cap < cfg->R || cap > kMaxCapacity) {
-        *msg = "capacity must satisfy R <= capacity < 2^24 - 64";
+        *msg = "capacity must satisfy R <= capacity <= 2^24 - 64";
         return PA_E_INVAL;
     }
     g->d = cfg->dim;

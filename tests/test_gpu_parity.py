@@ -300,3 +300,25 @@ def test_work_counters_match_the_oracle_count(d, L, R, scheme, J):
     assert c["site_updates"] == steps * theta * L ** d * (R // 64)
     assert c["spin_attempts"] == steps * theta * L ** d * R
     g.close()
+
+
+def test_largest_population():
+    """R = capacity = 2^24 - 64 on a 4x4 lattice: weight sums reach ~2^64 (the
+    scan's inclusive prefixes outgrow its 62-bit tile words and later tiles add
+    aggregates instead), 2048 scan tiles, and the 128-bit copy-number
+    arithmetic at its bound; systematic and multinomial steps against the
+    oracle, whole population."""
+    from paper_2401_07965_amd import pa
+    d, L, R = 2, 4, (1 << 24) - 64
+    print(f"[parity] largest population d={d} L={L} R={R}", flush=True)
+    g = pa.PARun(d, L, R, seed=2, run_id=0, capacity=R)
+    o = O.OracleRun(d, L, R, seed=2, run_id=0, capacity=R)
+    for beta, scheme in ((0.004, O.SYSTEMATIC), (0.008, O.MULTINOMIAL), (0.05, O.SYSTEMATIC)):
+        qg, qo = g.reweight(beta), o.reweight(beta)
+        assert rel_ok(qg, qo), (qg, qo)
+        assert g.resample(scheme) == o.resample(scheme) == R
+        g.sweep(1)
+        o.sweep(1)
+    assert o.pending is None and o.last_counts is not None
+    compare_state(g, o, "largest population")
+    g.close()
