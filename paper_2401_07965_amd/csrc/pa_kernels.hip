@@ -1360,7 +1360,8 @@ __global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const PaRunDesc *__res
 
 // A new resampling starts with a clean status (a frozen run stays frozen),
 // cleared tile flags for both prefix sums (weights, copy numbers) and their
-// tile tickets.
+// tile tickets.  The reweighting prepares its resampling the same way; this
+// launch serves a resampling retried after a failed one.
 __global__ void k_resample_prep(const PaRunDesc *__restrict__ runs)
 {
     const PaRunDesc &rd = runs[blockIdx.x];
