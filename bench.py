@@ -47,18 +47,22 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2401_07965_amd", "csrc", f)
                   for f in ("pa_kernels.hip", "pa_device.h", "pa_internal.h")]
 
 
-def kernel_source_hash():
-    """SHA-256 of the kernel sources' code: comments dropped and whitespace
-    collapsed, so that a profile stays valid across comment edits."""
-    import hashlib
+def code_only(text):
+    """C/C++ source without comments, whitespace collapsed."""
     import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def kernel_source_hash():
+    """SHA-256 of the kernel sources' code (code_only), so that a profile
+    stays valid across comment edits."""
+    import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(f, encoding="utf-8") as fh:
-            text = fh.read()
-        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
-        text = re.sub(r"//[^\n]*", " ", text)
-        h.update(" ".join(text.split()).encode())
+            h.update(code_only(fh.read()).encode())
     return h.hexdigest()
 
 
