@@ -203,7 +203,7 @@ def test_2d_L64_R1e5_sampled_full_size():
     betas = schedule(0.6, 201)
     rng = np.random.default_rng(0)
     for scheme in SCHEMES:
-        print(f"[parity] config 2 scheme {scheme}", flush=True)
+        print(f"[parity] 2D L=64 R=1e5 sampled step, scheme {scheme}", flush=True)
         g = pa.PARun(2, 64, 100000, seed=1, run_id=scheme)
         for i in range(1, 4):
             g.reweight(betas[i])
