@@ -321,7 +321,10 @@ def batched_bench(theta=10, scheme=3, verify_runs=8):
     runs; per sample d in {2,3}, L in {8,12,16,24}; R log-uniform in [1e3, 1e5]),
     beta_i = 3 i/150, theta = 10, systematic resampling.  Times one whole anneal
     of all runs as one HIP graph, the same eagerly, and the same runs one after
-    the other through the single-run calls; the results are bit-identical."""
+    the other through the single-run calls; the results are bit-identical.
+    Then, per disorder sample, one run of the sample's total size (Fig. 7's
+    alternative to combining M runs): its wall time and the ln Z difference
+    from the weighted combination."""
     import numpy as np
     import torch
     from paper_2401_07965_amd import pa, workloads
@@ -340,6 +343,25 @@ def batched_bench(theta=10, scheme=3, verify_runs=8):
     rec = B.records()
     comb = B.combine(groups, max(groups) + 1, len(betas) - 1)
     frozen = int(np.sum(rec[:, -1]["status"] & 16 != 0))
+    B.close()
+    # one run per disorder sample of the runs' total size (Fig. 7's alternative)
+    nsamp = max(groups) + 1
+    big_cfgs = []
+    for s in range(nsamp):
+        mine = [c for c, gs in zip(cfgs, groups) if gs == s]
+        big_cfgs.append(dict(dim=mine[0]["dim"], L=mine[0]["L"], R=sum(c["R"] for c in mine), seed=2, run_id=s,
+                             couplings=mine[0]["couplings"]))
+    G = pa.PABatch(big_cfgs, max_points=len(betas))
+    G.tune(theta)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    G.anneal(betas, theta, scheme, use_graph=True)
+    torch.cuda.synchronize()
+    big_s = time.perf_counter() - t0
+    grec = G.records()
+    G.close()
+    dlnz = [abs(comb[s]["lnZ"] - float(grec[s, -1]["lnZ"])) / (big_cfgs[s]["L"] ** big_cfgs[s]["dim"])
+            for s in range(nsamp)]
     # the same runs one by one (plain per-run PA through the single-run calls)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -357,7 +379,6 @@ def batched_bench(theta=10, scheme=3, verify_runs=8):
         g.close()
     torch.cuda.synchronize()
     seq = time.perf_counter() - t0
-    B.close()
     return {
         "workload": "256 +-J runs (16 samples x 16), d in {2,3}, L in {8,12,16,24}, "
                     "R log-uniform [1e3,1e5], beta 0->3 in 151 points, theta=10, systematic",
@@ -370,6 +391,10 @@ def batched_bench(theta=10, scheme=3, verify_runs=8):
         "tuned_threads": threads,
         "combined_lnZ_per_spin_sample0": comb[0]["lnZ"] / (cfgs[0]["L"] ** cfgs[0]["dim"]),
         "mean_n_eff": float(np.mean([c["n_eff"] for c in comb])),
+        # per sample, one run of the 16 runs' total size, annealed as a batch of 16
+        "one_large_run_per_sample_s": big_s,
+        "weighted_vs_large_run_lnZ_per_spin": {"mean_abs_diff": float(np.mean(dlnz)),
+                                                "max_abs_diff": float(np.max(dlnz))},
     }
 
 
