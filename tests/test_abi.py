@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -106,3 +107,21 @@ def test_binding_structures_match_the_header(libpa, tmp_path):
         assert int(got[s]) == ctypes.sizeof(cls), s
         for name, _ in cls._fields_:
             assert int(got[f"{s}.{name}"]) == getattr(cls, name).offset, (s, name)
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """The product path has no fallback: with the HIP library absent, the
+    binding raises instead of computing anything another way."""
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2401_07965_amd import pa\n"
+            "pa.LIB_PATH = %r\n"
+            "pa._lib = None\n"
+            "try:\n"
+            "    pa.lib()\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n"
+            "    sys.exit(0)\n"
+            "sys.exit(3)\n") % (ROOT, str(tmp_path / "libpa.so"))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "missing" in r.stdout
