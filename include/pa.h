@@ -26,12 +26,13 @@
  *    goes to that stream.  The context owns only host memory (pa_destroy).
  *  - A context is not thread-safe; distinct contexts may run concurrently on
  *    distinct streams.  Calls that return results to the host (pa_reweight,
- *    pa_resample, pa_observables, pa_free_energy, pa_export_state) synchronise
- *    the stream; pa_sweep only enqueues.
+ *    pa_resample, pa_resample_conditional, pa_observables, pa_free_energy,
+ *    pa_export_state, pa_log_weights) synchronise the stream; pa_sweep only
+ *    enqueues.
  *  - Deferred calls: pa_reweight, pa_resample, pa_resample_conditional and
  *    pa_observables given NULL result pointers only enqueue their kernels and
- *    return at once, so that a
- *    whole temperature step runs without waiting for the device.  A failure
+ *    return at once, so that a whole temperature step runs without waiting
+ *    for the device (and can be captured into a HIP graph).  A failure
  *    that pa_resample would report (PA_E_CAPACITY, PA_E_EXTINCT,
  *    PA_E_NONFINITE) then freezes the run instead: its population stays as it
  *    was before that resampling, every later kernel of the run does nothing,
@@ -118,7 +119,9 @@ typedef struct {
 
 /* Host copy of a run's state (pa_export_state / pa_import_state).  Array
  * pointers may be NULL to skip them; non-NULL arrays must hold R entries
- * (spins: ceil(R/64) * N words).  Memory is the caller's. */
+ * (spins: ceil(R/64) * N words).  Memory is the caller's.  The importance
+ * weights of a kept population are not part of it (pa_log_weights reads
+ * them); an imported population is uniform. */
 typedef struct {
     int64_t R;
     uint32_t step;        /* temperature index i */
