@@ -93,7 +93,7 @@ bool sweep_threads_ok(int N, int d, int t)
 }
 
 constexpr int kLdsPerCu = 163840;  // gfx950: 160 KiB of LDS per CU
-constexpr int kSweepWavesPerSimd = 3; // the sweep kernel's register use allows at least 3 waves per SIMD
+constexpr int kSweepWavesPerSimd = 3; // waves per SIMD the size choice assumes (the registers allow 4; workgroups of more than 4 waves measured slower)
 
 // Default sweep workgroup size, by a score: resident sweep waves per CU
 // (limited by the LDS of the lattice and queues and by registers; counted up

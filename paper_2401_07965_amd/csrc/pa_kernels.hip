@@ -475,21 +475,26 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
             rec->attempts += (unsigned long long)theta * (unsigned long long)N * (unsigned long long)Rlive;
         }
     }
-    uint64_t ce[16], cm[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        ce[k] = k < 8 ? ve[k] : 0;
-        cm[k] = k < 8 ? vm[k] : 0;
-    }
-    wave_vsum16(ce);
-    wave_vsum16(cm);
+    // the two bit-sliced counts reduced one after the other (fewer live registers)
     const int wave = tid >> 6, lane = tid & 63, nw = bs >> 6;
-    if (lane == 0) {
+    {
+        uint64_t c[16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            red[wave * 32 + k] = ce[k];
-            red[wave * 32 + 16 + k] = cm[k];
-        }
+        for (int k = 0; k < 16; ++k)
+            c[k] = k < 8 ? ve[k] : 0;
+        wave_vsum16(c);
+        if (lane == 0)
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                red[wave * 32 + k] = c[k];
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            c[k] = k < 8 ? vm[k] : 0;
+        wave_vsum16(c);
+        if (lane == 0)
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                red[wave * 32 + 16 + k] = c[k];
     }
     __syncthreads();
     if (wave == 0) {
