@@ -173,19 +173,25 @@ struct PlaneCtx {
     uint32_t t4, t8, t12;
 };
 
-// All-ones if bit b of the (wave-uniform) threshold t is set.
-__device__ __forceinline__ uint64_t tbit(uint32_t t, int b) { return 0ull - (uint64_t)((t >> b) & 1u); }
+// All-ones if bit b of the threshold t is set (one signed bit-field extract;
+// both halves alike).
+__device__ __forceinline__ uint64_t tbit(uint32_t t, int b)
+{
+    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)t, (uint32_t)b, 1u);
+    return ((uint64_t)m << 32) | m;
+}
 
-// The threshold bit of every replica on plane b: the classes are disjoint, so
-// Tp = m4 ? T4_b : (m8 ? T8_b : m12 & T12_b).
+// The threshold bit on plane b of every undecided replica.  The undecided
+// replicas all belong to the drawing classes, which are disjoint, so on them
+// Tp = m4 ? T4_b : T8_b in 2D and m4 ? T4_b : (m8 ? T8_b : T12_b) in 3D; the
+// value on other replicas is never used.
 template <int D>
-__device__ __forceinline__ uint64_t plane_threshold(const PlaneCtx &pc, int b, uint64_t m4, uint64_t m8,
-                                                    uint64_t m12)
+__device__ __forceinline__ uint64_t plane_threshold(const PlaneCtx &pc, int b, uint64_t m4, uint64_t m8)
 {
     constexpr int kSel = PA_T3((PA_A & PA_B) | (~PA_A & PA_C));
-    uint64_t t = m8 & tbit(pc.t8, b);
+    uint64_t t = tbit(pc.t8, b);
     if (D == 3)
-        t = pa_bop3<kSel>(m8, tbit(pc.t8, b), m12 & tbit(pc.t12, b));
+        t = pa_bop3<kSel>(m8, t, tbit(pc.t12, b));
     return pa_bop3<kSel>(m4, tbit(pc.t4, b), t);
 }
 
@@ -204,20 +210,13 @@ __device__ __forceinline__ pa_philox_out metro_philox(const PlaneCtx &pc, uint32
 
 template <int D>
 __device__ __forceinline__ void apply_pair(const PlaneCtx &pc, const pa_philox_out &o, uint32_t q, uint64_t m4,
-                                           uint64_t m8, uint64_t m12, uint64_t &und, uint64_t &acc)
+                                           uint64_t m8, uint64_t &und, uint64_t &acc)
 {
     const uint64_t P0 = (uint64_t)o.x0 | ((uint64_t)o.x1 << 32);
     const uint64_t P1 = (uint64_t)o.x2 | ((uint64_t)o.x3 << 32);
     const int b0 = 31 - 2 * (int)q;
-    plane_step(P0, plane_threshold<D>(pc, b0, m4, m8, m12), und, acc);
-    plane_step(P1, plane_threshold<D>(pc, b0 - 1, m4, m8, m12), und, acc);
-}
-
-template <int D>
-__device__ __forceinline__ void plane_pair(const PlaneCtx &pc, uint32_t s, uint32_t q, uint64_t m4, uint64_t m8,
-                                           uint64_t m12, uint64_t &und, uint64_t &acc)
-{
-    apply_pair<D>(pc, metro_philox(pc, s, q), q, m4, m8, m12, und, acc);
+    plane_step(P0, plane_threshold<D>(pc, b0, m4, m8), und, acc);
+    plane_step(P1, plane_threshold<D>(pc, b0 - 1, m4, m8), und, acc);
 }
 
 // Per-wave queue of word-sites whose replicas are still undecided after the
@@ -230,12 +229,13 @@ constexpr int kQueue = 128; // per wave; never more than 127 items are live
 
 struct WaveQueue {
     uint32_t *sq;  // site | next pair << 16
-    uint64_t *und, *m4, *m8;
+    uint64_t *und, *m4, *m8; // m8: 3D only
 };
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << (threadIdx.x & 63)) - 1ull; }
 
 // Appends this lane's item if `has`; returns the new item count (wave-uniform).
+template <int D>
 __device__ __forceinline__ uint32_t queue_push(const WaveQueue &Q, uint32_t head, uint32_t cnt, bool has,
                                                uint32_t sq, uint64_t und, uint64_t m4, uint64_t m8)
 {
@@ -245,7 +245,8 @@ __device__ __forceinline__ uint32_t queue_push(const WaveQueue &Q, uint32_t head
         Q.sq[slot] = sq;
         Q.und[slot] = und;
         Q.m4[slot] = m4;
-        Q.m8[slot] = m8;
+        if (D == 3)
+            Q.m8[slot] = m8;
     }
     __builtin_amdgcn_wave_barrier();
     return cnt + (uint32_t)__popcll(bal);
@@ -266,7 +267,8 @@ __device__ __forceinline__ void queue_pass(const WaveQueue &Q, const PlaneCtx &p
         sq = Q.sq[slot];
         und = Q.und[slot];
         m4 = Q.m4[slot];
-        m8 = Q.m8[slot];
+        if (D == 3)
+            m8 = Q.m8[slot];
     }
     __builtin_amdgcn_wave_barrier();
     head += n;
@@ -275,11 +277,11 @@ __device__ __forceinline__ void queue_pass(const WaveQueue &Q, const PlaneCtx &p
     if (act) {
         uint64_t acc = 0;
         ++calls;
-        plane_pair<D>(pc, s, q, m4, m8, D == 3 ? ~(m4 | m8) : 0ull, und, acc);
+        apply_pair<D>(pc, metro_philox(pc, s, q), q, m4, m8, und, acc);
         lat[s] ^= acc;
     }
     const bool again = act && und != 0 && q + 1 < 16;
-    cnt = queue_push(Q, head, cnt, again, s | ((q + 1) << 16), und, m4, m8);
+    cnt = queue_push<D>(Q, head, cnt, again, s | ((q + 1) << 16), und, m4, m8);
 }
 
 // The theta sweeps of one column in LDS.  ALL: every energy-change class has
@@ -366,13 +368,13 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
                         for (int k = 0; k < kInlinePairs; ++k)
                             if (und != 0) {
                                 ++calls;
-                                apply_pair<D>(pc, o[k], (uint32_t)k, m4, m8, m12, und, acc);
+                                apply_pair<D>(pc, o[k], (uint32_t)k, m4, m8, und, acc);
                                 q = (uint32_t)k + 1;
                             }
                     }
                     lat[s] = S ^ acc;
                 }
-                cnt = queue_push(Q, head, cnt, und != 0, s | (q << 16), und, m4, m8);
+                cnt = queue_push<D>(Q, head, cnt, und != 0, s | (q << 16), und, m4, m8);
                 while (cnt >= 64u)
                     queue_pass<D>(Q, pc, lat, head, cnt, calls);
             }
