@@ -319,18 +319,27 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
                     s = (uint32_t)(x + L * row);
                     const uint32_t jb = J ? (uint32_t)jl[s] : 0u;
                     const uint64_t S = lat[s];
+                    const uint64_t n0 = lat[x == L - 1 ? s - (L - 1) : s + 1];
+                    const uint64_t n1 = lat[x == 0 ? s + (L - 1) : s - 1];
+                    const uint64_t n2 = lat[y == L - 1 ? s - L * (L - 1) : s + L];
+                    const uint64_t n3 = lat[y == 0 ? s + L * (L - 1) : s - L];
                     // a_k: bond k unsatisfied (S ^ neighbour ^ [J = -1])
-                    const uint64_t a0 = bond<J>(S, lat[x == L - 1 ? s - (L - 1) : s + 1], jb, 0);
-                    const uint64_t a1 = bond<J>(S, lat[x == 0 ? s + (L - 1) : s - 1], jb, D);
-                    const uint64_t a2 = bond<J>(S, lat[y == L - 1 ? s - L * (L - 1) : s + L], jb, 1);
-                    const uint64_t a3 = bond<J>(S, lat[y == 0 ? s + L * (L - 1) : s - L], jb, D + 1);
+                    const uint64_t a0 = bond<J>(S, n0, jb, 0), a1 = bond<J>(S, n1, jb, D);
+                    const uint64_t a2 = bond<J>(S, n2, jb, 1), a3 = bond<J>(S, n3, jb, D + 1);
                     // u = number of unsatisfied bonds among 2d; dE = 4(d - u)
                     uint64_t always, m12;
                     if (D == 2) {
-                        const uint64_t s0 = a0 ^ a1, c0 = a0 & a1, s1 = a2 ^ a3, c1 = a2 & a3;
-                        always = c0 | c1 | (s0 & s1); // u >= 2
-                        m4 = (s0 ^ s1) & ~(c0 | c1);  // u == 1
-                        m8 = ~(s0 | s1 | c0 | c1);    // u == 0
+                        // pair sums s and carries c of (a0, a1) and (a2, a3); without
+                        // couplings S cancels from the sums and each carry is one
+                        // three-input operation on S and the neighbours
+                        constexpr int kBoth = PA_T3((PA_A ^ PA_B) & (PA_A ^ PA_C));
+                        const uint64_t s0 = J ? a0 ^ a1 : n0 ^ n1, s1 = J ? a2 ^ a3 : n2 ^ n3;
+                        const uint64_t c0 = J ? a0 & a1 : pa_bop3<kBoth>(S, n0, n1);
+                        const uint64_t c1 = J ? a2 & a3 : pa_bop3<kBoth>(S, n2, n3);
+                        const uint64_t cc = c0 | c1;
+                        always = pa_bop3<PA_T3(PA_A | (PA_B & PA_C))>(cc, s0, s1); // u >= 2
+                        m4 = pa_bop3<PA_T3((PA_A ^ PA_B) & ~PA_C)>(s0, s1, cc);    // u == 1
+                        m8 = pa_bop3<PA_T3(~(PA_A | PA_B | PA_C))>(s0, s1, cc);    // u == 0
                         m12 = 0;
                     } else {
                         const uint64_t a4 = bond<J>(S, lat[z == L - 1 ? s - LL * (L - 1) : s + LL], jb, 2);
@@ -367,10 +376,10 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
 #pragma unroll
                         for (int k = 0; k < kInlinePairs; ++k)
                             if (und != 0) {
-                                ++calls;
                                 apply_pair<D>(pc, o[k], (uint32_t)k, m4, m8, und, acc);
                                 q = (uint32_t)k + 1;
                             }
+                        calls += q;
                     }
                     lat[s] = S ^ acc;
                 }
