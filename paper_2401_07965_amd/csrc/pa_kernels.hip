@@ -292,7 +292,14 @@ struct SweepGeom {
     uint32_t mhalf, mL; // ceil(2^32 / half), ceil(2^32 / L)
 };
 
-template <int D, bool J, bool ALL>
+// Site k of colour c (k < N/2): row = y + L z = k div (L/2), x = 2 (k mod L/2)
+// + (y + z + c) mod 2.  Colour-c sites are independent and each one's random
+// bits are keyed by its site index, so the order in which lanes visit them
+// does not change any result.  FIX: the workgroup size is a multiple of L
+// (2D) or L^2 (3D), so from one iteration to the next a lane's site moves by
+// 2 * blockDim sites along y (2D) or z (3D) and its other coordinates stay:
+// their neighbour offsets are computed once per colour.
+template <int D, bool J, bool ALL, bool FIX>
 __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *jl, const SweepGeom &G, PlaneCtx pc,
                                                   const WaveQueue &Q, int theta, uint32_t t0, uint64_t sure4,
                                                   uint64_t sure8, uint64_t sure12, uint64_t draw4, uint64_t draw8,
@@ -301,28 +308,64 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
     const int L = G.L, half = G.half, nh = G.nh, LL = G.LL;
     const uint32_t mhalf = G.mhalf, mL = G.mL;
     const int tid = threadIdx.x, bs = blockDim.x;
+    // FIX: stride and steps per iteration of the coordinate that moves
+    const int vst = D == 2 ? L : LL, dv = D == 2 ? 2 * bs / L : 2 * bs / LL;
     uint32_t calls = 0;
     for (int tt = 0; tt < theta; ++tt) {
         pc.t = t0 + (uint32_t)tt;
         for (int c = 0; c < 2; ++c) {
             uint32_t head = 0, cnt = 0;
-            for (int kb = 0; kb < nh; kb += bs) {
+            int sf = 0, vf = 0, oxp = 0, oxm = 0, oyp = 0, oym = 0;
+            if (FIX) { // the lane's first site, and the offsets that stay
+                const int row = half > 1 ? (int)__umulhi((uint32_t)tid, mhalf) : tid;
+                const int m = tid - row * half;
+                const int z = (D == 2) ? 0 : (int)__umulhi((uint32_t)row, mL);
+                const int y = row - z * L;
+                const int x = 2 * m + ((y + z + c) & 1);
+                sf = x + L * row;
+                vf = D == 2 ? y : z;
+                oxp = x == L - 1 ? -(L - 1) : 1;
+                oxm = x == 0 ? L - 1 : -1;
+                oyp = y == L - 1 ? -L * (L - 1) : L;
+                oym = y == 0 ? L * (L - 1) : -L;
+            }
+            for (int kb = 0; kb < nh; kb += bs, sf += 2 * bs, vf += dv) {
                 const int k = kb + tid;
                 uint64_t und = 0, m4 = 0, m8 = 0;
                 uint32_t s = 0, q = 0;
                 if (k < nh) {
-                    const int row = half > 1 ? (int)__umulhi((uint32_t)k, mhalf) : k; // row = y + L z
-                    const int m = k - row * half;
-                    const int z = (D == 2) ? 0 : (int)__umulhi((uint32_t)row, mL);
-                    const int y = row - z * L;
-                    const int x = 2 * m + ((y + z + c) & 1);
-                    s = (uint32_t)(x + L * row);
+                    uint64_t n0, n1, n2, n3, n4 = 0, n5 = 0;
+                    if (FIX) {
+                        s = (uint32_t)sf;
+                        n0 = lat[sf + oxp];
+                        n1 = lat[sf + oxm];
+                        if (D == 2) {
+                            n2 = lat[vf == L - 1 ? sf - vst * (L - 1) : sf + vst];
+                            n3 = lat[vf == 0 ? sf + vst * (L - 1) : sf - vst];
+                        } else {
+                            n2 = lat[sf + oyp];
+                            n3 = lat[sf + oym];
+                            n4 = lat[vf == L - 1 ? sf - vst * (L - 1) : sf + vst];
+                            n5 = lat[vf == 0 ? sf + vst * (L - 1) : sf - vst];
+                        }
+                    } else {
+                        const int row = half > 1 ? (int)__umulhi((uint32_t)k, mhalf) : k; // row = y + L z
+                        const int m = k - row * half;
+                        const int z = (D == 2) ? 0 : (int)__umulhi((uint32_t)row, mL);
+                        const int y = row - z * L;
+                        const int x = 2 * m + ((y + z + c) & 1);
+                        s = (uint32_t)(x + L * row);
+                        n0 = lat[x == L - 1 ? s - (L - 1) : s + 1];
+                        n1 = lat[x == 0 ? s + (L - 1) : s - 1];
+                        n2 = lat[y == L - 1 ? s - L * (L - 1) : s + L];
+                        n3 = lat[y == 0 ? s + L * (L - 1) : s - L];
+                        if (D == 3) {
+                            n4 = lat[z == L - 1 ? s - LL * (L - 1) : s + LL];
+                            n5 = lat[z == 0 ? s + LL * (L - 1) : s - LL];
+                        }
+                    }
                     const uint32_t jb = J ? (uint32_t)jl[s] : 0u;
                     const uint64_t S = lat[s];
-                    const uint64_t n0 = lat[x == L - 1 ? s - (L - 1) : s + 1];
-                    const uint64_t n1 = lat[x == 0 ? s + (L - 1) : s - 1];
-                    const uint64_t n2 = lat[y == L - 1 ? s - L * (L - 1) : s + L];
-                    const uint64_t n3 = lat[y == 0 ? s + L * (L - 1) : s - L];
                     // a_k: bond k unsatisfied (S ^ neighbour ^ [J = -1])
                     const uint64_t a0 = bond<J>(S, n0, jb, 0), a1 = bond<J>(S, n1, jb, D);
                     const uint64_t a2 = bond<J>(S, n2, jb, 1), a3 = bond<J>(S, n3, jb, D + 1);
@@ -342,8 +385,7 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
                         m8 = pa_bop3<PA_T3(~(PA_A | PA_B | PA_C))>(s0, s1, cc);    // u == 0
                         m12 = 0;
                     } else {
-                        const uint64_t a4 = bond<J>(S, lat[z == L - 1 ? s - LL * (L - 1) : s + LL], jb, 2);
-                        const uint64_t a5 = bond<J>(S, lat[z == 0 ? s + LL * (L - 1) : s - LL], jb, 5);
+                        const uint64_t a4 = bond<J>(S, n4, jb, 2), a5 = bond<J>(S, n5, jb, 5);
                         constexpr int kXor3 = PA_T3(PA_A ^ PA_B ^ PA_C);
                         constexpr int kMaj = PA_T3((PA_A & PA_B) | (PA_A & PA_C) | (PA_B & PA_C));
                         // three-bond sums and carries, then u = 2 (cA + cB + lc) + ls
@@ -453,9 +495,20 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
     const WaveQueue Q = {qsites + (size_t)(tid >> 6) * kQueue, qbase, qbase + kQueue, qbase + 2 * kQueue};
     const SweepGeom G = {L, N, half, nh, LL, mhalf, mL};
     const bool all_draw = draw4 != 0 && draw8 != 0 && (D == 2 || draw12 != 0);
-    const uint32_t calls =
-        all_draw ? sweep_columns<D, J, true>(lat, jl, G, pc, Q, theta, t0, sure4, sure8, sure12, draw4, draw8, draw12)
-                 : sweep_columns<D, J, false>(lat, jl, G, pc, Q, theta, t0, sure4, sure8, sure12, draw4, draw8, draw12);
+    const bool fix = bs % (D == 2 ? L : LL) == 0;
+    uint32_t calls;
+    if (all_draw && fix)
+        calls = sweep_columns<D, J, true, true>(lat, jl, G, pc, Q, theta, t0, sure4, sure8, sure12, draw4, draw8,
+                                                draw12);
+    else if (all_draw)
+        calls = sweep_columns<D, J, true, false>(lat, jl, G, pc, Q, theta, t0, sure4, sure8, sure12, draw4, draw8,
+                                                 draw12);
+    else if (fix)
+        calls = sweep_columns<D, J, false, true>(lat, jl, G, pc, Q, theta, t0, sure4, sure8, sure12, draw4, draw8,
+                                                 draw12);
+    else
+        calls = sweep_columns<D, J, false, false>(lat, jl, G, pc, Q, theta, t0, sure4, sure8, sure12, draw4, draw8,
+                                                  draw12);
 
     // after the sweeps the queue region is free: per-wave partial counts of the measurement
     uint64_t *red = lat + N;
