@@ -184,23 +184,33 @@ __device__ __forceinline__ uint64_t tbit(uint32_t t, int b)
 // The threshold bit on plane b of every undecided replica.  The undecided
 // replicas all belong to the drawing classes, which are disjoint, so on them
 // Tp = m4 ? T4_b : T8_b in 2D and m4 ? T4_b : (m8 ? T8_b : T12_b) in 3D; the
-// value on other replicas is never used.
+// value on other replicas is never used.  `last` is the last class's bit
+// (T8_b in 2D, T12_b in 3D) as a mask, passed in so that it can come from a
+// vector register: one instruction takes at most one scalar operand.
 template <int D>
-__device__ __forceinline__ uint64_t plane_threshold(const PlaneCtx &pc, int b, uint64_t m4, uint64_t m8)
+__device__ __forceinline__ uint64_t plane_threshold(const PlaneCtx &pc, int b, uint64_t m4, uint64_t m8,
+                                                    uint64_t last)
 {
     constexpr int kSel = PA_T3((PA_A & PA_B) | (~PA_A & PA_C));
-    uint64_t t = tbit(pc.t8, b);
+    uint64_t t = last;
     if (D == 3)
-        t = pa_bop3<kSel>(m8, t, tbit(pc.t12, b));
+        t = pa_bop3<kSel>(m8, tbit(pc.t8, b), t);
     return pa_bop3<kSel>(m4, tbit(pc.t4, b), t);
 }
 
-// One plane: accept where u has 0 and the threshold 1; stay undecided where
-// they agree.
-__device__ __forceinline__ void plane_step(uint64_t P, uint64_t Tp, uint64_t &und, uint64_t &acc)
+template <int D>
+__device__ __forceinline__ uint64_t last_tbit(const PlaneCtx &pc, int b)
 {
-    acc |= pa_bop3<PA_T3(PA_A & ~PA_B & PA_C)>(und, P, Tp);
+    return tbit(D == 2 ? pc.t8 : pc.t12, b);
+}
+
+// One plane: returns the replicas accepted on it (u has 0, the threshold 1);
+// those where u and the threshold agree stay undecided.
+__device__ __forceinline__ uint64_t plane_step(uint64_t P, uint64_t Tp, uint64_t &und)
+{
+    const uint64_t a = pa_bop3<PA_T3(PA_A & ~PA_B & PA_C)>(und, P, Tp);
     und = pa_bop3<PA_T3(PA_A & ~(PA_B ^ PA_C))>(und, P, Tp);
+    return a;
 }
 
 __device__ __forceinline__ pa_philox_out metro_philox(const PlaneCtx &pc, uint32_t s, uint32_t q)
@@ -208,15 +218,27 @@ __device__ __forceinline__ pa_philox_out metro_philox(const PlaneCtx &pc, uint32
     return pa_philox(pc.seed, pc.run_id, s, pc.w, pc.step, (PA_PURPOSE_METRO << 28) | (pc.t << 8) | q);
 }
 
-template <int D>
+// Plane pair q; last0, last1: the last class's threshold bits on its planes.
+// The undecided set comes in as uin (its complement if INV) and leaves in und.
+template <int D, bool INV = false>
 __device__ __forceinline__ void apply_pair(const PlaneCtx &pc, const pa_philox_out &o, uint32_t q, uint64_t m4,
-                                           uint64_t m8, uint64_t &und, uint64_t &acc)
+                                           uint64_t m8, uint64_t last0, uint64_t last1, uint64_t uin,
+                                           uint64_t &und, uint64_t &acc)
 {
     const uint64_t P0 = (uint64_t)o.x0 | ((uint64_t)o.x1 << 32);
     const uint64_t P1 = (uint64_t)o.x2 | ((uint64_t)o.x3 << 32);
     const int b0 = 31 - 2 * (int)q;
-    plane_step(P0, plane_threshold<D>(pc, b0, m4, m8), und, acc);
-    plane_step(P1, plane_threshold<D>(pc, b0 - 1, m4, m8), und, acc);
+    const uint64_t T0 = plane_threshold<D>(pc, b0, m4, m8, last0);
+    uint64_t a0;
+    if (INV) {
+        a0 = pa_bop3<PA_T3(~PA_A & ~PA_B & PA_C)>(uin, P0, T0);
+        und = pa_bop3<PA_T3(~PA_A & ~(PA_B ^ PA_C))>(uin, P0, T0);
+    } else {
+        und = uin;
+        a0 = plane_step(P0, T0, und);
+    }
+    const uint64_t a1 = plane_step(P1, plane_threshold<D>(pc, b0 - 1, m4, m8, last1), und);
+    acc = pa_bop3<PA_T3(PA_A | PA_B | PA_C)>(acc, a0, a1);
 }
 
 // Per-wave queue of word-sites whose replicas are still undecided after the
@@ -277,7 +299,9 @@ __device__ __forceinline__ void queue_pass(const WaveQueue &Q, const PlaneCtx &p
     if (act) {
         uint64_t acc = 0;
         ++calls;
-        apply_pair<D>(pc, metro_philox(pc, s, q), q, m4, m8, und, acc);
+        const int b0 = 31 - 2 * (int)q;
+        apply_pair<D>(pc, metro_philox(pc, s, q), q, m4, m8, last_tbit<D>(pc, b0), last_tbit<D>(pc, b0 - 1), und,
+                      und, acc);
         lat[s] ^= acc;
     }
     const bool again = act && und != 0 && q + 1 < 16;
@@ -310,6 +334,14 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
     const int tid = threadIdx.x, bs = blockDim.x;
     // FIX: stride and steps per iteration of the coordinate that moves
     const int vst = D == 2 ? L : LL, dv = D == 2 ? 2 * bs / L : 2 * bs / LL;
+    // the last class's threshold bits on the inline planes, kept in vector
+    // registers for the whole launch
+    uint32_t tl[2 * kInlinePairs];
+#pragma unroll
+    for (int i = 0; i < 2 * kInlinePairs; ++i) {
+        tl[i] = (uint32_t)__builtin_amdgcn_sbfe((int)(D == 2 ? pc.t8 : pc.t12), 31u - (uint32_t)i, 1u);
+        asm volatile("" : "+v"(tl[i]));
+    }
     uint32_t calls = 0;
     for (int tt = 0; tt < theta; ++tt) {
         pc.t = t0 + (uint32_t)tt;
@@ -401,24 +433,31 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
                         m12 = none & ~ls;                                             // u == 0
                     }
                     uint64_t acc;
-                    if (ALL) { // every class draws: the rest of the word is undecided
+                    if (ALL) { // every class draws: the rest of the word (~always) is undecided
                         acc = always;
-                        und = ~always;
                     } else {
                         acc = always | (m4 & sure4) | (m8 & sure8) | (m12 & sure12);
                         und = (m4 & draw4) | (m8 & draw8) | (m12 & draw12);
                     }
-                    if (und != 0) {
+                    if (ALL ? always != ~0ull : und != 0) {
                         // nearly every site needs the first kInlinePairs pairs:
                         // their Philox outputs are independent and computed together
                         pa_philox_out o[kInlinePairs];
 #pragma unroll
                         for (int k = 0; k < kInlinePairs; ++k)
                             o[k] = metro_philox(pc, s, (uint32_t)k);
+                        const uint64_t l0 = ((uint64_t)tl[0] << 32) | tl[0], l1 = ((uint64_t)tl[1] << 32) | tl[1];
+                        if (ALL)
+                            apply_pair<D, true>(pc, o[0], 0u, m4, m8, l0, l1, always, und, acc);
+                        else
+                            apply_pair<D>(pc, o[0], 0u, m4, m8, l0, l1, und, und, acc);
+                        q = 1;
 #pragma unroll
-                        for (int k = 0; k < kInlinePairs; ++k)
+                        for (int k = 1; k < kInlinePairs; ++k)
                             if (und != 0) {
-                                apply_pair<D>(pc, o[k], (uint32_t)k, m4, m8, und, acc);
+                                apply_pair<D>(pc, o[k], (uint32_t)k, m4, m8,
+                                              ((uint64_t)tl[2 * k] << 32) | tl[2 * k],
+                                              ((uint64_t)tl[2 * k + 1] << 32) | tl[2 * k + 1], und, und, acc);
                                 q = (uint32_t)k + 1;
                             }
                         calls += q;
