@@ -31,15 +31,17 @@ SCHEMES = (("multinomial", 0), ("poisson", 1), ("nearest", 2), ("systematic", 3)
 
 # Roofline of the sweep kernel (integer VALU bound).
 # peak = 256 CUs x 64 int32 lanes/clock x 2.4 GHz.  The achieved rate counts
-# the algorithmic 32-bit lane operations of the 2D ferromagnet sweep on gfx950:
+# the fewest 32-bit lane operations known to do the 2D ferromagnet sweep's
+# work on gfx950 (three-input bitwise ops), per 64-bit word as two halves:
 # each Philox4x32-10 call is 10 rounds of two 32x32->64 multiplies and two
 # three-input xors (40); consuming its two bit planes for a 64-replica word is
-# 2 planes x 2 halves x (threshold select 2 + accept 2 + undecided 1) = 20;
-# a word-site update is 4 bond xors x 2 halves (8), the three energy-change
-# classes (20), the initial accept/undecided masks (8) and the flip (2) = 38.
+# 2 planes x 2 halves x (threshold select 1 + accept 1 + undecided 1) plus
+# merging the pair's acceptances (2) = 14; a word-site update is the two pair
+# sums and two carries of the bonds from the neighbour words (4 x 2), the
+# classes u >= 2 and u = 1 and their shared carry (3 x 2) and the flip (2) = 16.
 PEAK_INT_OPS = 256 * 64 * 2.4e9
-OPS_PER_PHILOX = 40 + 20   # generate a plane pair and decide 64 replicas on it
-OPS_PER_SITE_UPDATE = 38   # 2D, no couplings
+OPS_PER_PHILOX = 40 + 14   # generate a plane pair and decide 64 replicas on it
+OPS_PER_SITE_UPDATE = 16   # 2D, no couplings
 
 
 COUNTER_PROFILE = os.path.join(ROOT, "profiles", "k_sweep_2d_L64_R1e5_counters.md")
