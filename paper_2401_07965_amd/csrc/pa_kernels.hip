@@ -118,33 +118,72 @@ __global__ __launch_bounds__(kThreads) void k_init_labels(const PaRunDesc *__res
 }
 
 // ------------------------------------------------------------------ step 3: sweeps
-// Bit-sliced counter: adds a 1-bit-per-replica mask to an 8-plane count.
-__device__ __forceinline__ void vadd8(uint64_t c[8], uint64_t x)
+constexpr int kXor3 = PA_T3(PA_A ^ PA_B ^ PA_C);
+constexpr int kMaj = PA_T3((PA_A & PA_B) | (PA_A & PA_C) | (PA_B & PA_C));
+
+// Adds the masks a and b at plane P of a bit-sliced count (one full adder,
+// then the carry rippled up to plane 7).
+template <int P>
+__device__ __forceinline__ void vadd2_at(uint64_t c[8], uint64_t a, uint64_t b)
 {
+    uint64_t x = pa_bop3<kMaj>(c[P], a, b);
+    c[P] = pa_bop3<kXor3>(c[P], a, b);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = P + 1; k < 8; ++k) {
         const uint64_t t = c[k] & x;
         c[k] ^= x;
         x = t;
     }
 }
 
-// Sum of the 16-plane bit-sliced counters of all 64 lanes (ripple adds over
-// a butterfly); every lane ends with the wave total.
+// The value of lane l ^ M, for the butterfly levels below (all lanes active).
+// Levels 1 and 2 are quad permutations; from level 4 on, each lane's value
+// is its group's sum so far, so any partner in the other half of the next
+// larger group will do: the mirrors within 8 and 16 lanes stand in for xor 4
+// and xor 8.  xor 16 is a swizzle within 32 lanes, xor 32 a lane permute.
+template <int M>
+__device__ __forceinline__ uint32_t xlane(uint32_t v)
+{
+    if (M == 1)
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false); // quad_perm 1,0,3,2
+    if (M == 2)
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false); // quad_perm 2,3,0,1
+    if (M == 4)
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false); // row_half_mirror
+    if (M == 8)
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false); // row_mirror
+    if (M == 16)
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F); // and 0x1F, xor 0x10
+    return (uint32_t)__shfl_xor((int)v, 32, 64);
+}
+
+// One butterfly level: adds the partner's count.  Counts are below
+// 2^(8 + LV) before level LV (per-lane counts below 2^8), so only those
+// planes move and the carry lands in plane 8 + LV.
+template <int LV, int M>
+__device__ __forceinline__ void vsum_level(uint64_t c[16])
+{
+    uint64_t carry = 0;
+#pragma unroll
+    for (int k = 0; k < 8 + LV; ++k) {
+        const uint64_t o = ((uint64_t)xlane<M>((uint32_t)(c[k] >> 32)) << 32) | xlane<M>((uint32_t)c[k]);
+        const uint64_t sum = pa_bop3<kXor3>(c[k], o, carry);
+        carry = pa_bop3<kMaj>(c[k], o, carry);
+        c[k] = sum;
+    }
+    c[8 + LV] = carry;
+}
+
+// Sum of the bit-sliced counters of all 64 lanes: planes 0..7 in (counts
+// below 2^8, planes 8..15 zero), the 16-plane wave total out in every lane.
 __device__ __forceinline__ void wave_vsum16(uint64_t c[16])
 {
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-        uint64_t carry = 0;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const uint64_t o = pa_shfl_xor_u64(c[k], m);
-            const uint64_t x = c[k] ^ o;
-            const uint64_t s = x ^ carry;
-            carry = (c[k] & o) | (carry & x);
-            c[k] = s;
-        }
-    }
+    vsum_level<0, 1>(c);
+    vsum_level<1, 2>(c);
+    vsum_level<2, 4>(c);
+    vsum_level<3, 8>(c);
+    vsum_level<4, 16>(c);
+    vsum_level<5, 32>(c);
 }
 
 // All-ones if bit k of jb is set (one signed bit-field extract; both halves alike).
@@ -418,8 +457,6 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
                         m12 = 0;
                     } else {
                         const uint64_t a4 = bond<J>(S, n4, jb, 2), a5 = bond<J>(S, n5, jb, 5);
-                        constexpr int kXor3 = PA_T3(PA_A ^ PA_B ^ PA_C);
-                        constexpr int kMaj = PA_T3((PA_A & PA_B) | (PA_A & PA_C) | (PA_B & PA_C));
                         // three-bond sums and carries, then u = 2 (cA + cB + lc) + ls
                         const uint64_t sA = pa_bop3<kXor3>(a0, a1, a2), cA = pa_bop3<kMaj>(a0, a1, a2);
                         const uint64_t sB = pa_bop3<kXor3>(a3, a4, a5), cB = pa_bop3<kMaj>(a3, a4, a5);
@@ -551,21 +588,49 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
 
     // after the sweeps the queue region is free: per-wave partial counts of the measurement
     uint64_t *red = lat + N;
-    // measure: forward bonds once each, plus the down-spin count
+    // measure: forward bonds once each, plus the down-spin count, two sites
+    // (s and s + blockDim) per pass, added with full adders
     uint64_t ve[8] = {0, 0, 0, 0, 0, 0, 0, 0}, vm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int s = tid; s < N; s += bs) {
-        const int row = (int)__umulhi((uint32_t)s, mL);
-        const int x = s - row * L;
-        const int z = (D == 2) ? 0 : (int)__umulhi((uint32_t)row, mL);
-        const int y = row - z * L;
-        const uint32_t jb = J ? (uint32_t)jl[s] : 0u;
-        const uint64_t S = lat[s];
-        vadd8(ve, bond<J>(S, lat[x == L - 1 ? s - (L - 1) : s + 1], jb, 0));
-        vadd8(ve, bond<J>(S, lat[y == L - 1 ? s - L * (L - 1) : s + L], jb, 1));
-        if (D == 3)
-            vadd8(ve, bond<J>(S, lat[z == L - 1 ? s - LL * (L - 1) : s + LL], jb, 2));
-        vadd8(vm, S);
-        g[s] = S;
+    for (int s = tid; s < N; s += 2 * bs) {
+        uint64_t S[2] = {0, 0}, e[2][3] = {{0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int t = s + h * bs;
+            if (h == 0 || t < N) {
+                const int row = (int)__umulhi((uint32_t)t, mL);
+                const int x = t - row * L;
+                const int z = (D == 2) ? 0 : (int)__umulhi((uint32_t)row, mL);
+                const int y = row - z * L;
+                const uint32_t jb = J ? (uint32_t)jl[t] : 0u;
+                S[h] = lat[t];
+                e[h][0] = bond<J>(S[h], lat[x == L - 1 ? t - (L - 1) : t + 1], jb, 0);
+                e[h][1] = bond<J>(S[h], lat[y == L - 1 ? t - L * (L - 1) : t + L], jb, 1);
+                if (D == 3)
+                    e[h][2] = bond<J>(S[h], lat[z == L - 1 ? t - LL * (L - 1) : t + LL], jb, 2);
+                g[t] = S[h];
+            }
+        }
+        if (D == 2) {
+            const uint64_t k1 = pa_bop3<kMaj>(ve[0], e[0][0], e[0][1]);
+            ve[0] = pa_bop3<kXor3>(ve[0], e[0][0], e[0][1]);
+            const uint64_t k2 = pa_bop3<kMaj>(ve[0], e[1][0], e[1][1]);
+            ve[0] = pa_bop3<kXor3>(ve[0], e[1][0], e[1][1]);
+            vadd2_at<1>(ve, k1, k2);
+        } else {
+            // each site's three bonds as sum + 2 carry, then plane by plane
+            const uint64_t sA = pa_bop3<kXor3>(e[0][0], e[0][1], e[0][2]);
+            const uint64_t cA = pa_bop3<kMaj>(e[0][0], e[0][1], e[0][2]);
+            const uint64_t sB = pa_bop3<kXor3>(e[1][0], e[1][1], e[1][2]);
+            const uint64_t cB = pa_bop3<kMaj>(e[1][0], e[1][1], e[1][2]);
+            const uint64_t k1 = pa_bop3<kMaj>(ve[0], sA, sB);
+            ve[0] = pa_bop3<kXor3>(ve[0], sA, sB);
+            const uint64_t k2 = pa_bop3<kMaj>(ve[1], cA, cB);
+            ve[1] = pa_bop3<kXor3>(ve[1], cA, cB);
+            const uint64_t k3 = ve[1] & k1;
+            ve[1] ^= k1;
+            vadd2_at<2>(ve, k2, k3);
+        }
+        vadd2_at<0>(vm, S[0], S[1]);
     }
     if (theta > 0) {
         const uint64_t tot = pa_wave_sum_u64(calls);
@@ -1920,8 +1985,10 @@ __global__ __launch_bounds__(kThreads) void k_overlap(const PaRunDesc *__restric
     uint64_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     uint64_t c16[16];
     // up to 64 sites per thread with 256 threads and N <= 16384: fits 8 planes
-    for (int s = threadIdx.x; s < N; s += blockDim.x)
-        vadd8(v, a[s] ^ b[s]);
+    for (int s = threadIdx.x; s < N; s += 2 * blockDim.x) {
+        const int t = s + blockDim.x;
+        vadd2_at<0>(v, a[s] ^ b[s], t < N ? a[t] ^ b[t] : 0ull);
+    }
 #pragma unroll
     for (int k = 0; k < 16; ++k)
         c16[k] = k < 8 ? v[k] : 0;
