@@ -368,11 +368,12 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
                                                   uint64_t sure8, uint64_t sure12, uint64_t draw4, uint64_t draw8,
                                                   uint64_t draw12)
 {
-    const int L = G.L, half = G.half, nh = G.nh, LL = G.LL;
+    const int L = G.L, N = G.N, half = G.half, nh = G.nh, LL = G.LL;
     const uint32_t mhalf = G.mhalf, mL = G.mL;
     const int tid = threadIdx.x, bs = blockDim.x;
-    // FIX: stride and steps per iteration of the coordinate that moves
-    const int vst = D == 2 ? L : LL, dv = D == 2 ? 2 * bs / L : 2 * bs / LL;
+    // FIX: stride of the coordinate that moves (y in 2D, z in 3D); a step
+    // across the periodic boundary along it is a step modulo N
+    const uint32_t vst = D == 2 ? (uint32_t)L : (uint32_t)LL;
     // the last class's threshold bits on the inline planes, kept in vector
     // registers for the whole launch
     uint32_t tl[2 * kInlinePairs];
@@ -386,7 +387,7 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
         pc.t = t0 + (uint32_t)tt;
         for (int c = 0; c < 2; ++c) {
             uint32_t head = 0, cnt = 0;
-            int sf = 0, vf = 0, oxp = 0, oxm = 0, oyp = 0, oym = 0;
+            int sf = 0, oxp = 0, oxm = 0, oyp = 0, oym = 0;
             if (FIX) { // the lane's first site, and the offsets that stay
                 const int row = half > 1 ? (int)__umulhi((uint32_t)tid, mhalf) : tid;
                 const int m = tid - row * half;
@@ -394,13 +395,12 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
                 const int y = row - z * L;
                 const int x = 2 * m + ((y + z + c) & 1);
                 sf = x + L * row;
-                vf = D == 2 ? y : z;
                 oxp = x == L - 1 ? -(L - 1) : 1;
                 oxm = x == 0 ? L - 1 : -1;
                 oyp = y == L - 1 ? -L * (L - 1) : L;
                 oym = y == 0 ? L * (L - 1) : -L;
             }
-            for (int kb = 0; kb < nh; kb += bs, sf += 2 * bs, vf += dv) {
+            for (int kb = 0; kb < nh; kb += bs, sf += 2 * bs) {
                 const int k = kb + tid;
                 uint64_t und = 0, m4 = 0, m8 = 0;
                 uint32_t s = 0, q = 0;
@@ -410,14 +410,17 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
                         s = (uint32_t)sf;
                         n0 = lat[sf + oxp];
                         n1 = lat[sf + oxm];
+                        // (s +- vst) mod N as the unsigned smaller of the two candidates
+                        const uint32_t up = (uint32_t)sf + vst, dn = (uint32_t)sf - vst;
+                        const uint64_t nu = lat[min(up, up - (uint32_t)N)], nd = lat[min(dn, dn + (uint32_t)N)];
                         if (D == 2) {
-                            n2 = lat[vf == L - 1 ? sf - vst * (L - 1) : sf + vst];
-                            n3 = lat[vf == 0 ? sf + vst * (L - 1) : sf - vst];
+                            n2 = nu;
+                            n3 = nd;
                         } else {
                             n2 = lat[sf + oyp];
                             n3 = lat[sf + oym];
-                            n4 = lat[vf == L - 1 ? sf - vst * (L - 1) : sf + vst];
-                            n5 = lat[vf == 0 ? sf + vst * (L - 1) : sf - vst];
+                            n4 = nu;
+                            n5 = nd;
                         }
                     } else {
                         const int row = half > 1 ? (int)__umulhi((uint32_t)k, mhalf) : k; // row = y + L z
