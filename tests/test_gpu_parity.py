@@ -179,17 +179,21 @@ def test_repeat_runs_are_bit_identical():
     assert out[0][1] == out[1][1]
 
 
-def test_overlap_distribution():
-    from paper_2401_07965_amd import pa
-    J = ea_couplings(3, 4, 12)
+@pytest.mark.parametrize("d,L", [(3, 4), (3, 10), (2, 32)])
+def test_overlap_distribution(d, L):
+    """P(q) of two populations of the same couplings: N = 64 (one site per
+    thread), 1000 (three or four sites per thread, the last pair ragged) and
+    1024 (four)."""
+    J = ea_couplings(d, L, 12)
     betas = schedule(1.0, 6)
-    ga, oa = run_pair(3, 4, 300, O.SYSTEMATIC, betas, 2, seed=1, run_id=0, J=J,
+    print(f"[parity] overlap d={d} L={L}", flush=True)
+    ga, oa = run_pair(d, L, 300, O.SYSTEMATIC, betas, 2, seed=1, run_id=0, J=J,
                       observables=False)
-    gb, ob = run_pair(3, 4, 250, O.NEAREST_INT, betas, 2, seed=1, run_id=1, J=J,
+    gb, ob = run_pair(d, L, 250, O.NEAREST_INT, betas, 2, seed=1, run_id=1, J=J,
                       observables=False)
     h = ga.overlap(gb)
     R = min(oa.Rcur, ob.Rcur)
-    N = 64
+    N = L ** d
     same = (oa.spins[:R] == ob.spins[:R]).sum(axis=1)  # N - popcount(a ^ b)
     ref = np.bincount(same, minlength=N + 1)
     assert np.array_equal(h, ref)
