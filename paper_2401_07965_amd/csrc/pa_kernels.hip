@@ -347,6 +347,43 @@ __device__ __forceinline__ void queue_pass(const WaveQueue &Q, const PlaneCtx &p
     cnt = queue_push<D>(Q, head, cnt, again, s | ((q + 1) << 16), und, m4, m8);
 }
 
+// The last items of a colour: up to 64 at a time, each lane taking its
+// item's remaining plane pairs in turn until the item is decided, with no
+// requeueing (the site passes leave fewer than 64, so this is one batch).
+template <int D>
+__device__ __forceinline__ void queue_drain(const WaveQueue &Q, const PlaneCtx &pc, uint64_t *lat, uint32_t &head,
+                                            uint32_t &cnt, uint32_t &calls)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    while (cnt > 0u) {
+        const uint32_t n = cnt < 64u ? cnt : 64u;
+        const bool act = lane < n;
+        uint32_t sq = 0;
+        uint64_t und = 0, m4 = 0, m8 = 0;
+        if (act) {
+            const uint32_t slot = (head + lane) & (kQueue - 1);
+            sq = Q.sq[slot];
+            und = Q.und[slot];
+            m4 = Q.m4[slot];
+            if (D == 3)
+                m8 = Q.m8[slot];
+        }
+        __builtin_amdgcn_wave_barrier();
+        head += n;
+        cnt -= n;
+        const uint32_t s = sq & 0xFFFFu;
+        uint64_t acc = 0;
+        for (uint32_t q = sq >> 16; und != 0 && q < 16u; ++q) {
+            const int b0 = 31 - 2 * (int)q;
+            apply_pair<D>(pc, metro_philox(pc, s, q), q, m4, m8, last_tbit<D>(pc, b0), last_tbit<D>(pc, b0 - 1),
+                          und, und, acc);
+            ++calls;
+        }
+        if (act)
+            lat[s] ^= acc;
+    }
+}
+
 // The theta sweeps of one column in LDS.  ALL: every energy-change class has
 // a threshold strictly between 0 and 2^32 (the usual case), so no class is
 // decided without random bits.  Returns the Philox evaluations this lane made.
@@ -508,8 +545,7 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
                 while (cnt >= 64u)
                     queue_pass<D>(Q, pc, lat, head, cnt, calls);
             }
-            while (cnt > 0u)
-                queue_pass<D>(Q, pc, lat, head, cnt, calls);
+            queue_drain<D>(Q, pc, lat, head, cnt, calls);
             __syncthreads();
         }
     }
