@@ -107,7 +107,7 @@ int default_sweep_threads(int N, int d, bool J)
     int best = 0;
     double best_score = -1.0;
     for (int t = 64; t <= 768; t += 64) {
-        const size_t lds = pa_sweep_lds_bytes(N, t, J);
+        const size_t lds = pa_sweep_lds_bytes(N, d, t, J);
         if (!sweep_threads_ok(N, d, t) || lds > (size_t)lds_max)
             continue;
         const int w = t / 64;
@@ -460,7 +460,7 @@ pa_status make_batch(const pa_config *cfgs, int32_t nruns, int32_t max_points, v
     if (g_max_lds == 0 && (e = pa_query_lds(&g_max_lds)) != hipSuccess)
         return hip_fail(nullptr, e, "device query");
     for (const Geometry &g : geo)
-        if (pa_sweep_lds_bytes(g.N, default_sweep_threads(g.N, g.d, g.J != 0), g.J != 0) > (size_t)g_max_lds ||
+        if (pa_sweep_lds_bytes(g.N, g.d, default_sweep_threads(g.N, g.d, g.J != 0), g.J != 0) > (size_t)g_max_lds ||
             (size_t)g.H * 4 > (size_t)g_max_lds)
             return fail(nullptr, PA_E_INVAL, "lattice too large for the workgroup LDS of this device");
     b->jmask.resize(nruns);
@@ -1062,7 +1062,7 @@ pa_status pa_batch_tune(pa_batch *p, int32_t theta, int32_t *threads_out)
         int best_t = b->v.gthreads[g];
         for (int t = 64; t <= 768 && e == hipSuccess; t += 64) {
             if (!sweep_threads_ok(b->v.gN[g], b->v.gd[g], t) ||
-                pa_sweep_lds_bytes(b->v.gN[g], t, b->v.gJ[g] != 0) > (size_t)g_max_lds)
+                pa_sweep_lds_bytes(b->v.gN[g], b->v.gd[g], t, b->v.gJ[g] != 0) > (size_t)g_max_lds)
                 continue;
             e = pa_b_sweep_group(b->v, g, theta, t); // warm-up
             if (e == hipSuccess)

@@ -204,4 +204,4 @@ hipError_t pa_mlp_launch_grad(const PaMlpDev &m, int n, int adam, int t, float l
 hipError_t pa_mlp_launch_predict(const PaMlpDev &m, const float *X, int n, float *out);
 hipError_t pa_mlp_launch_propose(const PaBatchView &v, const PaMlpDev &m, double dbeta_max);
 hipError_t pa_query_lds(int *max_lds);
-size_t pa_sweep_lds_bytes(int N, int threads, bool J); // dynamic LDS of a sweep workgroup (J: bond masks)
+size_t pa_sweep_lds_bytes(int N, int d, int threads, bool J); // dynamic LDS of a sweep workgroup (J: bond masks)

@@ -227,21 +227,23 @@ __device__ __forceinline__ uint64_t tbit(uint32_t t, int b)
 // (T8_b in 2D, T12_b in 3D) as a mask, passed in so that it can come from a
 // vector register: one instruction takes at most one scalar operand.
 template <int D>
-__device__ __forceinline__ uint64_t plane_threshold(const PlaneCtx &pc, int b, uint64_t m4, uint64_t m8,
-                                                    uint64_t last)
+__device__ __forceinline__ uint64_t plane_threshold_m(uint64_t m4, uint64_t m8, uint64_t t4, uint64_t t8,
+                                                      uint64_t t12)
 {
     constexpr int kSel = PA_T3((PA_A & PA_B) | (~PA_A & PA_C));
-    uint64_t t = last;
-    if (D == 3)
-        t = pa_bop3<kSel>(m8, tbit(pc.t8, b), t);
-    return pa_bop3<kSel>(m4, tbit(pc.t4, b), t);
+    const uint64_t t = D == 2 ? t8 : pa_bop3<kSel>(m8, t8, t12);
+    return pa_bop3<kSel>(m4, t4, t);
 }
 
 template <int D>
-__device__ __forceinline__ uint64_t last_tbit(const PlaneCtx &pc, int b)
+__device__ __forceinline__ uint64_t plane_threshold(const PlaneCtx &pc, int b, uint64_t m4, uint64_t m8,
+                                                    uint64_t last)
 {
-    return tbit(D == 2 ? pc.t8 : pc.t12, b);
+    return plane_threshold_m<D>(m4, m8, tbit(pc.t4, b), D == 2 ? last : tbit(pc.t8, b), last);
 }
+
+// A threshold-bit mask (0 or all-ones) as a 64-bit mask.
+__device__ __forceinline__ uint64_t dup32(uint32_t m) { return ((uint64_t)m << 32) | m; }
 
 // One plane: returns the replicas accepted on it (u has 0, the threshold 1);
 // those where u and the threshold agree stay undecided.
@@ -257,17 +259,14 @@ __device__ __forceinline__ pa_philox_out metro_philox(const PlaneCtx &pc, uint32
     return pa_philox(pc.seed, pc.run_id, s, pc.w, pc.step, (PA_PURPOSE_METRO << 28) | (pc.t << 8) | q);
 }
 
-// Plane pair q; last0, last1: the last class's threshold bits on its planes.
-// The undecided set comes in as uin (its complement if INV) and leaves in und.
-template <int D, bool INV = false>
-__device__ __forceinline__ void apply_pair(const PlaneCtx &pc, const pa_philox_out &o, uint32_t q, uint64_t m4,
-                                           uint64_t m8, uint64_t last0, uint64_t last1, uint64_t uin,
-                                           uint64_t &und, uint64_t &acc)
+// A plane pair given its two planes' thresholds T0, T1.  The undecided set
+// comes in as uin (its complement if INV) and leaves in und.
+template <bool INV>
+__device__ __forceinline__ void pair_core(const pa_philox_out &o, uint64_t T0, uint64_t T1, uint64_t uin,
+                                          uint64_t &und, uint64_t &acc)
 {
     const uint64_t P0 = (uint64_t)o.x0 | ((uint64_t)o.x1 << 32);
     const uint64_t P1 = (uint64_t)o.x2 | ((uint64_t)o.x3 << 32);
-    const int b0 = 31 - 2 * (int)q;
-    const uint64_t T0 = plane_threshold<D>(pc, b0, m4, m8, last0);
     uint64_t a0;
     if (INV) {
         a0 = pa_bop3<PA_T3(~PA_A & ~PA_B & PA_C)>(uin, P0, T0);
@@ -276,8 +275,37 @@ __device__ __forceinline__ void apply_pair(const PlaneCtx &pc, const pa_philox_o
         und = uin;
         a0 = plane_step(P0, T0, und);
     }
-    const uint64_t a1 = plane_step(P1, plane_threshold<D>(pc, b0 - 1, m4, m8, last1), und);
+    const uint64_t a1 = plane_step(P1, T1, und);
     acc = pa_bop3<PA_T3(PA_A | PA_B | PA_C)>(acc, a0, a1);
+}
+
+// Plane pair q; last0, last1: the last class's threshold bits on its planes.
+template <int D, bool INV = false>
+__device__ __forceinline__ void apply_pair(const PlaneCtx &pc, const pa_philox_out &o, uint32_t q, uint64_t m4,
+                                           uint64_t m8, uint64_t last0, uint64_t last1, uint64_t uin,
+                                           uint64_t &und, uint64_t &acc)
+{
+    const int b0 = 31 - 2 * (int)q;
+    pair_core<INV>(o, plane_threshold<D>(pc, b0, m4, m8, last0), plane_threshold<D>(pc, b0 - 1, m4, m8, last1),
+                   uin, und, acc);
+}
+
+// Plane pair q of a queued item.  2D reads the threshold bits from the
+// launch's table (tt[4 q + 2 c + j]: class c's bit on plane j of pair q, as
+// a mask); 3D, whose lattice and bond masks leave no LDS to spare for the
+// largest lattices, extracts them.
+template <int D>
+__device__ __forceinline__ void apply_pair_queued(const PlaneCtx &pc, const uint32_t *tt, const pa_philox_out &o,
+                                                  uint32_t q, uint64_t m4, uint64_t m8, uint64_t &und, uint64_t &acc)
+{
+    if (D == 2) {
+        const uint4 a = *reinterpret_cast<const uint4 *>(tt + 4 * q);
+        pair_core<false>(o, plane_threshold_m<D>(m4, m8, dup32(a.x), dup32(a.z), 0ull),
+                         plane_threshold_m<D>(m4, m8, dup32(a.y), dup32(a.w), 0ull), und, und, acc);
+    } else {
+        const int b0 = 31 - 2 * (int)q;
+        apply_pair<D>(pc, o, q, m4, m8, tbit(pc.t12, b0), tbit(pc.t12, b0 - 1), und, und, acc);
+    }
 }
 
 // Per-wave queue of word-sites whose replicas are still undecided after the
@@ -287,10 +315,12 @@ __device__ __forceinline__ void apply_pair(const PlaneCtx &pc, const pa_philox_o
 // Philox outputs, taken in the same order.
 constexpr int kInlinePairs = 3;
 constexpr int kQueue = 128; // per wave; never more than 127 items are live
+constexpr int kTtab = 16 * 4; // 2D threshold-bit table: 16 plane pairs x 2 classes x 2 planes
 
 struct WaveQueue {
     uint32_t *sq;  // site | next pair << 16
     uint64_t *und, *m4, *m8; // m8: 3D only
+    const uint32_t *tt;      // 2D: threshold-bit masks per plane pair (apply_pair_queued)
 };
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << (threadIdx.x & 63)) - 1ull; }
@@ -338,9 +368,7 @@ __device__ __forceinline__ void queue_pass(const WaveQueue &Q, const PlaneCtx &p
     if (act) {
         uint64_t acc = 0;
         ++calls;
-        const int b0 = 31 - 2 * (int)q;
-        apply_pair<D>(pc, metro_philox(pc, s, q), q, m4, m8, last_tbit<D>(pc, b0), last_tbit<D>(pc, b0 - 1), und,
-                      und, acc);
+        apply_pair_queued<D>(pc, Q.tt, metro_philox(pc, s, q), q, m4, m8, und, acc);
         lat[s] ^= acc;
     }
     const bool again = act && und != 0 && q + 1 < 16;
@@ -374,9 +402,7 @@ __device__ __forceinline__ void queue_drain(const WaveQueue &Q, const PlaneCtx &
         const uint32_t s = sq & 0xFFFFu;
         uint64_t acc = 0;
         for (uint32_t q = sq >> 16; und != 0 && q < 16u; ++q) {
-            const int b0 = 31 - 2 * (int)q;
-            apply_pair<D>(pc, metro_philox(pc, s, q), q, m4, m8, last_tbit<D>(pc, b0), last_tbit<D>(pc, b0 - 1),
-                          und, und, acc);
+            apply_pair_queued<D>(pc, Q.tt, metro_philox(pc, s, q), q, m4, m8, und, acc);
             ++calls;
         }
         if (act)
@@ -562,7 +588,8 @@ template <int D, bool J>
 __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__restrict__ runs,
                                                             const PaBlk *__restrict__ map, int theta, uint32_t t0)
 {
-    // dynamic LDS: lattice [N] u64 | queues [waves][3][kQueue] u64 | queue sites [waves][kQueue] u32 | jmask [N]
+    // dynamic LDS: lattice [N] u64 | queues [waves][3][kQueue] u64 | queue sites [waves][kQueue] u32 |
+    // 2D threshold-bit table [16][4] u32 | jmask [N]
     extern __shared__ uint64_t lat[];
     const PaBlk blk = map[blockIdx.x];
     const PaRunDesc &rd = runs[blk.run];
@@ -577,8 +604,19 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
     const int tid = threadIdx.x, bs = blockDim.x, nwaves = bs >> 6;
     uint64_t *qbase = lat + N + (size_t)(tid >> 6) * 3 * kQueue;
     uint32_t *qsites = reinterpret_cast<uint32_t *>(lat + N + (size_t)nwaves * 3 * kQueue);
-    uint8_t *jl = reinterpret_cast<uint8_t *>(qsites + (size_t)nwaves * kQueue);
+    uint32_t *ttab = qsites + (size_t)nwaves * kQueue;
+    uint8_t *jl = reinterpret_cast<uint8_t *>(ttab + (D == 2 ? kTtab : 0));
     uint64_t *g = rd.dv.spins[cur] + (size_t)w * N;
+    const uint64_t T4 = uni64(rec->T[0]), T8 = uni64(rec->T[1]), T12 = uni64(rec->T[2]);
+    if (D == 2 && tid < 16) { // the threshold-bit masks of plane pair tid
+        const uint32_t b0 = 31u - 2u * (uint32_t)tid;
+        const uint32_t t[2] = {(uint32_t)T4, (uint32_t)T8};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            ttab[4 * tid + 2 * c] = (uint32_t)__builtin_amdgcn_sbfe((int)t[c], b0, 1u);
+            ttab[4 * tid + 2 * c + 1] = (uint32_t)__builtin_amdgcn_sbfe((int)t[c], b0 - 1u, 1u);
+        }
+    }
     for (int s = tid; s < N; s += bs) {
         lat[s] = g[s];
         if (J)
@@ -587,7 +625,6 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
     __syncthreads();
 
     const uint64_t two32 = 1ull << 32;
-    const uint64_t T4 = uni64(rec->T[0]), T8 = uni64(rec->T[1]), T12 = uni64(rec->T[2]);
     // classes whose threshold is 2^32 accept outright, those at 0 never accept
     const uint64_t sure4 = T4 >= two32 ? ~0ull : 0ull, sure8 = T8 >= two32 ? ~0ull : 0ull,
                    sure12 = T12 >= two32 ? ~0ull : 0ull;
@@ -607,7 +644,7 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
     pc.t4 = (uint32_t)T4;
     pc.t8 = (uint32_t)T8;
     pc.t12 = (uint32_t)T12;
-    const WaveQueue Q = {qsites + (size_t)(tid >> 6) * kQueue, qbase, qbase + kQueue, qbase + 2 * kQueue};
+    const WaveQueue Q = {qsites + (size_t)(tid >> 6) * kQueue, qbase, qbase + kQueue, qbase + 2 * kQueue, ttab};
     const SweepGeom G = {L, N, half, nh, LL, mhalf, mL};
     const bool all_draw = draw4 != 0 && draw8 != 0 && (D == 2 || draw12 != 0);
     const bool fix = bs % (D == 2 ? L : LL) == 0;
@@ -2167,7 +2204,7 @@ hipError_t sweep_launch(const PaBatchView &v, int g, int theta, int threads, uin
 {
     if (v.gncol[g] == 0)
         return hipSuccess;
-    const size_t lds = pa_sweep_lds_bytes(v.gN[g], threads, v.gJ[g] != 0);
+    const size_t lds = pa_sweep_lds_bytes(v.gN[g], v.gd[g], threads, v.gJ[g] != 0);
     if (v.gd[g] == 2 && v.gJ[g])
         k_sweep<2, true><<<v.gncol[g], threads, lds, st>>>(v.runs, v.gcol[g], theta, t0);
     else if (v.gd[g] == 2)
@@ -2182,9 +2219,10 @@ hipError_t sweep_launch(const PaBatchView &v, int g, int theta, int threads, uin
 } // namespace
 
 // ====================================================================== launchers
-size_t pa_sweep_lds_bytes(int N, int threads, bool J)
+size_t pa_sweep_lds_bytes(int N, int d, int threads, bool J)
 {
-    return (size_t)N * 8 + (size_t)(threads / 64) * kQueue * (3 * 8 + 4) + (J ? (((size_t)N + 7) & ~(size_t)7) : 0);
+    return (size_t)N * 8 + (size_t)(threads / 64) * kQueue * (3 * 8 + 4) + (d == 2 ? kTtab * 4 : 0) +
+           (J ? (((size_t)N + 7) & ~(size_t)7) : 0);
 }
 
 hipError_t pa_query_lds(int *max_lds)
