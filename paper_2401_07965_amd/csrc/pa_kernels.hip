@@ -220,12 +220,11 @@ __device__ __forceinline__ uint64_t tbit(uint32_t t, int b)
     return ((uint64_t)m << 32) | m;
 }
 
-// The threshold bit on plane b of every undecided replica.  The undecided
-// replicas all belong to the drawing classes, which are disjoint, so on them
-// Tp = m4 ? T4_b : T8_b in 2D and m4 ? T4_b : (m8 ? T8_b : T12_b) in 3D; the
-// value on other replicas is never used.  `last` is the last class's bit
-// (T8_b in 2D, T12_b in 3D) as a mask, passed in so that it can come from a
-// vector register: one instruction takes at most one scalar operand.
+// The threshold bit on one plane of every undecided replica, from the
+// classes' bits t4, t8, t12 on that plane (masks).  The undecided replicas
+// all belong to the drawing classes, which are disjoint, so on them
+// Tp = m4 ? t4 : t8 in 2D and m4 ? t4 : (m8 ? t8 : t12) in 3D; the value on
+// other replicas is never used.
 template <int D>
 __device__ __forceinline__ uint64_t plane_threshold_m(uint64_t m4, uint64_t m8, uint64_t t4, uint64_t t8,
                                                       uint64_t t12)
@@ -235,6 +234,9 @@ __device__ __forceinline__ uint64_t plane_threshold_m(uint64_t m4, uint64_t m8, 
     return pa_bop3<kSel>(m4, t4, t);
 }
 
+// The same on plane (bit) b.  `last` is the last class's bit (T8_b in 2D,
+// T12_b in 3D) as a mask, passed in so that it can come from a vector
+// register: one instruction takes at most one scalar operand.
 template <int D>
 __device__ __forceinline__ uint64_t plane_threshold(const PlaneCtx &pc, int b, uint64_t m4, uint64_t m8,
                                                     uint64_t last)
