@@ -326,3 +326,29 @@ def test_largest_population():
     assert o.pending is None and o.last_counts is not None
     compare_state(g, o, "largest population")
     g.close()
+
+
+@pytest.mark.parametrize("d,L,R,glass", [(2, 8, 130, False), (2, 6, 70, True), (3, 4, 200, True)])
+def test_sweeps_at_beta_zero_flip_every_spin(d, L, R, glass):
+    """Sweeps right after the initial sampling run at beta = 0, where every
+    energy-change class accepts outright (threshold 2^32): one sweep negates
+    every spin, a second restores it, no random bits are drawn, and the
+    energies are the oracle's."""
+    from paper_2401_07965_amd import pa
+    J = ea_couplings(d, L, 7) if glass else None
+    print(f"[parity] sweeps at beta = 0, d={d} L={L} R={R} glass={glass}", flush=True)
+    g = pa.PARun(d, L, R, seed=8, run_id=2, couplings=J)
+    o = O.OracleRun(d, L, R, seed=8, run_id=2, J=J)
+    start = compare_state(g, o, "initial")
+    s0 = pa.unpack_spins(start["spins"], R)
+    g.sweep(1)
+    o.sweep(1)
+    st = compare_state(g, o, "one sweep")
+    assert np.array_equal(pa.unpack_spins(st["spins"], R), -s0)
+    assert np.array_equal(st["energy"], start["energy"])  # E(-s) = E(s)
+    g.sweep(1)
+    o.sweep(1)
+    st = compare_state(g, o, "two sweeps")
+    assert np.array_equal(pa.unpack_spins(st["spins"], R), s0)
+    assert g.counters()["philox_calls"] == 0 == o.philox_calls
+    g.close()
