@@ -13,6 +13,7 @@
 #include "pa_internal.h"
 
 #include <climits>
+#include <type_traits>
 
 namespace {
 
@@ -465,11 +466,14 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
                 oyp = y == L - 1 ? -L * (L - 1) : L;
                 oym = y == 0 ? L * (L - 1) : -L;
             }
-            for (int kb = 0; kb < nh; kb += bs, sf += 2 * bs) {
+            // one pass over bs sites of the colour; RAGGED: some lanes have no
+            // site (only the last pass, when bs does not divide N/2)
+            auto pass = [&](const int kb, auto ragged) {
+                constexpr bool RAGGED = decltype(ragged)::value;
                 const int k = kb + tid;
                 uint64_t und = 0, m4 = 0, m8 = 0;
                 uint32_t s = 0, q = 0;
-                if (k < nh) {
+                if (!RAGGED || k < nh) {
                     uint64_t n0, n1, n2, n3, n4 = 0, n5 = 0;
                     if (FIX) {
                         s = (uint32_t)sf;
@@ -572,7 +576,12 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
                 cnt = queue_push<D>(Q, head, cnt, und != 0, s | (q << 16), und, m4, m8);
                 while (cnt >= 64u)
                     queue_pass<D>(Q, pc, lat, head, cnt, calls);
-            }
+            };
+            int kb = 0;
+            for (; kb + bs <= nh; kb += bs, sf += 2 * bs)
+                pass(kb, std::false_type{});
+            if (kb < nh)
+                pass(kb, std::true_type{});
             queue_drain<D>(Q, pc, lat, head, cnt, calls);
             __syncthreads();
         }
