@@ -235,6 +235,23 @@ def test_3d_L10_R5e5_sampled_full_size():
     g.close()
 
 
+def test_3d_L16_R1e6_sampled_full_size():
+    """3D +-J glass, L = 16, R = 10^6 (the learned-schedule workload's size and
+    the sweep's fixed-axis walk in 3D), systematic, theta = 10: sampled step."""
+    from paper_2401_07965_amd import pa
+    J = ea_couplings(3, 16, 1)
+    print("[parity] 3D L=16 R=1e6 sampled step", flush=True)
+    g = pa.PARun(3, 16, 1000000, seed=1, run_id=0, couplings=J)
+    for b in (0.01, 0.02):
+        g.reweight(b)
+        g.resample(O.SYSTEMATIC)
+        g.sweep(10)
+    rows = np.concatenate([np.arange(64), np.arange(999936, 1000000),
+                           np.random.default_rng(2).integers(0, 999000, 64)])
+    sampled_step(g, 3, 16, J, O.SYSTEMATIC, 0.03, 10, rows, 1, 0, 1000000)
+    g.close()
+
+
 def test_philox_probe_matches_the_oracle_generator():
     """The throughput probe evaluates the same generator as the sweeps."""
     import torch
