@@ -60,6 +60,12 @@ def lib():
                                 _c.c_uint32, _c.c_uint32, _c.c_uint32, _c.c_uint32, _c.c_int32,
                                 _c.c_double, _c.POINTER(_c.c_uint64)]
         L.orc_sweep.restype = None
+        L.orc_wolff_threshold.argtypes = [_c.c_double]
+        L.orc_wolff_threshold.restype = _c.c_uint64
+        L.orc_wolff.argtypes = [_c.c_int, _c.c_int, _i8p, _c.c_int64, _i64p, _i8p, _i32p,
+                                _c.c_uint32, _c.c_uint32, _c.c_uint32, _c.c_uint32, _c.c_int32,
+                                _c.c_double, _i64p]
+        L.orc_wolff.restype = None
         L.orc_reweight.argtypes = [_c.c_int64, _i32p, _c.c_double, _c.POINTER(_c.c_double), _u64p,
                                    _c.POINTER(_c.c_uint64)]
         L.orc_reweight.restype = None
@@ -147,6 +153,25 @@ def sweep_rows(d, L, J, rows, spins, E, seed, run_id, step, t0, theta, beta):
     lib().orc_sweep(d, L, np.ascontiguousarray(J, np.int8), len(rows), rows, spins, E, seed,
                     run_id, step, t0, theta, float(beta), ctypes.byref(calls))
     return calls.value
+
+
+def wolff_rows(d, L, J, rows, spins, E, seed, run_id, step, t0, nsteps, beta):
+    """nsteps Wolff single-cluster updates (in place) of the replicas listed in
+    ``rows`` (the cluster-update driver; see orc_wolff for the random-number
+    layout).  Returns the cluster sizes, [len(rows)][nsteps]."""
+    rows = np.ascontiguousarray(rows, np.int64)
+    assert spins.dtype == np.int8 and spins.flags.c_contiguous and E.dtype == np.int32
+    sizes = np.zeros((len(rows), max(int(nsteps), 0)), np.int64)
+    lib().orc_wolff(d, L, np.ascontiguousarray(J, np.int8), len(rows), rows, spins, E, seed, run_id,
+                    step, t0, nsteps, float(beta), sizes.reshape(-1) if sizes.size else
+                    np.zeros(1, np.int64))
+    return sizes
+
+
+def wolff_threshold(beta):
+    """T_p = min(2^32, floor(2^32 (1 - pa_exp(-2 beta)))): a bond joins the
+    cluster iff it is satisfied and the replica's uniform u < T_p."""
+    return int(lib().orc_wolff_threshold(float(beta)))
 
 
 def reweight(E, dbeta):
@@ -368,6 +393,14 @@ class OracleRun:
         self.philox_calls += sweep_rows(self.d, self.L, self.J, np.arange(self.Rcur), self.spins, self.E,
                                         self.seed, self.run_id, self.step, self.t, theta, self.beta)
         self.t += theta
+
+    def cluster(self, nsteps):
+        """nsteps Wolff updates at the current beta (the update counter t is
+        shared with the sweeps); returns the cluster sizes [Rcur][nsteps]."""
+        sizes = wolff_rows(self.d, self.L, self.J, np.arange(self.Rcur), self.spins, self.E, self.seed,
+                           self.run_id, self.step, self.t, nsteps, self.beta)
+        self.t += nsteps
+        return sizes
 
     def magnetization(self):
         return self.spins.astype(np.int64).sum(axis=1)

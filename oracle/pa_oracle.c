@@ -70,6 +70,8 @@ static void philox4(uint32_t seed, uint32_t run_id, uint32_t c0, uint32_t c1,
 #define PURPOSE_RS_POIS 5u
 #define PURPOSE_RS_MULT 6u
 #define PURPOSE_RS_SYS 7u
+#define PURPOSE_WSEED 8u
+#define PURPOSE_WBOND 9u
 
 /* Threads the oracle's OpenMP loops use (reported with its timings). */
 int orc_threads(void) { return omp_get_max_threads(); }
@@ -312,6 +314,104 @@ void orc_sweep(int d, int L, const int8_t *J, int64_t nrows, const int64_t *rep,
     free(gstart);
     if (calls)
         *calls = total_calls;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cluster updates as the driver of step 3 (Sec. 1 names them among the     */
+/* update algorithms the scheme can use; reading: Wolff's single-cluster    */
+/* update).  One update of replica r = 64w + b at (step i, update t):        */
+/*  - the seed site is s0 = floor(x0 N / 2^32), x0 from                      */
+/*    Philox(ctr = (b, w, i, WSEED<<28 | t<<8));                             */
+/*  - the bond (s, mu) joining s and s + e_mu is active iff it is satisfied */
+/*    (J sigma_s sigma_{s+e_mu} = +1) and u < T_p, T_p = min(2^32,           */
+/*    floor(2^32 (1 - pa_exp(-2 beta)))), u the replica's 32-bit uniform of  */
+/*    the bit planes of Philox(ctr = (s, w, i, WBOND<<28 | t<<8 | mu<<4 | q)), */
+/*    q = 0..15, laid out as for the Metropolis decisions;                   */
+/*  - the cluster is the set of sites joined to s0 by active bonds, found   */
+/*    by a breadth-first search here; all its spins flip.                   */
+/* Whether a bond is active is fixed before the search, so the cluster does  */
+/* not depend on the order in which it is grown.  csize (if not NULL) gets   */
+/* the cluster sizes, row-major [nrows][nsteps].                            */
+/* ------------------------------------------------------------------------ */
+uint64_t orc_wolff_threshold(double beta)
+{
+    double p = 1.0 - orc_exp(-(2.0 * beta));
+    double t = floor(ldexp(p, 32));
+    uint64_t T = (uint64_t)t;
+    if (T > ((uint64_t)1 << 32))
+        T = (uint64_t)1 << 32;
+    return T;
+}
+
+/* u < T for replica b of word w on bond (s, mu), compared from the most   */
+/* significant bit down (bit 31 - k of u is bit b of plane k), stopping at   */
+/* the first bit where u and T differ; equal in all 32 bits means u = T.    */
+static int bond_active(uint32_t seed, uint32_t run_id, uint32_t s, uint32_t w, uint32_t step,
+                       uint32_t t, int mu, uint32_t b, uint64_t T)
+{
+    if (T >= ((uint64_t)1 << 32))
+        return 1;
+    for (uint32_t q = 0; q < 16; ++q) {
+        uint32_t x[4];
+        philox4(seed, run_id, s, w, step, (PURPOSE_WBOND << 28) | (t << 8) | ((uint32_t)mu << 4) | q, x);
+        const uint64_t planes[2] = {(uint64_t)x[0] | ((uint64_t)x[1] << 32), (uint64_t)x[2] | ((uint64_t)x[3] << 32)};
+        for (int h = 0; h < 2; ++h) {
+            int bit = 31 - (int)(2 * q) - h;
+            uint32_t ub = (uint32_t)(planes[h] >> b) & 1u, tb = (uint32_t)(T >> bit) & 1u;
+            if (ub != tb)
+                return ub < tb;
+        }
+    }
+    return 0;
+}
+
+void orc_wolff(int d, int L, const int8_t *J, int64_t nrows, const int64_t *rep, int8_t *spins,
+               int32_t *E, uint32_t seed, uint32_t run_id, uint32_t step, uint32_t t0, int32_t nsteps,
+               double beta, int64_t *csize)
+{
+    int64_t N = n_sites(d, L);
+    uint64_t T = orc_wolff_threshold(beta);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t n = 0; n < nrows; ++n) {
+        uint32_t w = (uint32_t)(rep[n] >> 6), b = (uint32_t)(rep[n] & 63);
+        int8_t *sp = spins + n * N;
+        uint8_t *in = (uint8_t *)malloc((size_t)N);
+        int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)N);
+        for (int32_t k = 0; k < nsteps; ++k) {
+            uint32_t t = t0 + (uint32_t)k;
+            uint32_t x[4];
+            philox4(seed, run_id, b, w, step, (PURPOSE_WSEED << 28) | (t << 8), x);
+            int64_t s0 = (int64_t)(((uint64_t)x[0] * (uint64_t)N) >> 32);
+            memset(in, 0, (size_t)N);
+            int64_t head = 0, tail = 0;
+            queue[tail++] = s0;
+            in[s0] = 1;
+            while (head < tail) {
+                int64_t s = queue[head++];
+                for (int mu = 0; mu < d; ++mu)
+                    for (int dir = -1; dir <= 1; dir += 2) {
+                        int64_t nb = neighbor(s, L, mu, dir);
+                        if (in[nb])
+                            continue;
+                        int64_t owner = dir > 0 ? s : nb; /* bond (owner, mu) */
+                        if (J[owner * d + mu] * sp[s] * sp[nb] != 1)
+                            continue;
+                        if (bond_active(seed, run_id, (uint32_t)owner, w, step, t, mu, b, T)) {
+                            in[nb] = 1;
+                            queue[tail++] = nb;
+                        }
+                    }
+            }
+            for (int64_t s = 0; s < N; ++s)
+                if (in[s])
+                    sp[s] = (int8_t)-sp[s];
+            E[n] = (int32_t)orc_energy(d, L, J, sp);
+            if (csize)
+                csize[n * nsteps + k] = tail;
+        }
+        free(in);
+        free(queue);
+    }
 }
 
 /* ------------------------------------------------------------------------ */
