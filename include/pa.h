@@ -168,6 +168,21 @@ pa_status pa_init(const pa_config *cfg, void *workspace, uint64_t workspace_byte
  * (s, w, i, 2<<28 | t<<8 | q), q = k/2, t = the sweep index within step i. */
 pa_status pa_sweep(pa_ctx *ctx, int32_t theta);
 
+/* Step 3 of Sec. 2 with cluster updates as the driver (Sec. 1 names them
+ * among the update algorithms the scheme can use): nsteps >= 0 Wolff
+ * single-cluster updates of every replica at the current beta.  Replica
+ * r = 64w+b seeds its cluster at site floor(x0 N / 2^32), x0 of Philox
+ * counter (b, w, i, 8<<28 | t<<8); a bond (s, mu) joins the cluster iff it
+ * is satisfied (J sigma_s sigma_{s+e_mu} = +1) and the replica's uniform
+ * u < min(2^32, floor(2^32 (1 - exp(-2 beta)))), u's bit 31-k being bit b of
+ * plane k of counters (s, w, i, 9<<28 | t<<8 | mu<<4 | q), q = k/2; the whole
+ * cluster flips.  t counts sweeps and cluster updates together within step i
+ * (at most 2^20).  Energies and magnetisations are recounted afterwards.
+ * PA_E_INVAL if nsteps < 0, if the step's updates would pass 2^20, or if a
+ * lattice needs more LDS per workgroup than the device has (4 N 8 bytes, plus
+ * N with couplings: N <= 5120 on 160 KiB).  Enqueued on the run's stream. */
+pa_status pa_cluster(pa_ctx *ctx, int32_t nsteps);
+
 /* Step 2 of Sec. 2: for beta_next >= beta, ln Q of Eq. (1) over the current
  * population, written as -dbeta E_min + ln((1/R) sum_j exp(-dbeta (E_j - E_min))).
  * Also fixes the integer resampling weights floor(2^40 exp(-dbeta (E_j - E_min))).

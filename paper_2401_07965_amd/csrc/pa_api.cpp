@@ -668,6 +668,28 @@ pa_status pa_sweep(pa_ctx *c, int32_t theta)
     return PA_OK;
 }
 
+pa_status pa_cluster(pa_ctx *c, int32_t nsteps)
+{
+    if (!c)
+        return fail(nullptr, PA_E_INVAL, "ctx is NULL");
+    Batch *b = &c->b;
+    if (nsteps < 0)
+        return fail(b, PA_E_INVAL, "nsteps must be >= 0");
+    if ((uint64_t)b->sweeps + (uint64_t)nsteps > (1u << 20))
+        return fail(b, PA_E_INVAL, "more than 2^20 sweeps and cluster updates at one temperature");
+    for (int g = 0; g < b->v.ngroups; ++g)
+        if (pa_cluster_lds_bytes(b->v.gN[g], b->v.gJ[g] != 0) > (size_t)g_max_lds)
+            return fail(b, PA_E_INVAL, "lattice too large for cluster updates (LDS of one workgroup)");
+    if (nsteps == 0)
+        return PA_OK;
+    hipError_t e = pa_b_cluster(b->v, nsteps, b->sweeps);
+    if (e != hipSuccess)
+        return hip_fail(b, e, "pa_cluster");
+    b->sweeps += (uint32_t)nsteps;
+    b->sweeps_total += (uint64_t)nsteps;
+    return PA_OK;
+}
+
 pa_status pa_reweight(pa_ctx *c, double beta_next, double *lnQ_out)
 {
     if (!c)

@@ -23,6 +23,8 @@ typedef unsigned __int128 pa_u128;
 #define PA_PURPOSE_RS_POIS 5u
 #define PA_PURPOSE_RS_MULT 6u
 #define PA_PURPOSE_RS_SYS 7u
+#define PA_PURPOSE_WSEED 8u
+#define PA_PURPOSE_WBOND 9u
 
 struct pa_philox_out {
     uint32_t x0, x1, x2, x3;

@@ -205,3 +205,5 @@ hipError_t pa_mlp_launch_predict(const PaMlpDev &m, const float *X, int n, float
 hipError_t pa_mlp_launch_propose(const PaBatchView &v, const PaMlpDev &m, double dbeta_max);
 hipError_t pa_query_lds(int *max_lds);
 size_t pa_sweep_lds_bytes(int N, int d, int threads, bool J); // dynamic LDS of a sweep workgroup (J: bond masks)
+size_t pa_cluster_lds_bytes(int N, bool J);                   // dynamic LDS of a cluster-update workgroup
+hipError_t pa_b_cluster(const PaBatchView &v, int nsteps, uint32_t t0); // Wolff updates of every run

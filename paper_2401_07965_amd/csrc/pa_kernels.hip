@@ -413,6 +413,97 @@ __device__ __forceinline__ void queue_drain(const WaveQueue &Q, const PlaneCtx &
     }
 }
 
+// Recount of a column after its updates: each replica's unsatisfied-bond
+// count U and number of down spins, bit-sliced (forward bonds once each, two
+// sites per pass added with full adders, then a wave butterfly and the waves'
+// partial counts in red[32 per wave]): E = 2U - dN, M = N - 2 n_down.  Also
+// writes the lattice back to g.  Per-lane counts stay below 2^8: at most
+// ceil(N / blockDim) sites per lane, d bonds each (the launch checks).
+template <int D, bool J>
+__device__ __forceinline__ void recount_column(const uint64_t *lat, const uint8_t *jl, uint64_t *g, uint64_t *red,
+                                               const PaRunDesc &rd, int cur, uint32_t w, int64_t Rlive, int L,
+                                               int N, int LL, uint32_t mL)
+{
+    const int tid = threadIdx.x, bs = blockDim.x;
+    uint64_t ve[8] = {0, 0, 0, 0, 0, 0, 0, 0}, vm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int s = tid; s < N; s += 2 * bs) {
+        uint64_t S[2] = {0, 0}, e[2][3] = {{0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int t = s + h * bs;
+            if (h == 0 || t < N) {
+                const int row = (int)__umulhi((uint32_t)t, mL);
+                const int x = t - row * L;
+                const int z = (D == 2) ? 0 : (int)__umulhi((uint32_t)row, mL);
+                const int y = row - z * L;
+                const uint32_t jb = J ? (uint32_t)jl[t] : 0u;
+                S[h] = lat[t];
+                e[h][0] = bond<J>(S[h], lat[x == L - 1 ? t - (L - 1) : t + 1], jb, 0);
+                e[h][1] = bond<J>(S[h], lat[y == L - 1 ? t - L * (L - 1) : t + L], jb, 1);
+                if (D == 3)
+                    e[h][2] = bond<J>(S[h], lat[z == L - 1 ? t - LL * (L - 1) : t + LL], jb, 2);
+                g[t] = S[h];
+            }
+        }
+        if (D == 2) {
+            const uint64_t k1 = pa_bop3<kMaj>(ve[0], e[0][0], e[0][1]);
+            ve[0] = pa_bop3<kXor3>(ve[0], e[0][0], e[0][1]);
+            const uint64_t k2 = pa_bop3<kMaj>(ve[0], e[1][0], e[1][1]);
+            ve[0] = pa_bop3<kXor3>(ve[0], e[1][0], e[1][1]);
+            vadd2_at<1>(ve, k1, k2);
+        } else {
+            // each site's three bonds as sum + 2 carry, then plane by plane
+            const uint64_t sA = pa_bop3<kXor3>(e[0][0], e[0][1], e[0][2]);
+            const uint64_t cA = pa_bop3<kMaj>(e[0][0], e[0][1], e[0][2]);
+            const uint64_t sB = pa_bop3<kXor3>(e[1][0], e[1][1], e[1][2]);
+            const uint64_t cB = pa_bop3<kMaj>(e[1][0], e[1][1], e[1][2]);
+            const uint64_t k1 = pa_bop3<kMaj>(ve[0], sA, sB);
+            ve[0] = pa_bop3<kXor3>(ve[0], sA, sB);
+            const uint64_t k2 = pa_bop3<kMaj>(ve[1], cA, cB);
+            ve[1] = pa_bop3<kXor3>(ve[1], cA, cB);
+            const uint64_t k3 = ve[1] & k1;
+            ve[1] ^= k1;
+            vadd2_at<2>(ve, k2, k3);
+        }
+        vadd2_at<0>(vm, S[0], S[1]);
+    }
+    // the two bit-sliced counts reduced one after the other (fewer live registers)
+    const int wave = tid >> 6, lane = tid & 63, nw = bs >> 6;
+    {
+        uint64_t c[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            c[k] = k < 8 ? ve[k] : 0;
+        wave_vsum16(c);
+        if (lane == 0)
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                red[wave * 32 + k] = c[k];
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            c[k] = k < 8 ? vm[k] : 0;
+        wave_vsum16(c);
+        if (lane == 0)
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                red[wave * 32 + 16 + k] = c[k];
+    }
+    __syncthreads();
+    if (wave == 0) {
+        uint32_t U = 0, nd = 0;
+        for (int v = 0; v < nw; ++v)
+            for (int k = 0; k < 16; ++k) {
+                U += (uint32_t)((red[v * 32 + k] >> lane) & 1u) << k;
+                nd += (uint32_t)((red[v * 32 + 16 + k] >> lane) & 1u) << k;
+            }
+        const int64_t r = 64 * (int64_t)w + lane;
+        if (r < Rlive) {
+            rd.dv.E[cur][r] = 2 * (int32_t)U - D * N;
+            rd.dv.M[cur][r] = N - 2 * (int32_t)nd;
+        }
+    }
+}
+
 // The theta sweeps of one column in LDS.  ALL: every energy-change class has
 // a threshold strictly between 0 and 2^32 (the usual case), so no class is
 // decided without random bits.  Returns the Philox evaluations this lane made.
@@ -674,51 +765,6 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
                                                   draw12);
 
     // after the sweeps the queue region is free: per-wave partial counts of the measurement
-    uint64_t *red = lat + N;
-    // measure: forward bonds once each, plus the down-spin count, two sites
-    // (s and s + blockDim) per pass, added with full adders
-    uint64_t ve[8] = {0, 0, 0, 0, 0, 0, 0, 0}, vm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int s = tid; s < N; s += 2 * bs) {
-        uint64_t S[2] = {0, 0}, e[2][3] = {{0, 0, 0}, {0, 0, 0}};
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int t = s + h * bs;
-            if (h == 0 || t < N) {
-                const int row = (int)__umulhi((uint32_t)t, mL);
-                const int x = t - row * L;
-                const int z = (D == 2) ? 0 : (int)__umulhi((uint32_t)row, mL);
-                const int y = row - z * L;
-                const uint32_t jb = J ? (uint32_t)jl[t] : 0u;
-                S[h] = lat[t];
-                e[h][0] = bond<J>(S[h], lat[x == L - 1 ? t - (L - 1) : t + 1], jb, 0);
-                e[h][1] = bond<J>(S[h], lat[y == L - 1 ? t - L * (L - 1) : t + L], jb, 1);
-                if (D == 3)
-                    e[h][2] = bond<J>(S[h], lat[z == L - 1 ? t - LL * (L - 1) : t + LL], jb, 2);
-                g[t] = S[h];
-            }
-        }
-        if (D == 2) {
-            const uint64_t k1 = pa_bop3<kMaj>(ve[0], e[0][0], e[0][1]);
-            ve[0] = pa_bop3<kXor3>(ve[0], e[0][0], e[0][1]);
-            const uint64_t k2 = pa_bop3<kMaj>(ve[0], e[1][0], e[1][1]);
-            ve[0] = pa_bop3<kXor3>(ve[0], e[1][0], e[1][1]);
-            vadd2_at<1>(ve, k1, k2);
-        } else {
-            // each site's three bonds as sum + 2 carry, then plane by plane
-            const uint64_t sA = pa_bop3<kXor3>(e[0][0], e[0][1], e[0][2]);
-            const uint64_t cA = pa_bop3<kMaj>(e[0][0], e[0][1], e[0][2]);
-            const uint64_t sB = pa_bop3<kXor3>(e[1][0], e[1][1], e[1][2]);
-            const uint64_t cB = pa_bop3<kMaj>(e[1][0], e[1][1], e[1][2]);
-            const uint64_t k1 = pa_bop3<kMaj>(ve[0], sA, sB);
-            ve[0] = pa_bop3<kXor3>(ve[0], sA, sB);
-            const uint64_t k2 = pa_bop3<kMaj>(ve[1], cA, cB);
-            ve[1] = pa_bop3<kXor3>(ve[1], cA, cB);
-            const uint64_t k3 = ve[1] & k1;
-            ve[1] ^= k1;
-            vadd2_at<2>(ve, k2, k3);
-        }
-        vadd2_at<0>(vm, S[0], S[1]);
-    }
     if (theta > 0) {
         const uint64_t tot = pa_wave_sum_u64(calls);
         if ((tid & 63) == 0)
@@ -730,41 +776,146 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
             rec->attempts += (unsigned long long)theta * (unsigned long long)N * (unsigned long long)Rlive;
         }
     }
-    // the two bit-sliced counts reduced one after the other (fewer live registers)
-    const int wave = tid >> 6, lane = tid & 63, nw = bs >> 6;
-    {
-        uint64_t c[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k)
-            c[k] = k < 8 ? ve[k] : 0;
-        wave_vsum16(c);
-        if (lane == 0)
-#pragma unroll
-            for (int k = 0; k < 16; ++k)
-                red[wave * 32 + k] = c[k];
-#pragma unroll
-        for (int k = 0; k < 16; ++k)
-            c[k] = k < 8 ? vm[k] : 0;
-        wave_vsum16(c);
-        if (lane == 0)
-#pragma unroll
-            for (int k = 0; k < 16; ++k)
-                red[wave * 32 + 16 + k] = c[k];
+    recount_column<D, J>(lat, jl, g, lat + N, rd, cur, w, Rlive, L, N, LL, mL);
+}
+
+// ------------------------------------------------------------------ cluster updates
+// The cluster-update driver (Sec. 1 names cluster updates among the update
+// algorithms the scheme can use): nsteps Wolff single-cluster updates of
+// every replica at the run's current beta.  For replica b of column w at
+// (step i, update t):
+//  - seed site floor(x0 N / 2^32), x0 of Philox(b, w, i, WSEED<<28 | t<<8);
+//  - bond (s, mu) to s + e_mu active iff satisfied and u < T_p, T_p =
+//    min(2^32, floor(2^32 (1 - pa_exp(-2 beta)))), u's bits from the planes
+//    of Philox(s, w, i, WBOND<<28 | t<<8 | mu<<4 | q), q = 0..15, decided
+//    from the most significant bit as for the Metropolis thresholds;
+//  - the cluster is every site joined to the seed by active bonds; it flips.
+// Growth is bit-parallel over the 64 replicas: each pass, every site takes
+// the replicas newly added at a neighbour last pass (frontier F) across
+// satisfied bonds whose activity the pass decides for just those replicas;
+// a site writes only its own words, and a (bond, replica) pair is decided at
+// most once.  The component does not depend on the order of growth.
+
+// Activity of bond (owner, mu) for the replicas in cnd.
+__device__ __forceinline__ uint64_t wolff_bond(const PlaneCtx &pc, uint32_t owner, uint32_t mu, uint64_t cnd,
+                                               uint64_t T)
+{
+    if (T >= (1ull << 32))
+        return cnd;
+    if (T == 0)
+        return 0;
+    uint64_t und = cnd, acc = 0;
+    for (uint32_t q = 0; q < 16u && und != 0; ++q) {
+        const pa_philox_out o = pa_philox(pc.seed, pc.run_id, owner, pc.w, pc.step,
+                                          (PA_PURPOSE_WBOND << 28) | (pc.t << 8) | (mu << 4) | q);
+        const int b0 = 31 - 2 * (int)q;
+        pair_core<false>(o, tbit((uint32_t)T, b0), tbit((uint32_t)T, b0 - 1), und, und, acc);
     }
-    __syncthreads();
-    if (wave == 0) {
-        uint32_t U = 0, nd = 0;
-        for (int v = 0; v < nw; ++v)
-            for (int k = 0; k < 16; ++k) {
-                U += (uint32_t)((red[v * 32 + k] >> lane) & 1u) << k;
-                nd += (uint32_t)((red[v * 32 + 16 + k] >> lane) & 1u) << k;
-            }
-        const int64_t r = 64 * (int64_t)w + lane;
-        if (r < Rlive) {
-            rd.dv.E[cur][r] = 2 * (int32_t)U - D * N;
-            rd.dv.M[cur][r] = N - 2 * (int32_t)nd;
+    return acc;
+}
+
+template <int D, bool J>
+__global__ __launch_bounds__(kThreads) void k_cluster(const PaRunDesc *__restrict__ runs,
+                                                      const PaBlk *__restrict__ map, int nsteps, uint32_t t0)
+{
+    // dynamic LDS: lattice [N] | cluster C [N] | frontiers F0, F1 [N] (at
+    // least 32 per wave in all, reused by the recount) | jmask [N] bytes
+    extern __shared__ uint64_t lat[];
+    const PaBlk blk = map[blockIdx.x];
+    const PaRunDesc &rd = runs[blk.run];
+    PaRecord *rec = rd.dv.rec;
+    const uint32_t w = blk.idx;
+    const int64_t Rlive = (int64_t)rec->Rcur;
+    if ((int64_t)w * 64 >= Rlive || frozen(rec))
+        return;
+    const int L = uni(rd.L), N = uni(rd.N), LL = L * L;
+    const int cur = uni(rec->cur);
+    const int tid = threadIdx.x, bs = blockDim.x;
+    uint64_t *C = lat + N, *F0 = C + N, *F1 = F0 + N;
+    const int nred = 3 * N > 32 * (bs >> 6) ? 3 * N : 32 * (bs >> 6);
+    uint8_t *jl = reinterpret_cast<uint8_t *>(lat + N + nred);
+    uint64_t *g = rd.dv.spins[cur] + (size_t)w * N;
+    for (int s = tid; s < N; s += bs) {
+        lat[s] = g[s];
+        if (J)
+            jl[s] = rd.dv.jmask[s];
+    }
+    const uint32_t mL = uni((uint32_t)(((1ull << 32) + (uint64_t)L - 1) / (uint64_t)L));
+    const double p = 1.0 - pa_exp(-(2.0 * rec->beta));
+    const double tf = floor(ldexp(p, 32));
+    uint64_t T = (uint64_t)tf;
+    if (T > (1ull << 32))
+        T = 1ull << 32;
+    PlaneCtx pc;
+    pc.seed = uni(rd.seed);
+    pc.run_id = uni(rd.run_id);
+    pc.w = w;
+    pc.step = uni(rec->step);
+    for (int k = 0; k < nsteps; ++k) {
+        pc.t = t0 + (uint32_t)k;
+        for (int s = tid; s < N; s += bs)
+            C[s] = F0[s] = 0;
+        __syncthreads();
+        if (tid < 64) { // the seed of replica tid
+            const pa_philox_out o = pa_philox(pc.seed, pc.run_id, (uint32_t)tid, w, pc.step,
+                                              (PA_PURPOSE_WSEED << 28) | (pc.t << 8));
+            const uint32_t s0 = (uint32_t)(((uint64_t)o.x0 * (uint64_t)N) >> 32);
+            atomicOr((unsigned long long *)&C[s0], 1ull << tid);
+            atomicOr((unsigned long long *)&F0[s0], 1ull << tid);
         }
+        __syncthreads();
+        uint64_t *Fc = F0, *Fn = F1;
+        // every pass that continues adds a (site, replica) pair: at most 64 N
+        for (int pass = 0; pass <= 64 * N; ++pass) {
+            int any = 0;
+            for (int s = tid; s < N; s += bs) {
+                const int row = (int)__umulhi((uint32_t)s, mL);
+                const int x = s - row * L;
+                const int z = (D == 2) ? 0 : (int)__umulhi((uint32_t)row, mL);
+                const int y = row - z * L;
+                const uint32_t jb = J ? (uint32_t)jl[s] : 0u;
+                const uint64_t S = lat[s], cs = C[s];
+                uint64_t add = 0;
+#pragma unroll
+                for (int mu = 0; mu < D; ++mu) {
+                    const int c = mu == 0 ? x : (mu == 1 ? y : z);
+                    const int st = mu == 0 ? 1 : (mu == 1 ? L : LL);
+                    const int up = c == L - 1 ? s - st * (L - 1) : s + st;
+                    const int dn = c == 0 ? s + st * (L - 1) : s - st;
+                    // bond (s, mu) to up, owned by s; bond (dn, mu) to s, owned by dn
+                    uint64_t f = Fc[up] & ~cs;
+                    if (f) {
+                        const uint64_t cnd = f & ~bond<J>(S, lat[up], jb, mu);
+                        if (cnd)
+                            add |= wolff_bond(pc, (uint32_t)s, (uint32_t)mu, cnd, T);
+                    }
+                    f = Fc[dn] & ~cs;
+                    if (f) {
+                        const uint64_t cnd = f & ~bond<J>(S, lat[dn], jb, D + mu);
+                        if (cnd)
+                            add |= wolff_bond(pc, (uint32_t)dn, (uint32_t)mu, cnd, T);
+                    }
+                }
+                add &= ~cs;
+                if (add) {
+                    C[s] = cs | add;
+                    any = 1;
+                }
+                Fn[s] = add;
+            }
+            if (!__syncthreads_or(any))
+                break;
+            uint64_t *tmp = Fc;
+            Fc = Fn;
+            Fn = tmp;
+        }
+        for (int s = tid; s < N; s += bs)
+            lat[s] ^= C[s];
+        __syncthreads();
     }
+    if (tid == 0 && w == 0) // once per run; no block reads it during the launch
+        rec->sweeps = t0 + (uint32_t)nsteps;
+    recount_column<D, J>(lat, jl, g, lat + N, rd, cur, w, Rlive, L, N, LL, mL);
 }
 
 // The sweep counter advances after the sweeps (a separate launch, so that no
@@ -2234,6 +2385,33 @@ size_t pa_sweep_lds_bytes(int N, int d, int threads, bool J)
 {
     return (size_t)N * 8 + (size_t)(threads / 64) * kQueue * (3 * 8 + 4) + (d == 2 ? kTtab * 4 : 0) +
            (J ? (((size_t)N + 7) & ~(size_t)7) : 0);
+}
+
+size_t pa_cluster_lds_bytes(int N, bool J)
+{
+    const size_t nred = (size_t)3 * N > (size_t)32 * (kThreads / 64) ? (size_t)3 * N : (size_t)32 * (kThreads / 64);
+    return ((size_t)N + nred) * 8 + (J ? (((size_t)N + 7) & ~(size_t)7) : 0);
+}
+
+hipError_t pa_b_cluster(const PaBatchView &v, int nsteps, uint32_t t0)
+{
+    for (int g = 0; g < v.ngroups; ++g) {
+        if (v.gncol[g] == 0)
+            continue;
+        const size_t lds = pa_cluster_lds_bytes(v.gN[g], v.gJ[g] != 0);
+        if (v.gd[g] == 2 && v.gJ[g])
+            k_cluster<2, true><<<v.gncol[g], kThreads, lds, v.stream>>>(v.runs, v.gcol[g], nsteps, t0);
+        else if (v.gd[g] == 2)
+            k_cluster<2, false><<<v.gncol[g], kThreads, lds, v.stream>>>(v.runs, v.gcol[g], nsteps, t0);
+        else if (v.gJ[g])
+            k_cluster<3, true><<<v.gncol[g], kThreads, lds, v.stream>>>(v.runs, v.gcol[g], nsteps, t0);
+        else
+            k_cluster<3, false><<<v.gncol[g], kThreads, lds, v.stream>>>(v.runs, v.gcol[g], nsteps, t0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t pa_query_lds(int *max_lds)

@@ -114,6 +114,7 @@ def lib():
         L.pa_required_bytes.argtypes = [P(pa_config), P(ctypes.c_uint64)]
         L.pa_init.argtypes = [P(pa_config), v, ctypes.c_uint64, v, P(v)]
         L.pa_sweep.argtypes = [v, ctypes.c_int32]
+        L.pa_cluster.argtypes = [v, ctypes.c_int32]
         L.pa_reweight.argtypes = [v, ctypes.c_double, P(ctypes.c_double)]
         L.pa_resample.argtypes = [v, ctypes.c_int, P(ctypes.c_int64)]
         L.pa_resample_conditional.argtypes = [v, ctypes.c_int, ctypes.c_double, P(ctypes.c_int64),
@@ -170,7 +171,7 @@ def lib():
         L.pa_destroy.restype = None
         L.pa_last_error.argtypes = [v]
         L.pa_last_error.restype = ctypes.c_char_p
-        for name in ("pa_required_bytes", "pa_init", "pa_sweep", "pa_reweight", "pa_resample",
+        for name in ("pa_required_bytes", "pa_init", "pa_sweep", "pa_cluster", "pa_reweight", "pa_resample",
                      "pa_observables", "pa_free_energy", "pa_export_state", "pa_import_state",
                      "pa_overlap", "pa_get_counters", "pa_step_alpha", "pa_step_rule",
                      "pa_philox_probe"):
@@ -221,6 +222,10 @@ def pa_init(cfg, workspace_ptr, workspace_bytes, stream_ptr):
 
 def pa_sweep(ctx, theta):
     _check(lib().pa_sweep(ctx, int(theta)), ctx)
+
+
+def pa_cluster(ctx, nsteps):
+    _check(lib().pa_cluster(ctx, int(nsteps)), ctx)
 
 
 def pa_reweight(ctx, beta_next, wait=True):
@@ -399,6 +404,11 @@ class PARun:
 
     def sweep(self, theta):
         pa_sweep(self.ctx, theta)
+
+    def cluster(self, nsteps):
+        """nsteps Wolff single-cluster updates of every replica (the
+        cluster-update driver); enqueued, like sweep."""
+        pa_cluster(self.ctx, nsteps)
 
     def observables(self, wait=True):
         return pa_observables(self.ctx, wait)
