@@ -538,6 +538,61 @@ def scheme_error_study(L=64, R=20000, theta=5, runs=128):
                         f"beta_i = i/300 to 0.6", "by_scheme": out}
 
 
+def cluster_study(L=64, R=100000, beta_c=0.4406868, updates=10):
+    """The cluster-update driver (Wolff updates, pa_cluster) beside Metropolis
+    sweeps on the bench lattice at beta_c: time per update of all R replicas,
+    mean cluster size (spins that flip, from the exported states), and the
+    autocorrelation across the population of E and |m| after k updates of
+    either kind, from the same annealed starting population."""
+    import numpy as np
+    import torch
+    from paper_2401_07965_amd import pa
+    st = torch.cuda.current_stream()
+
+    def annealed():
+        g = pa.PARun(D, L, R, seed=5, run_id=0)
+        for i in range(1, 21):
+            g.reweight(beta_c * i / 20, wait=False)
+            g.resample(3, wait=False)
+            g.sweep(2)
+        return g
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        fn()
+        e1.record(st)
+        e1.synchronize()
+        return e0.elapsed_time(e1)
+
+    out = {"workload": f"2D Ising FM L={L}, R={R}, beta={beta_c} after 20 annealing steps (theta=2), "
+                       "one run per driver from the same seed"}
+    corr = {}
+    for name in ("cluster", "metropolis"):
+        g = annealed()
+        step = g.cluster if name == "cluster" else g.sweep
+        step(1)  # warm
+        out[f"ms_per_{name}_update"] = min(timed(lambda: step(5)) for _ in range(3)) / 5
+        s0 = g.export()
+        E0 = s0["energy"].astype(np.float64)
+        m0 = np.abs(s0["magnetization"]).astype(np.float64)
+        ce, cm = [], []
+        for k in range(1, updates + 1):
+            step(1)
+            sk = g.export()
+            if k == 1:
+                flips = np.unpackbits((s0["spins"] ^ sk["spins"]).view(np.uint8)).sum()
+                out[f"{name}_mean_flipped_fraction"] = float(flips) / (R * L ** D)
+            ce.append(float(np.corrcoef(E0, sk["energy"].astype(np.float64))[0, 1]))
+            cm.append(float(np.corrcoef(m0, np.abs(sk["magnetization"]).astype(np.float64))[0, 1]))
+        corr[name] = {"energy": ce, "abs_m": cm}
+        g.close()
+    out["autocorrelation_after_k_updates"] = corr
+    out["cluster_flipped_spins_per_ns"] = (out["cluster_mean_flipped_fraction"] * R * L ** D
+                                           / (out["ms_per_cluster_update"] * 1e6))
+    return out
+
+
 def rmsd_study(L=64, R=20000, theta=2, runs=500):
     """Fig. 8's workload: 500 seeded runs of the 2D FM L = 64, R = 2 10^4,
     theta = 2, beta_i = i/300 to 0.6, systematic, one batched anneal; groups of
@@ -755,6 +810,7 @@ def main():
         out["conditional"] = conditional_study()
         out["scheme_errors"] = scheme_error_study()
         out["rmsd"] = rmsd_study()
+        out["cluster"] = cluster_study()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
