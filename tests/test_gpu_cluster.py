@@ -17,7 +17,8 @@ pytestmark = pytest.mark.gpu
                                                 (2, 6, 200, True, O.POISSON),
                                                 (2, 16, 130, False, O.NEAREST_INT),
                                                 (3, 4, 130, True, O.MULTINOMIAL),
-                                                (3, 6, 70, False, O.SYSTEMATIC)])
+                                                (3, 6, 70, False, O.SYSTEMATIC),
+                                                (3, 16, 70, True, O.SYSTEMATIC)])
 def test_cluster_anneal_matches_oracle(d, L, R, glass, scheme):
     from paper_2401_07965_amd import pa
     J = ea_couplings(d, L, 3) if glass else None
