@@ -179,8 +179,9 @@ pa_status pa_sweep(pa_ctx *ctx, int32_t theta);
  * cluster flips.  t counts sweeps and cluster updates together within step i
  * (at most 2^20).  Energies and magnetisations are recounted afterwards.
  * PA_E_INVAL if nsteps < 0, if the step's updates would pass 2^20, or if a
- * lattice needs more LDS per workgroup than the device has (4 N 8 bytes, plus
- * N with couplings: N <= 5120 on 160 KiB).  Enqueued on the run's stream. */
+ * lattice needs more LDS per workgroup than the device has (4 N 8 bytes and
+ * 24 KiB of queues, plus N with couplings: N <= 4352, or 4220 with
+ * couplings, on 160 KiB).  Enqueued on the run's stream. */
 pa_status pa_cluster(pa_ctx *ctx, int32_t nsteps);
 
 /* Step 2 of Sec. 2: for beta_next >= beta, ln Q of Eq. (1) over the current

@@ -814,12 +814,75 @@ __device__ __forceinline__ uint64_t wolff_bond(const PlaneCtx &pc, uint32_t owne
     return acc;
 }
 
+// Bond decisions are batched per wave: a site's candidate bonds (site,
+// direction k = 2 mu + [towards -e_mu], candidate replicas) go to a queue
+// and are decided 64 at a time, one per lane, so that a decision does not
+// run a whole wave for the one lane that needs it.
+constexpr int kClusterQueue = 128; // per wave; never more than 127 items are live
+// Lanes of a cluster-update workgroup: one workgroup per CU fits in LDS, so
+// its waves are all the latency hiding there is.
+constexpr int kClusterThreads = 1024;
+
+struct ClusterQueue {
+    uint32_t *sk;  // site | k << 16
+    uint64_t *cnd; // candidate replicas
+};
+
+__device__ __forceinline__ uint32_t cluster_push(const ClusterQueue &Q, uint32_t head, uint32_t cnt, bool has,
+                                                 uint32_t sk, uint64_t cnd)
+{
+    const uint64_t bal = __ballot(has);
+    if (has) {
+        const uint32_t slot = (head + cnt + (uint32_t)__popcll(bal & lanemask_lt())) & (kClusterQueue - 1);
+        Q.sk[slot] = sk;
+        Q.cnd[slot] = cnd;
+    }
+    __builtin_amdgcn_wave_barrier();
+    return cnt + (uint32_t)__popcll(bal);
+}
+
+// Decides up to 64 queued bonds and adds the replicas they join to Fn[site].
+template <int D>
+__device__ __forceinline__ void cluster_pass(const ClusterQueue &Q, const PlaneCtx &pc, uint64_t T, uint64_t *Fn,
+                                             int L, int LL, uint32_t mL, uint32_t &head, uint32_t &cnt)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t n = cnt < 64u ? cnt : 64u;
+    const bool act = lane < n;
+    uint32_t sk = 0;
+    uint64_t cnd = 0;
+    if (act) {
+        const uint32_t slot = (head + lane) & (kClusterQueue - 1);
+        sk = Q.sk[slot];
+        cnd = Q.cnd[slot];
+    }
+    __builtin_amdgcn_wave_barrier();
+    head += n;
+    cnt -= n;
+    if (act) {
+        const int s = (int)(sk & 0xFFFFu), k = (int)(sk >> 16), mu = k >> 1;
+        const int row = (int)__umulhi((uint32_t)s, mL);
+        const int x = s - row * L;
+        const int z = (D == 2) ? 0 : (int)__umulhi((uint32_t)row, mL);
+        const int y = row - z * L;
+        const int c = mu == 0 ? x : (mu == 1 ? y : z);
+        const int st = mu == 0 ? 1 : (mu == 1 ? L : LL);
+        // bond (s, mu) to s + e_mu is owned by s, bond (s - e_mu, mu) by s - e_mu
+        const int owner = (k & 1) ? (c == 0 ? s + st * (L - 1) : s - st) : s;
+        const uint64_t a = wolff_bond(pc, (uint32_t)owner, (uint32_t)mu, cnd, T);
+        if (a)
+            atomicOr((unsigned long long *)&Fn[s], (unsigned long long)a);
+    }
+}
+
 template <int D, bool J>
-__global__ __launch_bounds__(kThreads) void k_cluster(const PaRunDesc *__restrict__ runs,
+__global__ __launch_bounds__(kClusterThreads) void k_cluster(const PaRunDesc *__restrict__ runs,
                                                       const PaBlk *__restrict__ map, int nsteps, uint32_t t0)
 {
     // dynamic LDS: lattice [N] | cluster C [N] | frontiers F0, F1 [N] (at
-    // least 32 per wave in all, reused by the recount) | jmask [N] bytes
+    // least 32 per wave in all, reused by the recount) | queue candidates
+    // [waves][kClusterQueue] u64 | queue sites [waves][kClusterQueue] u32 |
+    // jmask [N] bytes
     extern __shared__ uint64_t lat[];
     const PaBlk blk = map[blockIdx.x];
     const PaRunDesc &rd = runs[blk.run];
@@ -832,8 +895,11 @@ __global__ __launch_bounds__(kThreads) void k_cluster(const PaRunDesc *__restric
     const int cur = uni(rec->cur);
     const int tid = threadIdx.x, bs = blockDim.x;
     uint64_t *C = lat + N, *F0 = C + N, *F1 = F0 + N;
-    const int nred = 3 * N > 32 * (bs >> 6) ? 3 * N : 32 * (bs >> 6);
-    uint8_t *jl = reinterpret_cast<uint8_t *>(lat + N + nred);
+    const int nw = bs >> 6, nred = 3 * N > 32 * nw ? 3 * N : 32 * nw;
+    uint64_t *qc = lat + N + nred;                                        // [waves][kClusterQueue]
+    uint32_t *qs = reinterpret_cast<uint32_t *>(qc + nw * kClusterQueue); // [waves][kClusterQueue]
+    uint8_t *jl = reinterpret_cast<uint8_t *>(qs + nw * kClusterQueue);
+    const ClusterQueue Q = {qs + (tid >> 6) * kClusterQueue, qc + (tid >> 6) * kClusterQueue};
     uint64_t *g = rd.dv.spins[cur] + (size_t)w * N;
     for (int s = tid; s < N; s += bs) {
         lat[s] = g[s];
@@ -867,38 +933,45 @@ __global__ __launch_bounds__(kThreads) void k_cluster(const PaRunDesc *__restric
         uint64_t *Fc = F0, *Fn = F1;
         // every pass that continues adds a (site, replica) pair: at most 64 N
         for (int pass = 0; pass <= 64 * N; ++pass) {
-            int any = 0;
-            for (int s = tid; s < N; s += bs) {
-                const int row = (int)__umulhi((uint32_t)s, mL);
-                const int x = s - row * L;
+            for (int s = tid; s < N; s += bs)
+                Fn[s] = 0;
+            __builtin_amdgcn_wave_barrier(); // a wave's queue only adds to its own sites
+            uint32_t head = 0, cnt = 0;
+            for (int kb = 0; kb < N; kb += bs) {
+                const int s = kb + tid;
+                const bool in = s < N;
+                const int t = in ? s : 0;
+                const int row = (int)__umulhi((uint32_t)t, mL);
+                const int x = t - row * L;
                 const int z = (D == 2) ? 0 : (int)__umulhi((uint32_t)row, mL);
                 const int y = row - z * L;
-                const uint32_t jb = J ? (uint32_t)jl[s] : 0u;
-                const uint64_t S = lat[s], cs = C[s];
-                uint64_t add = 0;
+                const uint32_t jb = J ? (uint32_t)jl[t] : 0u;
+                const uint64_t S = lat[t], cs = C[t];
 #pragma unroll
-                for (int mu = 0; mu < D; ++mu) {
+                for (int k = 0; k < 2 * D; ++k) {
+                    const int mu = k >> 1;
                     const int c = mu == 0 ? x : (mu == 1 ? y : z);
                     const int st = mu == 0 ? 1 : (mu == 1 ? L : LL);
-                    const int up = c == L - 1 ? s - st * (L - 1) : s + st;
-                    const int dn = c == 0 ? s + st * (L - 1) : s - st;
-                    // bond (s, mu) to up, owned by s; bond (dn, mu) to s, owned by dn
-                    uint64_t f = Fc[up] & ~cs;
-                    if (f) {
-                        const uint64_t cnd = f & ~bond<J>(S, lat[up], jb, mu);
-                        if (cnd)
-                            add |= wolff_bond(pc, (uint32_t)s, (uint32_t)mu, cnd, T);
-                    }
-                    f = Fc[dn] & ~cs;
-                    if (f) {
-                        const uint64_t cnd = f & ~bond<J>(S, lat[dn], jb, D + mu);
-                        if (cnd)
-                            add |= wolff_bond(pc, (uint32_t)dn, (uint32_t)mu, cnd, T);
-                    }
+                    const int nb = (k & 1) ? (c == 0 ? t + st * (L - 1) : t - st)
+                                           : (c == L - 1 ? t - st * (L - 1) : t + st);
+                    // the replicas newly added at the neighbour, not yet here,
+                    // across a satisfied bond (coupling bit mu or D + mu)
+                    uint64_t cnd = in ? Fc[nb] & ~cs : 0;
+                    if (cnd)
+                        cnd &= ~bond<J>(S, lat[nb], jb, (k & 1) ? D + mu : mu);
+                    cnt = cluster_push(Q, head, cnt, cnd != 0, (uint32_t)t | ((uint32_t)k << 16), cnd);
+                    while (cnt >= 64u)
+                        cluster_pass<D>(Q, pc, T, Fn, L, LL, mL, head, cnt);
                 }
-                add &= ~cs;
+            }
+            while (cnt > 0u)
+                cluster_pass<D>(Q, pc, T, Fn, L, LL, mL, head, cnt);
+            __builtin_amdgcn_wave_barrier();
+            int any = 0;
+            for (int s = tid; s < N; s += bs) {
+                const uint64_t add = Fn[s] & ~C[s];
                 if (add) {
-                    C[s] = cs | add;
+                    C[s] |= add;
                     any = 1;
                 }
                 Fn[s] = add;
@@ -2389,8 +2462,8 @@ size_t pa_sweep_lds_bytes(int N, int d, int threads, bool J)
 
 size_t pa_cluster_lds_bytes(int N, bool J)
 {
-    const size_t nred = (size_t)3 * N > (size_t)32 * (kThreads / 64) ? (size_t)3 * N : (size_t)32 * (kThreads / 64);
-    return ((size_t)N + nred) * 8 + (J ? (((size_t)N + 7) & ~(size_t)7) : 0);
+    const size_t nw = kClusterThreads / 64, nred = (size_t)3 * N > 32 * nw ? (size_t)3 * N : 32 * nw;
+    return ((size_t)N + nred) * 8 + nw * kClusterQueue * (8 + 4) + (J ? (((size_t)N + 7) & ~(size_t)7) : 0);
 }
 
 hipError_t pa_b_cluster(const PaBatchView &v, int nsteps, uint32_t t0)
@@ -2400,13 +2473,13 @@ hipError_t pa_b_cluster(const PaBatchView &v, int nsteps, uint32_t t0)
             continue;
         const size_t lds = pa_cluster_lds_bytes(v.gN[g], v.gJ[g] != 0);
         if (v.gd[g] == 2 && v.gJ[g])
-            k_cluster<2, true><<<v.gncol[g], kThreads, lds, v.stream>>>(v.runs, v.gcol[g], nsteps, t0);
+            k_cluster<2, true><<<v.gncol[g], kClusterThreads, lds, v.stream>>>(v.runs, v.gcol[g], nsteps, t0);
         else if (v.gd[g] == 2)
-            k_cluster<2, false><<<v.gncol[g], kThreads, lds, v.stream>>>(v.runs, v.gcol[g], nsteps, t0);
+            k_cluster<2, false><<<v.gncol[g], kClusterThreads, lds, v.stream>>>(v.runs, v.gcol[g], nsteps, t0);
         else if (v.gJ[g])
-            k_cluster<3, true><<<v.gncol[g], kThreads, lds, v.stream>>>(v.runs, v.gcol[g], nsteps, t0);
+            k_cluster<3, true><<<v.gncol[g], kClusterThreads, lds, v.stream>>>(v.runs, v.gcol[g], nsteps, t0);
         else
-            k_cluster<3, false><<<v.gncol[g], kThreads, lds, v.stream>>>(v.runs, v.gcol[g], nsteps, t0);
+            k_cluster<3, false><<<v.gncol[g], kClusterThreads, lds, v.stream>>>(v.runs, v.gcol[g], nsteps, t0);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
