@@ -1,17 +1,25 @@
 #!/usr/bin/env python3
 """Throughput of the population-annealing hot path on one MI355X.
 
-Workload (the 2D resampling-scheme study): 2D Ising ferromagnet, L = 64
-periodic, target population R = 10^5, theta = 10 checkerboard Metropolis
-sweeps per temperature, beta_i = 0.6 i / 200 (201 points), run once with each
-of the four resampling schemes (multinomial, Poisson, nearest integer,
-systematic; run_id = scheme index, seed 1).  Synthetic lattices, seeded.
+Headline workload (the largest single-run configuration, the learned-schedule
+study's system): 3D +-J Edwards-Anderson spin glass, L = 16 periodic
+(N = 4096), couplings -1 with probability 1/2 from seed 1, target population
+R = 10^6 replicas (15 625 words of 64), theta = 10 checkerboard Metropolis
+sweeps per temperature, beta_i = 3 i / 300 (301 points), systematic
+resampling, seed 1, run_id 0.  Synthetic, seeded.
 
-One step = one temperature step of all four runs: reweight (Q of Eq. (1)),
-resample (copy numbers, prefix sums, gather), theta sweeps, observables.
-The runs are independent and each has its own stream, so their kernels
-overlap.  ``value`` = spin-flip attempts (theta N R_i summed over the runs)
-per ns of wall time over the timed steps, inputs resident in HBM throughout.
+One step = one temperature step of the run: reweight (Q of Eq. (1)),
+resample (copy numbers, prefix sums, gather), theta sweeps, observables, all
+enqueued without a host wait on the run's stream.  ``value`` = spin-flip
+attempts (theta N R_i, from the device's own counters) per ns of wall time
+over the timed steps, inputs resident in HBM throughout.
+
+Beside the headline: the sweep kernel's roofline (its rate against the
+Philox-generation bound, the binding ceiling, and its HBM rate), the whole
+anneal, the other workloads (2D ferromagnet with the four schemes and their
+free-energy errors against the exact partition function; two 3D glass
+populations with ln Q per step and P(q); the uneven batch; the learned
+schedule at equal free-energy error) and the paper's figure studies.
 
 Prints one JSON line.  Only one GPU is used; --gpus above 1 is refused.
 """
@@ -26,27 +34,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-D, L, R, THETA, BETA_F, POINTS, SEED = 2, 64, 100000, 10, 0.6, 201, 1
+# headline workload: 3D +-J glass L = 16, R = 10^6
+D, L, R, THETA, BETA_F, POINTS, SEED, COUPLING_SEED = 3, 16, 1000000, 10, 3.0, 301, 1, 1
+SCHEME = 3  # systematic
 SCHEMES = (("multinomial", 0), ("poisson", 1), ("nearest", 2), ("systematic", 3))
 
-# Roofline of the sweep kernel (integer VALU bound).
-# peak = 256 CUs x 64 int32 lanes/clock x 2.4 GHz.  The achieved rate counts
-# the fewest 32-bit lane operations known to do the 2D ferromagnet sweep's
-# work on gfx950 (three-input bitwise ops), per 64-bit word as two halves:
-# each Philox4x32-10 call is 10 rounds of two 32x32->64 multiplies and two
-# three-input xors (40); consuming its two bit planes for a 64-replica word is
-# 2 planes x 2 halves x (threshold select 1 + accept 1 + undecided 1) plus
-# merging the pair's acceptances (2) = 14; a word-site update is the two pair
-# sums and two carries of the bonds from the neighbour words (4 x 2), the
-# classes u >= 2 and u = 1 and their shared carry (3 x 2) and the flip (2) = 16.
-PEAK_INT_OPS = 256 * 64 * 2.4e9
-OPS_PER_PHILOX = 40 + 14   # generate a plane pair and decide 64 replicas on it
-OPS_PER_SITE_UPDATE = 16   # 2D, no couplings
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
+PEAK_INT_OPS = 256 * 64 * 2.4e9  # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, int32 lane-ops/s
+OPS_PER_PHILOX = 40              # 10 rounds x (2 wide multiplies + 2 three-input xors)
 
+# Op model (a lower-bound instruction price, reported beside the roofline):
+# per Philox call, generating its two planes (40) and deciding the 64
+# replicas of a word on them: per plane and half-word a class-threshold
+# select (2 three-input ops in 3D, 1 in 2D), the acceptance and the
+# undecided update (2), then merging the pair's acceptances (2); per
+# word-site update the bonds, the energy-change classes and the flip.
+OP_MODEL = {
+    "3d_pmj": {"per_philox": 40 + 2 * 2 * (2 + 2) + 2, "per_site_update": 6 * 3 + 26 + 2},
+    "2d_fm": {"per_philox": 40 + 2 * 2 * (1 + 2) + 2, "per_site_update": 16},
+}
 
-COUNTER_PROFILE = os.path.join(ROOT, "profiles", "k_sweep_2d_L64_R1e5_counters.md")
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+COUNTER_PROFILES = {
+    "config5": os.path.join(PROFILE_DIR, "k_sweep_3d_pmj_L16_R1e6_counters.md"),
+    "config3": os.path.join(PROFILE_DIR, "k_sweep_3d_pmj_L10_R5e5_counters.md"),
+    "config2": os.path.join(PROFILE_DIR, "k_sweep_2d_fm_L64_R1e5_counters.md"),
+}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2401_07965_amd", "csrc", f)
                   for f in ("pa_kernels.hip", "pa_device.h", "pa_internal.h")]
+KAUFMAN_L64 = os.path.join(ROOT, "tests", "golden", "kaufman_2d_L64.json")
 
 
 def code_only(text):
@@ -68,14 +84,14 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def profiled_counters():
-    """HBM traffic and VALU figures of the sweep from the committed counter
-    profile, or None when the kernel sources changed since it was taken."""
+def profiled_counters(which):
+    """The machine-readable figures of a committed counter profile, or None
+    when the kernel sources changed since it was taken."""
     import re
     try:
-        with open(COUNTER_PROFILE) as fh:
+        with open(COUNTER_PROFILES[which]) as fh:
             text = fh.read()
-    except OSError:
+    except (OSError, KeyError):
         return None
     vals = dict(re.findall(r"^- (\w+): (\S+)\s*$", text, re.M))
     if vals.get("kernel_source_sha256") != kernel_source_hash():
@@ -83,154 +99,161 @@ def profiled_counters():
     return vals
 
 
-def betas():
-    return [i * BETA_F / (POINTS - 1) for i in range(POINTS)]
+def schedule(beta_f=BETA_F, points=POINTS):
+    return [i * beta_f / (points - 1) for i in range(points)]
 
 
-def make_runs(pa, streams=None):
-    """The four runs; each on its own stream when streams are given (the runs are
-    independent, so one run's small resampling kernels overlap another's sweep)."""
-    streams = streams or [None] * len(SCHEMES)
-    return [pa.PARun(D, L, R, seed=SEED, run_id=rid, stream=st) for (_, rid), st in zip(SCHEMES, streams)]
+def headline_couplings():
+    from paper_2401_07965_amd import workloads
+    return workloads.pm_j_couplings(D, L, COUPLING_SEED)
 
 
-def gpu_bench(steps, warmup):
-    """Times `steps` temperature steps of the four runs, each run on its own
-    stream.  Every call inside the timed region is deferred (nothing waits for
-    the device); the sweep and the reweight + resample of each run are
-    bracketed by HIP events on the run's stream.  Launches of different runs
-    overlap, so kernel time is the union of those intervals over the four
-    streams (the time during which that kernel was running).  Attempts and
-    work counters come from the device records."""
+def union_length(intervals):
+    """Total length of the union of (start, end) intervals."""
+    tot, cur_a, cur_b = 0.0, None, None
+    for a, b in sorted(intervals):
+        if cur_b is None or a > cur_b:
+            if cur_b is not None:
+                tot += cur_b - cur_a
+            cur_a, cur_b = a, b
+        else:
+            cur_b = max(cur_b, b)
+    if cur_b is not None:
+        tot += cur_b - cur_a
+    return tot
+
+
+def resample_bytes(N, R_old, R_new):
+    """Algorithmic HBM bytes of reweighting and resampling: per old replica the
+    energy read and the copy number / offset writes and reads (20 B); per new
+    replica its spins read and written (2 N/8 B) plus energy, magnetisation and
+    label read and written and the ancestor read (28 B)."""
+    return R_old * (4 + 4 + 4 + 4 + 4) + R_new * (2 * N / 8 + 3 * 4 * 2 + 4)
+
+
+def sweep_bytes(N, words):
+    """Algorithmic HBM bytes of one sweep launch over `words` 64-replica
+    columns: each column's spins read once and written once (the theta sweeps
+    run in LDS), and every replica's energy and magnetisation written."""
+    return words * (2 * N * 8 + 64 * 8)
+
+
+class Step:
+    """Deferred temperature steps of one run on its stream, with HIP events
+    around its reweight + resample and its sweep (the stream the kernels run
+    on: torch.cuda.Event records on the stream it is given)."""
+
+    def __init__(self, make_run, sched, stream):
+        self.make_run, self.sched, self.stream = make_run, sched, stream
+        self.run = make_run()
+        self.i = 0
+        self.closed = {"philox_calls": 0, "site_updates": 0, "spin_attempts": 0}
+        self.restarts = 0
+
+    def __call__(self, events=None):
+        import torch
+        i = self.i + 1
+        if i == len(self.sched):  # anneal finished: start the next one (step 1 of the method)
+            c = self.run.counters()
+            for k in self.closed:
+                self.closed[k] += c[k]
+            self.run.close()
+            self.run = self.make_run()
+            self.restarts += 1
+            i = 1
+        self.i = i
+        g = self.run
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)] if events is not None else None
+        if ev:
+            ev[0].record(self.stream)
+        g.reweight(self.sched[i], wait=False)
+        g.resample(SCHEME, wait=False)
+        if ev:
+            ev[1].record(self.stream)
+        g.sweep(THETA)
+        if ev:
+            ev[2].record(self.stream)
+        g.observables(wait=False)
+        if ev:
+            events.append((i, ev))
+
+    def totals(self):
+        c = self.run.counters()
+        return {k: self.closed[k] + c[k] for k in self.closed}
+
+
+def make_headline_run(stream):
+    from paper_2401_07965_amd import pa
+    J = headline_couplings()
+    return lambda: pa.PARun(D, L, R, seed=SEED, run_id=0, couplings=J, stream=stream)
+
+
+def headline_bench(steps, warmup):
+    """The timed region: `steps` temperature steps of the headline run after
+    `warmup` untimed ones, bracketed by device synchronisations.  Sweep and
+    resampling kernel times come from HIP events on the run's stream; the
+    counts of attempts, Philox evaluations and word-site updates from the
+    device records."""
     import torch
     from paper_2401_07965_amd import pa
     pa.lib()
-    sched = betas()
-    streams = [torch.cuda.Stream() for _ in SCHEMES]  # default priority
-    state = {"i": 0, "runs": make_runs(pa, streams)}
-    keys = ("philox_calls", "site_updates", "spin_attempts")
-    done = dict.fromkeys(keys, 0)  # counters of runs closed inside the window
-    Rsum = {"start": 0, "end": 0}
-
-    def one_step(acc):
-        i = state["i"] + 1
-        if i == POINTS:  # anneal finished: start the next anneal (step 1 of the method)
-            for g in state["runs"]:
-                if acc is not None:
-                    c = g.counters()
-                    for k in keys:
-                        done[k] += c[k]
-                    Rsum["end"] += g.observables()["R"]
-                g.close()
-            state["runs"] = make_runs(pa, streams)
-            if acc is not None:
-                Rsum["start"] += R * len(SCHEMES)
-            i = 1
-        state["i"] = i
-        for (name, rid), g, stream in zip(SCHEMES, state["runs"], streams):
-            if acc is None:
-                g.reweight(sched[i], wait=False)
-                g.resample(rid, wait=False)
-                g.sweep(THETA)
-                g.observables(wait=False)
-                continue
-            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-            ev[0].record(stream)
-            g.reweight(sched[i], wait=False)
-            g.resample(rid, wait=False)
-            ev[1].record(stream)
-            g.sweep(THETA)
-            ev[2].record(stream)
-            g.observables(wait=False)
-            acc.append(ev)
-
+    stream = torch.cuda.Stream()  # default priority
+    step = Step(make_headline_run(stream), schedule(), stream)
     for _ in range(warmup):
-        one_step(None)
-    base = [g.counters() for g in state["runs"]]  # synchronises; raises if a run failed
-    Rsum["start"] += sum(g.observables()["R"] for g in state["runs"])
-    acc = []
+        step()
+    base = step.totals()  # synchronises; raises if the run failed
+    ev = []
     torch.cuda.synchronize()
-    ref = torch.cuda.Event(enable_timing=True)
-    ref.record(streams[0])
     t0 = time.perf_counter()
     for _ in range(steps):
-        one_step(acc)
+        step(ev)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    tot = dict(done)
-    for g in state["runs"]:
-        c = g.counters()
-        for k in keys:
-            tot[k] += c[k]
-        Rsum["end"] += g.observables()["R"]
-    # counters of the runs alive at the window start count from their values then
-    for b in base:
-        for k in keys:
-            tot[k] -= b[k]
-    sweep_iv = [(ref.elapsed_time(e[1]), ref.elapsed_time(e[2])) for e in acc]
-    resample_iv = [(ref.elapsed_time(e[0]), ref.elapsed_time(e[1])) for e in acc]
-    iso = isolated_steps(state, streams, sched, ISO_STEPS)
-    for g in state["runs"]:
-        g.close()
-    attempts = tot["spin_attempts"]
-    new_replicas = attempts // (THETA * L ** D)
-    # replicas before each resampling: the new ones, shifted by one step
-    old_replicas = new_replicas + Rsum["start"] - Rsum["end"]
-    return dict(elapsed=elapsed, attempts=attempts, sweep_ms=[b - a for a, b in sweep_iv], iso=iso,
-                sweep_union_s=union_length(sweep_iv) / 1e3, calls=tot["philox_calls"],
-                updates=tot["site_updates"], resample_s=union_length(resample_iv) / 1e3,
-                resample_bytes=resample_bytes(old_replicas, new_replicas))
+    tot = step.totals()
+    d = {k: tot[k] - base[k] for k in tot}
+    sweep_ms = [e[1].elapsed_time(e[2]) for _, e in ev]
+    res_ms = [e[0].elapsed_time(e[1]) for _, e in ev]
+    words = d["site_updates"] // (THETA * L ** D)  # 64-replica columns swept
+    step.run.close()
+    return dict(elapsed=elapsed, attempts=d["spin_attempts"], calls=d["philox_calls"],
+                updates=d["site_updates"], words=words, sweep_ms=sweep_ms, res_ms=res_ms,
+                res_bytes=steps * resample_bytes(L ** D, R, R), restarts=step.restarts,
+                beta_range=[schedule()[ev[0][0]], schedule()[ev[-1][0]]] if ev else None)
 
 
-ISO_STEPS = 6
-
-
-def isolated_steps(state, streams, sched, nsteps):
-    """After the timed region (untimed): `nsteps` more steps with one run at a
-    time on the device, HIP events around its reweight + resample and its
-    sweep.  Gives the per-launch sweep time and the resampling rate without
-    the other runs' kernels alongside.  On every other step a gate kernel
-    (the generator probe, a few hundred us) runs first on the stream, so that
-    the whole reweight + resample is queued before its first kernel starts:
-    the rate of the kernels themselves ("pre-queued"); on the others the host
-    issues the launches while the device runs them ("host-paced")."""
+def anneal_row():
+    """One whole anneal of the headline workload (300 steps, deferred calls,
+    one synchronisation at the end): wall time, attempts per ns, and the sweep
+    kernel's rate (HIP events) in windows of beta."""
     import torch
-    from paper_2401_07965_amd import pa
-    gate = torch.empty(1 << 20, dtype=torch.int32, device="cuda")
-    sweep_ms, attempts = [], 0
-    res = {True: [0.0, 0.0], False: [0.0, 0.0]}  # pre-queued?: [ms, bytes]
-    i = state["i"]
-    for k in range(nsteps):
-        i += 1
-        if i == POINTS:
-            break
-        queued = k % 2 == 0
-        for (name, rid), g, stream in zip(SCHEMES, state["runs"], streams):
-            R_old = g.observables()["R"]
-            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-            if queued:
-                pa.philox_probe(gate, 128, stream)
-            ev[0].record(stream)
-            g.reweight(sched[i], wait=False)
-            g.resample(rid, wait=False)
-            ev[1].record(stream)
-            g.sweep(THETA)
-            ev[2].record(stream)
-            R_new = g.observables()["R"]  # waits for the stream
-            res[queued][0] += ev[0].elapsed_time(ev[1])
-            res[queued][1] += resample_bytes(R_old, R_new)
-            sweep_ms.append(ev[1].elapsed_time(ev[2]))
-            attempts += THETA * L ** D * R_new
-    if not sweep_ms:
-        return None
-
-    def rate(q):
-        return res[q][1] / (res[q][0] * 1e-3) / 1e9 if res[q][0] > 0 else None
-    return {"steps": len(sweep_ms) // len(SCHEMES),
-            "sweep_attempts_per_ns": attempts / (sum(sweep_ms) * 1e-3) / 1e9,
-            "sweep_avg_launch_ms": sum(sweep_ms) / len(sweep_ms),
-            "resample_GB_per_s": rate(True),
-            "resample_GB_per_s_host_paced": rate(False)}
+    stream = torch.cuda.Stream()
+    step = Step(make_headline_run(stream), schedule(), stream)
+    ev = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(POINTS - 1):
+        step(ev)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tot = step.totals()
+    lnZ = step.run.free_energy()
+    obs = step.run.observables()
+    step.run.close()
+    att_step = THETA * L ** D * R  # systematic resampling keeps R
+    windows = {}
+    for lo in (0.0, 0.5, 1.0, 1.5, 2.0, 2.5):
+        ms = [e[1].elapsed_time(e[2]) for i, e in ev if lo < schedule()[i] <= lo + 0.5 + 1e-12]
+        windows[f"({lo:.1f},{lo + 0.5:.1f}]"] = att_step * len(ms) / (sum(ms) * 1e-3) / 1e9
+    sweep_total_ms = sum(e[1].elapsed_time(e[2]) for _, e in ev)
+    res_total_ms = sum(e[0].elapsed_time(e[1]) for _, e in ev)
+    return {"workload": "the headline workload, one whole anneal beta 0 -> 3 (300 steps)",
+            "wall_s": wall, "attempts_per_ns": tot["spin_attempts"] / wall / 1e9,
+            "sweep_attempts_per_ns": tot["spin_attempts"] / (sweep_total_ms * 1e-3) / 1e9,
+            "sweep_attempts_per_ns_by_beta": windows,
+            "sweep_share_of_wall": sweep_total_ms * 1e-3 / wall,
+            "resample_GB_per_s": resample_bytes(L ** D, R, R) * (POINTS - 1) / (res_total_ms * 1e-3) / 1e9,
+            "philox_calls_per_attempt": tot["philox_calls"] / (64.0 * tot["site_updates"]),
+            "lnZ_per_spin_final": lnZ / L ** D, "e_final": obs["e"]}
 
 
 def philox_rate():
@@ -254,28 +277,144 @@ def philox_rate():
     return out.numel() * 3 * iters / (best * 1e-3)
 
 
-def union_length(intervals):
-    """Total length of the union of (start, end) intervals."""
-    tot, cur_a, cur_b = 0.0, None, None
-    for a, b in sorted(intervals):
-        if cur_b is None or a > cur_b:
-            if cur_b is not None:
-                tot += cur_b - cur_a
-            cur_a, cur_b = a, b
-        else:
-            cur_b = max(cur_b, b)
-    if cur_b is not None:
-        tot += cur_b - cur_a
-    return tot
+def sweep_roofline(kernel, N, attempts, calls, updates, words, launch_ms, rate, model, profile):
+    """Roofline of one sweep kernel.  The sweep is bound by integer VALU work,
+    and within it by generating the random bits its decisions need (Philox
+    calls counted by the kernel, equal to the oracle's count): the binding
+    ceiling is the device's measured Philox rate divided by the calls per
+    attempt.  achieved = attempts per launch / mean launch time (HIP events);
+    the HBM rate and an instruction-price model are reported beside it."""
+    n = len(launch_ms)
+    t = sum(launch_ms) * 1e-3
+    cpa = calls / (64.0 * updates)
+    achieved = attempts / t / 1e9
+    peak = rate / cpa / 1e9
+    hbm = sweep_bytes(N, words / n) * n / t / 1e9
+    ops = OP_MODEL[model]["per_philox"] * calls + OP_MODEL[model]["per_site_update"] * updates
+    out = {
+        "kernel": kernel, "bound": "alu", "achieved": achieved, "peak": peak, "unit": "attempts/ns",
+        "frac": achieved / peak,
+        "peak_basis": "measured Philox4x32-10 calls/ns (pa_philox_probe) / Philox calls per attempt "
+                      "of these launches",
+        "philox_calls_per_ns": rate / 1e9, "philox_calls_per_attempt": cpa,
+        "philox_calls_per_ns_chip": PEAK_INT_OPS / OPS_PER_PHILOX / 1e9,
+        "attempts_per_launch": attempts / n, "avg_launch_ms": sum(launch_ms) / n, "launches": n,
+        "hbm": {"achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm / HBM_PEAK_GBS,
+                "algorithmic_bytes_per_launch": sweep_bytes(N, words / n)},
+        "op_model": {"ops_per_philox_call": OP_MODEL[model]["per_philox"],
+                     "ops_per_site_update": OP_MODEL[model]["per_site_update"],
+                     "achieved_Tops": ops / t / 1e12, "peak_Tops": PEAK_INT_OPS / 1e12,
+                     "frac": ops / t / PEAK_INT_OPS},
+        "traffic": None,
+    }
+    if profile:
+        out["traffic"] = float(profile["traffic_bytes_per_launch"])
+        out["traffic_unit"] = "bytes/launch"
+        out["valu_busy"] = float(profile["valu_busy"])
+        out["counter_profile"] = os.path.relpath(profile["path"], ROOT)
+    return out
 
 
-def resample_bytes(R_old, R_new):
-    """Algorithmic HBM bytes of reweighting and resampling: per
-    old replica the energy read and the copy number / offset writes and reads;
-    per new replica the spins read and written (2 N/8 bytes) plus energy,
-    magnetisation and label read and written."""
-    N = L ** D
-    return R_old * (4 + 4 + 4 + 4 + 4) + R_new * (2 * N / 8 + 3 * 4 * 2 + 4)
+def config2_row(steps_timed=None):
+    """2D Ising ferromagnet L = 64, R = 10^5, theta = 10, beta_i = 0.6 i/200
+    (201 points), one run per resampling scheme (run_id = scheme, seed 1),
+    each on its own stream: one whole anneal of the four runs (deferred
+    calls), its rate and the sweep kernel's (union of its HIP-event intervals
+    over the four streams); then per scheme ln Z_hat at beta = 0.6 against
+    the exact finite-lattice value (Kaufman), with e, |m|, family entropy and
+    rho_t."""
+    import torch
+    from paper_2401_07965_amd import pa
+    d2, L2, R2, bf, pts = 2, 64, 100000, 0.6, 201
+    sched = schedule(bf, pts)
+    streams = [torch.cuda.Stream() for _ in SCHEMES]
+    runs = [pa.PARun(d2, L2, R2, seed=1, run_id=rid, stream=st) for (_, rid), st in zip(SCHEMES, streams)]
+    ev = []
+    torch.cuda.synchronize()
+    ref = torch.cuda.Event(enable_timing=True)
+    ref.record(streams[0])
+    t0 = time.perf_counter()
+    for i in range(1, pts):
+        for (name, rid), g, st in zip(SCHEMES, runs, streams):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            g.reweight(sched[i], wait=False)
+            g.resample(rid, wait=False)
+            e[0].record(st)
+            g.sweep(THETA)
+            e[1].record(st)
+            g.observables(wait=False)
+            ev.append(e)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    with open(KAUFMAN_L64) as f:
+        exact = {p["i"]: p for p in json.load(f)["points"]}[pts - 1]
+    N2 = L2 * L2
+    attempts, calls, updates, by = 0, 0, 0, {}
+    for (name, rid), g in zip(SCHEMES, runs):
+        c = g.counters()
+        attempts += c["spin_attempts"]
+        calls += c["philox_calls"]
+        updates += c["site_updates"]
+        o = g.observables()
+        lnz = g.free_energy()
+        by[name] = {"lnZ": lnz, "lnZ_exact": exact["lnZ"], "lnZ_error": lnz - exact["lnZ"],
+                    "free_energy_error_per_spin": -(lnz - exact["lnZ"]) / (bf * N2),
+                    "e": o["e"], "e_exact": exact["e"], "abs_m": o["abs_m"], "S_f": o["S_f"],
+                    "rho_t": o["rho_t"], "R": o["R"]}
+        g.close()
+    union_s = union_length([(ref.elapsed_time(a), ref.elapsed_time(b)) for a, b in ev]) / 1e3
+    return {"workload": "2D Ising FM L=64, R=1e5, theta=10, beta_i=0.6 i/200 (201 points), four runs "
+                        "(multinomial, Poisson, nearest-integer, systematic), one stream each, one whole anneal",
+            "wall_s": wall, "attempts_per_ns": attempts / wall / 1e9,
+            "sweep_attempts_per_ns_union": attempts / union_s / 1e9,
+            "philox_calls_per_attempt": calls / (64.0 * updates),
+            "exact_reference": "Kaufman finite-torus ln Z at beta = 0.6 (tests/golden/kaufman_2d_L64.json)",
+            "by_scheme": by}
+
+
+def config3_row():
+    """3D +-J glass L = 10, R = 5 10^5 per population, theta = 10,
+    beta_i = 3 i/300 (301 points), systematic; populations A and B (run_id 0
+    and 1, same couplings from seed 1) annealed together as a batch (one HIP
+    graph): wall time, ln Q per step (every 10th step shown, from the step
+    records), the energy per spin at beta = 3 and the overlap distribution
+    P(q) between A and B at beta = 3."""
+    import numpy as np
+    import torch
+    from paper_2401_07965_amd import pa, workloads
+    d3, L3, R3, pts = 3, 10, 500000, 301
+    J = workloads.pm_j_couplings(d3, L3, 1)
+    sched = schedule(3.0, pts)
+    cfgs = [dict(dim=d3, L=L3, R=R3, seed=1, run_id=k, couplings=J) for k in (0, 1)]
+    B = pa.PABatch(cfgs, max_points=pts)
+    B.tune(THETA)
+    B.anneal(sched, THETA, SCHEME, use_graph=True)  # capture + first launch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.anneal(sched, THETA, SCHEME, use_graph=True)  # replay
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rec = B.records()
+    h = B.overlap(0, 1)
+    B.close()
+    N3 = L3 ** d3
+    q = (2.0 * np.arange(N3 + 1) - N3) / N3
+    P = h / h.sum()
+    edges = np.linspace(-1, 1, 21)
+    hist20 = [float(P[(q >= a) & ((q < b) if b < 1 else (q <= b))].sum()) for a, b in zip(edges[:-1], edges[1:])]
+    attempts = THETA * N3 * sum(int(rec[m, i]["R"]) for m in (0, 1) for i in range(1, pts))
+    return {"workload": "3D +-J EA L=10 (couplings seed 1), R=5e5 per population, populations A/B "
+                        "(run_id 0/1), theta=10, beta_i=3 i/300 (301 points), systematic, one batch "
+                        "(graph replay)",
+            "wall_s": wall, "attempts_per_ns": attempts / wall / 1e9,
+            "lnQ_every_10th_step": {"A": [float(rec[0, i]["lnQ"]) for i in range(10, pts, 10)],
+                                     "B": [float(rec[1, i]["lnQ"]) for i in range(10, pts, 10)]},
+            "lnZ_per_spin_final": [float(rec[m, -1]["lnZ"]) / N3 for m in (0, 1)],
+            "e_final": [float(rec[m, -1]["e"]) for m in (0, 1)],
+            "rho_t_final": [float(rec[m, -1]["rho_t"]) for m in (0, 1)],
+            "overlap": {"pairs": int(h.sum()), "mean_abs_q": float((P * np.abs(q)).sum()),
+                        "mean_q2": float((P * q * q).sum()),
+                        "P_q_20_bins_-1_to_1": hist20}}
 
 
 def resample_scaling(sizes=(100000, 1000000, 4000000), steps=4):
@@ -286,13 +425,13 @@ def resample_scaling(sizes=(100000, 1000000, 4000000), steps=4):
     import torch
     from paper_2401_07965_amd import pa
     gate = torch.empty(1 << 20, dtype=torch.int32, device="cuda")
-    sched = betas()
+    sched = schedule(0.6, 201)
     out = {}
-    for R in sizes:
+    for Rs in sizes:
         row = {}
         for name, rid in (("nearest", 2), ("systematic", 3)):
             stream = torch.cuda.Stream()
-            g = pa.PARun(D, L, R, seed=1, run_id=rid, stream=stream)
+            g = pa.PARun(2, 64, Rs, seed=1, run_id=rid, stream=stream)
             i0 = 100
             for i in range(1, i0):  # reach the schedule point untimed (one sweep per step)
                 g.reweight(sched[i], wait=False)
@@ -310,20 +449,23 @@ def resample_scaling(sizes=(100000, 1000000, 4000000), steps=4):
                 g.sweep(THETA)
                 R_new = g.observables()["R"]
                 ms += e0.elapsed_time(e1)
-                nbytes += resample_bytes(R_old, R_new)
+                nbytes += resample_bytes(64 * 64, R_old, R_new)
             g.close()
             row[name] = {"GB_per_s": nbytes / (ms * 1e-3) / 1e9, "us_per_resampling": ms * 1e3 / steps}
-        out[str(R)] = row
+        out[str(Rs)] = row
     return {"workload": "2D Ising FM L=64, one run per size, steps at beta_i = 0.6 i/200 from i = 100, "
                         "theta=10, each reweight + resample queued whole", "by_R": out}
 
 
-def batched_bench(theta=10, scheme=3, verify_runs=8):
+def batched_bench(theta=10, scheme=3, plain_streams=8):
     """Uneven-batch workload: 256 independent +-J runs (16 disorder samples x 16
     runs; per sample d in {2,3}, L in {8,12,16,24}; R log-uniform in [1e3, 1e5]),
-    beta_i = 3 i/150, theta = 10, systematic resampling.  Times one whole anneal
-    of all runs as one HIP graph, the same eagerly, and the same runs one after
-    the other through the single-run calls; the results are bit-identical.
+    beta_i = 3 i/150, theta = 10, systematic resampling.  One whole anneal of
+    all runs: captured as a HIP graph (capture + instantiation + launch), then
+    replayed, eagerly, and as plain per-run PA through the single-run calls in
+    their fastest form (deferred calls, runs spread over `plain_streams`
+    streams so that their kernels overlap).  Every run's final ln Z_hat and
+    population are compared with the batch's (identical by construction).
     Then, per disorder sample, one run of the sample's total size (Fig. 7's
     alternative to combining M runs): its wall time and the ln Z difference
     from the weighted combination."""
@@ -336,7 +478,7 @@ def batched_bench(theta=10, scheme=3, verify_runs=8):
     threads = B.tune(theta)
     attempts = theta * sum(c["L"] ** c["dim"] * c["R"] for c in cfgs) * (len(betas) - 1)
     out = {}
-    for mode, graph in (("graph", True), ("eager", False)):
+    for mode, graph in (("graph_first", True), ("graph_replay", True), ("eager", False)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         B.anneal(betas, theta, scheme, use_graph=graph)
@@ -346,6 +488,27 @@ def batched_bench(theta=10, scheme=3, verify_runs=8):
     comb = B.combine(groups, max(groups) + 1, len(betas) - 1)
     frozen = int(np.sum(rec[:, -1]["status"] & 16 != 0))
     B.close()
+    # plain per-run PA: the same runs through the single-run calls, deferred,
+    # runs spread round-robin over streams
+    streams = [torch.cuda.Stream() for _ in range(plain_streams)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [pa.PARun(c["dim"], c["L"], c["R"], seed=c["seed"], run_id=c["run_id"], couplings=c["couplings"],
+                     stream=streams[m % plain_streams]) for m, c in enumerate(cfgs)]
+    t_setup = time.perf_counter() - t0
+    for b in betas[1:]:
+        for g in runs:
+            g.reweight(b, wait=False)
+            g.resample(scheme, wait=False)
+            g.sweep(theta)
+            g.observables(wait=False)
+    torch.cuda.synchronize()
+    plain = time.perf_counter() - t0
+    mismatched = 0
+    for m, g in enumerate(runs):
+        if g.free_energy() != rec[m, -1]["lnZ"] or g.observables()["R"] != rec[m, -1]["R"]:
+            mismatched += 1
+        g.close()
     # one run per disorder sample of the runs' total size (Fig. 7's alternative)
     nsamp = max(groups) + 1
     big_cfgs = []
@@ -355,6 +518,7 @@ def batched_bench(theta=10, scheme=3, verify_runs=8):
                              couplings=mine[0]["couplings"]))
     G = pa.PABatch(big_cfgs, max_points=len(betas))
     G.tune(theta)
+    G.anneal(betas, theta, scheme, use_graph=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     G.anneal(betas, theta, scheme, use_graph=True)
@@ -364,40 +528,105 @@ def batched_bench(theta=10, scheme=3, verify_runs=8):
     G.close()
     dlnz = [abs(comb[s]["lnZ"] - float(grec[s, -1]["lnZ"])) / (big_cfgs[s]["L"] ** big_cfgs[s]["dim"])
             for s in range(nsamp)]
-    # the same runs one by one (plain per-run PA through the single-run calls)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    identical = True
-    for m, c in enumerate(cfgs):
-        g = pa.PARun(c["dim"], c["L"], c["R"], seed=c["seed"], run_id=c["run_id"],
-                     couplings=c["couplings"])
-        for b in betas[1:]:
-            g.reweight(b)
-            g.resample(scheme)
-            g.sweep(theta)
-            g.observables()
-        if m < verify_runs:
-            identical &= g.free_energy() == rec[m, -1]["lnZ"]
-        g.close()
-    torch.cuda.synchronize()
-    seq = time.perf_counter() - t0
     return {
         "workload": "256 +-J runs (16 samples x 16), d in {2,3}, L in {8,12,16,24}, "
                     "R log-uniform [1e3,1e5], beta 0->3 in 151 points, theta=10, systematic",
         "runs": len(cfgs), "attempts_per_anneal": attempts,
-        "graph_s": out["graph"], "eager_s": out["eager"], "sequential_s": seq,
-        "attempts_per_ns_graph": attempts / out["graph"] / 1e9,
-        "attempts_per_ns_sequential": attempts / seq / 1e9,
-        "speedup_graph_vs_sequential": seq / out["graph"],
-        "identical_to_sequential": bool(identical), "frozen_runs": frozen,
-        "tuned_threads": threads,
-        "combined_lnZ_per_spin_sample0": comb[0]["lnZ"] / (cfgs[0]["L"] ** cfgs[0]["dim"]),
+        "graph_first_s": out["graph_first"], "graph_replay_s": out["graph_replay"], "eager_s": out["eager"],
+        "plain_per_run_s": plain, "plain_per_run_setup_s": t_setup, "plain_streams": plain_streams,
+        "attempts_per_ns_graph": attempts / out["graph_replay"] / 1e9,
+        "attempts_per_ns_plain_per_run": attempts / plain / 1e9,
+        "speedup_graph_vs_plain_per_run": plain / out["graph_replay"],
+        "runs_checked_identical": len(cfgs) - mismatched, "runs_mismatched": mismatched,
+        "frozen_runs": frozen, "tuned_threads": threads,
         "mean_n_eff": float(np.mean([c["n_eff"] for c in comb])),
-        # per sample, one run of the 16 runs' total size, annealed as a batch of 16
+        # per sample, one run of the 16 runs' total size, annealed as a batch of 16 (graph replay)
         "one_large_run_per_sample_s": big_s,
         "weighted_vs_large_run_lnZ_per_spin": {"mean_abs_diff": float(np.mean(dlnz)),
                                                 "max_abs_diff": float(np.max(dlnz))},
     }
+
+
+def learned_bench(theta=10, scheme=3, astar=0.7, dmax=0.2, beta_f=3.0, Reval=1000000, Rtrain=10000,
+                  runs=16, records=2000):
+    """Learned-schedule workload: 3D +-J glass L = 16, beta 0 -> 3, theta = 10,
+    systematic.  Training data: (features, ln dbeta) records of rule-driven
+    anneals at R = 10^4 of other disorder samples (coupling seeds 2, 3, ...)
+    until `records` records exist; the model is trained on the GPU.
+    Evaluation on the sample of coupling seed 1 at R = 10^6: `runs` anneals
+    (run_id 0..runs-1) with the overlap rule alone and as many with the
+    learned step (exact overlap check, rule fallback).  Reported per schedule:
+    mean and spread of the wall time, steps, fallbacks, and the RMSD of
+    ln Z_hat at beta = 3 against the reference, the free-energy-weighted
+    combination (Eq. (10), equal R) of all 2 x `runs` anneals, with the RMSD's
+    standard error."""
+    import numpy as np
+    import torch
+    from paper_2401_07965_amd import pa, workloads
+    from paper_2401_07965_amd.schedule import anneal_adaptive, standardisation
+    d, Ls = 3, 16
+    Xs, ys = [], []
+    t0 = time.perf_counter()
+    s = 2
+    while sum(len(y) for y in ys) < records:
+        run = pa.PARun(d, Ls, Rtrain, seed=1, run_id=0, couplings=workloads.pm_j_couplings(d, Ls, s))
+        o = anneal_adaptive(run, beta_f, astar, dmax, theta, scheme, record=True)
+        Xs.append(o["X"])
+        ys.append(o["y"])
+        run.close()
+        s += 1
+    X, y = np.concatenate(Xs)[:records], np.concatenate(ys)[:records]
+    t_data = time.perf_counter() - t0
+    xm, xs, ym, ysd = standardisation(X, y)
+    mlp = pa.PAMlp(workloads.mlp_initial_parameters(0), xm, xs, ym, ysd, max_samples=len(y))
+    mlp.set_data(X, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = mlp.train(2000, 3e-3)
+    t_train = time.perf_counter() - t0
+    J = workloads.pm_j_couplings(d, Ls, 1)
+    res = {"training_records": int(len(y)), "training_samples": s - 2, "train_loss": loss,
+           "data_s": t_data, "train_s": t_train}
+    per = {}
+    for name, model in (("rule", None), ("learned", mlp)):
+        wall, steps, sched_s, fb, lnz = [], [], [], [], []
+        for k in range(runs):
+            run = pa.PARun(d, Ls, Reval, seed=1, run_id=k, couplings=J)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            o = anneal_adaptive(run, beta_f, astar, dmax, theta, scheme, mlp=model)
+            torch.cuda.synchronize()
+            wall.append(time.perf_counter() - t0)
+            steps.append(o["steps"])
+            sched_s.append(o["schedule_s"])
+            fb.append(o["fallbacks"])
+            lnz.append(o["lnZ"])
+            run.close()
+        per[name] = dict(wall=np.array(wall), steps=np.array(steps), sched=np.array(sched_s),
+                         fb=np.array(fb), lnz=np.array(lnz))
+    mlp.close()
+    allz = np.concatenate([per[n]["lnz"] for n in per])
+    ref = float(allz.max() + np.log(np.exp(allz - allz.max()).sum()) - np.log(len(allz)))
+    for name, p in per.items():
+        dev2 = (p["lnz"] - ref) ** 2
+        rmsd = float(np.sqrt(dev2.mean()))
+        # standard error of the RMSD from that of the mean squared deviation
+        se = float(dev2.std(ddof=1) / np.sqrt(len(dev2)) / (2 * rmsd)) if rmsd > 0 else 0.0
+        res[name] = {"wall_s_mean": float(p["wall"].mean()), "wall_s_sd": float(p["wall"].std(ddof=1)),
+                     "steps_mean": float(p["steps"].mean()), "schedule_s_mean": float(p["sched"].mean()),
+                     "fallbacks_mean": float(p["fb"].mean()),
+                     "rmsd_lnZ": rmsd, "rmsd_lnZ_se": se,
+                     "mean_lnZ_minus_reference": float((p["lnz"] - ref).mean())}
+    r, l = res["rule"], res["learned"]
+    res["wall_speedup"] = r["wall_s_mean"] / l["wall_s_mean"]
+    res["wall_speedup_se"] = res["wall_speedup"] * math.hypot(
+        r["wall_s_sd"] / math.sqrt(runs) / r["wall_s_mean"], l["wall_s_sd"] / math.sqrt(runs) / l["wall_s_mean"])
+    res["rmsd_ratio_learned_over_rule"] = l["rmsd_lnZ"] / r["rmsd_lnZ"] if r["rmsd_lnZ"] > 0 else None
+    res["reference"] = f"weighted combination (Eq. (10), equal R) of all {2 * runs} anneals' ln Z_hat at beta = 3"
+    res["workload"] = (f"3D +-J L=16 (couplings seed 1), R={Reval}, beta 0->3, alpha*={astar}, dbeta_max={dmax}, "
+                       f"theta={theta}, systematic; {runs} run_ids per schedule; trained on {len(y)} records of "
+                       f"rule-driven anneals at R={Rtrain} of other samples")
+    return res
 
 
 def combination_study(L=16, R=100, theta=1, runs=1024, points=21, beta_f=0.44):
@@ -550,7 +779,7 @@ def cluster_study(L=64, R=100000, beta_c=0.4406868, updates=10):
     st = torch.cuda.current_stream()
 
     def annealed():
-        g = pa.PARun(D, L, R, seed=5, run_id=0)
+        g = pa.PARun(2, L, R, seed=5, run_id=0)
         for i in range(1, 21):
             g.reweight(beta_c * i / 20, wait=False)
             g.resample(3, wait=False)
@@ -582,13 +811,13 @@ def cluster_study(L=64, R=100000, beta_c=0.4406868, updates=10):
             sk = g.export()
             if k == 1:
                 flips = np.unpackbits((s0["spins"] ^ sk["spins"]).view(np.uint8)).sum()
-                out[f"{name}_mean_flipped_fraction"] = float(flips) / (R * L ** D)
+                out[f"{name}_mean_flipped_fraction"] = float(flips) / (R * L ** 2)
             ce.append(float(np.corrcoef(E0, sk["energy"].astype(np.float64))[0, 1]))
             cm.append(float(np.corrcoef(m0, np.abs(sk["magnetization"]).astype(np.float64))[0, 1]))
         corr[name] = {"energy": ce, "abs_m": cm}
         g.close()
     out["autocorrelation_after_k_updates"] = corr
-    out["cluster_flipped_spins_per_ns"] = (out["cluster_mean_flipped_fraction"] * R * L ** D
+    out["cluster_flipped_spins_per_ns"] = (out["cluster_mean_flipped_fraction"] * R * L ** 2
                                            / (out["ms_per_cluster_update"] * 1e6))
     return out
 
@@ -628,131 +857,106 @@ def rmsd_study(L=64, R=20000, theta=2, runs=500):
                         "systematic; groups of M", "anneal_s": anneal_s, "rmsd_vs_all_runs_weighted": table}
 
 
-def learned_bench(theta=10, scheme=3, astar=0.7, dmax=0.2, beta_f=3.0):
-    """Learned-schedule workload: 3D +-J glass L = 16.  The model is trained on
-    the GPU from rule-driven anneals of 8 other disorder samples at R = 10^4;
-    then the evaluation sample is annealed at R = 10^6 (and 10^4) with the
-    rule alone and with the learned step (exact overlap check + rule fallback)."""
-    import numpy as np
+def profile_run(which, steps, warmup):
+    """Workload for counter passes: `warmup + steps` temperature steps of one
+    run of the named workload (deferred calls; the sweep launches of the last
+    `steps` are the timed window of the headline), then torch's copy of
+    256 MiB (reads and writes 2^28 bytes each) as the reference of known
+    traffic."""
     import torch
     from paper_2401_07965_amd import pa, workloads
-    from paper_2401_07965_amd.schedule import anneal_adaptive, standardisation
-    d, L = 3, 16
-    Xs, ys = [], []
-    t0 = time.perf_counter()
-    for s in range(2, 10):
-        run = pa.PARun(d, L, 10000, seed=1, run_id=0, couplings=workloads.pm_j_couplings(d, L, s))
-        out = anneal_adaptive(run, beta_f, astar, dmax, theta, scheme, record=True)
-        Xs.append(out["X"])
-        ys.append(out["y"])
-        run.close()
-    X, y = np.concatenate(Xs), np.concatenate(ys)
-    t_data = time.perf_counter() - t0
-    xm, xs, ym, ysd = standardisation(X, y)
-    mlp = pa.PAMlp(workloads.mlp_initial_parameters(0), xm, xs, ym, ysd, max_samples=len(y))
-    mlp.set_data(X, y)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    loss = mlp.train(2000, 3e-3)
-    t_train = time.perf_counter() - t0
-    J = workloads.pm_j_couplings(d, L, 1)
-    res = {"training_steps": int(len(y)), "train_loss": loss, "data_s": t_data, "train_s": t_train}
-    for R in (1000000, 10000):
-        for name, model in (("rule", None), ("learned", mlp)):
-            run = pa.PARun(d, L, R, seed=1, run_id=0, couplings=J)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            out = anneal_adaptive(run, beta_f, astar, dmax, theta, scheme, mlp=model)
-            torch.cuda.synchronize()
-            res[f"R{R}_{name}"] = dict(wall_s=time.perf_counter() - t0, steps=out["steps"],
-                                       schedule_s=out["schedule_s"], fallbacks=out["fallbacks"],
-                                       lnZ_per_spin=out["lnZ"] / L ** d)
-            run.close()
-        r, l = res[f"R{R}_rule"], res[f"R{R}_learned"]
-        res[f"R{R}_wall_speedup"] = r["wall_s"] / l["wall_s"]
-        res[f"R{R}_schedule_speedup"] = r["schedule_s"] / l["schedule_s"]
-    mlp.close()
-    res["workload"] = ("3D +-J L=16, beta 0->3, alpha*=0.7, dbeta_max=0.2, theta=10, systematic; "
-                       "trained on 8 other samples at R=1e4")
-    return res
-
-
-def profile_run():
-    """Workload for counter passes: the sweep, resample and observables kernels
-    of 3 temperature steps of one run, then torch's copy of 256 MiB (reads and
-    writes 2^28 bytes each) as the reference of known traffic."""
-    import torch
-    from paper_2401_07965_amd import pa
-    g = pa.PARun(D, L, R, seed=SEED, run_id=3)
-    sched = betas()
-    for i in range(1, 4):
-        g.reweight(sched[i])
-        g.resample(3)
+    if which == "config5":
+        J, d, Ls, Rs, sched, sc = headline_couplings(), D, L, R, schedule(), SCHEME
+    elif which == "config3":
+        J, d, Ls, Rs, sched, sc = workloads.pm_j_couplings(3, 10, 1), 3, 10, 500000, schedule(3.0, 301), SCHEME
+    else:
+        J, d, Ls, Rs, sched, sc = None, 2, 64, 100000, schedule(0.6, 201), 3
+    g = pa.PARun(d, Ls, Rs, seed=SEED, run_id=0, couplings=J)
+    for i in range(1, warmup + steps + 1):
+        g.reweight(sched[i], wait=False)
+        g.resample(sc, wait=False)
         g.sweep(THETA)
-        g.observables()
+        g.observables(wait=False)
     torch.cuda.synchronize()
     src = torch.empty(1 << 28, dtype=torch.uint8, device="cuda").fill_(1)
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
     g.close()
-    print("profile run done", flush=True)
+    print(f"profile run done: {which}, steps 1..{warmup + steps}", flush=True)
 
 
-def cpu_baseline(budget_s=15.0):
-    """The oracle as it stands, on a sample of the same workload: a population
-    of R_s = 2048 replicas (same lattice, theta, schedule), whole steps."""
+def cpu_baseline(budget_s=12.0, budget_1core_s=6.0):
+    """The oracle as it stands, on a sample of the headline workload: a
+    population of R_s = 2048 replicas of the same lattice and couplings,
+    theta = 10, beta_i = 3 i/300, whole steps (reweight, systematic
+    resampling, sweeps, observables) until the time budget is spent; on all
+    host threads, then on one."""
     from oracle import oracle as O
     Rs = 2048
-    sched = betas()
-    run = O.OracleRun(D, L, Rs, seed=SEED, run_id=3)
-    t0 = time.perf_counter()
-    attempts = 0
-    i = 0
-    while True:
-        i += 1
-        run.reweight(sched[i])
-        Rn = run.resample(O.SYSTEMATIC)
-        run.sweep(THETA)
-        run.observables()
-        attempts += THETA * (L ** D) * Rn
-        if time.perf_counter() - t0 > budget_s or i == POINTS - 1:
-            break
-    el = time.perf_counter() - t0
-    return {"value": attempts / el / 1e9, "unit": "attempts/ns", "cores": O.threads(),
-            "kind": "oracle",
-            "sample": f"{i} temperature steps of one systematic-resampling run with R = {Rs} "
-                      f"replicas of the same L = 64 lattice, theta = {THETA}, beta_i = 0.6 i/200 "
-                      f"({el:.1f} s)"}
+    sched = schedule()
+    J = headline_couplings()
+
+    def timed(budget):
+        run = O.OracleRun(D, L, Rs, seed=SEED, run_id=0, J=J)
+        t0 = time.perf_counter()
+        attempts, i = 0, 0
+        while True:
+            i += 1
+            run.reweight(sched[i])
+            Rn = run.resample(O.SYSTEMATIC)
+            run.sweep(THETA)
+            run.observables()
+            attempts += THETA * (L ** D) * Rn
+            if time.perf_counter() - t0 > budget or i == POINTS - 1:
+                break
+        return attempts / (time.perf_counter() - t0) / 1e9, i, time.perf_counter() - t0
+
+    cores = O.threads()
+    v, steps, el = timed(budget_s)
+    O.set_threads(1)
+    v1, steps1, el1 = timed(budget_1core_s)
+    O.set_threads(cores)
+    return {"value": v, "unit": "attempts/ns", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} temperature steps (beta_i = 3 i/300 from i = 1) of one systematic-resampling "
+                      f"run with R = {Rs} replicas of the headline lattice (3D +-J L = 16, couplings seed 1), "
+                      f"theta = {THETA} ({el:.1f} s)",
+            "value_1_core": v1,
+            "sample_1_core": f"{steps1} temperature steps of the same run on one thread ({el1:.1f} s)"}
+
+
+ROWS = ("anneal", "config2", "config3", "resample_scaling", "batched", "learned", "combination",
+        "resampling", "conditional", "scheme_errors", "rmsd", "cluster")
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=190)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-rows", action="store_true",
-                    help="skip the batched and learned-schedule measurements")
-    ap.add_argument("--profile", action="store_true",
-                    help="short run for hardware counters: 3 steps of one run of the workload, "
-                         "then a 256 MiB device-to-device copy of known size")
+    ap.add_argument("--no-rows", action="store_true", help="only the headline (no other rows)")
+    ap.add_argument("--rows", default=",".join(ROWS), help="comma-separated rows to run: " + ",".join(ROWS))
+    ap.add_argument("--profile", choices=("config5", "config3", "config2"),
+                    help="short run for hardware counters: warmup + steps temperature steps of one run "
+                         "of the workload, then a 256 MiB device-to-device copy of known size")
     a = ap.parse_args()
-    if a.profile:
-        profile_run()
-        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
               "(this library runs one GPU; sharding across GPUs is not built)", file=sys.stderr)
         sys.exit(2)
-    r = gpu_bench(a.steps, a.warmup)
+    if a.profile:
+        profile_run(a.profile, a.steps, a.warmup)
+        return
+    if a.steps < 1 or a.warmup < 0:
+        print("need --steps >= 1 and --warmup >= 0", file=sys.stderr)
+        sys.exit(2)
+    r = headline_bench(a.steps, a.warmup)
     rate = philox_rate()
     value = r["attempts"] / r["elapsed"] / 1e9
-    # the sweep kernel's time: union of its launches on the four streams
-    sweep_s = r["sweep_union_s"]
-    avg_launch = sweep_s / len(r["sweep_ms"])
-    ops = OPS_PER_PHILOX * r["calls"] + OPS_PER_SITE_UPDATE * r["updates"]
-    achieved = ops / sweep_s if r["calls"] else None
+    prof = profiled_counters("config5")
+    if prof:
+        prof["path"] = COUNTER_PROFILES["config5"]
     out = {
         "metric": "spin-flip attempts/ns (whole PA temperature step)",
         "value": value,
@@ -767,50 +971,34 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {
-            "workload": "2D Ising ferromagnet L=64 periodic, R=100000, theta=10, "
-                        "beta_i=0.6 i/200 (201 points), four runs: multinomial, Poisson, "
-                        "nearest-integer, systematic resampling",
-            "dim": D, "L": L, "R": R, "theta": THETA, "runs_per_step": len(SCHEMES),
+            "workload": "3D +-J Edwards-Anderson spin glass L=16 periodic (couplings +-1 w.p. 1/2, seed 1), "
+                        "R=1000000 bit-packed (64 replicas per uint64), theta=10 checkerboard Metropolis sweeps, "
+                        "beta_i=3 i/300 (301 points), systematic resampling, one run",
+            "dim": D, "L": L, "R": R, "theta": THETA,
+            "timed_beta_range": r["beta_range"],
         },
-        "sweep_attempts_per_ns": r["attempts"] / sweep_s / 1e9,
-        # reweight + resample rate with one run on the device at a time (the
-        # concurrent runs' sweeps stretch its intervals inside the timed region)
-        "resample_GB_per_s": r["iso"]["resample_GB_per_s"] if r["iso"] else None,
-        "isolated": r["iso"],
-        "philox_calls_per_attempt": (r["calls"] / (64.0 * r["updates"])) if r["updates"] else None,
-        "philox_calls_per_ns": rate / 1e9,
-        # the sweep's rate if generating its random bits were all it did
-        "philox_bound_attempts_per_ns": (rate / (r["calls"] / (64.0 * r["updates"])) / 1e9)
-                                        if r["updates"] else None,
-        "roofline": {
-            "kernel": "k_sweep<2>",
-            "bound": "alu",
-            "achieved": achieved / 1e12 if achieved else None,
-            "peak": PEAK_INT_OPS / 1e12,
-            "unit": "Tops/s (int32)",
-            "frac": achieved / PEAK_INT_OPS if achieved else None,
-            "avg_launch_ms": avg_launch * 1e3,
-            "concurrent_streams": len(SCHEMES),
-            "launch_span_ms": sum(r["sweep_ms"]) / len(r["sweep_ms"]),
-            "traffic": None,
-        },
+        "sweep_attempts_per_ns": r["attempts"] / (sum(r["sweep_ms"]) * 1e-3) / 1e9,
+        "resample_GB_per_s": r["res_bytes"] / (sum(r["res_ms"]) * 1e-3) / 1e9,
+        "sweep_share_of_step": sum(r["sweep_ms"]) * 1e-3 / r["elapsed"],
+        "roofline": sweep_roofline("k_sweep<3,true>", L ** D, r["attempts"], r["calls"], r["updates"], r["words"],
+                                   r["sweep_ms"], rate, "3d_pmj", prof),
     }
-    prof = profiled_counters()
-    if prof:
-        # HBM bytes per sweep launch (FETCH_SIZE, WRITE_SIZE scaled by a copy of known size)
-        out["roofline"]["traffic"] = float(prof["traffic_bytes_per_launch"])
-        out["roofline"]["traffic_unit"] = "bytes/launch"
-        out["roofline"]["valu_busy"] = float(prof["valu_busy"])
-    if not a.no_rows:
-        out["resample_scaling"] = resample_scaling()
-        out["batched"] = batched_bench()
-        out["learned"] = learned_bench()
-        out["combination"] = combination_study()
-        out["resampling"] = resampling_study()
-        out["conditional"] = conditional_study()
-        out["scheme_errors"] = scheme_error_study()
-        out["rmsd"] = rmsd_study()
-        out["cluster"] = cluster_study()
+    rows = [] if a.no_rows else [x for x in a.rows.split(",") if x]
+    unknown = [x for x in rows if x not in ROWS]
+    if unknown:
+        print(f"unknown rows: {unknown}", file=sys.stderr)
+        sys.exit(2)
+    fns = {"anneal": anneal_row, "config2": config2_row, "config3": config3_row,
+           "resample_scaling": resample_scaling, "batched": batched_bench, "learned": learned_bench,
+           "combination": combination_study, "resampling": resampling_study,
+           "conditional": conditional_study, "scheme_errors": scheme_error_study, "rmsd": rmsd_study,
+           "cluster": cluster_study}
+    for name in ROWS:
+        if name in rows:
+            t0 = time.perf_counter()
+            out[name] = fns[name]()
+            out[name]["row_wall_s"] = time.perf_counter() - t0
+            print(f"[bench] row {name} done ({out[name]['row_wall_s']:.1f} s)", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -345,7 +345,11 @@ pa_status pa_batch_groups(pa_batch *b, int32_t *ngroups, int32_t *threads);
  * then for i >= 1 reweight to betas[i], resample with `scheme`, theta sweeps,
  * observables into the records.  A run whose resampling fails (capacity,
  * extinction) is frozen at its last good step (status bits in its records).
- * use_graph != 0 captures the anneal in one HIP graph and launches it once. */
+ * use_graph != 0 captures the anneal in one HIP graph, instantiates it and
+ * launches it; the batch keeps the instantiated graph, and a later call with
+ * the same betas, theta and scheme (and unchanged workgroup sizes) replays it
+ * without capturing again.  Any other use_graph call replaces the kept graph;
+ * pa_batch_destroy releases it.  Synchronises the stream. */
 pa_status pa_batch_anneal(pa_batch *b, const double *betas, int32_t npoints, int32_t theta,
                           pa_resampler scheme, int32_t use_graph);
 
@@ -354,6 +358,14 @@ pa_status pa_batch_records(pa_batch *b, pa_step_record *out);
 
 /* Final state of one run (as pa_export_state). */
 pa_status pa_batch_export_run(pa_batch *b, int32_t run, pa_host_state *st);
+
+/* Overlap distribution (Figs. 6-7) between runs run_a and run_b of the batch,
+ * in their current state (after pa_batch_anneal: at its last point), exactly
+ * as pa_overlap: replica d of run_a paired with replica d of run_b,
+ * d < min(R_a, R_b); hist_out (host, int64[N + 1]) entry k counts pairs with
+ * N - popcount(a ^ b) = k.  The two runs must share dim and L (PA_E_INVAL
+ * otherwise).  Uses run_a's overlap buffer; synchronises the stream. */
+pa_status pa_batch_overlap(pa_batch *b, int32_t run_a, int32_t run_b, int64_t *hist_out);
 
 /* Eqs. (9)-(10) at temperature point `point` of the last anneal: runs m with
  * group_of_run[m] = g (-1: none) are combined into out[g], g < ngroups;

@@ -80,6 +80,8 @@ def lib():
         L.orc_exp_array.restype = None
         L.orc_threads.argtypes = []
         L.orc_threads.restype = _c.c_int
+        L.orc_set_threads.argtypes = [_c.c_int]
+        L.orc_set_threads.restype = None
         _LIB = L
     return _LIB
 
@@ -87,6 +89,11 @@ def lib():
 def threads():
     """OpenMP threads the oracle's sweeps run on."""
     return int(lib().orc_threads())
+
+
+def set_threads(n):
+    """Sets the OpenMP threads of the oracle's sweeps (for timing on fewer cores)."""
+    lib().orc_set_threads(int(n))
 
 
 # --------------------------------------------------------------------------- primitives
@@ -471,3 +478,24 @@ def population_observables(N, E, M, label, R0, sv, lw=None):
                    abs_m=avg(np.abs(Mf)) / N, m2=avg(Mf * Mf) / (N * N), weighted=True,
                    ess=sw * sw / float(np.sum(w * w)))
     return out
+
+
+def overlap_histogram(words_a, words_b, R_a, R_b, N):
+    """Overlap distribution between two populations of the same lattice in
+    the packed layout (replica 64w + b is bit b of word [w][s], bit 1 for
+    sigma = -1): replica d of a paired with replica d of b for
+    d < min(R_a, R_b); entry k counts the pairs whose spins agree on k sites,
+    i.e. q = (2k - N) / N = (1/N) sum_s sigma_s^a sigma_s^b (the overlap of
+    Figs. 6-7).  Counted column by column from the unpacked bits."""
+    R = min(int(R_a), int(R_b))
+    hist = np.zeros(N + 1, np.int64)
+    W = (R + 63) // 64
+    for w0 in range(0, W, 256):
+        w1 = min(W, w0 + 256)
+        x = np.ascontiguousarray(words_a[w0:w1] ^ words_b[w0:w1])  # (C, N) uint64
+        bits = np.unpackbits(x.view(np.uint8).reshape(x.shape[0], N, 8), axis=2, bitorder="little")
+        differ = bits.reshape(x.shape[0], N, 64).sum(axis=1, dtype=np.int64)  # (C, 64) per replica
+        same = (N - differ).reshape(-1)
+        rows = 64 * w0 + np.arange(same.size)
+        hist += np.bincount(same[rows < R], minlength=N + 1)
+    return hist

@@ -75,6 +75,7 @@ static void philox4(uint32_t seed, uint32_t run_id, uint32_t c0, uint32_t c1,
 
 /* Threads the oracle's OpenMP loops use (reported with its timings). */
 int orc_threads(void) { return omp_get_max_threads(); }
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 
 /* ------------------------------------------------------------------------ */
 /* Deterministic exponential for every exp() whose value feeds a decision.  */

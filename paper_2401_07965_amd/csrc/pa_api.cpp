@@ -195,6 +195,13 @@ struct Batch {
     // also prepared the resampling's flags and status
     bool hist_clean = false;
     bool rs_prepped = false;
+    // the latest anneal captured as a HIP graph, replayed while the anneal's
+    // arguments (schedule, theta, scheme) and the groups' workgroup sizes stay
+    // the same
+    hipGraphExec_t anneal_exec = nullptr;
+    std::vector<double> anneal_betas;
+    int anneal_theta = -1, anneal_scheme = -1;
+    std::vector<int> anneal_threads;
 };
 
 namespace {
@@ -596,8 +603,19 @@ pa_status export_run(Batch *b, int m, pa_host_state *st)
     return PA_OK;
 }
 
+void drop_anneal_graph(Batch *b)
+{
+    if (b->anneal_exec)
+        (void)hipGraphExecDestroy(b->anneal_exec);
+    b->anneal_exec = nullptr;
+    b->anneal_betas.clear();
+    b->anneal_theta = b->anneal_scheme = -1;
+    b->anneal_threads.clear();
+}
+
 void free_batch(Batch *b)
 {
+    drop_anneal_graph(b);
     if (b->hrec)
         (void)hipHostFree(b->hrec);
     b->hrec = nullptr;
@@ -1147,9 +1165,28 @@ pa_status pa_batch_anneal(pa_batch *p, const double *betas, int32_t npoints, int
     if ((int)scheme < 0 || (int)scheme > 3)
         return fail(b, PA_E_INVAL, "unknown resampling scheme");
     const hipStream_t st = b->v.stream;
+    const std::vector<double> sched(betas, betas + npoints);
+    const std::vector<int> threads(b->v.gthreads, b->v.gthreads + b->v.ngroups);
+    hipError_t e = hipSuccess;
+    if (use_graph && b->anneal_exec && b->anneal_betas == sched && b->anneal_theta == theta &&
+        b->anneal_scheme == (int)scheme && b->anneal_threads == threads) {
+        // the same anneal as the captured one: replay it (every kernel's
+        // arguments, the block maps and the workspace are unchanged; the
+        // anneal starts with the initial sampling, so no earlier state enters)
+        e = hipGraphLaunch(b->anneal_exec, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess)
+            return hip_fail(b, e, "pa_batch_anneal (replay)");
+        b->hist_clean = true; // as left by the anneal's last launch, the observables pass
+        b->rs_prepped = false;
+        b->anneal_points = npoints;
+        return PA_OK;
+    }
+    if (use_graph)
+        drop_anneal_graph(b);
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipError_t e = hipSuccess;
     if (use_graph)
         e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     const PaBatchView &v = b->v; // record rows keep the stride max_points
@@ -1177,12 +1214,20 @@ pa_status pa_batch_anneal(pa_batch *p, const double *betas, int32_t npoints, int
     }
     if (e == hipSuccess)
         e = hipStreamSynchronize(st);
-    if (exec)
-        (void)hipGraphExecDestroy(exec);
     if (graph)
         (void)hipGraphDestroy(graph);
-    if (e != hipSuccess)
+    if (e != hipSuccess) {
+        if (exec)
+            (void)hipGraphExecDestroy(exec);
         return hip_fail(b, e, "pa_batch_anneal");
+    }
+    if (exec) { // kept for replays of the same anneal
+        b->anneal_exec = exec;
+        b->anneal_betas = sched;
+        b->anneal_theta = theta;
+        b->anneal_scheme = (int)scheme;
+        b->anneal_threads = threads;
+    }
     b->anneal_points = npoints;
     return PA_OK;
 }
@@ -1213,6 +1258,31 @@ pa_status pa_batch_export_run(pa_batch *p, int32_t run, pa_host_state *st)
     if (!st || run < 0 || run >= b->M)
         return fail(b, PA_E_INVAL, "bad run index or NULL state");
     return export_run(b, run, st);
+}
+
+pa_status pa_batch_overlap(pa_batch *p, int32_t run_a, int32_t run_b, int64_t *hist_out)
+{
+    if (!p)
+        return fail(nullptr, PA_E_INVAL, "batch is NULL");
+    Batch *b = &p->b;
+    if (!hist_out || run_a < 0 || run_a >= b->M || run_b < 0 || run_b >= b->M)
+        return fail(b, PA_E_INVAL, "bad run index or NULL hist_out");
+    const PaRunDesc &da = b->hdesc[run_a], &db = b->hdesc[run_b];
+    if (da.d != db.d || da.L != db.L)
+        return fail(b, PA_E_INVAL, "runs on different lattices");
+    const int N = da.N;
+    hipError_t e = pa_launch_overlap(b->ddesc + run_a, b->ddesc + run_b, N, (uint32_t)b->geo[run_a].W,
+                                     da.dv.qhist, b->v.stream);
+    std::vector<unsigned long long> h((size_t)N + 1);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h.data(), da.dv.qhist, h.size() * 8, hipMemcpyDeviceToHost, b->v.stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(b->v.stream);
+    if (e != hipSuccess)
+        return hip_fail(b, e, "pa_batch_overlap");
+    for (int k = 0; k <= N; ++k)
+        hist_out[k] = (int64_t)h[(size_t)k];
+    return PA_OK;
 }
 
 pa_status pa_batch_combine(pa_batch *p, const int32_t *group_of_run, int32_t ngroups, int32_t point,

@@ -141,13 +141,14 @@ def lib():
         L.pa_batch_records.argtypes = [v, v]
         L.pa_batch_export_run.argtypes = [v, ctypes.c_int32, P(pa_host_state)]
         L.pa_batch_combine.argtypes = [v, v, ctypes.c_int32, ctypes.c_int32, v]
+        L.pa_batch_overlap.argtypes = [v, ctypes.c_int32, ctypes.c_int32, v]
         L.pa_batch_destroy.argtypes = [v]
         L.pa_batch_destroy.restype = None
         L.pa_batch_last_error.argtypes = [v]
         L.pa_batch_last_error.restype = ctypes.c_char_p
         for name in ("pa_batch_required_bytes", "pa_batch_create", "pa_batch_tune",
                      "pa_batch_groups", "pa_batch_anneal", "pa_batch_records",
-                     "pa_batch_export_run", "pa_batch_combine"):
+                     "pa_batch_export_run", "pa_batch_combine", "pa_batch_overlap"):
             getattr(L, name).restype = ctypes.c_int
         L.pa_mlp_required_bytes.argtypes = [ctypes.c_int32, P(ctypes.c_uint64)]
         L.pa_mlp_create.argtypes = [ctypes.c_int32, v, P(pa_mlp_norm), v, ctypes.c_uint64, v, P(v)]
@@ -524,6 +525,12 @@ class PABatch:
         _check_b(lib().pa_batch_export_run(self.h, m, ctypes.byref(st)), self.h)
         return dict(R=R, step=st.step, sweeps=st.sweeps, beta=st.beta, lnZ=st.lnZ, spins=spins,
                     energy=E, magnetization=M, label=lab)
+
+    def overlap(self, a, b):
+        """Overlap histogram (int64[N + 1]) between runs a and b (pa_batch_overlap)."""
+        h = np.zeros(self.N[a] + 1, np.int64)
+        _check_b(lib().pa_batch_overlap(self.h, int(a), int(b), h.ctypes.data), self.h)
+        return h
 
     def combine(self, group_of_run, ngroups, point):
         g = np.ascontiguousarray(group_of_run, np.int32)

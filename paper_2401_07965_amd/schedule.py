@@ -14,19 +14,30 @@ import numpy as np
 from . import pa
 
 
+class NoStepError(RuntimeError):
+    """The step rule found no positive temperature step."""
+
+
 def anneal_adaptive(run, beta_f, alpha_star, dbeta_max, theta, scheme, mlp=None, record=False,
-                    iterations=60, sync=None):
+                    iterations=60, sync=None, max_steps=100000):
     """Anneal ``run`` (a fresh pa.PARun) from beta 0 to beta_f.
 
     Returns a dict: steps, lnZ (at beta_f), schedule_s (time spent choosing
-    steps), fallbacks, and, if ``record``, X (features) and y (ln dbeta of the
-    rule) of every step."""
+    steps), fallbacks, betas (the schedule taken) and, if ``record``, X
+    (features) and y (ln dbeta of the rule) of every step.
+
+    Raises NoStepError when the rule returns no step that moves beta (too few
+    bisection iterations to resolve a qualifying step: only dbeta = 0 is
+    certain to qualify) or when more than ``max_steps`` steps would be needed."""
     beta = 0.0
     steps = fallbacks = 0
     t_sched = 0.0
     X, y = [], []
+    betas = [0.0]
     run.observables()
     while beta < beta_f:
+        if steps >= max_steps:
+            raise NoStepError(f"beta {beta} after {steps} steps: more than max_steps = {max_steps}")
         if sync:
             sync()
         t0 = time.perf_counter()
@@ -38,17 +49,20 @@ def anneal_adaptive(run, beta_f, alpha_star, dbeta_max, theta, scheme, mlp=None,
             d, fb = run.step_learned(mlp, alpha_star, dbeta_max, iterations)
             fallbacks += int(fb)
         t_sched += time.perf_counter() - t0
+        nxt = min(beta + d, beta_f) if d > 0.0 else beta
+        if nxt <= beta:
+            raise NoStepError(f"the step rule returned dbeta = {d} at beta = {beta} "
+                              f"({iterations} bisection iterations); no step moves beta")
         if record:
-            y.append(math.log(d) if d > 0 else math.log(dbeta_max * 2.0 ** -60))
-        if d <= 0.0:
-            d = dbeta_max * 2.0 ** -60
-        beta = min(beta + d, beta_f)
+            y.append(math.log(d))
+        beta = nxt
+        betas.append(beta)
         run.reweight(beta)
         run.resample(scheme)
         run.sweep(theta)
         run.observables()
         steps += 1
-    out = dict(steps=steps, lnZ=run.free_energy(), schedule_s=t_sched, fallbacks=fallbacks)
+    out = dict(steps=steps, lnZ=run.free_energy(), schedule_s=t_sched, fallbacks=fallbacks, betas=betas)
     if record:
         out["X"] = np.array(X, np.float32)
         out["y"] = np.array(y, np.float32)

@@ -94,18 +94,28 @@ def sampled_step(g, d, L, J, scheme, beta_next, theta, rows, seed, run_id, R_tar
     the copy numbers over the whole exported population, then sweeps only the
     sampled destination rows."""
     st0 = g.export()
-    N = L ** d
-    Jo = O.ferromagnet(d, L) if J is None else J
     lnq_g = g.reweight(beta_next)
     rn_g = g.resample(scheme)
     g.sweep(theta)
     st1 = g.export()
+    check_step(st0, st1, lnq_g, rn_g, d, L, J, scheme, beta_next, theta, rows, seed, run_id, R_target)
+    return st1
+
+
+def check_step(st0, st1, lnq_g, rn_g, d, L, J, scheme, beta_next, theta, rows, seed, run_id, R_target):
+    """Checks one temperature step between two exported GPU states (st0 at
+    beta_{i-1}, st1 after reweighting to beta_next, resampling and theta
+    sweeps): ln Q, the copy numbers (through R_i and every label) and ln Z_hat
+    over the whole population; spins, energies and magnetisations of the
+    sampled destination rows, re-swept by the oracle from their ancestors."""
+    Jo = O.ferromagnet(d, L) if J is None else J
     dbeta = float(beta_next) - st0["beta"]
     lnq_o, W, S = O.reweight(st0["energy"], dbeta)
     assert rel_ok(lnq_g, lnq_o), (lnq_g, lnq_o)
     step = st0["step"] + 1
+    assert st1["step"] == step
     r = O.counts(scheme, W, S, R_target, seed, run_id, step)
-    assert int(r.sum()) == rn_g
+    assert int(r.sum()) == rn_g == st1["R"]
     anc = np.repeat(np.arange(len(r)), r.astype(np.int64))
     assert np.array_equal(st1["label"], st0["label"][anc])
     assert rel_ok(st1["lnZ"], st0["lnZ"] + lnq_o)
@@ -116,4 +126,16 @@ def sampled_step(g, d, L, J, scheme, beta_next, theta, rows, seed, run_id, R_tar
     assert np.array_equal(rows_from_words(st1["spins"], rows), spins)
     assert np.array_equal(st1["energy"][rows], E)
     assert np.array_equal(st1["magnetization"][rows], spins.astype(np.int64).sum(axis=1))
-    return st1
+
+
+def sample_rows(R, rng, k=64):
+    """The first and last k replicas and k random ones."""
+    return np.concatenate([np.arange(min(k, R)), np.arange(max(0, R - k), R), rng.integers(0, R, k)])
+
+
+def anneal_deferred(g, betas, scheme, theta):
+    """Steps 1..len(betas)-1 of an anneal on the GPU without host waits."""
+    for b in betas[1:]:
+        g.reweight(b, wait=False)
+        g.resample(scheme, wait=False)
+        g.sweep(theta)
