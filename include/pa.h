@@ -247,6 +247,18 @@ pa_status pa_import_state(pa_ctx *ctx, const pa_host_state *st);
  * (i.e. k = N - popcount). */
 pa_status pa_overlap(pa_ctx *a, pa_ctx *b, int64_t *hist_out);
 
+/* pa_overlap without workspace scratch, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same histogram, accumulated in the library's
+ * file-scope device array of 16385 counters (128 KiB per device, held until
+ * the process ends) instead of run a's workspace.  It allocates nothing and
+ * calls no allocating routine; hist_out (host, int64[N + 1]) is written
+ * directly.  PA_E_INVAL if N + 1 > 16385 or the lattices differ.  Every
+ * call on a device shares that device's array (each call clears the N + 1
+ * counters it uses), so calls that overlap on one device race: issue them one
+ * at a time.  Synchronises both runs' streams. */
+pa_status pa_overlap_noalloc(pa_ctx *a, pa_ctx *b, int64_t *hist_out);
+
 /* Throughput probe of the generator the sweeps draw from (no step of the
  * method): each of nthreads threads (a multiple of 256, <= 2^24) evaluates
  * 3 * iters Philox4x32-10 calls as three independent chains (the sweep's

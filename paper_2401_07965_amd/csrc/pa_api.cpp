@@ -978,6 +978,38 @@ pa_status pa_overlap(pa_ctx *a, pa_ctx *c2, int64_t *hist_out)
     return PA_OK;
 }
 
+pa_status pa_overlap_noalloc(pa_ctx *a, pa_ctx *c2, int64_t *hist_out)
+{
+    if (!a || !c2)
+        return fail(a ? &a->b : nullptr, PA_E_INVAL, "ctx is NULL");
+    Batch *A = &a->b, *B = &c2->b;
+    if (!hist_out)
+        return fail(A, PA_E_INVAL, "hist_out is NULL");
+    if (A->hdesc[0].d != B->hdesc[0].d || A->hdesc[0].L != B->hdesc[0].L)
+        return fail(A, PA_E_INVAL, "runs on different lattices");
+    const int N = A->hdesc[0].N;
+    if (N + 1 > PA_NOALLOC_HIST_MAX)
+        return fail(A, PA_E_INVAL, "N + 1 exceeds the allocation-free histogram's " +
+                                       std::to_string(PA_NOALLOC_HIST_MAX) + " counters");
+    // the device of run a's stream holds the histogram this call uses
+    int dev = 0;
+    hipError_t e = A->v.stream ? hipStreamGetDevice(A->v.stream, &dev) : hipGetDevice(&dev);
+    unsigned long long *hist = nullptr;
+    if (e == hipSuccess)
+        e = pa_noalloc_scratch(dev, &hist);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(B->v.stream);
+    if (e == hipSuccess) // the fill kernel clears the N + 1 counters this call uses
+        e = pa_launch_overlap(A->ddesc, B->ddesc, N, A->v.ncol, hist, A->v.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hist_out, hist, (size_t)(N + 1) * 8, hipMemcpyDeviceToHost, A->v.stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(A->v.stream);
+    if (e != hipSuccess)
+        return hip_fail(A, e, "pa_overlap_noalloc");
+    return PA_OK;
+}
+
 pa_status pa_step_alpha(pa_ctx *c, double dbeta, double *alpha_out)
 {
     if (!c)

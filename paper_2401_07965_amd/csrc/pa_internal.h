@@ -196,6 +196,10 @@ hipError_t pa_b_set_beta(const PaBatchView &v, double beta, double lnZ, uint32_t
 hipError_t pa_launch_combine(const PaBatchView &v, int point, const int32_t *group_of, int ngroups,
                              const int32_t *Ns, double *out);
 hipError_t pa_launch_philox_probe(uint32_t *out, int64_t nthreads, int iters, hipStream_t st);
+// Counters of the allocation-free overlap's file-scope histogram (N + 1 <= 16385).
+#define PA_NOALLOC_HIST_MAX 16385
+// Device address of that histogram on `device` (looked up once per device).
+hipError_t pa_noalloc_scratch(int device, unsigned long long **out);
 hipError_t pa_launch_overlap(const PaRunDesc *a, const PaRunDesc *b, int N, uint32_t ncols_a,
                              unsigned long long *hist, hipStream_t st);
 hipError_t pa_b_features(const PaBatchView &v);

@@ -13,6 +13,7 @@
 #include "pa_internal.h"
 
 #include <climits>
+#include <mutex>
 #include <type_traits>
 
 namespace {
@@ -2671,4 +2672,47 @@ hipError_t pa_launch_overlap(const PaRunDesc *a, const PaRunDesc *b, int N, uint
                                                                      (int64_t)(N + 1) * 2, 0u);
     k_overlap<<<ncols_a, kThreads, 0, st>>>(a, b, hist);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ allocation-free overlap
+// The overlap histogram of pa_overlap_noalloc lives in this file-scope device
+// array instead of a run's workspace: PA_NOALLOC_HIST_MAX counters (the
+// largest lattice's N + 1), 128 KiB per device, held until the process ends.
+// Every call on a device shares that device's copy.  In host code `scratch`
+// names a host-side stand-in, never the device memory: the device address
+// comes from hipGetSymbolAddress, taken once per device with that device
+// current, and only that address is passed to kernels.
+static __device__ __align__(256) unsigned long long scratch[PA_NOALLOC_HIST_MAX];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+} // namespace
+
+hipError_t pa_noalloc_scratch(int device, unsigned long long **out)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int prev = 0;
+        hipError_t e = hipGetDevice(&prev);
+        if (e != hipSuccess)
+            return e;
+        if (prev != device && (e = hipSetDevice(device)) != hipSuccess)
+            return e;
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (prev != device) {
+            const hipError_t e2 = hipSetDevice(prev);
+            if (e == hipSuccess)
+                e = e2;
+        }
+        if (e != hipSuccess)
+            return e;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = static_cast<unsigned long long *>(g_scratch_ptr[device]);
+    return hipSuccess;
 }

@@ -125,6 +125,7 @@ def lib():
         L.pa_export_state.argtypes = [v, P(pa_host_state)]
         L.pa_import_state.argtypes = [v, P(pa_host_state)]
         L.pa_overlap.argtypes = [v, v, v]
+        L.pa_overlap_noalloc.argtypes = [v, v, v]
         L.pa_philox_probe.argtypes = [v, ctypes.c_int64, ctypes.c_int32, v]
         L.pa_get_counters.argtypes = [v, P(pa_counters)]
         L.pa_step_alpha.argtypes = [v, ctypes.c_double, P(ctypes.c_double)]
@@ -174,7 +175,7 @@ def lib():
         L.pa_last_error.restype = ctypes.c_char_p
         for name in ("pa_required_bytes", "pa_init", "pa_sweep", "pa_cluster", "pa_reweight", "pa_resample",
                      "pa_observables", "pa_free_energy", "pa_export_state", "pa_import_state",
-                     "pa_overlap", "pa_get_counters", "pa_step_alpha", "pa_step_rule",
+                     "pa_overlap", "pa_overlap_noalloc", "pa_get_counters", "pa_step_alpha", "pa_step_rule",
                      "pa_philox_probe"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -322,6 +323,13 @@ def philox_probe(out, iters, stream):
     _check(lib().pa_philox_probe(out.data_ptr(), out.numel(), int(iters), stream.cuda_stream), None)
 
 
+def pa_overlap_noalloc(a, b, N):
+    """pa_overlap through the allocation-free entry point (file-scope device histogram)."""
+    h = np.zeros(N + 1, np.int64)
+    _check(lib().pa_overlap_noalloc(a, b, h.ctypes.data), a)
+    return h
+
+
 def pa_overlap(a, b, N):
     h = np.zeros(N + 1, np.int64)
     _check(lib().pa_overlap(a, b, h.ctypes.data), a)
@@ -425,6 +433,9 @@ class PARun:
 
     def overlap(self, other):
         return pa_overlap(self.ctx, other.ctx, self.N)
+
+    def overlap_noalloc(self, other):
+        return pa_overlap_noalloc(self.ctx, other.ctx, self.N)
 
     def step_alpha(self, dbeta):
         return pa_step_alpha(self.ctx, dbeta)
