@@ -387,7 +387,7 @@ def config3_row():
     sched = schedule(3.0, pts)
     cfgs = [dict(dim=d3, L=L3, R=R3, seed=1, run_id=k, couplings=J) for k in (0, 1)]
     B = pa.PABatch(cfgs, max_points=pts)
-    B.tune(THETA)
+    B.tune(THETA, 1.5)
     B.anneal(sched, THETA, SCHEME, use_graph=True)  # capture + first launch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -475,7 +475,7 @@ def batched_bench(theta=10, scheme=3, plain_streams=8):
     cfgs, groups = workloads.uneven_batch()
     betas = workloads.linear_schedule(3.0, 151)
     B = pa.PABatch(cfgs, max_points=len(betas))
-    threads = B.tune(theta)
+    threads = B.tune(theta, 1.5)
     attempts = theta * sum(c["L"] ** c["dim"] * c["R"] for c in cfgs) * (len(betas) - 1)
     out = {}
     for mode, graph in (("graph_first", True), ("graph_replay", True), ("eager", False)):
@@ -517,7 +517,7 @@ def batched_bench(theta=10, scheme=3, plain_streams=8):
         big_cfgs.append(dict(dim=mine[0]["dim"], L=mine[0]["L"], R=sum(c["R"] for c in mine), seed=2, run_id=s,
                              couplings=mine[0]["couplings"]))
     G = pa.PABatch(big_cfgs, max_points=len(betas))
-    G.tune(theta)
+    G.tune(theta, 1.5)
     G.anneal(betas, theta, scheme, use_graph=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

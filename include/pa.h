@@ -344,11 +344,21 @@ pa_status pa_batch_required_bytes(const pa_config *cfgs, int32_t nruns, int32_t 
 pa_status pa_batch_create(const pa_config *cfgs, int32_t nruns, int32_t max_points, void *workspace,
                           uint64_t workspace_bytes, void *stream, pa_batch **out);
 
-/* Autotuner: times the sweep workgroup size (64..768 lanes, where the
- * lattice allows) per group with theta sweeps, keeps the fastest and
- * re-draws the initial populations.  Results do not depend on the choice.
- * threads_out (optional): one entry per group. */
-pa_status pa_batch_tune(pa_batch *b, int32_t theta, int32_t *threads_out);
+/* Autotuner: times the sweep workgroup size (64..768 lanes in steps of 64,
+ * where the lattice allows) per group with theta sweeps of the current
+ * populations under the Metropolis thresholds of `beta` (a temperature of the
+ * coming anneal: the cost of a sweep depends on the thresholds), keeps the
+ * fastest and re-draws the initial populations.  Results do not depend on
+ * the choice.  threads_out (optional): one entry per group.  ms_out
+ * (optional): float[ngroups * 12], entry [g * 12 + t/64 - 1] the time of
+ * workgroup size t for group g in ms, -1 where t is not usable.
+ * PA_E_INVAL unless 1 <= theta <= 64 and beta >= 0 is finite. */
+pa_status pa_batch_tune(pa_batch *b, int32_t theta, double beta, int32_t *threads_out, float *ms_out);
+
+/* Sets group `group`'s sweep workgroup size (as pa_batch_tune would) to
+ * `threads`: 64..768 in steps of 64, within the device's LDS and at most 255
+ * bonds per lane (PA_E_INVAL otherwise). */
+pa_status pa_batch_set_threads(pa_batch *b, int32_t group, int32_t threads);
 
 /* Groups of the batch (see pa_batch_create) and their sweep workgroup sizes. */
 pa_status pa_batch_groups(pa_batch *b, int32_t *ngroups, int32_t *threads);

@@ -87,9 +87,10 @@ pa_status check_config(const pa_config *cfg, Geometry *g, std::string *msg)
 
 // Sweep workgroup sizes: 64..768 lanes, at most 255 unsatisfied bonds per
 // lane for the measurement's 8-plane counters.
+constexpr int kSweepMaxLanes = 768;
 bool sweep_threads_ok(int N, int d, int t)
 {
-    return t >= 64 && t <= 768 && t % 64 == 0 && (int64_t)((N + t - 1) / t) * d <= 255;
+    return t >= 64 && t <= kSweepMaxLanes && t % 64 == 0 && (int64_t)((N + t - 1) / t) * d <= 255;
 }
 
 constexpr int kLdsPerCu = 163840;  // gfx950: 160 KiB of LDS per CU
@@ -1113,26 +1114,31 @@ pa_status pa_batch_create(const pa_config *cfgs, int32_t nruns, int32_t max_poin
     return PA_OK;
 }
 
-pa_status pa_batch_tune(pa_batch *p, int32_t theta, int32_t *threads_out)
+pa_status pa_batch_tune(pa_batch *p, int32_t theta, double beta, int32_t *threads_out, float *ms_out)
 {
     if (!p)
         return fail(nullptr, PA_E_INVAL, "batch is NULL");
     Batch *b = &p->b;
     if (theta < 1 || theta > 64)
         return fail(b, PA_E_INVAL, "theta must be in [1, 64]");
-    // Each candidate sweeps the current populations; the populations are
-    // re-initialised afterwards (initial sampling is deterministic), so tuning
-    // leaves no trace.  Every candidate gives the same bits by construction.
-    hipEvent_t e0, e1;
+    if (!std::isfinite(beta) || beta < 0.0)
+        return fail(b, PA_E_INVAL, "beta must be finite and >= 0");
+    // Each candidate sweeps the current populations with the thresholds of
+    // `beta`; the populations are re-initialised afterwards (initial sampling
+    // is deterministic), so tuning leaves no trace.  Every candidate gives the
+    // same bits by construction.
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess)
         e = hipEventCreate(&e1);
-    if (e != hipSuccess)
-        return hip_fail(b, e, "pa_batch_tune");
+    if (e == hipSuccess)
+        e = pa_b_tune_beta(b->v, beta);
     for (int g = 0; g < b->v.ngroups && e == hipSuccess; ++g) {
         float best = 1e30f;
         int best_t = b->v.gthreads[g];
-        for (int t = 64; t <= 768 && e == hipSuccess; t += 64) {
+        for (int t = 64; t <= kSweepMaxLanes && e == hipSuccess; t += 64) {
+            if (ms_out)
+                ms_out[g * (kSweepMaxLanes / 64) + t / 64 - 1] = -1.0f;
             if (!sweep_threads_ok(b->v.gN[g], b->v.gd[g], t) ||
                 pa_sweep_lds_bytes(b->v.gN[g], b->v.gd[g], t, b->v.gJ[g] != 0) > (size_t)g_max_lds)
                 continue;
@@ -1148,6 +1154,8 @@ pa_status pa_batch_tune(pa_batch *p, int32_t theta, int32_t *threads_out)
             float ms = 0.f;
             if (e == hipSuccess)
                 e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && ms_out)
+                ms_out[g * (kSweepMaxLanes / 64) + t / 64 - 1] = ms;
             if (e == hipSuccess && ms < best) {
                 best = ms;
                 best_t = t;
@@ -1161,10 +1169,27 @@ pa_status pa_batch_tune(pa_batch *p, int32_t theta, int32_t *threads_out)
         e = launch_init(b);
     if (e == hipSuccess)
         e = hipStreamSynchronize(b->v.stream);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_batch_tune");
+    return PA_OK;
+}
+
+pa_status pa_batch_set_threads(pa_batch *p, int32_t group, int32_t threads)
+{
+    if (!p)
+        return fail(nullptr, PA_E_INVAL, "batch is NULL");
+    Batch *b = &p->b;
+    if (group < 0 || group >= b->v.ngroups)
+        return fail(b, PA_E_INVAL, "no such group");
+    if (!sweep_threads_ok(b->v.gN[group], b->v.gd[group], threads) ||
+        pa_sweep_lds_bytes(b->v.gN[group], b->v.gd[group], threads, b->v.gJ[group] != 0) > (size_t)g_max_lds)
+        return fail(b, PA_E_INVAL, "workgroup size not usable for this group (64..768 lanes in steps of 64, "
+                                   "within the LDS and the per-lane site bound)");
+    b->v.gthreads[group] = threads;
     return PA_OK;
 }
 

@@ -191,6 +191,7 @@ hipError_t pa_b_reweight(const PaBatchView &v, double beta_next, bool hist_clean
 hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze, int kq, bool prepped);
 hipError_t pa_b_observables(const PaBatchView &v, int point);
 hipError_t pa_b_rule(const PaBatchView &v, double alpha_star, double dbeta_max, int iterations, int bisect);
+hipError_t pa_b_tune_beta(const PaBatchView &v, double beta); // every run's thresholds at beta
 hipError_t pa_b_set_beta(const PaBatchView &v, double beta, double lnZ, uint32_t step, uint32_t sweeps,
                          uint64_t R);
 hipError_t pa_launch_combine(const PaBatchView &v, int point, const int32_t *group_of, int ngroups,

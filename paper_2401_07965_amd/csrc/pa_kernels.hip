@@ -294,21 +294,24 @@ __device__ __forceinline__ void apply_pair(const PlaneCtx &pc, const pa_philox_o
                    uin, und, acc);
 }
 
-// Plane pair q of a queued item.  2D reads the threshold bits from the
-// launch's table (tt[4 q + 2 c + j]: class c's bit on plane j of pair q, as
-// a mask); 3D, whose lattice and bond masks leave no LDS to spare for the
-// largest lattices, extracts them.
+// Plane pair q of a queued item: the threshold bits come from the launch's
+// table, tt[ttab_stride<D>() q + 2 c + j] = class c's bit on plane j of pair q as
+// a mask (classes dE = 4, 8 and, in 3D, 12).
 template <int D>
-__device__ __forceinline__ void apply_pair_queued(const PlaneCtx &pc, const uint32_t *tt, const pa_philox_out &o,
-                                                  uint32_t q, uint64_t m4, uint64_t m8, uint64_t &und, uint64_t &acc)
+constexpr int ttab_stride() { return D == 2 ? 4 : 8; }
+
+template <int D>
+__device__ __forceinline__ void apply_pair_queued(const uint32_t *tt, const pa_philox_out &o, uint32_t q,
+                                                  uint64_t m4, uint64_t m8, uint64_t &und, uint64_t &acc)
 {
+    const uint4 a = *reinterpret_cast<const uint4 *>(tt + ttab_stride<D>() * q);
     if (D == 2) {
-        const uint4 a = *reinterpret_cast<const uint4 *>(tt + 4 * q);
         pair_core<false>(o, plane_threshold_m<D>(m4, m8, dup32(a.x), dup32(a.z), 0ull),
                          plane_threshold_m<D>(m4, m8, dup32(a.y), dup32(a.w), 0ull), und, und, acc);
     } else {
-        const int b0 = 31 - 2 * (int)q;
-        apply_pair<D>(pc, o, q, m4, m8, tbit(pc.t12, b0), tbit(pc.t12, b0 - 1), und, und, acc);
+        const uint2 b = *reinterpret_cast<const uint2 *>(tt + ttab_stride<D>() * q + 4);
+        pair_core<false>(o, plane_threshold_m<D>(m4, m8, dup32(a.x), dup32(a.z), dup32(b.x)),
+                         plane_threshold_m<D>(m4, m8, dup32(a.y), dup32(a.w), dup32(b.y)), und, und, acc);
     }
 }
 
@@ -319,12 +322,14 @@ __device__ __forceinline__ void apply_pair_queued(const PlaneCtx &pc, const uint
 // Philox outputs, taken in the same order.
 constexpr int kInlinePairs = 3;
 constexpr int kQueue = 128; // per wave; never more than 127 items are live
-constexpr int kTtab = 16 * 4; // 2D threshold-bit table: 16 plane pairs x 2 classes x 2 planes
+// threshold-bit table: 16 plane pairs x (2 classes in 2D, 3 in 3D, padded to 4) x 2 planes
+template <int D>
+constexpr int ttab_words() { return 16 * ttab_stride<D>(); }
 
 struct WaveQueue {
     uint32_t *sq;  // site | next pair << 16
     uint64_t *und, *m4, *m8; // m8: 3D only
-    const uint32_t *tt;      // 2D: threshold-bit masks per plane pair (apply_pair_queued)
+    const uint32_t *tt;      // threshold-bit masks per plane pair (apply_pair_queued)
 };
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << (threadIdx.x & 63)) - 1ull; }
@@ -372,7 +377,7 @@ __device__ __forceinline__ void queue_pass(const WaveQueue &Q, const PlaneCtx &p
     if (act) {
         uint64_t acc = 0;
         ++calls;
-        apply_pair_queued<D>(pc, Q.tt, metro_philox(pc, s, q), q, m4, m8, und, acc);
+        apply_pair_queued<D>(Q.tt, metro_philox(pc, s, q), q, m4, m8, und, acc);
         lat[s] ^= acc;
     }
     const bool again = act && und != 0 && q + 1 < 16;
@@ -406,7 +411,7 @@ __device__ __forceinline__ void queue_drain(const WaveQueue &Q, const PlaneCtx &
         const uint32_t s = sq & 0xFFFFu;
         uint64_t acc = 0;
         for (uint32_t q = sq >> 16; und != 0 && q < 16u; ++q) {
-            apply_pair_queued<D>(pc, Q.tt, metro_philox(pc, s, q), q, m4, m8, und, acc);
+            apply_pair_queued<D>(Q.tt, metro_philox(pc, s, q), q, m4, m8, und, acc);
             ++calls;
         }
         if (act)
@@ -520,11 +525,14 @@ struct SweepGeom {
 // (2D) or L^2 (3D), so from one iteration to the next a lane's site moves by
 // 2 * blockDim sites along y (2D) or z (3D) and its other coordinates stay:
 // their neighbour offsets are computed once per colour.
+// zp: the number of leading inline plane pairs on which every drawing class's
+// threshold has 0 bits (their planes lie above the largest threshold): there
+// a differing bit can only reject, so such a pair decides as und &= ~(P0 | P1).
 template <int D, bool J, bool ALL, bool FIX>
 __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *jl, const SweepGeom &G, PlaneCtx pc,
                                                   const WaveQueue &Q, int theta, uint32_t t0, uint64_t sure4,
                                                   uint64_t sure8, uint64_t sure12, uint64_t draw4, uint64_t draw8,
-                                                  uint64_t draw12)
+                                                  uint64_t draw12, int zp)
 {
     const int L = G.L, N = G.N, half = G.half, nh = G.nh, LL = G.LL;
     const uint32_t mhalf = G.mhalf, mL = G.mL;
@@ -648,17 +656,29 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
                         for (int k = 0; k < kInlinePairs; ++k)
                             o[k] = metro_philox(pc, s, (uint32_t)k);
                         const uint64_t l0 = ((uint64_t)tl[0] << 32) | tl[0], l1 = ((uint64_t)tl[1] << 32) | tl[1];
-                        if (ALL)
+                        if (zp > 0) { // nothing accepts on these planes
+                            const uint64_t P0 = (uint64_t)o[0].x0 | ((uint64_t)o[0].x1 << 32);
+                            const uint64_t P1 = (uint64_t)o[0].x2 | ((uint64_t)o[0].x3 << 32);
+                            und = ALL ? pa_bop3<PA_T3(~(PA_A | PA_B | PA_C))>(always, P0, P1)
+                                      : pa_bop3<PA_T3(PA_A & ~(PA_B | PA_C))>(und, P0, P1);
+                        } else if (ALL) {
                             apply_pair<D, true>(pc, o[0], 0u, m4, m8, l0, l1, always, und, acc);
-                        else
+                        } else {
                             apply_pair<D>(pc, o[0], 0u, m4, m8, l0, l1, und, und, acc);
+                        }
                         q = 1;
 #pragma unroll
                         for (int k = 1; k < kInlinePairs; ++k)
                             if (und != 0) {
-                                apply_pair<D>(pc, o[k], (uint32_t)k, m4, m8,
-                                              ((uint64_t)tl[2 * k] << 32) | tl[2 * k],
-                                              ((uint64_t)tl[2 * k + 1] << 32) | tl[2 * k + 1], und, und, acc);
+                                if (k < zp) {
+                                    const uint64_t P0 = (uint64_t)o[k].x0 | ((uint64_t)o[k].x1 << 32);
+                                    const uint64_t P1 = (uint64_t)o[k].x2 | ((uint64_t)o[k].x3 << 32);
+                                    und = pa_bop3<PA_T3(PA_A & ~(PA_B | PA_C))>(und, P0, P1);
+                                } else {
+                                    apply_pair<D>(pc, o[k], (uint32_t)k, m4, m8,
+                                                  ((uint64_t)tl[2 * k] << 32) | tl[2 * k],
+                                                  ((uint64_t)tl[2 * k + 1] << 32) | tl[2 * k + 1], und, und, acc);
+                                }
                                 q = (uint32_t)k + 1;
                             }
                         calls += q;
@@ -692,7 +712,7 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
                                                             const PaBlk *__restrict__ map, int theta, uint32_t t0)
 {
     // dynamic LDS: lattice [N] u64 | queues [waves][3][kQueue] u64 | queue sites [waves][kQueue] u32 |
-    // 2D threshold-bit table [16][4] u32 | jmask [N]
+    // threshold-bit table [16][4 or 8] u32 | jmask [N]
     extern __shared__ uint64_t lat[];
     const PaBlk blk = map[blockIdx.x];
     const PaRunDesc &rd = runs[blk.run];
@@ -708,16 +728,16 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
     uint64_t *qbase = lat + N + (size_t)(tid >> 6) * 3 * kQueue;
     uint32_t *qsites = reinterpret_cast<uint32_t *>(lat + N + (size_t)nwaves * 3 * kQueue);
     uint32_t *ttab = qsites + (size_t)nwaves * kQueue;
-    uint8_t *jl = reinterpret_cast<uint8_t *>(ttab + (D == 2 ? kTtab : 0));
+    uint8_t *jl = reinterpret_cast<uint8_t *>(ttab + ttab_words<D>());
     uint64_t *g = rd.dv.spins[cur] + (size_t)w * N;
     const uint64_t T4 = uni64(rec->T[0]), T8 = uni64(rec->T[1]), T12 = uni64(rec->T[2]);
-    if (D == 2 && tid < 16) { // the threshold-bit masks of plane pair tid
+    if (tid < 16) { // the threshold-bit masks of plane pair tid
         const uint32_t b0 = 31u - 2u * (uint32_t)tid;
-        const uint32_t t[2] = {(uint32_t)T4, (uint32_t)T8};
+        const uint32_t t[3] = {(uint32_t)T4, (uint32_t)T8, (uint32_t)T12};
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            ttab[4 * tid + 2 * c] = (uint32_t)__builtin_amdgcn_sbfe((int)t[c], b0, 1u);
-            ttab[4 * tid + 2 * c + 1] = (uint32_t)__builtin_amdgcn_sbfe((int)t[c], b0 - 1u, 1u);
+        for (int c = 0; c < (D == 2 ? 2 : 3); ++c) {
+            ttab[ttab_stride<D>() * tid + 2 * c] = (uint32_t)__builtin_amdgcn_sbfe((int)t[c], b0, 1u);
+            ttab[ttab_stride<D>() * tid + 2 * c + 1] = (uint32_t)__builtin_amdgcn_sbfe((int)t[c], b0 - 1u, 1u);
         }
     }
     for (int s = tid; s < N; s += bs) {
@@ -751,19 +771,23 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
     const SweepGeom G = {L, N, half, nh, LL, mhalf, mL};
     const bool all_draw = draw4 != 0 && draw8 != 0 && (D == 2 || draw12 != 0);
     const bool fix = bs % (D == 2 ? L : LL) == 0;
+    // leading planes on which every drawing class's threshold bit is 0: the
+    // leading zeros of their thresholds' or (each drawing threshold is < 2^32)
+    const uint32_t tor = (uint32_t)((T4 & draw4) | (T8 & draw8) | (D == 3 ? (T12 & draw12) : 0ull));
+    const int zp = uni(min(kInlinePairs, (tor ? (int)__builtin_clz(tor) : 32) / 2));
     uint32_t calls;
     if (all_draw && fix)
         calls = sweep_columns<D, J, true, true>(lat, jl, G, pc, Q, theta, t0, sure4, sure8, sure12, draw4, draw8,
-                                                draw12);
+                                                draw12, zp);
     else if (all_draw)
         calls = sweep_columns<D, J, true, false>(lat, jl, G, pc, Q, theta, t0, sure4, sure8, sure12, draw4, draw8,
-                                                 draw12);
+                                                 draw12, zp);
     else if (fix)
         calls = sweep_columns<D, J, false, true>(lat, jl, G, pc, Q, theta, t0, sure4, sure8, sure12, draw4, draw8,
-                                                 draw12);
+                                                 draw12, zp);
     else
         calls = sweep_columns<D, J, false, false>(lat, jl, G, pc, Q, theta, t0, sure4, sure8, sure12, draw4, draw8,
-                                                  draw12);
+                                                  draw12, zp);
 
     // after the sweeps the queue region is free: per-wave partial counts of the measurement
     if (theta > 0) {
@@ -2418,6 +2442,19 @@ __global__ void k_set_beta(const PaRunDesc *__restrict__ runs, double beta, doub
     }
 }
 
+// Metropolis thresholds of every run set to those of `beta` (the autotuner
+// times sweeps at a temperature of the anneal; the populations are drawn
+// again afterwards).
+__global__ void k_tune_beta(const PaRunDesc *__restrict__ runs, double beta)
+{
+    PaRecord *rec = runs[blockIdx.x].dv.rec;
+    if (threadIdx.x == 0) {
+        rec->T[0] = pa_threshold(beta, 4);
+        rec->T[1] = pa_threshold(beta, 8);
+        rec->T[2] = pa_threshold(beta, 12);
+    }
+}
+
 // Generator throughput probe: Metropolis-purpose counters as the sweep forms
 // them, three independent chains per thread, outputs folded into one word.
 __global__ __launch_bounds__(kThreads) void k_philox_probe(uint32_t *__restrict__ out, int iters)
@@ -2457,7 +2494,8 @@ hipError_t sweep_launch(const PaBatchView &v, int g, int theta, int threads, uin
 // ====================================================================== launchers
 size_t pa_sweep_lds_bytes(int N, int d, int threads, bool J)
 {
-    return (size_t)N * 8 + (size_t)(threads / 64) * kQueue * (3 * 8 + 4) + (d == 2 ? kTtab * 4 : 0) +
+    return (size_t)N * 8 + (size_t)(threads / 64) * kQueue * (3 * 8 + 4) +
+           (size_t)(d == 2 ? ttab_words<2>() : ttab_words<3>()) * 4 +
            (J ? (((size_t)N + 7) & ~(size_t)7) : 0);
 }
 
@@ -2648,6 +2686,12 @@ hipError_t pa_b_set_beta(const PaBatchView &v, double beta, double lnZ, uint32_t
                          uint64_t R)
 {
     k_set_beta<<<v.nruns, 64, 0, v.stream>>>(v.runs, beta, lnZ, step, sweeps, R);
+    return hipGetLastError();
+}
+
+hipError_t pa_b_tune_beta(const PaBatchView &v, double beta)
+{
+    k_tune_beta<<<v.nruns, 64, 0, v.stream>>>(v.runs, beta);
     return hipGetLastError();
 }
 

@@ -135,7 +135,8 @@ def lib():
                                               P(ctypes.c_uint64)]
         L.pa_batch_create.argtypes = [P(pa_config), ctypes.c_int32, ctypes.c_int32, v,
                                       ctypes.c_uint64, v, P(v)]
-        L.pa_batch_tune.argtypes = [v, ctypes.c_int32, v]
+        L.pa_batch_tune.argtypes = [v, ctypes.c_int32, ctypes.c_double, v, v]
+        L.pa_batch_set_threads.argtypes = [v, ctypes.c_int32, ctypes.c_int32]
         L.pa_batch_groups.argtypes = [v, P(ctypes.c_int32), v]
         L.pa_batch_anneal.argtypes = [v, v, ctypes.c_int32, ctypes.c_int32, ctypes.c_int,
                                       ctypes.c_int32]
@@ -147,7 +148,7 @@ def lib():
         L.pa_batch_destroy.restype = None
         L.pa_batch_last_error.argtypes = [v]
         L.pa_batch_last_error.restype = ctypes.c_char_p
-        for name in ("pa_batch_required_bytes", "pa_batch_create", "pa_batch_tune",
+        for name in ("pa_batch_required_bytes", "pa_batch_create", "pa_batch_tune", "pa_batch_set_threads",
                      "pa_batch_groups", "pa_batch_anneal", "pa_batch_records",
                      "pa_batch_export_run", "pa_batch_combine", "pa_batch_overlap"):
             getattr(L, name).restype = ctypes.c_int
@@ -507,10 +508,22 @@ class PABatch:
         _check_b(lib().pa_batch_groups(self.h, ctypes.byref(ng), t.ctypes.data), self.h)
         return t[:ng.value].tolist()
 
-    def tune(self, theta=10):
+    def tune(self, theta=10, beta=1.0, times=False):
+        """Autotunes each group's sweep workgroup size with theta sweeps at the
+        thresholds of beta; returns the chosen sizes (and, with times=True, a
+        dict {group: {threads: ms}} of every candidate's time)."""
         t = np.zeros(16, np.int32)
-        _check_b(lib().pa_batch_tune(self.h, int(theta), t.ctypes.data), self.h)
-        return self.groups()
+        ms = np.zeros(16 * 12, np.float32)
+        _check_b(lib().pa_batch_tune(self.h, int(theta), float(beta), t.ctypes.data, ms.ctypes.data), self.h)
+        chosen = self.groups()
+        if not times:
+            return chosen
+        tab = {g: {64 * (k + 1): float(ms[g * 12 + k]) for k in range(12) if ms[g * 12 + k] >= 0}
+               for g in range(len(chosen))}
+        return chosen, tab
+
+    def set_threads(self, group, threads):
+        _check_b(lib().pa_batch_set_threads(self.h, int(group), int(threads)), self.h)
 
     def anneal(self, betas, theta, scheme, use_graph=True):
         b = np.ascontiguousarray(betas, np.float64)

@@ -155,3 +155,27 @@ def test_weighted_combination_matches_oracle():
                       "e_plain", "c_plain", "chi_plain"):
                 assert rel_ok(out[g][k], ref[k], 1e-12), (point, g, k, out[g][k], ref[k])
     B.close()
+
+
+def test_tune_at_a_temperature_and_pinned_sizes_change_nothing():
+    """The autotuner times every usable workgroup size at the thresholds of a
+    given beta and reports the times; any size set by hand gives the same bits."""
+    from paper_2401_07965_amd import pa
+    betas = schedule(2.0, 9)
+    cfgs = configs(seed=6)
+    B = pa.PABatch(cfgs, max_points=len(betas))
+    B.anneal(betas, 3, O.SYSTEMATIC, use_graph=False)
+    ref = B.records().copy()
+    chosen, times = B.tune(3, 1.2, times=True)
+    for g, t in enumerate(chosen):
+        assert t in times[g] and times[g][t] == min(times[g].values()) and times[g][t] > 0
+    for g in range(len(chosen)):
+        for t in sorted(times[g])[::3]:
+            B.set_threads(g, t)
+            B.anneal(betas, 3, O.SYSTEMATIC, use_graph=False)
+            assert np.array_equal(B.records(), ref), (g, t)
+    with pytest.raises(pa.PAError):
+        B.set_threads(0, 100)  # not a multiple of 64
+    with pytest.raises(pa.PAError):
+        B.set_threads(99, 64)  # no such group
+    B.close()
