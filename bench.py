@@ -548,18 +548,20 @@ def batched_bench(theta=10, scheme=3, plain_streams=8):
 
 
 def learned_bench(theta=10, scheme=3, astar=0.7, dmax=0.2, beta_f=3.0, Reval=1000000, Rtrain=10000,
-                  runs=16, records=2000):
+                  runs=16, records=2000, bracket=1.25, refine=6):
     """Learned-schedule workload: 3D +-J glass L = 16, beta 0 -> 3, theta = 10,
     systematic.  Training data: (features, ln dbeta) records of rule-driven
     anneals at R = 10^4 of other disorder samples (coupling seeds 2, 3, ...)
     until `records` records exist; the model is trained on the GPU.
     Evaluation on the sample of coupling seed 1 at R = 10^6: `runs` anneals
     (run_id 0..runs-1) with the overlap rule alone and as many with the
-    learned step (exact overlap check, rule fallback).  Reported per schedule:
-    mean and spread of the wall time, steps, fallbacks, and the RMSD of
-    ln Z_hat at beta = 3 against the reference, the free-energy-weighted
-    combination (Eq. (10), equal R) of all 2 x `runs` anneals, with the RMSD's
-    standard error."""
+    learned step (the model's proposal refined in a bracket by a few exact
+    overlap evaluations, the rule as fallback), both driven by deferred calls
+    (only the step choice waits for the device).  Reported per schedule: mean
+    and spread of the wall time, steps, fallbacks, the spread of ln Z_hat at
+    beta = 3 over the runs and its mean, and the RMSD against the reference,
+    the free-energy-weighted combination (Eq. (10), equal R) of all
+    2 x `runs` anneals, with standard errors."""
     import numpy as np
     import torch
     from paper_2401_07965_amd import pa, workloads
@@ -594,7 +596,8 @@ def learned_bench(theta=10, scheme=3, astar=0.7, dmax=0.2, beta_f=3.0, Reval=100
             run = pa.PARun(d, Ls, Reval, seed=1, run_id=k, couplings=J)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            o = anneal_adaptive(run, beta_f, astar, dmax, theta, scheme, mlp=model)
+            o = anneal_adaptive(run, beta_f, astar, dmax, theta, scheme, mlp=model, bracket=bracket,
+                                refine=refine, deferred=True, sync=torch.cuda.synchronize)
             torch.cuda.synchronize()
             wall.append(time.perf_counter() - t0)
             steps.append(o["steps"])
@@ -612,9 +615,12 @@ def learned_bench(theta=10, scheme=3, astar=0.7, dmax=0.2, beta_f=3.0, Reval=100
         rmsd = float(np.sqrt(dev2.mean()))
         # standard error of the RMSD from that of the mean squared deviation
         se = float(dev2.std(ddof=1) / np.sqrt(len(dev2)) / (2 * rmsd)) if rmsd > 0 else 0.0
+        sd = float(p["lnz"].std(ddof=1))
         res[name] = {"wall_s_mean": float(p["wall"].mean()), "wall_s_sd": float(p["wall"].std(ddof=1)),
                      "steps_mean": float(p["steps"].mean()), "schedule_s_mean": float(p["sched"].mean()),
                      "fallbacks_mean": float(p["fb"].mean()),
+                     "lnZ_mean": float(p["lnz"].mean()), "lnZ_mean_se": sd / math.sqrt(len(p["lnz"])),
+                     "lnZ_sd": sd, "lnZ_sd_se": sd / math.sqrt(2 * (len(p["lnz"]) - 1)),
                      "rmsd_lnZ": rmsd, "rmsd_lnZ_se": se,
                      "mean_lnZ_minus_reference": float((p["lnz"] - ref).mean())}
     r, l = res["rule"], res["learned"]
@@ -622,6 +628,10 @@ def learned_bench(theta=10, scheme=3, astar=0.7, dmax=0.2, beta_f=3.0, Reval=100
     res["wall_speedup_se"] = res["wall_speedup"] * math.hypot(
         r["wall_s_sd"] / math.sqrt(runs) / r["wall_s_mean"], l["wall_s_sd"] / math.sqrt(runs) / l["wall_s_mean"])
     res["rmsd_ratio_learned_over_rule"] = l["rmsd_lnZ"] / r["rmsd_lnZ"] if r["rmsd_lnZ"] > 0 else None
+    res["lnZ_sd_ratio_learned_over_rule"] = l["lnZ_sd"] / r["lnZ_sd"] if r["lnZ_sd"] > 0 else None
+    res["lnZ_mean_difference"] = l["lnZ_mean"] - r["lnZ_mean"]
+    res["lnZ_mean_difference_se"] = math.hypot(l["lnZ_mean_se"], r["lnZ_mean_se"])
+    res["learned_step"] = f"proposal refined in a bracket of {bracket} by {refine} halvings, rule as fallback"
     res["reference"] = f"weighted combination (Eq. (10), equal R) of all {2 * runs} anneals' ln Z_hat at beta = 3"
     res["workload"] = (f"3D +-J L=16 (couplings seed 1), R={Reval}, beta 0->3, alpha*={astar}, dbeta_max={dmax}, "
                        f"theta={theta}, systematic; {runs} run_ids per schedule; trained on {len(y)} records of "

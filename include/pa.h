@@ -435,11 +435,21 @@ pa_status pa_mlp_predict(pa_mlp *m, const float *X, int32_t n, float *dbeta_out)
 /* The model inputs of the current population (uses the family entropy of
  * the latest pa_observables). */
 pa_status pa_features(pa_ctx *ctx, float *out8);
-/* Learned step: the model's proposal, clamped to (0, dbeta_max], is taken if
- * alpha(proposal) >= alpha_star (exact check as in pa_step_rule); otherwise
- * pa_step_rule's bisection decides and *fallback_out = 1. */
-pa_status pa_step_learned(pa_ctx *ctx, pa_mlp *m, double alpha_star, double dbeta_max,
-                          int32_t iterations, double *dbeta_out, int32_t *fallback_out);
+/* Learned step: the model's proposal c = min(prediction, dbeta_max) is kept
+ * only where alpha(c) >= alpha_star (exact check as in pa_step_rule).
+ * refine = 0: c itself if it qualifies.  refine > 0 (bracket > 1): the
+ * proposal seeds a short exact search instead: if c qualifies, the top of
+ * [c, min(bracket c, dbeta_max)] if that qualifies, else that bracket halved
+ * `refine` times keeping the lower end qualified; if c does not qualify but
+ * c / bracket does, [c / bracket, c] halved `refine` times.  Where none of
+ * this applies (c <= 0, or neither end qualifies) pa_step_rule's bisection
+ * over [0, dbeta_max] with `iterations` halvings decides and
+ * *fallback_out = 1.  Every step returned has alpha >= alpha_star.
+ * 1 <= iterations <= 200, 0 <= refine <= 64, bracket >= 1.
+ * proposal_out (optional): c.  Synchronises the stream. */
+pa_status pa_step_learned(pa_ctx *ctx, pa_mlp *m, double alpha_star, double dbeta_max, int32_t iterations,
+                          double bracket, int32_t refine, double *dbeta_out, int32_t *fallback_out,
+                          double *proposal_out);
 void pa_mlp_destroy(pa_mlp *m);
 const char *pa_mlp_last_error(const pa_mlp *m);
 

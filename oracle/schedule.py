@@ -64,3 +64,39 @@ def step_rule(E, alpha_star, dbeta_max, iterations=60):
         else:
             hi = mid
     return lo
+
+
+def learned_step(E, cand, alpha_star, dbeta_max, iterations=60, bracket=1.0, refine=0):
+    """The learned step's exact check of a proposal (reading of the adaptive
+    step with a learned proposal; the rule stays the arbiter).
+
+    c = min(cand, dbeta_max).  refine = 0: c if alpha(c) >= alpha_star.
+    refine > 0: if c qualifies, the top of [c, min(bracket c, dbeta_max)] if
+    it qualifies, else that interval halved `refine` times keeping the lower
+    end qualified; if c fails but c / bracket qualifies, [c / bracket, c]
+    halved `refine` times.  Otherwise (or c <= 0) the rule decides.
+    Returns (dbeta, fallback)."""
+    A = target(alpha_star)
+    c = min(float(cand), float(dbeta_max))
+    if c > 0.0:
+        ok = qualifies(E, c, A)
+        if ok and (refine == 0 or c >= dbeta_max):
+            return c, False
+        if refine > 0:
+            if ok:
+                lo, hi = c, min(bracket * c, float(dbeta_max))
+                if qualifies(E, hi, A):
+                    return hi, False
+                inside = True
+            else:
+                lo, hi = c / bracket, c
+                inside = qualifies(E, lo, A)
+            if inside:
+                for _ in range(refine):
+                    mid = 0.5 * (lo + hi)
+                    if qualifies(E, mid, A):
+                        lo = mid
+                    else:
+                        hi = mid
+                return lo, False
+    return step_rule(E, alpha_star, dbeta_max, iterations), True

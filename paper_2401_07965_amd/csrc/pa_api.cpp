@@ -1604,14 +1604,17 @@ pa_status pa_features(pa_ctx *c, float *out8)
 }
 
 pa_status pa_step_learned(pa_ctx *c, pa_mlp *m, double alpha_star, double dbeta_max, int32_t iterations,
-                          double *dbeta_out, int32_t *fallback_out)
+                          double bracket, int32_t refine, double *dbeta_out, int32_t *fallback_out,
+                          double *proposal_out)
 {
     if (!c)
         return fail(nullptr, PA_E_INVAL, "ctx is NULL");
     Batch *b = &c->b;
     if (!m || !dbeta_out || !(alpha_star > 0.0 && alpha_star < 1.0) || !std::isfinite(dbeta_max) ||
-        dbeta_max <= 0.0 || iterations < 1 || iterations > 200)
-        return fail(b, PA_E_INVAL, "need a model, 0 < alpha_star < 1, dbeta_max > 0, 1 <= iterations <= 200");
+        dbeta_max <= 0.0 || iterations < 1 || iterations > 200 || !std::isfinite(bracket) || bracket < 1.0 ||
+        refine < 0 || refine > 64)
+        return fail(b, PA_E_INVAL, "need a model, 0 < alpha_star < 1, dbeta_max > 0, 1 <= iterations <= 200, "
+                                   "bracket >= 1, 0 <= refine <= 64");
     pa_status u = need_uniform(b, "pa_step_learned");
     if (u != PA_OK)
         return u;
@@ -1625,7 +1628,7 @@ pa_status pa_step_learned(pa_ctx *c, pa_mlp *m, double alpha_star, double dbeta_
     if (e == hipSuccess)
         e = pa_mlp_launch_propose(b->v, m->d, dbeta_max);
     if (e == hipSuccess)
-        e = pa_b_check_candidate(b->v, alpha_star, dbeta_max, iterations);
+        e = pa_b_check_candidate(b->v, alpha_star, dbeta_max, iterations, bracket, refine);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_step_learned");
     pa_status s = ctx_records(b, "pa_step_learned");
@@ -1634,6 +1637,8 @@ pa_status pa_step_learned(pa_ctx *c, pa_mlp *m, double alpha_star, double dbeta_
     *dbeta_out = b->hrec[0].rule_dbeta;
     if (fallback_out)
         *fallback_out = (int32_t)b->hrec[0].fallback;
+    if (proposal_out)
+        *proposal_out = b->hrec[0].cand_dbeta;
     return PA_OK;
 }
 

@@ -204,7 +204,8 @@ hipError_t pa_noalloc_scratch(int device, unsigned long long **out);
 hipError_t pa_launch_overlap(const PaRunDesc *a, const PaRunDesc *b, int N, uint32_t ncols_a,
                              unsigned long long *hist, hipStream_t st);
 hipError_t pa_b_features(const PaBatchView &v);
-hipError_t pa_b_check_candidate(const PaBatchView &v, double alpha_star, double dbeta_max, int iterations);
+hipError_t pa_b_check_candidate(const PaBatchView &v, double alpha_star, double dbeta_max, int iterations,
+                                double bracket, int refine);
 hipError_t pa_mlp_launch_grad(const PaMlpDev &m, int n, int adam, int t, float lr);
 hipError_t pa_mlp_launch_predict(const PaMlpDev &m, const float *X, int n, float *out);
 hipError_t pa_mlp_launch_propose(const PaBatchView &v, const PaMlpDev &m, double dbeta_max);

@@ -1301,8 +1301,17 @@ __global__ __launch_bounds__(kRuleThreads) void k_features(const PaRunDesc *__re
 
 // The learned proposal is kept if it passes the exact overlap check;
 // otherwise the bisection of the rule decides (fallback).
+// The learned step's exact check: the model's proposal c (clamped to
+// dbeta_max) is kept only where alpha >= alpha*.  With refine > 0 it seeds a
+// short search instead of being taken as it is: if c qualifies, the bracket
+// [c, min(bracket c, dbeta_max)] (whose top is taken if it qualifies), else
+// [c / bracket, c] if its bottom qualifies, is halved `refine` times keeping
+// the lower end qualified.  Where neither applies (or c <= 0) the rule itself
+// decides: the bisection of k_rule over [0, dbeta_max] (the fallback).
+// Every value returned has alpha >= alpha*, tested exactly.
 __global__ __launch_bounds__(kRuleThreads) void k_check_candidate(const PaRunDesc *__restrict__ runs,
-                                                                  double alpha_star, double dbeta_max, int iterations)
+                                                                  double alpha_star, double dbeta_max, int iterations,
+                                                                  double bracket, int refine)
 {
     __shared__ uint64_t su[16];
     __shared__ uint64_t wcache[kRuleCache];
@@ -1316,16 +1325,55 @@ __global__ __launch_bounds__(kRuleThreads) void k_check_candidate(const PaRunDes
     const uint64_t R = rec->Rcur;
     const uint64_t A = (uint64_t)rint(ldexp(alpha_star, 32));
     const double cand = rec->cand_dbeta;
-    const Overlap oc = rule_overlap(rd.dv.hist, hmin, nlev, R, cand, wcache, su);
-    if (cand > 0.0 && qualifies(oc, A)) {
+    auto overlap = [&](double db) { return rule_overlap(rd.dv.hist, hmin, nlev, R, db, wcache, su); };
+    auto publish = [&](double db, const Overlap &o, uint32_t fb) {
         if (threadIdx.x == 0) {
-            rec->rule_dbeta = cand;
-            rec->rule_alpha = u128_to_double(oc.num) / u128_to_double(oc.den);
-            rec->fallback = 0;
+            rec->rule_dbeta = db;
+            rec->rule_alpha = u128_to_double(o.num) / u128_to_double(o.den);
+            rec->fallback = fb;
         }
-        return;
+    };
+    if (cand > 0.0) {
+        const Overlap oc = overlap(cand);
+        const bool ok = qualifies(oc, A);
+        if (ok && (refine == 0 || cand >= dbeta_max)) {
+            publish(cand, oc, 0u);
+            return;
+        }
+        if (refine > 0) {
+            double lo = cand, hi = cand;
+            Overlap olo = oc;
+            bool bracketed = false;
+            if (ok) {
+                hi = bracket * cand < dbeta_max ? bracket * cand : dbeta_max;
+                const Overlap oh = overlap(hi);
+                if (qualifies(oh, A)) {
+                    publish(hi, oh, 0u);
+                    return;
+                }
+                bracketed = true;
+            } else {
+                lo = cand / bracket;
+                olo = overlap(lo);
+                bracketed = qualifies(olo, A);
+            }
+            if (bracketed) {
+                for (int it = 0; it < refine; ++it) {
+                    const double mid = 0.5 * (lo + hi);
+                    const Overlap om = overlap(mid);
+                    if (qualifies(om, A)) {
+                        lo = mid;
+                        olo = om;
+                    } else {
+                        hi = mid;
+                    }
+                }
+                publish(lo, olo, 0u);
+                return;
+            }
+        }
     }
-    const Overlap top = rule_overlap(rd.dv.hist, hmin, nlev, R, dbeta_max, wcache, su);
+    const Overlap top = overlap(dbeta_max);
     double best = dbeta_max;
     Overlap obest = top;
     if (!qualifies(top, A)) {
@@ -1333,7 +1381,7 @@ __global__ __launch_bounds__(kRuleThreads) void k_check_candidate(const PaRunDes
         obest.num = obest.den = 1;
         for (int it = 0; it < iterations; ++it) {
             const double mid = 0.5 * (lo + hi);
-            const Overlap om = rule_overlap(rd.dv.hist, hmin, nlev, R, mid, wcache, su);
+            const Overlap om = overlap(mid);
             if (qualifies(om, A)) {
                 lo = mid;
                 obest = om;
@@ -1343,11 +1391,7 @@ __global__ __launch_bounds__(kRuleThreads) void k_check_candidate(const PaRunDes
         }
         best = lo;
     }
-    if (threadIdx.x == 0) {
-        rec->rule_dbeta = best;
-        rec->rule_alpha = u128_to_double(obest.num) / u128_to_double(obest.den);
-        rec->fallback = 1;
-    }
+    publish(best, obest, 1u);
 }
 
 // ------------------------------------------------------------------ resampling
@@ -2620,9 +2664,11 @@ hipError_t pa_b_features(const PaBatchView &v)
 }
 
 // after pa_b_features and the model's proposal (the histogram is current)
-hipError_t pa_b_check_candidate(const PaBatchView &v, double alpha_star, double dbeta_max, int iterations)
+hipError_t pa_b_check_candidate(const PaBatchView &v, double alpha_star, double dbeta_max, int iterations,
+                                double bracket, int refine)
 {
-    k_check_candidate<<<v.nruns, kRuleThreads, 0, v.stream>>>(v.runs, alpha_star, dbeta_max, iterations);
+    k_check_candidate<<<v.nruns, kRuleThreads, 0, v.stream>>>(v.runs, alpha_star, dbeta_max, iterations, bracket,
+                                                              refine);
     return hipGetLastError();
 }
 

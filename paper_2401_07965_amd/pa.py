@@ -160,8 +160,8 @@ def lib():
         L.pa_mlp_params.argtypes = [v, v]
         L.pa_mlp_predict.argtypes = [v, v, ctypes.c_int32, v]
         L.pa_features.argtypes = [v, v]
-        L.pa_step_learned.argtypes = [v, v, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
-                                      P(ctypes.c_double), P(ctypes.c_int32)]
+        L.pa_step_learned.argtypes = [v, v, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                      ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int32), P(ctypes.c_double)]
         L.pa_mlp_destroy.argtypes = [v]
         L.pa_mlp_destroy.restype = None
         L.pa_mlp_last_error.argtypes = [v]
@@ -452,11 +452,17 @@ class PARun:
         _check(lib().pa_features(self.ctx, out.ctypes.data), self.ctx)
         return out
 
-    def step_learned(self, mlp, alpha_star, dbeta_max, iterations=60):
+    def step_learned(self, mlp, alpha_star, dbeta_max, iterations=60, bracket=1.0, refine=0, proposal=False):
+        """(dbeta, fallback) of pa_step_learned; with proposal=True also the
+        model's clamped proposal."""
         d = ctypes.c_double()
         fb = ctypes.c_int32()
-        _check(lib().pa_step_learned(self.ctx, mlp.h, float(alpha_star), float(dbeta_max),
-                                     int(iterations), ctypes.byref(d), ctypes.byref(fb)), self.ctx)
+        c = ctypes.c_double()
+        _check(lib().pa_step_learned(self.ctx, mlp.h, float(alpha_star), float(dbeta_max), int(iterations),
+                                     float(bracket), int(refine), ctypes.byref(d), ctypes.byref(fb),
+                                     ctypes.byref(c)), self.ctx)
+        if proposal:
+            return d.value, bool(fb.value), c.value
         return d.value, bool(fb.value)
 
     def close(self):

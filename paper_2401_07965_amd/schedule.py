@@ -19,8 +19,15 @@ class NoStepError(RuntimeError):
 
 
 def anneal_adaptive(run, beta_f, alpha_star, dbeta_max, theta, scheme, mlp=None, record=False,
-                    iterations=60, sync=None, max_steps=100000):
+                    iterations=60, sync=None, max_steps=100000, bracket=1.0, refine=0, deferred=False):
     """Anneal ``run`` (a fresh pa.PARun) from beta 0 to beta_f.
+
+    Each step's dbeta comes from the overlap rule or, with ``mlp``, from the
+    learned step (its proposal checked exactly, refined in ``bracket`` with
+    ``refine`` halvings, the rule as fallback).  With ``deferred`` the
+    reweighting, resampling and observables of a step are enqueued without
+    waiting; only the step choice waits for the device.  ``sync`` (if given)
+    runs before each step choice is timed.
 
     Returns a dict: steps, lnZ (at beta_f), schedule_s (time spent choosing
     steps), fallbacks, betas (the schedule taken) and, if ``record``, X
@@ -46,7 +53,7 @@ def anneal_adaptive(run, beta_f, alpha_star, dbeta_max, theta, scheme, mlp=None,
         if mlp is None:
             d = run.step_rule(alpha_star, dbeta_max, iterations)
         else:
-            d, fb = run.step_learned(mlp, alpha_star, dbeta_max, iterations)
+            d, fb = run.step_learned(mlp, alpha_star, dbeta_max, iterations, bracket, refine)
             fallbacks += int(fb)
         t_sched += time.perf_counter() - t0
         nxt = min(beta + d, beta_f) if d > 0.0 else beta
@@ -57,10 +64,10 @@ def anneal_adaptive(run, beta_f, alpha_star, dbeta_max, theta, scheme, mlp=None,
             y.append(math.log(d))
         beta = nxt
         betas.append(beta)
-        run.reweight(beta)
-        run.resample(scheme)
+        run.reweight(beta, wait=not deferred)
+        run.resample(scheme, wait=not deferred)
         run.sweep(theta)
-        run.observables()
+        run.observables(wait=not deferred)
         steps += 1
     out = dict(steps=steps, lnZ=run.free_energy(), schedule_s=t_sched, fallbacks=fallbacks, betas=betas)
     if record:

@@ -111,4 +111,13 @@ def test_features_and_learned_check():
             assert d == float(np.exp(np.float32(0.0) * 1.0 + logd)) or rel_ok(d, 1e-4, 1e-6)
             assert S.qualifies(st["energy"], d, S.target(0.8))
         m.close()
+    # proposals refined in a bracket: exactly the oracle's steps, fallbacks included
+    rule = S.step_rule(st["energy"], 0.8, 0.5, 60)
+    for f in (0.02, 0.5, 0.9, 0.99, 1.0, 1.01, 1.1, 1.3, 5.0):
+        m = pa.PAMlp(p, np.zeros(8), np.ones(8), math.log(f * rule), 1.0, max_samples=8)
+        for bracket, refine in ((1.25, 6), (2.0, 10), (1.0, 0)):
+            d, fb, c = g.step_learned(m, 0.8, 0.5, 60, bracket, refine, proposal=True)
+            ref, rfb = S.learned_step(st["energy"], c, 0.8, 0.5, 60, bracket, refine)
+            assert (d, fb) == (ref, rfb), (f, bracket, refine, d, ref)
+        m.close()
     g.close()

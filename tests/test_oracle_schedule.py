@@ -71,3 +71,52 @@ def test_step_rule_brackets_the_target(astar):
     assert not S.qualifies(E, d + 1e-12, A)
     # a tiny population spread admits the whole range
     assert S.step_rule(np.full(10, -40), astar, dmax) == dmax
+
+
+def _population(seed, R=4000):
+    return np.random.default_rng(seed).normal(-3000, 40, R).round().astype(np.int64) * 4
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_learned_step_is_exactly_checked_and_near_the_rule(seed):
+    """Whatever the proposal, the learned step returns a step with
+    alpha >= alpha*; refined from a bracket, it lies within the bracket's
+    width / 2^refine below the largest qualifying step (the 200-halving rule:
+    alpha falls with the step, so every qualifying step is below it and the
+    halving keeps it inside the bracket)."""
+    E = _population(seed)
+    astar, dmax = 0.7, 0.05
+    A = S.target(astar)
+    best = S.step_rule(E, astar, dmax, 200)
+    for f in (0.3, 0.8, 0.97, 1.0, 1.03, 1.15, 3.0, 40.0):
+        cand = f * best
+        for bracket, refine in ((1.0, 0), (1.25, 6), (1.25, 12), (2.0, 8)):
+            d, fb = S.learned_step(E, cand, astar, dmax, 60, bracket, refine)
+            assert S.qualifies(E, d, A), (f, bracket, refine)
+            assert d <= best * (1 + 1e-12)
+            if fb:
+                assert d == S.step_rule(E, astar, dmax, 60)
+            elif refine == 0:
+                assert d == min(cand, dmax)
+            else:
+                c = min(cand, dmax)
+                lo = c if S.qualifies(E, c, A) else c / bracket
+                hi = min(bracket * c, dmax) if S.qualifies(E, c, A) else c
+                assert lo <= best <= hi or d == hi
+                if lo <= best <= hi and d != hi:  # the bracket holds the best step
+                    assert best - d <= (hi - lo) / 2 ** refine * (1 + 1e-12)
+        # a proposal within the bracket of the best step never falls back
+        if 1 / 1.25 < f <= 1.0 or 1.0 < f < 1.25:
+            assert not S.learned_step(E, cand, astar, dmax, 60, 1.25, 6)[1]
+
+
+def test_learned_step_falls_back_outside_the_bracket_and_for_no_proposal():
+    E = _population(5)
+    astar, dmax = 0.8, 0.05
+    rule = S.step_rule(E, astar, dmax, 60)
+    for cand in (0.0, -1.0, 3.0 * rule):
+        d, fb = S.learned_step(E, cand, astar, dmax, 60, 1.25, 6)
+        assert fb and d == rule
+    # dbeta_max itself qualifies: a proposal above it is clamped and kept
+    d, fb = S.learned_step(E, 1.0, astar, 1e-6, 60, 1.25, 6)
+    assert not fb and d == 1e-6

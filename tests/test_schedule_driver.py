@@ -19,6 +19,9 @@ class FakeRun:
     def step_rule(self, alpha_star, dbeta_max, iterations=60):
         return self.steps.pop(0) if self.steps else dbeta_max
 
+    def step_learned(self, mlp, alpha_star, dbeta_max, iterations=60, bracket=1.0, refine=0):
+        return self.step_rule(alpha_star, dbeta_max, iterations), False
+
     def reweight(self, beta, wait=True):
         self.betas.append(beta)
 
@@ -53,3 +56,9 @@ def test_step_cap():
     with pytest.raises(NoStepError):
         anneal_adaptive(run, 1.0, 0.7, 0.5, 1, 3, max_steps=10)
     assert len(run.betas) == 10
+
+
+def test_learned_and_deferred_paths_sequence_the_same_calls():
+    run = FakeRun([0.5, 0.5])
+    out = anneal_adaptive(run, 1.0, 0.7, 0.5, 1, 3, mlp=object(), bracket=1.25, refine=6, deferred=True)
+    assert run.betas == [0.5, 1.0] and out["fallbacks"] == 0 and out["steps"] == 2
