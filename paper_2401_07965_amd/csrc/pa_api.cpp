@@ -191,10 +191,12 @@ struct Batch {
     uint32_t sweeps = 0;
     bool reweighted = false;
     int anneal_points = 0;
-    // launch bookkeeping: the level histogram is zero (init or observables
-    // ran since it was last built); the latest launch was a reweighting, which
-    // also prepared the resampling's flags and status
-    bool hist_clean = false;
+    // launch bookkeeping: the state of the runs' level histograms (PA_HIST_*:
+    // the observables pass builds them from zero, so do the step rule and the
+    // reweighting when they find them not valid; the reweighting clears them
+    // after use); the latest launch was a reweighting, which also prepared the
+    // resampling's flags and status
+    int hist_state = PA_HIST_STALE;
     bool rs_prepped = false;
     // the latest anneal captured as a HIP graph, replayed while the anneal's
     // arguments (schedule, theta, scheme) and the groups' workgroup sizes stay
@@ -203,6 +205,8 @@ struct Batch {
     std::vector<double> anneal_betas;
     int anneal_theta = -1, anneal_scheme = -1;
     std::vector<int> anneal_threads;
+    int anneal_end_hist = PA_HIST_STALE; // bookkeeping after the captured anneal
+    bool anneal_end_rs = false;
 };
 
 namespace {
@@ -210,16 +214,16 @@ namespace {
 // Launch wrappers that keep the bookkeeping above.
 hipError_t launch_init(Batch *b)
 {
-    hipError_t e = pa_b_init(b->v);
-    b->hist_clean = true;
+    hipError_t e = pa_b_init(b->v); // clears the histograms
+    b->hist_state = PA_HIST_ZERO;
     b->rs_prepped = false;
     return e;
 }
 
 hipError_t launch_reweight(Batch *b, double beta_next)
 {
-    hipError_t e = pa_b_reweight(b->v, beta_next, b->hist_clean);
-    b->hist_clean = false;
+    hipError_t e = pa_b_reweight(b->v, beta_next, b->hist_state);
+    b->hist_state = PA_HIST_ZERO;
     b->rs_prepped = true;
     return e;
 }
@@ -228,21 +232,40 @@ hipError_t launch_resample(Batch *b, int scheme, int freeze, int kq)
 {
     hipError_t e = pa_b_resample(b->v, scheme, freeze, kq, b->rs_prepped);
     b->rs_prepped = false;
+    if (b->hist_state == PA_HIST_VALID) // a histogram of the replaced population
+        b->hist_state = PA_HIST_STALE;
     return e;
 }
 
+// The observables pass also builds the level histogram unless it is valid.
 hipError_t launch_observables(Batch *b, int point)
 {
-    hipError_t e = pa_b_observables(b->v, point);
-    b->hist_clean = true;
+    hipError_t e = pa_b_observables(b->v, point, b->hist_state);
+    b->hist_state = PA_HIST_VALID;
     b->rs_prepped = false;
     return e;
 }
 
-// Kernels that build the histogram themselves, or replace the population.
-void touched_histogram(Batch *b)
+// Sweeps (cluster updates: cluster != 0) of every run change the energies.
+hipError_t launch_updates(Batch *b, int n, uint32_t t0, int cluster)
 {
-    b->hist_clean = false;
+    hipError_t e = cluster ? pa_b_cluster(b->v, n, t0) : pa_b_sweep(b->v, n, t0);
+    if (b->hist_state == PA_HIST_VALID)
+        b->hist_state = PA_HIST_STALE;
+    return e;
+}
+
+// The step rule and the learned step build the histogram when it is not valid.
+void histogram_built(Batch *b)
+{
+    b->hist_state = PA_HIST_VALID;
+    b->rs_prepped = false;
+}
+
+// An imported population: the histogram describes another one.
+void population_replaced(Batch *b)
+{
+    b->hist_state = PA_HIST_STALE;
     b->rs_prepped = false;
 }
 
@@ -679,7 +702,7 @@ pa_status pa_sweep(pa_ctx *c, int32_t theta)
         return fail(b, PA_E_INVAL, "more than 2^20 sweeps at one temperature");
     if (theta == 0)
         return PA_OK;
-    hipError_t e = pa_b_sweep(b->v, theta, b->sweeps);
+    hipError_t e = launch_updates(b, theta, b->sweeps, 0);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_sweep");
     b->sweeps += (uint32_t)theta;
@@ -701,7 +724,7 @@ pa_status pa_cluster(pa_ctx *c, int32_t nsteps)
             return fail(b, PA_E_INVAL, "lattice too large for cluster updates (LDS of one workgroup)");
     if (nsteps == 0)
         return PA_OK;
-    hipError_t e = pa_b_cluster(b->v, nsteps, b->sweeps);
+    hipError_t e = launch_updates(b, nsteps, b->sweeps, 1);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_cluster");
     b->sweeps += (uint32_t)nsteps;
@@ -933,7 +956,7 @@ pa_status pa_import_state(pa_ctx *c, const pa_host_state *st)
         e = hipMemcpy(d.dv.label[k], st->label, (size_t)R * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = pa_b_set_beta(b->v, st->beta, st->lnZ, st->step, st->sweeps, (uint64_t)R);
-    touched_histogram(b);
+    population_replaced(b);
     if (e == hipSuccess)
         e = hipStreamSynchronize(b->v.stream);
     if (e != hipSuccess)
@@ -1021,8 +1044,8 @@ pa_status pa_step_alpha(pa_ctx *c, double dbeta, double *alpha_out)
     pa_status u = need_uniform(b, "pa_step_alpha");
     if (u != PA_OK)
         return u;
-    touched_histogram(b);
-    hipError_t e = pa_b_rule(b->v, 0.0, dbeta, 0, 0);
+    hipError_t e = pa_b_rule(b->v, 0.0, dbeta, 0, 0, b->hist_state);
+    histogram_built(b);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_step_alpha");
     pa_status s = ctx_records(b, "pa_step_alpha");
@@ -1043,8 +1066,8 @@ pa_status pa_step_rule(pa_ctx *c, double alpha_star, double dbeta_max, int32_t i
     pa_status u = need_uniform(b, "pa_step_rule");
     if (u != PA_OK)
         return u;
-    touched_histogram(b);
-    hipError_t e = pa_b_rule(b->v, alpha_star, dbeta_max, iterations, 1);
+    hipError_t e = pa_b_rule(b->v, alpha_star, dbeta_max, iterations, 1, b->hist_state);
+    histogram_built(b);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_step_rule");
     pa_status s = ctx_records(b, "pa_step_rule");
@@ -1235,8 +1258,8 @@ pa_status pa_batch_anneal(pa_batch *p, const double *betas, int32_t npoints, int
             e = hipStreamSynchronize(st);
         if (e != hipSuccess)
             return hip_fail(b, e, "pa_batch_anneal (replay)");
-        b->hist_clean = true; // as left by the anneal's last launch, the observables pass
-        b->rs_prepped = false;
+        b->hist_state = b->anneal_end_hist; // as the captured anneal left the bookkeeping
+        b->rs_prepped = b->anneal_end_rs;
         b->anneal_points = npoints;
         return PA_OK;
     }
@@ -1246,7 +1269,6 @@ pa_status pa_batch_anneal(pa_batch *p, const double *betas, int32_t npoints, int
     hipGraphExec_t exec = nullptr;
     if (use_graph)
         e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-    const PaBatchView &v = b->v; // record rows keep the stride max_points
     if (e == hipSuccess)
         e = launch_init(b);
     if (e == hipSuccess)
@@ -1256,7 +1278,7 @@ pa_status pa_batch_anneal(pa_batch *p, const double *betas, int32_t npoints, int
         if (e == hipSuccess)
             e = launch_resample(b, (int)scheme, 1, -1);
         if (e == hipSuccess && theta > 0)
-            e = pa_b_sweep(v, theta, 0u); // every run was just resampled
+            e = launch_updates(b, theta, 0u, 0); // every run was just resampled
         if (e == hipSuccess)
             e = launch_observables(b, i);
     }
@@ -1279,6 +1301,8 @@ pa_status pa_batch_anneal(pa_batch *p, const double *betas, int32_t npoints, int
         return hip_fail(b, e, "pa_batch_anneal");
     }
     if (exec) { // kept for replays of the same anneal
+        b->anneal_end_hist = b->hist_state;
+        b->anneal_end_rs = b->rs_prepped;
         b->anneal_exec = exec;
         b->anneal_betas = sched;
         b->anneal_theta = theta;
@@ -1592,8 +1616,8 @@ pa_status pa_features(pa_ctx *c, float *out8)
     pa_status u = need_uniform(b, "pa_features");
     if (u != PA_OK)
         return u;
-    touched_histogram(b);
-    hipError_t e = pa_b_features(b->v);
+    hipError_t e = pa_b_features(b->v, b->hist_state);
+    histogram_built(b);
     if (e != hipSuccess)
         return hip_fail(b, e, "pa_features");
     pa_status s = ctx_records(b, "pa_features");
@@ -1623,8 +1647,8 @@ pa_status pa_step_learned(pa_ctx *c, pa_mlp *m, double alpha_star, double dbeta_
         if (e != hipSuccess)
             return hip_fail(b, e, "pa_step_learned");
     }
-    touched_histogram(b);
-    hipError_t e = pa_b_features(b->v);
+    hipError_t e = pa_b_features(b->v, b->hist_state);
+    histogram_built(b);
     if (e == hipSuccess)
         e = pa_mlp_launch_propose(b->v, m->d, dbeta_max);
     if (e == hipSuccess)

@@ -185,12 +185,18 @@ hipError_t pa_b_init(const PaBatchView &v);
 hipError_t pa_b_sweep(const PaBatchView &v, int theta, uint32_t t0); // t0: sweeps already done at this beta
 hipError_t pa_b_sweep_group(const PaBatchView &v, int g, int theta, int threads);
 // hist_clean: the level histogram is zero (observables or init ran since it was last built)
-hipError_t pa_b_reweight(const PaBatchView &v, double beta_next, bool hist_clean);
+// State of each run's level histogram, tracked by the host: all zero (with
+// the energy extremes reset), valid for the current population, or stale.
+#define PA_HIST_ZERO 0
+#define PA_HIST_VALID 1
+#define PA_HIST_STALE 2
+hipError_t pa_b_reweight(const PaBatchView &v, double beta_next, int hist_state);
 // kq >= 0: conditional, resample only when ESS < kq 2^-16 R_cur (else keep the population)
 // prepped: a pa_b_reweight came right before (it clears the resampling's flags and status)
 hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze, int kq, bool prepped);
-hipError_t pa_b_observables(const PaBatchView &v, int point);
-hipError_t pa_b_rule(const PaBatchView &v, double alpha_star, double dbeta_max, int iterations, int bisect);
+hipError_t pa_b_observables(const PaBatchView &v, int point, int hist_state); // builds the histogram if not valid
+hipError_t pa_b_rule(const PaBatchView &v, double alpha_star, double dbeta_max, int iterations, int bisect,
+                     int hist_state);
 hipError_t pa_b_tune_beta(const PaBatchView &v, double beta); // every run's thresholds at beta
 hipError_t pa_b_set_beta(const PaBatchView &v, double beta, double lnZ, uint32_t step, uint32_t sweeps,
                          uint64_t R);
@@ -203,7 +209,7 @@ hipError_t pa_launch_philox_probe(uint32_t *out, int64_t nthreads, int iters, hi
 hipError_t pa_noalloc_scratch(int device, unsigned long long **out);
 hipError_t pa_launch_overlap(const PaRunDesc *a, const PaRunDesc *b, int N, uint32_t ncols_a,
                              unsigned long long *hist, hipStream_t st);
-hipError_t pa_b_features(const PaBatchView &v);
+hipError_t pa_b_features(const PaBatchView &v, int hist_state);
 hipError_t pa_b_check_candidate(const PaBatchView &v, double alpha_star, double dbeta_max, int iterations,
                                 double bracket, int refine);
 hipError_t pa_mlp_launch_grad(const PaMlpDev &m, int n, int adam, int t, float lr);

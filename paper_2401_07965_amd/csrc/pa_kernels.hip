@@ -1110,9 +1110,16 @@ __global__ __launch_bounds__(1024) void k_reweight(const PaRunDesc *__restrict__
     const int64_t ntiles = (rd.cap + PA_SCAN_TILE - 1) / PA_SCAN_TILE;
     for (int64_t t = threadIdx.x; t < 2 * ntiles; t += blockDim.x)
         rd.dv.tiles[t].word = 0ull;
+    const int hmin = (emin + DN) >> 2, hmax = (emax + DN) >> 2;
+    const int nlev = hmax - hmin + 1;
     if (rec->weighted) {
         __syncthreads(); // every thread has read the record before thread 0 writes it
+        // the level histogram is not needed any more: back to zero for the next build
+        for (int k = threadIdx.x; k < nlev; k += blockDim.x)
+            rd.dv.hist[hmin + k] = 0;
         if (threadIdx.x == 0) {
+            rec->emin = INT_MAX;
+            rec->emax = INT_MIN;
             rec->ticket[0] = rec->ticket[1] = 0u;
             rec->status = 0;
             rec->skip = 0;
@@ -1129,8 +1136,6 @@ __global__ __launch_bounds__(1024) void k_reweight(const PaRunDesc *__restrict__
         }
         return;
     }
-    const int hmin = (emin + DN) >> 2, hmax = (emax + DN) >> 2;
-    const int nlev = hmax - hmin + 1;
     const int chunk = (nlev + (int)blockDim.x - 1) / (int)blockDim.x;
     const int lo = (int)threadIdx.x * chunk;
     const int hi = lo + chunk < nlev ? lo + chunk : nlev;
@@ -1153,7 +1158,12 @@ __global__ __launch_bounds__(1024) void k_reweight(const PaRunDesc *__restrict__
     pa_block_sum_u64x<5>(x, su);
     const uint64_t S = x[0];
     const pa_u128 S2 = (pa_u128)x[1] + ((pa_u128)x[2] << 32) + ((pa_u128)x[3] << 64) + ((pa_u128)x[4] << 96);
+    // every level was read before the block sums returned: back to zero for the next build
+    for (int k = threadIdx.x; k < nlev; k += blockDim.x)
+        rd.dv.hist[hmin + k] = 0;
     if (threadIdx.x == 0) {
+        rec->emin = INT_MAX;
+        rec->emax = INT_MIN;
         rec->ticket[0] = rec->ticket[1] = 0u;
         rec->status = 0;
         rec->skip = 0;
@@ -2131,16 +2141,58 @@ __global__ __launch_bounds__(kThreads) void k_commit(const PaRunDesc *__restrict
 }
 
 // ------------------------------------------------------------------ step 4: observables
+// Counters of the level histogram a block of the observables pass keeps in
+// LDS: its energies' levels, from its lowest; a wider spread (high
+// temperatures, large lattices) goes to the run's histogram directly.
+constexpr int kObsLevels = 2048;
+
 __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restrict__ runs,
-                                                      const PaBlk *__restrict__ map)
+                                                      const PaBlk *__restrict__ map, int build_hist)
 {
     __shared__ uint64_t su[16];
     __shared__ double sd[16];
+    __shared__ uint32_t lh[kObsLevels];
+    __shared__ int s_lo[kThreads / 64], s_hi[kThreads / 64];
     RepCtx c;
     if (!rep_ctx(runs, map, &c))
         return;
     const PaDev &dv = c.rd->dv;
     const int cur = c.rec->cur;
+    const int DN = c.rd->d * c.rd->N;
+    // the level histogram of the population (for the next reweighting, the
+    // step rule and the step model): the block's energy range first, then
+    // per-block counts in LDS merged with one atomic per populated level
+    int hlo = 0, nlh = 0;
+    if (build_hist) {
+        int64_t lo = INT_MAX, hi = INT_MIN;
+        for (int64_t d = c.beg + threadIdx.x; d < c.end; d += blockDim.x) {
+            const int64_t e = dv.E[cur][d];
+            lo = e < lo ? e : lo;
+            hi = e > hi ? e : hi;
+        }
+        lo = pa_wave_min_i64(lo);
+        hi = pa_wave_max_i64(hi);
+        if ((threadIdx.x & 63) == 0) {
+            s_lo[threadIdx.x >> 6] = (int)lo;
+            s_hi[threadIdx.x >> 6] = (int)hi;
+        }
+        __syncthreads();
+        int blo = s_lo[0], bhi = s_hi[0];
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+            blo = s_lo[k] < blo ? s_lo[k] : blo;
+            bhi = s_hi[k] > bhi ? s_hi[k] : bhi;
+        }
+        hlo = (blo + DN) >> 2;
+        nlh = ((bhi + DN) >> 2) - hlo + 1;
+        if (nlh <= kObsLevels)
+            for (int k = threadIdx.x; k < nlh; k += blockDim.x)
+                lh[k] = 0;
+        if (threadIdx.x == 0) {
+            atomicMin(&c.rec->emin, blo);
+            atomicMax(&c.rec->emax, bhi);
+        }
+        __syncthreads();
+    }
     uint64_t sE = 0, sE2 = 0, sA = 0, sM2 = 0, sE3 = 0; // sE3: int64 bits (|sum| < 2^63 per block)
     const int lane = threadIdx.x & 63;
     // a weighted population: sums of w, wE, wE^2, wE^3, w|M|, wM^2, w^2 with w = pa_exp(lw)
@@ -2152,6 +2204,13 @@ __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restric
         uint32_t lab = 0xFFFFFFFFu;
         if (valid) {
             const int64_t e = dv.E[cur][d], m = dv.M[cur][d];
+            if (build_hist) {
+                const int h = ((int)e + DN) >> 2;
+                if (nlh <= kObsLevels)
+                    atomicAdd(&lh[h - hlo], 1u);
+                else
+                    atomicAdd(&dv.hist[h], 1u);
+            }
             sE += (uint64_t)e;
             sE2 += (uint64_t)(e * e);
             sE3 += (uint64_t)(e * e * e);
@@ -2180,7 +2239,11 @@ __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restric
             atomicAdd(&dv.fam[lab], (uint32_t)(stop - lane));
         }
     }
-    sE = pa_block_sum_u64(sE, su);
+    sE = pa_block_sum_u64(sE, su); // (its barrier also ends the LDS counting)
+    if (build_hist && nlh <= kObsLevels)
+        for (int k = threadIdx.x; k < nlh; k += blockDim.x)
+            if (lh[k])
+                atomicAdd(&dv.hist[hlo + k], lh[k]);
     sE2 = pa_block_sum_u64(sE2, su);
     sA = pa_block_sum_u64(sA, su);
     sM2 = pa_block_sum_u64(sM2, su);
@@ -2273,13 +2336,6 @@ __global__ __launch_bounds__(kThreads) void k_obs_final(const PaRunDesc *__restr
         for (int k = threadIdx.x; k < nparts; k += blockDim.x)
             v = v + rd.dv.partial[k];
     const double t = pa_block_sum_f64(v, sd);
-    // the level histogram starts from zero at the next reweighting
-    for (int i = threadIdx.x; i < rd.H; i += blockDim.x)
-        rd.dv.hist[i] = 0;
-    if (threadIdx.x == 0) {
-        rec->emin = INT_MAX;
-        rec->emax = INT_MIN;
-    }
     double ws[PA_WPARTS];
     if (wt) {
         const int64_t chunks = (rd.cap + PA_CHUNK - 1) / PA_CHUNK;
@@ -2621,19 +2677,22 @@ hipError_t pa_b_sweep(const PaBatchView &v, int theta, uint32_t t0)
     return e;
 }
 
-static hipError_t hist_launch(const PaBatchView &v)
+// The level histogram of the current populations, from the state the host
+// tracks: valid (nothing to do), zero (build it) or stale (clear, then build).
+static hipError_t hist_launch(const PaBatchView &v, int state)
 {
-    k_hist_prep<<<v.nruns, kThreads, 0, v.stream>>>(v.runs);
+    if (state == PA_HIST_VALID)
+        return hipSuccess;
+    if (state == PA_HIST_STALE)
+        k_hist_prep<<<v.nruns, kThreads, 0, v.stream>>>(v.runs);
     k_hist<<<v.nhrep, kThreads, (size_t)v.maxH * 4, v.stream>>>(v.runs, v.hrep);
     return hipGetLastError();
 }
 
-hipError_t pa_b_reweight(const PaBatchView &v, double beta_next, bool hist_clean)
+
+hipError_t pa_b_reweight(const PaBatchView &v, double beta_next, int hist_state)
 {
-    if (!hist_clean)
-        k_hist_prep<<<v.nruns, kThreads, 0, v.stream>>>(v.runs);
-    k_hist<<<v.nhrep, kThreads, (size_t)v.maxH * 4, v.stream>>>(v.runs, v.hrep);
-    hipError_t e = hipGetLastError();
+    hipError_t e = hist_launch(v, hist_state);
     if (e != hipSuccess)
         return e;
     k_reweight<<<v.nruns, 1024, 0, v.stream>>>(v.runs, beta_next);
@@ -2645,18 +2704,19 @@ hipError_t pa_b_reweight(const PaBatchView &v, double beta_next, bool hist_clean
     return hipGetLastError();
 }
 
-hipError_t pa_b_rule(const PaBatchView &v, double alpha_star, double dbeta_max, int iterations, int bisect)
+hipError_t pa_b_rule(const PaBatchView &v, double alpha_star, double dbeta_max, int iterations, int bisect,
+                     int hist_state)
 {
-    hipError_t e = hist_launch(v);
+    hipError_t e = hist_launch(v, hist_state);
     if (e != hipSuccess)
         return e;
     k_rule<<<v.nruns, kRuleThreads, 0, v.stream>>>(v.runs, alpha_star, dbeta_max, iterations, bisect);
     return hipGetLastError();
 }
 
-hipError_t pa_b_features(const PaBatchView &v)
+hipError_t pa_b_features(const PaBatchView &v, int hist_state)
 {
-    hipError_t e = hist_launch(v);
+    hipError_t e = hist_launch(v, hist_state);
     if (e != hipSuccess)
         return e;
     k_features<<<v.nruns, kRuleThreads, 0, v.stream>>>(v.runs);
@@ -2719,9 +2779,11 @@ hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze, int kq, b
     return hipGetLastError();
 }
 
-hipError_t pa_b_observables(const PaBatchView &v, int point)
+hipError_t pa_b_observables(const PaBatchView &v, int point, int hist_state)
 {
-    k_obs_rep<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
+    if (hist_state == PA_HIST_STALE)
+        k_hist_prep<<<v.nruns, kThreads, 0, v.stream>>>(v.runs);
+    k_obs_rep<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep, hist_state != PA_HIST_VALID);
     k_obs_fam<<<v.nfam, kThreads, 0, v.stream>>>(v.runs, v.fam);
     k_obs_final<<<v.nruns, kThreads, 0, v.stream>>>(v.runs, point >= 0 ? v.steprec : nullptr, v.npoints,
                                                     point);

@@ -1,7 +1,8 @@
-"""Call sequences that reuse or rebuild what a reweighting prepared: the level
-histogram (returned to zero by the observables pass), the resampling's flags
-and status (cleared by the reweighting), and the E_min its weights are
-counted from.  Every sequence must leave the population, ln Z_hat and the
+"""Call sequences that reuse or rebuild what a reweighting prepared or
+consumed: the level histogram (built by the sweeps' recount, cleared by the
+reweighting after use, rebuilt by the step rule when it is not valid), the
+resampling's flags and status (cleared by the reweighting), and the E_min
+its weights are counted from.  Every sequence must leave the population, ln Z_hat and the
 copy numbers the oracle gives for the same calls."""
 import numpy as np
 import pytest
@@ -28,9 +29,9 @@ def step_both(g, o, beta, scheme, theta=3):
 
 @pytest.mark.parametrize("scheme", [O.NEAREST_INT, O.SYSTEMATIC])
 def test_observables_and_rule_between_reweight_and_resample(scheme):
-    """The observables pass zeroes the histogram and the rule rebuilds it (new
-    E_min) between a reweighting and its resampling: the resampling still
-    uses the reweighting's weights."""
+    """After a reweighting has cleared the histogram, an observables pass and
+    the rule (which rebuilds it, with its own E_min) run before the
+    resampling: the resampling still uses the reweighting's weights."""
     print(f"[call orders] observables / rule between reweight and resample, scheme={scheme}", flush=True)
     g, o = pair(run_id=scheme)
     for i, beta in enumerate((0.1, 0.2, 0.3, 0.4, 0.5), 1):
@@ -118,3 +119,40 @@ def test_import_then_reweight_uses_the_imported_population():
     assert not weighted and np.all(lw == 0.0)
     g.close()
     src.close()
+
+
+@pytest.mark.parametrize("scheme", [O.SYSTEMATIC, O.POISSON])
+def test_histogram_built_by_split_sweeps_cluster_updates_and_no_sweeps(scheme):
+    """The sweeps' recount builds the level histogram the next reweighting
+    (and the step rule) reads.  Sweeps split over several calls, cluster
+    updates between sweeps, steps with no sweep at all, the rule and a
+    second reweighting before a resampling: every step ends where the oracle
+    does (a histogram counted twice or left stale would change the weights)."""
+    print(f"[call orders] split sweeps, cluster updates, empty steps, scheme={scheme}", flush=True)
+    g, o = pair(R=700, L=8, seed=9, run_id=scheme)
+    plan = [("split", 0.1), ("cluster", 0.2), ("none", 0.25), ("rule", 0.3), ("twice", 0.4), ("split", 0.5),
+            ("none", 0.55), ("none", 0.6), ("cluster", 0.7)]
+    for i, (kind, beta) in enumerate(plan, 1):
+        if kind == "twice":  # a reweighting replaced by a second one
+            g.reweight(beta - 0.05)
+            o.reweight(beta - 0.05)
+        if kind == "rule":
+            assert g.step_rule(0.6, 0.2) > 0.0
+        assert rel_ok(g.reweight(beta), o.reweight(beta)), i
+        assert g.resample(scheme) == o.resample(scheme), i
+        if kind == "split":
+            for n in (1, 2, 1):
+                g.sweep(n)
+                o.sweep(n)
+        elif kind == "cluster":
+            g.sweep(1)
+            o.sweep(1)
+            g.cluster(1)
+            o.cluster(1)
+            g.sweep(2)
+            o.sweep(2)
+        elif kind != "none":
+            g.sweep(3)
+            o.sweep(3)
+        compare_state(g, o, f"step {i} ({kind})")
+    g.close()
