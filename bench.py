@@ -221,10 +221,13 @@ def headline_bench(steps, warmup):
                 beta_range=[schedule()[ev[0][0]], schedule()[ev[-1][0]]] if ev else None)
 
 
-def anneal_row():
+def anneal_row(rate=None):
     """One whole anneal of the headline workload (300 steps, deferred calls,
     one synchronisation at the end): wall time, attempts per ns, and the sweep
-    kernel's rate (HIP events) in windows of beta."""
+    kernel's rate (HIP events) in windows of beta.  Then the same anneal once
+    more with the work counters read at the window boundaries (synchronising
+    there): the Philox calls per attempt of each window and, with the
+    device's Philox rate, the sweep's fraction of its Philox bound."""
     import torch
     stream = torch.cuda.Stream()
     step = Step(make_headline_run(stream), schedule(), stream)
@@ -240,16 +243,33 @@ def anneal_row():
     obs = step.run.observables()
     step.run.close()
     att_step = THETA * L ** D * R  # systematic resampling keeps R
-    windows = {}
+    windows, win_ms = {}, {}
     for lo in (0.0, 0.5, 1.0, 1.5, 2.0, 2.5):
         ms = [e[1].elapsed_time(e[2]) for i, e in ev if lo < schedule()[i] <= lo + 0.5 + 1e-12]
         windows[f"({lo:.1f},{lo + 0.5:.1f}]"] = att_step * len(ms) / (sum(ms) * 1e-3) / 1e9
+        win_ms[f"({lo:.1f},{lo + 0.5:.1f}]"] = sum(ms)
+    by_window = {}
+    if rate:
+        step2 = Step(make_headline_run(stream), schedule(), stream)
+        prev = step2.totals()
+        for k, w in enumerate(win_ms):
+            for _ in range(50):
+                step2()
+            cur = step2.totals()
+            calls = cur["philox_calls"] - prev["philox_calls"]
+            cpa = calls / (64.0 * (cur["site_updates"] - prev["site_updates"]))
+            by_window[w] = {"philox_calls_per_attempt": cpa,
+                            "philox_bound_attempts_per_ns": rate / cpa / 1e9,
+                            "frac": windows[w] * cpa / (rate / 1e9)}
+            prev = cur
+        step2.run.close()
     sweep_total_ms = sum(e[1].elapsed_time(e[2]) for _, e in ev)
     res_total_ms = sum(e[0].elapsed_time(e[1]) for _, e in ev)
     return {"workload": "the headline workload, one whole anneal beta 0 -> 3 (300 steps)",
             "wall_s": wall, "attempts_per_ns": tot["spin_attempts"] / wall / 1e9,
             "sweep_attempts_per_ns": tot["spin_attempts"] / (sweep_total_ms * 1e-3) / 1e9,
             "sweep_attempts_per_ns_by_beta": windows,
+            "philox_bound_by_beta": by_window,
             "sweep_share_of_wall": sweep_total_ms * 1e-3 / wall,
             "resample_GB_per_s": resample_bytes(L ** D, R, R) * (POINTS - 1) / (res_total_ms * 1e-3) / 1e9,
             "philox_calls_per_attempt": tot["philox_calls"] / (64.0 * tot["site_updates"]),
@@ -998,7 +1018,7 @@ def main():
     if unknown:
         print(f"unknown rows: {unknown}", file=sys.stderr)
         sys.exit(2)
-    fns = {"anneal": anneal_row, "config2": config2_row, "config3": config3_row,
+    fns = {"anneal": lambda: anneal_row(rate), "config2": config2_row, "config3": config3_row,
            "resample_scaling": resample_scaling, "batched": batched_bench, "learned": learned_bench,
            "combination": combination_study, "resampling": resampling_study,
            "conditional": conditional_study, "scheme_errors": scheme_error_study, "rmsd": rmsd_study,

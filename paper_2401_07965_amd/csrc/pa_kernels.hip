@@ -1097,8 +1097,7 @@ __device__ __forceinline__ pa_u128 block_sum_u128(pa_u128 v, uint64_t *su)
 // per-replica passes (k_rw_max, k_rw_sum, k_rw_final) do the rest.
 __global__ __launch_bounds__(1024) void k_reweight(const PaRunDesc *__restrict__ runs, double beta_next)
 {
-    __shared__ double sd[16];
-    __shared__ uint64_t su[16 * 5];
+    __shared__ uint64_t su[16 * 6];
     const PaRunDesc &rd = runs[blockIdx.x];
     PaRecord *rec = rd.dv.rec;
     if (frozen(rec))
@@ -1151,16 +1150,35 @@ __global__ __launch_bounds__(1024) void k_reweight(const PaRunDesc *__restrict__
         s += (uint64_t)n * W;
         s2 += (pa_u128)((uint64_t)n * W) * W;
     }
-    const double Q = pa_block_sum_f64(q, sd);
-    // S and the four 32-bit limbs of sum n W^2 (a limb's block total stays below 2^42)
-    uint64_t x[5] = {s, (uint64_t)s2 & 0xFFFFFFFFull, (uint64_t)(s2 >> 32) & 0xFFFFFFFFull,
-                     (uint64_t)(s2 >> 64) & 0xFFFFFFFFull, (uint64_t)(s2 >> 96)};
-    pa_block_sum_u64x<5>(x, su);
-    const uint64_t S = x[0];
-    const pa_u128 S2 = (pa_u128)x[1] + ((pa_u128)x[2] << 32) + ((pa_u128)x[3] << 64) + ((pa_u128)x[4] << 96);
-    // every level was read before the block sums returned: back to zero for the next build
+    // one exchange through LDS for all block sums: Q (a double, the waves'
+    // butterfly totals added in wave order, so the same bits every run), S and
+    // the four 32-bit limbs of sum n W^2 (a limb's block total stays below 2^42)
+    uint64_t x[6] = {s, (uint64_t)s2 & 0xFFFFFFFFull, (uint64_t)(s2 >> 32) & 0xFFFFFFFFull,
+                     (uint64_t)(s2 >> 64) & 0xFFFFFFFFull, (uint64_t)(s2 >> 96),
+                     (uint64_t)__double_as_longlong(pa_wave_sum_f64(q))};
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+        x[i] = pa_wave_sum_u64(x[i]);
+    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+            su[wave * 6 + i] = x[i];
+    __syncthreads(); // also: every level has been read
+    double Q = 0.0;
+    uint64_t t[5] = {0, 0, 0, 0, 0};
+    for (int k = 0; k < nwaves; ++k) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+            t[i] += su[k * 6 + i];
+        Q = Q + __longlong_as_double((long long)su[k * 6 + 5]);
+    }
+    const uint64_t S = t[0];
+    const pa_u128 S2 = (pa_u128)t[1] + ((pa_u128)t[2] << 32) + ((pa_u128)t[3] << 64) + ((pa_u128)t[4] << 96);
+    // back to zero for the next build of the level histogram
     for (int k = threadIdx.x; k < nlev; k += blockDim.x)
         rd.dv.hist[hmin + k] = 0;
+    // the record's new values, the exponentials on separate lanes
     if (threadIdx.x == 0) {
         rec->emin = INT_MAX;
         rec->emax = INT_MIN;
@@ -1176,9 +1194,8 @@ __global__ __launch_bounds__(1024) void k_reweight(const PaRunDesc *__restrict__
         rec->dbeta = dbeta;
         rec->beta_next = beta_next;
         rec->lnQ = -dbeta * (double)emin + log(Q / (double)rec->Rcur);
-        rec->Tn[0] = pa_threshold(beta_next, 4);
-        rec->Tn[1] = pa_threshold(beta_next, 8);
-        rec->Tn[2] = pa_threshold(beta_next, 12);
+    } else if (threadIdx.x < 4) {
+        rec->Tn[threadIdx.x - 1] = pa_threshold(beta_next, 4 * (int)threadIdx.x);
     }
 }
 
