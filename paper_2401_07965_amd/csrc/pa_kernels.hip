@@ -1726,6 +1726,7 @@ __global__ __launch_bounds__(kThreads) void k_counts_systematic(const PaRunDesc 
     const uint64_t S = c.rec->S, Rt = (uint64_t)rd.R0;
     const uint32_t U = pa_philox(rd.seed, rd.run_id, 0u, 0u, c.rec->step + 1, PA_PURPOSE_RS_SYS << 28).x0;
     const uint64_t *C = rd.dv.C;
+    const int64_t Rprev = (int64_t)c.rec->Rcur;
     __shared__ double sd[16];
     double sv = 0.0;
     for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x) {
@@ -1733,7 +1734,12 @@ __global__ __launch_bounds__(kThreads) void k_counts_systematic(const PaRunDesc 
         const uint64_t hi = sys_below(cj, Rt, S, U);
         const uint64_t lo = j > 0 ? sys_below(cp, Rt, S, U) : 0;
         const uint32_t r = (uint32_t)(hi - lo);
-        rd.dv.r[j] = r;
+        // the points below C_{j-1} are the copies of the replicas before j: the
+        // copies of j are destinations [N(C_{j-1}), N(C_j)) with no prefix sum
+        for (uint64_t d = lo; d < hi; ++d)
+            rd.dv.anc[d] = (uint32_t)j;
+        if (j == Rprev - 1)
+            c.rec->Rnew = hi; // N(S) = Rt: the size is kept
         sv = sv + sv_term(r, cj - cp, (double)S, (double)Rt); // C is the inclusive sum of W
     }
     sv_store(c, sv, sd);
@@ -2787,7 +2793,9 @@ hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze, int kq, b
     }
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
-    if ((e = scan_launch<uint32_t, false, 1>(v)) != hipSuccess)
+    // the ancestor map and the new size from the copy numbers' prefix sum
+    // (systematic: written by the copy-number kernel in closed form)
+    if (scheme != 3 && (e = scan_launch<uint32_t, false, 1>(v)) != hipSuccess)
         return e;
     k_gather_spins<<<v.ncol, kThreads, 0, v.stream>>>(v.runs, v.col);
     if (kq >= 0)
