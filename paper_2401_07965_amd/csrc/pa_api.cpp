@@ -153,12 +153,11 @@ uint64_t carve_run(const Geometry &g, char *base, PaDev *dv)
     d.hist = (uint32_t *)take((uint64_t)g.H * 4);
     d.wtab = (uint64_t *)take((uint64_t)g.H * 8);
     d.r = (uint32_t *)take(slots * 4);
-    d.P = (uint32_t *)take(slots * 4);
     d.anc = (uint32_t *)take(slots * 4);
     d.C = (uint64_t *)take(slots * 8);
     d.qhist = (unsigned long long *)take((uint64_t)(g.N + 1) * 8);
     // tile flags of the two prefix sums of a resampling (weights, copy numbers)
-    d.tiles = (PaScanTile *)take((uint64_t)((g.cap + PA_SCAN_TILE - 1) / PA_SCAN_TILE) * 2 * sizeof(PaScanTile));
+    d.tiles = (PaScanTile *)take((uint64_t)(2 * pa_tiles_per_sum(g.cap)) * sizeof(PaScanTile));
     d.partial = (double *)take(chunks * 8);
     d.fam = (uint32_t *)take((uint64_t)g.R * 4);
     d.lw = (double *)take(slots * 8);
@@ -305,7 +304,7 @@ pa_status hip_fail(Batch *b, hipError_t e, const char *where)
 
 // Whole layout of a batch: tables first, then each run's buffers.
 struct Tables {
-    std::vector<PaBlk> rep, hrep, fam, col, tile;
+    std::vector<PaBlk> rep, hrep, crep, fam, col, tile;
     std::vector<std::vector<PaBlk>> gcol;
     std::vector<int> gd, gN, gJ, gthreads;
 };
@@ -322,6 +321,8 @@ uint64_t layout(const std::vector<Geometry> &geo, int max_points, char *base, Ba
             tb.rep.push_back({(uint32_t)m, (uint32_t)c});
         for (int64_t c = 0; c < (g.cap + PA_HCHUNK - 1) / PA_HCHUNK; ++c)
             tb.hrep.push_back({(uint32_t)m, (uint32_t)c});
+        for (int64_t c = 0; c < (g.cap + pa_counts_tile(g.cap) - 1) / pa_counts_tile(g.cap); ++c)
+            tb.crep.push_back({(uint32_t)m, (uint32_t)c});
         for (int64_t c = 0; c < (g.R + PA_CHUNK - 1) / PA_CHUNK; ++c)
             tb.fam.push_back({(uint32_t)m, (uint32_t)c});
         for (int64_t w = 0; w < g.W; ++w)
@@ -350,6 +351,7 @@ uint64_t layout(const std::vector<Geometry> &geo, int max_points, char *base, Ba
     char *p_desc = take(sizeof(PaRunDesc) * (uint64_t)M);
     char *p_rep = take(sizeof(PaBlk) * tb.rep.size());
     char *p_hrep = take(sizeof(PaBlk) * tb.hrep.size());
+    char *p_crep = take(sizeof(PaBlk) * tb.crep.size());
     char *p_fam = take(sizeof(PaBlk) * tb.fam.size());
     char *p_col = take(sizeof(PaBlk) * tb.col.size());
     char *p_tile = take(sizeof(PaBlk) * tb.tile.size());
@@ -390,6 +392,8 @@ uint64_t layout(const std::vector<Geometry> &geo, int max_points, char *base, Ba
         v.nrep = (uint32_t)tb.rep.size();
         v.hrep = (const PaBlk *)p_hrep;
         v.nhrep = (uint32_t)tb.hrep.size();
+        v.crep = (const PaBlk *)p_crep;
+        v.ncrep = (uint32_t)tb.crep.size();
         v.fam = (const PaBlk *)p_fam;
         v.nfam = (uint32_t)tb.fam.size();
         v.col = (const PaBlk *)p_col;
@@ -529,6 +533,7 @@ pa_status make_batch(const pa_config *cfgs, int32_t nruns, int32_t max_points, v
     up(b->ddesc, b->hdesc.data(), sizeof(PaRunDesc) * nruns);
     up(b->v.rep, t.rep.data(), sizeof(PaBlk) * t.rep.size());
     up(b->v.hrep, t.hrep.data(), sizeof(PaBlk) * t.hrep.size());
+    up(b->v.crep, t.crep.data(), sizeof(PaBlk) * t.crep.size());
     up(b->v.fam, t.fam.data(), sizeof(PaBlk) * t.fam.size());
     up(b->v.col, t.col.data(), sizeof(PaBlk) * t.col.size());
     up(b->v.tile, t.tile.data(), sizeof(PaBlk) * t.tile.size());

@@ -93,6 +93,19 @@ struct PaScanTile {
 #define PA_CHUNK 1024  // replicas (or families) per workgroup of the per-replica kernels
 #define PA_HCHUNK 4096 // replicas per workgroup of the energy histogram (LDS-private counts)
 
+// Tile flags of a run's two prefix sums of a resampling (weights, copy
+// numbers): ceil(cap / PA_CHUNK) each, enough for tiles of PA_CHUNK or more
+// slots.
+__host__ __device__ inline int64_t pa_tiles_per_sum(int64_t cap) { return (cap + PA_CHUNK - 1) / PA_CHUNK; }
+
+// Replica slots per tile of the passes that sum the weights or draw and sum
+// nearest-integer or Poisson copy numbers: 4 per thread of 256, or 16 per
+// thread once the run is large enough that the look-back over the smaller
+// tiles would take longer than the work.  A run's tiles depend on its
+// capacity alone, so a run's results do not depend on the batch it is in.
+#define PA_COUNTS_WIDE_CAP (1 << 18)
+__host__ __device__ inline int64_t pa_counts_tile(int64_t cap) { return cap >= PA_COUNTS_WIDE_CAP ? 4096 : 1024; }
+
 // Device buffers of one run, carved from the caller's workspace.
 struct PaDev {
     uint64_t *spins[2]; // [W][N] words, bit b of word (w, s) = replica 64w+b at site s
@@ -101,7 +114,7 @@ struct PaDev {
     uint8_t *jmask; // per site: bit mu = J(s,mu) is -1, bit d+mu = J(s-e_mu,mu) is -1
     uint32_t *hist; // [H] replicas per energy level h = (E + dN) / 4
     uint64_t *wtab; // [H] integer weight per level above the lowest
-    uint32_t *r, *P, *anc;
+    uint32_t *r, *anc;
     uint64_t *C;
     unsigned long long *qhist; // [N+1] overlap histogram
     PaScanTile *tiles;
@@ -159,6 +172,8 @@ struct PaBatchView {
     uint32_t nrep;
     const PaBlk *hrep; // chunks of PA_HCHUNK replica slots (histogram)
     uint32_t nhrep;
+    const PaBlk *crep; // tiles of the copy-number pass (pa_counts_tile slots)
+    uint32_t ncrep;
     const PaBlk *fam;  // chunks of PA_CHUNK families
     uint32_t nfam;
     const PaBlk *col;  // all 64-replica columns (capacity)

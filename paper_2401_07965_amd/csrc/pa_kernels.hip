@@ -1106,8 +1106,8 @@ __global__ __launch_bounds__(1024) void k_reweight(const PaRunDesc *__restrict__
     const double dbeta = beta_next - rec->beta;
     const int32_t emin = rec->emin, emax = rec->emax;
     // the resampling that follows starts with clean tile flags, tickets and status
-    const int64_t ntiles = (rd.cap + PA_SCAN_TILE - 1) / PA_SCAN_TILE;
-    for (int64_t t = threadIdx.x; t < 2 * ntiles; t += blockDim.x)
+    const int64_t ntiles = 2 * pa_tiles_per_sum(rd.cap);
+    for (int64_t t = threadIdx.x; t < ntiles; t += blockDim.x)
         rd.dv.tiles[t].word = 0ull;
     const int hmin = (emin + DN) >> 2, hmax = (emax + DN) >> 2;
     const int nlev = hmax - hmin + 1;
@@ -1586,10 +1586,8 @@ __global__ void k_cond_decide(const PaRunDesc *__restrict__ runs, uint32_t kq)
 }
 
 
-// Nearest integer: floor(tauhat) + [u S < (R W mod S) 2^32], u = x0 of
-// Philox(j, 0, i, RS_NI<<28).
 // Sampling variance, Eq. (5): each chunk sums (r_j - tauhat_j)^2 over its
-// replicas with a fixed per-thread stride and the block's fixed tree into
+// replicas in a fixed order (per thread, then the block's fixed tree) into
 // partial[chunk]; k_commit adds the partials in chunk order.
 __device__ __forceinline__ double sv_term(uint32_t r, uint64_t W, double S, double Rt)
 {
@@ -1605,98 +1603,34 @@ __device__ __forceinline__ void sv_store(const RepCtx &c, double acc, double *sd
         c.rd->dv.partial[c.beg / PA_CHUNK] = t;
 }
 
-__global__ __launch_bounds__(kThreads) void k_counts_nearest(const PaRunDesc *__restrict__ runs,
-                                                             const PaBlk *__restrict__ map)
+// Poisson by inversion: tauhat = R W / S; tauhat > 32 is cut into
+// ceil(tauhat/32) equal pieces, piece p using u from Philox(j, p, i, RS_POIS<<28).
+__device__ __forceinline__ uint32_t poisson_copies(const PaRunDesc &rd, uint64_t W, uint64_t S, uint64_t Rt,
+                                                   int64_t j, uint32_t step)
 {
-    RepCtx c;
-    if (!rs_ctx(runs, map, &c))
-        return;
-    const bool wt = c.rec->weighted != 0u;
-    const PaRunDesc &rd = *c.rd;
-    const int DN = rd.d * rd.N;
-    const int hmin = (c.rec->wemin + DN) >> 2;
-    const uint64_t S = c.rec->S, Rt = (uint64_t)rd.R0;
-    const uint32_t step = c.rec->step + 1;
-    const int32_t *E = rd.dv.E[c.rec->cur];
-    __shared__ double sd[16];
-    double sv = 0.0;
-    for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x) {
-        const uint64_t W = rep_weight(c, wt, E, j, DN, hmin);
-        const uint64_t a = Rt * W;
-        const uint64_t qt = a / S;
-        const uint64_t rho = a - qt * S;
-        const pa_philox_out o = pa_philox(rd.seed, rd.run_id, (uint32_t)j, 0u, step, PA_PURPOSE_RS_NI << 28);
-        const bool extra = ((pa_u128)o.x0 * S) < ((pa_u128)rho << 32);
-        const uint32_t r = (uint32_t)qt + (extra ? 1u : 0u);
-        rd.dv.r[j] = r;
-        sv = sv + sv_term(r, W, (double)S, (double)Rt);
-    }
-    sv_store(c, sv, sd);
-}
-
-// Poisson by inversion; tauhat > 32 is cut into ceil(tauhat/32) equal pieces,
-// piece p using u from Philox(j, p, i, RS_POIS<<28).
-__global__ __launch_bounds__(kThreads) void k_counts_poisson(const PaRunDesc *__restrict__ runs,
-                                                             const PaBlk *__restrict__ map)
-{
-    RepCtx c;
-    if (!rs_ctx(runs, map, &c))
-        return;
-    const bool wt = c.rec->weighted != 0u;
-    const PaRunDesc &rd = *c.rd;
-    const int DN = rd.d * rd.N;
-    const int hmin = (c.rec->wemin + DN) >> 2;
-    const uint64_t S = c.rec->S, Rt = (uint64_t)rd.R0;
-    const uint32_t step = c.rec->step + 1;
-    const int32_t *E = rd.dv.E[c.rec->cur];
-    __shared__ double sd[16];
-    double sv = 0.0;
-    for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x) {
-        const uint64_t W = rep_weight(c, wt, E, j, DN, hmin);
-        const double tau = ((double)W / (double)S) * (double)Rt;
-        uint32_t m = 1;
-        if (tau > 32.0)
-            m = (uint32_t)ceil(tau / 32.0);
-        const double mu = tau / (double)m;
-        uint32_t tot = 0;
-        for (uint32_t p = 0; p < m; ++p) {
-            const pa_philox_out o = pa_philox(rd.seed, rd.run_id, (uint32_t)j, p, step, PA_PURPOSE_RS_POIS << 28);
-            const double u = ((double)(o.x0 >> 5) * 67108864.0 + (double)(o.x1 >> 6)) *
-                             (1.0 / 9007199254740992.0);
-            uint32_t k = 0;
-            double pr = pa_exp(-mu);
-            double F = pr;
-            while (u >= F) {
-                k += 1;
-                pr = (pr * mu) / (double)k;
-                const double Fn = F + pr;
-                if (Fn == F)
-                    break;
-                F = Fn;
-            }
-            tot += k;
+    const double tau = ((double)W / (double)S) * (double)Rt;
+    uint32_t m = 1;
+    if (tau > 32.0)
+        m = (uint32_t)ceil(tau / 32.0);
+    const double mu = tau / (double)m;
+    uint32_t tot = 0;
+    for (uint32_t p = 0; p < m; ++p) {
+        const pa_philox_out o = pa_philox(rd.seed, rd.run_id, (uint32_t)j, p, step, PA_PURPOSE_RS_POIS << 28);
+        const double u = ((double)(o.x0 >> 5) * 67108864.0 + (double)(o.x1 >> 6)) * (1.0 / 9007199254740992.0);
+        uint32_t k = 0;
+        double pr = pa_exp(-mu);
+        double F = pr;
+        while (u >= F) {
+            k += 1;
+            pr = (pr * mu) / (double)k;
+            const double Fn = F + pr;
+            if (Fn == F)
+                break;
+            F = Fn;
         }
-        rd.dv.r[j] = tot;
-        sv = sv + sv_term(tot, W, (double)S, (double)Rt);
+        tot += k;
     }
-    sv_store(c, sv, sd);
-}
-
-__global__ __launch_bounds__(kThreads) void k_weights(const PaRunDesc *__restrict__ runs,
-                                                      const PaBlk *__restrict__ map)
-{
-    RepCtx c;
-    if (!rs_ctx(runs, map, &c))
-        return;
-    const PaRunDesc &rd = *c.rd;
-    const bool wt = c.rec->weighted != 0u;
-    const int DN = rd.d * rd.N;
-    const int hmin = (c.rec->wemin + DN) >> 2;
-    const int32_t *E = rd.dv.E[c.rec->cur];
-    for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x) {
-        rd.dv.C[j] = rep_weight(c, wt, E, j, DN, hmin);
-        rd.dv.r[j] = 0; // the multinomial draws add to it; the systematic counts overwrite it
-    }
+    return tot;
 }
 
 // Systematic: #points (k + U/2^32) S/R below c, k < R, is
@@ -1714,35 +1648,6 @@ __device__ __forceinline__ uint64_t sys_below(uint64_t c, uint64_t Rt, uint64_t 
     const uint64_t rho = (uint64_t)(cR - (pa_u128)q * S);
     const uint64_t n = q + ((((pa_u128)rho) << 32) > ((pa_u128)U * S) ? 1u : 0u);
     return n < Rt ? n : Rt;
-}
-
-__global__ __launch_bounds__(kThreads) void k_counts_systematic(const PaRunDesc *__restrict__ runs,
-                                                                const PaBlk *__restrict__ map)
-{
-    RepCtx c;
-    if (!rs_ctx(runs, map, &c))
-        return;
-    const PaRunDesc &rd = *c.rd;
-    const uint64_t S = c.rec->S, Rt = (uint64_t)rd.R0;
-    const uint32_t U = pa_philox(rd.seed, rd.run_id, 0u, 0u, c.rec->step + 1, PA_PURPOSE_RS_SYS << 28).x0;
-    const uint64_t *C = rd.dv.C;
-    const int64_t Rprev = (int64_t)c.rec->Rcur;
-    __shared__ double sd[16];
-    double sv = 0.0;
-    for (int64_t j = c.beg + threadIdx.x; j < c.end; j += blockDim.x) {
-        const uint64_t cj = C[j], cp = j > 0 ? C[j - 1] : 0ull;
-        const uint64_t hi = sys_below(cj, Rt, S, U);
-        const uint64_t lo = j > 0 ? sys_below(cp, Rt, S, U) : 0;
-        const uint32_t r = (uint32_t)(hi - lo);
-        // the points below C_{j-1} are the copies of the replicas before j: the
-        // copies of j are destinations [N(C_{j-1}), N(C_j)) with no prefix sum
-        for (uint64_t d = lo; d < hi; ++d)
-            rd.dv.anc[d] = (uint32_t)j;
-        if (j == Rprev - 1)
-            c.rec->Rnew = hi; // N(S) = Rt: the size is kept
-        sv = sv + sv_term(r, cj - cp, (double)S, (double)Rt); // C is the inclusive sum of W
-    }
-    sv_store(c, sv, sd);
 }
 
 // Multinomial: U_k = floor(r S / 2^128), r = 128 bits of Philox(k, 0, i,
@@ -1801,59 +1706,66 @@ __global__ __launch_bounds__(kThreads) void k_sv_partial(const PaRunDesc *__rest
     sv_store(c, acc, sd);
 }
 
-// Decoupled look-back scan (Merrill & Garland 2016) of each run's first
-// Rcur entries: the workgroups of a run (from the tile map) take their tile
-// index from the run's own atomic ticket, so every tile a tile waits on (same
-// run, lower index) belongs to a workgroup that is already running.  Entries
-// past Rcur count as 0.  The first wave looks back over up to 64 preceding
-// tiles at once (one flag per lane): the nearest tile with an inclusive
-// prefix ends the look-back, the aggregates of the tiles after it add up.
-// WHICH = 0: inclusive sums of the weights C in place; WHICH = 1: exclusive
-// sums P of the copy numbers r, and with them the ancestor map
-// anc[P_j + k] = j, k < r_j (kept below the capacity; a resampling that
-// overflows is not applied).
-template <typename T, bool INCLUSIVE, int WHICH>
-__global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const PaRunDesc *__restrict__ runs,
-                                                          const PaBlk *__restrict__ map)
+// Decoupled look-back (Merrill & Garland 2016), run by a tile's first wave:
+// the tile publishes its aggregate, looks back over up to 64 preceding tiles
+// at once (one flag per lane; the nearest tile with an inclusive prefix ends
+// the look-back, the aggregates of the tiles after it add up), then
+// publishes its own inclusive prefix.  Returns the exclusive prefix in every
+// lane of the wave.  The workgroups of a run take their tile index from the
+// run's own atomic ticket, so every tile a tile waits on (same run, lower
+// index) belongs to a workgroup that is already running; a wait past the
+// spin limit sets the run's timeout status and gives up (the resampling is
+// then not applied).
+__device__ __forceinline__ unsigned long long tile_lookback(PaScanTile *tiles, uint32_t tile,
+                                                            unsigned long long agg, PaRecord *rec)
 {
-    static_assert(PA_SCAN_ITEMS * sizeof(T) % 16 == 0, "items of a thread are whole 16-byte vectors");
-    constexpr int kVec = PA_SCAN_ITEMS * (int)sizeof(T) / 16;
-    __shared__ uint32_t s_tile;
-    __shared__ unsigned long long s_wave[PA_SCAN_THREADS / 64];
-    __shared__ unsigned long long s_excl;
-    const PaBlk b = map[blockIdx.x];
-    const PaRunDesc &rd = runs[b.run];
-    PaRecord *rec = rd.dv.rec;
-    if (frozen(rec) || rec->keep)
-        return; // every tile of a frozen (or kept) run returns: none waits
-    if (threadIdx.x == 0)
-        s_tile = atomicAdd(&rec->ticket[WHICH], 1u);
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    const int64_t n = (int64_t)rec->Rcur;
-    const int64_t ntiles = (rd.cap + PA_SCAN_TILE - 1) / PA_SCAN_TILE;
-    const T *in = WHICH == 0 ? (const T *)rd.dv.C : (const T *)rd.dv.r;
-    T *out = WHICH == 0 ? (T *)rd.dv.C : (T *)rd.dv.P;
-    unsigned long long *total = WHICH == 0 ? &rec->Ctot : &rec->Rnew;
-    PaScanTile *tiles = rd.dv.tiles + (WHICH ? ntiles : 0);
-    const int64_t base = (int64_t)tile * PA_SCAN_TILE + (int64_t)threadIdx.x * PA_SCAN_ITEMS;
-    const bool whole = base + PA_SCAN_ITEMS <= n; // the thread's items are all live
-    alignas(16) T v[PA_SCAN_ITEMS];
-    if (whole) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(in + base);
-        uint4 *dv = reinterpret_cast<uint4 *>(v);
-#pragma unroll
-        for (int k = 0; k < kVec; ++k)
-            dv[k] = src[k];
-    } else {
-#pragma unroll
-        for (int k = 0; k < PA_SCAN_ITEMS; ++k)
-            v[k] = base + k < n ? in[base + k] : (T)0;
+    const int lane = threadIdx.x & 63;
+    unsigned long long *me = &tiles[tile].word;
+    unsigned long long excl = 0;
+    if (lane == 0) // tile 0's aggregate is its inclusive prefix
+        __hip_atomic_store(me, (tile == 0 ? PA_TILE_INCL : PA_TILE_AGG) | agg, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    if (tile == 0)
+        return 0;
+    int64_t top = (int64_t)tile - 1; // the window: tiles top - lane
+    uint32_t spins = 0;
+    for (;;) {
+        const int64_t p = top - lane;
+        unsigned long long word = PA_TILE_INCL; // before tile 0: an inclusive prefix of 0
+        if (p >= 0)
+            word = __hip_atomic_load(&tiles[p].word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t f = (uint32_t)(word >> 62);
+        const unsigned long long val = word & PA_TILE_VALUE;
+        const uint64_t inc = __ballot(f == 2u), pending = __ballot(f == 0u);
+        const int first = inc ? __ffsll((long long)inc) - 1 : 64;
+        const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1ull); // lanes 0..first
+        if (pending & need) { // a tile the prefix needs has not published yet
+            if (++spins > (1u << 26)) {
+                if (lane == 0)
+                    atomicOr(&rec->status, PA_ST_SCAN_TIMEOUT);
+                break; // gave up; the status bit is set
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += pa_wave_sum_u64(((need >> lane) & 1ull) ? val : 0ull);
+        if (first < 64)
+            break;
+        top -= 64;
     }
-    unsigned long long run = 0;
-#pragma unroll
-    for (int k = 0; k < PA_SCAN_ITEMS; ++k)
-        run += (unsigned long long)v[k];
+    // a prefix too wide for the word stays unpublished: later tiles then
+    // add this tile's aggregate themselves
+    if (lane == 0 && excl + agg <= PA_TILE_VALUE)
+        __hip_atomic_store(me, PA_TILE_INCL | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return excl;
+}
+
+// Exclusive prefix of each thread's `run` within the workgroup (waves by
+// shuffles, then the waves' totals through LDS); *agg: the workgroup total.
+template <int THREADS>
+__device__ __forceinline__ unsigned long long block_excl_scan(unsigned long long run, unsigned long long *s_wave,
+                                                              unsigned long long *agg)
+{
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     unsigned long long incl = run;
 #pragma unroll
@@ -1865,83 +1777,335 @@ __global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan(const PaRunDesc *__res
     if (lane == 63)
         s_wave[wave] = incl;
     __syncthreads();
-    unsigned long long wave_off = 0, agg = 0;
-    for (int k = 0; k < PA_SCAN_THREADS / 64; ++k) {
+    unsigned long long wave_off = 0, a = 0;
+    for (int k = 0; k < THREADS / 64; ++k) {
         if (k < wave)
             wave_off += s_wave[k];
-        agg += s_wave[k];
+        a += s_wave[k];
     }
-    const unsigned long long thread_excl = wave_off + incl - run;
-    if (wave == 0) {
-        unsigned long long *me = &tiles[tile].word;
-        unsigned long long excl = 0;
-        if (lane == 0) // tile 0's aggregate is its inclusive prefix
-            __hip_atomic_store(me, (tile == 0 ? PA_TILE_INCL : PA_TILE_AGG) | agg, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        if (tile > 0) {
-            int64_t top = (int64_t)tile - 1; // the window: tiles top - lane
-            uint32_t spins = 0;
-            for (;;) {
-                const int64_t p = top - lane;
-                unsigned long long word = PA_TILE_INCL; // before tile 0: an inclusive prefix of 0
-                if (p >= 0)
-                    word = __hip_atomic_load(&tiles[p].word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t f = (uint32_t)(word >> 62);
-                const unsigned long long val = word & PA_TILE_VALUE;
-                const uint64_t inc = __ballot(f == 2u), pending = __ballot(f == 0u);
-                const int first = inc ? __ffsll((long long)inc) - 1 : 64;
-                const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1ull); // lanes 0..first
-                if (pending & need) { // a tile the prefix needs has not published yet
-                    if (++spins > (1u << 26)) {
-                        if (lane == 0)
-                            atomicOr(&rec->status, PA_ST_SCAN_TIMEOUT);
-                        break; // gave up; the status bit is set
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                excl += pa_wave_sum_u64(((need >> lane) & 1ull) ? val : 0ull);
-                if (first < 64)
-                    break;
-                top -= 64;
-            }
-            // a prefix too wide for the word stays unpublished: later tiles then
-            // add this tile's aggregate themselves
-            if (lane == 0 && excl + agg <= PA_TILE_VALUE)
-                __hip_atomic_store(me, PA_TILE_INCL | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (lane == 0) {
+    *agg = a;
+    return wave_off + incl - run;
+}
+
+// The ancestor map from a replica's copy number r and exclusive offset P:
+// anc[P + k] = j for k < r (kept below the capacity; a resampling that
+// overflows is not applied).
+__device__ __forceinline__ void write_ancestors(uint32_t *anc, unsigned long long P, uint32_t r, int64_t j,
+                                                int64_t cap)
+{
+    for (unsigned long long d = P; d < P + r && d < (unsigned long long)cap; ++d)
+        anc[d] = (uint32_t)j;
+}
+
+// Multinomial copy numbers' exclusive prefix sum, written only as the
+// ancestor map: each run's first Rcur copy numbers (entries past Rcur count
+// as 0), PA_SCAN_ITEMS consecutive ones per thread, tiles of PA_SCAN_TILE.
+__global__ __launch_bounds__(PA_SCAN_THREADS) void k_scan_counts(const PaRunDesc *__restrict__ runs,
+                                                                 const PaBlk *__restrict__ map)
+{
+    static_assert(PA_SCAN_ITEMS % 4 == 0, "items of a thread are whole 16-byte vectors");
+    __shared__ uint32_t s_tile;
+    __shared__ unsigned long long s_wave[PA_SCAN_THREADS / 64];
+    __shared__ unsigned long long s_excl;
+    const PaBlk b = map[blockIdx.x];
+    const PaRunDesc &rd = runs[b.run];
+    PaRecord *rec = rd.dv.rec;
+    if (frozen(rec) || rec->keep)
+        return; // every tile of a frozen (or kept) run returns: none waits
+    if (threadIdx.x == 0)
+        s_tile = atomicAdd(&rec->ticket[1], 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const int64_t n = (int64_t)rec->Rcur;
+    const int64_t ntiles = (rd.cap + PA_SCAN_TILE - 1) / PA_SCAN_TILE;
+    PaScanTile *tiles = rd.dv.tiles + pa_tiles_per_sum(rd.cap);
+    const int64_t base = (int64_t)tile * PA_SCAN_TILE + (int64_t)threadIdx.x * PA_SCAN_ITEMS;
+    alignas(16) uint32_t v[PA_SCAN_ITEMS];
+    if (base + PA_SCAN_ITEMS <= n) {
+#pragma unroll
+        for (int k = 0; k < PA_SCAN_ITEMS / 4; ++k)
+            reinterpret_cast<uint4 *>(v)[k] = reinterpret_cast<const uint4 *>(rd.dv.r + base)[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < PA_SCAN_ITEMS; ++k)
+            v[k] = base + k < n ? rd.dv.r[base + k] : 0u;
+    }
+    unsigned long long run = 0;
+#pragma unroll
+    for (int k = 0; k < PA_SCAN_ITEMS; ++k)
+        run += v[k];
+    unsigned long long agg;
+    const unsigned long long thread_excl = block_excl_scan<PA_SCAN_THREADS>(run, s_wave, &agg);
+    if ((threadIdx.x >> 6) == 0) {
+        const unsigned long long excl = tile_lookback(tiles, tile, agg, rec);
+        if ((threadIdx.x & 63) == 0) {
             s_excl = excl;
             if ((int64_t)tile == ntiles - 1)
-                *total = excl + agg;
+                rec->Rnew = excl + agg;
         }
     }
     __syncthreads();
     unsigned long long acc = s_excl + thread_excl;
-    alignas(16) T o[PA_SCAN_ITEMS];
 #pragma unroll
     for (int k = 0; k < PA_SCAN_ITEMS; ++k) {
-        if (INCLUSIVE)
-            acc += (unsigned long long)v[k];
-        o[k] = (T)acc;
-        if (WHICH == 1 && base + k < n)
-            for (unsigned long long d = acc; d < acc + v[k] && d < (unsigned long long)rd.cap; ++d)
-                rd.dv.anc[d] = (uint32_t)(base + k);
-        if (!INCLUSIVE)
-            acc += (unsigned long long)v[k];
+        if (base + k < n)
+            write_ancestors(rd.dv.anc, acc, v[k], base + k, rd.cap);
+        acc += v[k];
     }
-    if (whole) {
-        uint4 *dst = reinterpret_cast<uint4 *>(out + base);
-        const uint4 *so = reinterpret_cast<const uint4 *>(o);
+}
+
+// The chunk sums of the sampling-variance terms: a wave's slots are one
+// chunk when it holds PA_CHUNK of them (ITEMS = 16), else the tile is one
+// chunk (ITEMS = 4: block sum).  The barriers it contains (or adds) publish
+// what the first wave wrote to LDS before.
+template <int ITEMS>
+__device__ __forceinline__ void store_chunk_sv(const PaRunDesc &rd, uint32_t tile, double sv, double *sd)
+{
+    constexpr int kTile = kThreads * ITEMS;
+    if (64 * ITEMS == PA_CHUNK) {
+        const double t = pa_wave_sum_f64(sv);
+        const int64_t chunk = (int64_t)tile * (kTile / PA_CHUNK) + (threadIdx.x >> 6);
+        if ((threadIdx.x & 63) == 0 && chunk * PA_CHUNK < rd.cap)
+            rd.dv.partial[chunk] = t;
+        __syncthreads();
+    } else {
+        static_assert(64 * ITEMS == PA_CHUNK || kTile == PA_CHUNK, "chunks of whole waves or whole tiles");
+        const double t = pa_block_sum_f64(sv, sd);
+        if (threadIdx.x == 0)
+            rd.dv.partial[tile] = t;
+    }
+}
+
+// Integer weights and their inclusive prefix sums C in one pass: tile t (the
+// run's ticket order) holds replica slots [T t, T (t + 1)), T = kThreads
+// ITEMS = pa_counts_tile(cap), ITEMS consecutive ones per thread; each weight
+// is taken from the replica's energy level (or a weighted population's own)
+// as the tile is loaded.  MULTINOMIAL: writes C and returns the copy numbers
+// to zero for the draws.  SYSTEMATIC: writes no C but each replica's copy
+// range [N(C_{j-1}), N(C_j)) straight into the ancestor map (the points
+// below C_{j-1} are the copies of the replicas before j), the new size
+// N(C_{R-1}) and the sampling variance per chunk.
+constexpr int PA_SCAN_SYSTEMATIC = 0, PA_SCAN_MULTINOMIAL = 1;
+template <int MODE, int ITEMS>
+__device__ __forceinline__ void weights_scan_tile(const PaRunDesc &rd, PaRecord *rec, uint32_t tile,
+                                                  unsigned long long *s_wave, unsigned long long *s_excl,
+                                                  double *sd)
+{
+    constexpr int kTile = kThreads * ITEMS;
+    const int64_t n = (int64_t)rec->Rcur;
+    const int64_t ntiles = (rd.cap + kTile - 1) / kTile;
+    PaScanTile *tiles = rd.dv.tiles;
+    const int64_t base = (int64_t)tile * kTile + (int64_t)threadIdx.x * ITEMS;
+    const bool whole = base + ITEMS <= n; // the thread's slots are all live
+    const bool wt = rec->weighted != 0u;
+    const int DN = rd.d * rd.N;
+    const int hmin = (rec->wemin + DN) >> 2;
+    const int32_t *E = rd.dv.E[rec->cur];
+    uint64_t v[ITEMS];
+    if (whole && !wt) {
+        alignas(16) int32_t e[ITEMS];
 #pragma unroll
-        for (int k = 0; k < kVec; ++k)
-            dst[k] = so[k];
+        for (int k = 0; k < ITEMS / 4; ++k)
+            reinterpret_cast<uint4 *>(e)[k] = reinterpret_cast<const uint4 *>(E + base)[k];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+            v[k] = weight_of(e[k], DN, hmin, rd.dv.wtab);
     } else {
 #pragma unroll
-        for (int k = 0; k < PA_SCAN_ITEMS; ++k)
-            if (base + k < n)
-                out[base + k] = o[k];
+        for (int k = 0; k < ITEMS; ++k)
+            v[k] = base + k < n ? (wt ? rd.dv.Wj[base + k] : weight_of(E[base + k], DN, hmin, rd.dv.wtab)) : 0ull;
     }
+    if (MODE == PA_SCAN_MULTINOMIAL) {
+        if (whole) {
+#pragma unroll
+            for (int k = 0; k < ITEMS / 4; ++k)
+                reinterpret_cast<uint4 *>(rd.dv.r + base)[k] = make_uint4(0u, 0u, 0u, 0u);
+        } else {
+            for (int k = 0; k < ITEMS; ++k)
+                if (base + k < n)
+                    rd.dv.r[base + k] = 0u;
+        }
+    }
+    unsigned long long run = 0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+        run += v[k];
+    unsigned long long agg;
+    const unsigned long long thread_excl = block_excl_scan<kThreads>(run, s_wave, &agg);
+    if ((threadIdx.x >> 6) == 0) {
+        const unsigned long long excl = tile_lookback(tiles, tile, agg, rec);
+        if ((threadIdx.x & 63) == 0) {
+            *s_excl = excl;
+            if ((int64_t)tile == ntiles - 1)
+                rec->Ctot = excl + agg;
+        }
+    }
+    if (MODE == PA_SCAN_MULTINOMIAL) {
+        __syncthreads();
+        unsigned long long acc = *s_excl + thread_excl;
+        alignas(16) uint64_t o[ITEMS];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            acc += v[k];
+            o[k] = acc;
+        }
+        if (whole) {
+#pragma unroll
+            for (int k = 0; k < ITEMS / 2; ++k)
+                reinterpret_cast<uint4 *>(rd.dv.C + base)[k] = reinterpret_cast<const uint4 *>(o)[k];
+        } else {
+            for (int k = 0; k < ITEMS; ++k)
+                if (base + k < n)
+                    rd.dv.C[base + k] = o[k];
+        }
+        return;
+    }
+    // systematic: N(c) = #points (k + U/2^32) S/R below c, k < R
+    __syncthreads();
+    const uint64_t S = rec->S, Rt = (uint64_t)rd.R0;
+    const uint32_t U = pa_philox(rd.seed, rd.run_id, 0u, 0u, rec->step + 1, PA_PURPOSE_RS_SYS << 28).x0;
+    unsigned long long acc = *s_excl + thread_excl;
+    uint64_t lo = sys_below(acc, Rt, S, U); // N(C_{base-1}); N(0) = 0
+    double sv = 0.0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int64_t j = base + k;
+        if (j < n) {
+            acc += v[k];
+            const uint64_t hi = sys_below(acc, Rt, S, U);
+            for (uint64_t d = lo; d < hi; ++d)
+                rd.dv.anc[d] = (uint32_t)j;
+            if (j == n - 1)
+                rec->Rnew = hi; // N(S) = Rt: the size is kept
+            sv = sv + sv_term((uint32_t)(hi - lo), v[k], (double)S, (double)Rt);
+            lo = hi;
+        }
+    }
+    store_chunk_sv<ITEMS>(rd, tile, sv, sd);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_weights_scan(const PaRunDesc *__restrict__ runs,
+                                                           const PaBlk *__restrict__ map)
+{
+    __shared__ uint32_t s_tile;
+    __shared__ unsigned long long s_wave[kThreads / 64];
+    __shared__ unsigned long long s_excl;
+    __shared__ double sd[16];
+    const PaBlk b = map[blockIdx.x];
+    const PaRunDesc &rd = runs[b.run];
+    PaRecord *rec = rd.dv.rec;
+    if (frozen(rec) || rec->keep)
+        return; // every tile of a frozen (or kept) run returns: none waits
+    if (threadIdx.x == 0)
+        s_tile = atomicAdd(&rec->ticket[0], 1u);
+    __syncthreads();
+    static_assert(kThreads * 16 == 4096 && kThreads * 4 == 1024, "the tiles of pa_counts_tile");
+    if (pa_counts_tile(rd.cap) == 4096)
+        weights_scan_tile<MODE, 16>(rd, rec, s_tile, s_wave, &s_excl, sd);
+    else
+        weights_scan_tile<MODE, 4>(rd, rec, s_tile, s_wave, &s_excl, sd);
+}
+
+// Nearest-integer (SCHEME 2: floor(tauhat) + [u S < (R W mod S) 2^32], u =
+// x0 of Philox(j, 0, i, RS_NI<<28)) or Poisson (SCHEME 1) copy numbers drawn
+// and summed in one pass: tile t (the run's ticket order) holds replica slots
+// [T t, T (t + 1)), T = kThreads ITEMS = pa_counts_tile(cap), ITEMS
+// consecutive ones per thread.  Each thread draws its replicas' copy
+// numbers, the workgroup sums them, the look-back gives the tile's offset,
+// and the ancestor map is written from it.  The sampling-variance terms of
+// chunk c (PA_CHUNK slots) go to partial[c].
+template <int SCHEME, int ITEMS>
+__device__ __forceinline__ void counts_scan_tile(const PaRunDesc &rd, PaRecord *rec, uint32_t *s_tile,
+                                                 unsigned long long *s_wave, unsigned long long *s_excl,
+                                                 double *sd)
+{
+    constexpr int kTile = kThreads * ITEMS;
+    const uint32_t tile = *s_tile;
+    const int64_t n = (int64_t)rec->Rcur;
+    const int64_t ntiles = (rd.cap + kTile - 1) / kTile;
+    PaScanTile *tiles = rd.dv.tiles + pa_tiles_per_sum(rd.cap);
+    const int64_t base = (int64_t)tile * kTile + (int64_t)threadIdx.x * ITEMS;
+    const bool wt = rec->weighted != 0u;
+    const int DN = rd.d * rd.N;
+    const int hmin = (rec->wemin + DN) >> 2;
+    const uint64_t S = rec->S, Rt = (uint64_t)rd.R0;
+    const uint32_t step = rec->step + 1;
+    const int32_t *E = rd.dv.E[rec->cur];
+    alignas(16) int32_t e[ITEMS];
+    if (base + ITEMS <= n && !wt) {
+#pragma unroll
+        for (int k = 0; k < ITEMS / 4; ++k)
+            reinterpret_cast<uint4 *>(e)[k] = reinterpret_cast<const uint4 *>(E + base)[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+            e[k] = (!wt && base + k < n) ? E[base + k] : 0;
+    }
+    uint32_t r[ITEMS];
+    double sv = 0.0;
+    unsigned long long run = 0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int64_t j = base + k;
+        r[k] = 0;
+        if (j >= n)
+            continue;
+        const uint64_t W = wt ? rd.dv.Wj[j] : weight_of(e[k], DN, hmin, rd.dv.wtab);
+        if (SCHEME == 2) {
+            const uint64_t a = Rt * W;
+            const uint64_t qt = a / S;
+            const uint64_t rho = a - qt * S;
+            const pa_philox_out o = pa_philox(rd.seed, rd.run_id, (uint32_t)j, 0u, step, PA_PURPOSE_RS_NI << 28);
+            const bool extra = ((pa_u128)o.x0 * S) < ((pa_u128)rho << 32);
+            r[k] = (uint32_t)qt + (extra ? 1u : 0u);
+        } else {
+            r[k] = poisson_copies(rd, W, S, Rt, j, step);
+        }
+        sv = sv + sv_term(r[k], W, (double)S, (double)Rt);
+        run += r[k];
+    }
+    unsigned long long agg;
+    const unsigned long long thread_excl = block_excl_scan<kThreads>(run, s_wave, &agg);
+    if ((threadIdx.x >> 6) == 0) {
+        const unsigned long long excl = tile_lookback(tiles, tile, agg, rec);
+        if ((threadIdx.x & 63) == 0) {
+            *s_excl = excl;
+            if ((int64_t)tile == ntiles - 1)
+                rec->Rnew = excl + agg;
+        }
+    }
+    store_chunk_sv<ITEMS>(rd, tile, sv, sd);
+    unsigned long long acc = *s_excl + thread_excl;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        if (base + k < n)
+            write_ancestors(rd.dv.anc, acc, r[k], base + k, rd.cap);
+        acc += r[k];
+    }
+}
+
+template <int SCHEME>
+__global__ __launch_bounds__(kThreads) void k_counts_scan(const PaRunDesc *__restrict__ runs,
+                                                          const PaBlk *__restrict__ map)
+{
+    __shared__ uint32_t s_tile;
+    __shared__ unsigned long long s_wave[kThreads / 64];
+    __shared__ unsigned long long s_excl;
+    __shared__ double sd[16];
+    const PaBlk b = map[blockIdx.x];
+    const PaRunDesc &rd = runs[b.run];
+    PaRecord *rec = rd.dv.rec;
+    if (frozen(rec) || rec->keep)
+        return; // every tile of a frozen (or kept) run returns: none waits
+    if (threadIdx.x == 0)
+        s_tile = atomicAdd(&rec->ticket[1], 1u);
+    __syncthreads();
+    static_assert(kThreads * 16 == 4096 && kThreads * 4 == 1024, "the tiles of pa_counts_tile");
+    if (pa_counts_tile(rd.cap) == 4096)
+        counts_scan_tile<SCHEME, 16>(rd, rec, &s_tile, s_wave, &s_excl, sd);
+    else
+        counts_scan_tile<SCHEME, 4>(rd, rec, &s_tile, s_wave, &s_excl, sd);
 }
 
 // A new resampling starts with a clean status (a frozen run stays frozen),
@@ -1952,8 +2116,8 @@ __global__ void k_resample_prep(const PaRunDesc *__restrict__ runs)
 {
     const PaRunDesc &rd = runs[blockIdx.x];
     PaRecord *rec = rd.dv.rec;
-    const int64_t ntiles = (rd.cap + PA_SCAN_TILE - 1) / PA_SCAN_TILE;
-    for (int64_t t = threadIdx.x; t < 2 * ntiles; t += blockDim.x)
+    const int64_t ntiles = 2 * pa_tiles_per_sum(rd.cap);
+    for (int64_t t = threadIdx.x; t < ntiles; t += blockDim.x)
         rd.dv.tiles[t].word = 0ull;
     if (threadIdx.x == 0) {
         rec->ticket[0] = rec->ticket[1] = 0u;
@@ -2755,13 +2919,12 @@ hipError_t pa_b_check_candidate(const PaBatchView &v, double alpha_star, double 
     return hipGetLastError();
 }
 
-template <typename T, bool INCL, int WHICH>
-static hipError_t scan_launch(const PaBatchView &v)
-{
-    k_scan<T, INCL, WHICH><<<v.ntile, PA_SCAN_THREADS, 0, v.stream>>>(v.runs, v.tile);
-    return hipGetLastError();
-}
-
+// Launches per scheme (after the reweighting): nearest integer and Poisson
+// draw the copy numbers and sum them into the ancestor map in one pass;
+// systematic sums the weights and writes the ancestor map from each
+// replica's closed-form copy range in the same pass; multinomial sums the
+// weights, draws, adds the sampling variance and sums the copy numbers.
+// Then the gather and the commit.
 hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze, int kq, bool prepped)
 {
     hipError_t e;
@@ -2771,31 +2934,26 @@ hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze, int kq, b
         k_cond_decide<<<v.nruns, 64, 0, v.stream>>>(v.runs, (uint32_t)kq);
     switch (scheme) {
     case 2:
-        k_counts_nearest<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
+        k_counts_scan<2><<<v.ncrep, kThreads, 0, v.stream>>>(v.runs, v.crep);
         break;
     case 1:
-        k_counts_poisson<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
+        k_counts_scan<1><<<v.ncrep, kThreads, 0, v.stream>>>(v.runs, v.crep);
         break;
     case 3:
     case 0:
-        k_weights<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
-        if ((e = scan_launch<uint64_t, true, 0>(v)) != hipSuccess)
-            return e;
         if (scheme == 3) {
-            k_counts_systematic<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
+            k_weights_scan<PA_SCAN_SYSTEMATIC><<<v.ncrep, kThreads, 0, v.stream>>>(v.runs, v.crep);
         } else {
+            k_weights_scan<PA_SCAN_MULTINOMIAL><<<v.ncrep, kThreads, 0, v.stream>>>(v.runs, v.crep);
             k_counts_multinomial<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
             k_sv_partial<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
+            k_scan_counts<<<v.ntile, PA_SCAN_THREADS, 0, v.stream>>>(v.runs, v.tile);
         }
         break;
     default:
         return hipErrorInvalidValue;
     }
     if ((e = hipGetLastError()) != hipSuccess)
-        return e;
-    // the ancestor map and the new size from the copy numbers' prefix sum
-    // (systematic: written by the copy-number kernel in closed form)
-    if (scheme != 3 && (e = scan_launch<uint32_t, false, 1>(v)) != hipSuccess)
         return e;
     k_gather_spins<<<v.ncol, kThreads, 0, v.stream>>>(v.runs, v.col);
     if (kq >= 0)

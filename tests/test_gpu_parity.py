@@ -345,6 +345,36 @@ def test_largest_population():
     g.close()
 
 
+def test_largest_population_nearest_and_poisson():
+    """Nearest-integer and Poisson resampling at R = 2^24 - 64 - 2^14 on a 4x4
+    lattice (capacity 2^24 - 64): the copy numbers are drawn and summed in one
+    pass over 4096-slot tiles (4096 tiles) with the 128-bit rounding test at
+    its bound; sizes, a capacity failure if one occurs, and the whole
+    population against the oracle; the sampling variance within 1e-9."""
+    from paper_2401_07965_amd import pa
+    d, L, cap = 2, 4, (1 << 24) - 64
+    R = cap - (1 << 14)
+    print(f"[parity] largest population, nearest and Poisson, R={R}", flush=True)
+    g = pa.PARun(d, L, R, seed=3, run_id=1, capacity=cap)
+    o = O.OracleRun(d, L, R, seed=3, run_id=1, capacity=cap)
+    for beta, scheme in ((0.004, O.NEAREST_INT), (0.01, O.POISSON), (0.05, O.NEAREST_INT)):
+        qg, qo = g.reweight(beta), o.reweight(beta)
+        assert rel_ok(qg, qo), (qg, qo)
+        try:
+            rg = g.resample(scheme)
+        except pa.CapacityError:
+            with pytest.raises(O.CapacityError):
+                o.resample(scheme)
+            continue
+        assert rg == o.resample(scheme), scheme
+        sv = g.observables()["sv"]
+        assert rel_ok(sv, o.last_sv, 1e-9) or abs(sv - o.last_sv) < 1e-14, (sv, o.last_sv)
+        g.sweep(1)
+        o.sweep(1)
+    compare_state(g, o, "largest population, nearest and Poisson")
+    g.close()
+
+
 @pytest.mark.parametrize("d,L,R,glass", [(2, 8, 130, False), (2, 6, 70, True), (3, 4, 200, True)])
 def test_sweeps_at_beta_zero_flip_every_spin(d, L, R, glass):
     """Sweeps right after the initial sampling run at beta = 0, where every
