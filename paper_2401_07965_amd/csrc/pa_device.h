@@ -55,21 +55,43 @@ __device__ __forceinline__ uint64_t pa_bop3(uint64_t a, uint64_t b, uint64_t c)
 
 // Philox4x32-10: ten rounds of (x0,x1,x2,x3) -> (hi(B x2) ^ x1 ^ k0, lo(B x2),
 // hi(A x0) ^ x3 ^ k1, lo(A x0)) with A = 0xD2511F53, B = 0xCD9E8D57 and the key
-// advanced by (0x9E3779B9, 0xBB67AE85) between rounds.  From the third round
-// on every word varies per lane, and each output takes one three-way xor;
-// the first two rounds keep plain xors so that words common to a wavefront
-// stay in scalar registers.
-__device__ __forceinline__ pa_philox_out pa_philox(uint32_t k0, uint32_t k1, uint32_t x0,
-                                                   uint32_t x1, uint32_t x2, uint32_t x3)
+// advanced by (0x9E3779B9, 0xBB67AE85) between rounds.  The callers vary x0
+// per lane and keep x1..x3 and the key common to a wavefront, so the first
+// rounds keep plain xors that let common words meet in scalar registers
+// (round 2's x3 is lo(A x0) of a common x0); from the third round on every
+// word varies per lane and each output takes one three-way xor.
+// Calls that differ in x3 alone share two products: the first round's
+// A x0 (a0), and the third round's B x2, whose x2 = hi(A y0) ^ lo(A x0) ^ k1'
+// (y0 = hi(B x2) ^ x1 ^ k0 of the first round, k1' the second round's key)
+// does not involve x3 (b2).
+struct pa_philox_shared {
+    uint64_t a0, b2;
+};
+
+__device__ __forceinline__ pa_philox_shared pa_philox_share(uint32_t k0, uint32_t k1, uint32_t x0, uint32_t x1,
+                                                            uint32_t x2)
 {
+    const uint64_t a0 = (uint64_t)0xD2511F53u * x0;
+    const uint32_t y0 = (uint32_t)(((uint64_t)0xCD9E8D57u * x2) >> 32) ^ x1 ^ k0;
+    const uint32_t x2r2 = (uint32_t)(((uint64_t)0xD2511F53u * y0) >> 32) ^ (uint32_t)a0 ^ (k1 + 0xBB67AE85u);
+    return {a0, (uint64_t)0xCD9E8D57u * x2r2};
+}
+
+__device__ __forceinline__ pa_philox_out pa_philox_with(uint32_t k0, uint32_t k1, const pa_philox_shared &sh,
+                                                        uint32_t x1, uint32_t x2, uint32_t x3)
+{
+    uint32_t x0 = 0;
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint64_t p0 = (uint64_t)0xD2511F53u * x0;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+        const uint64_t p0 = round == 0 ? sh.a0 : (uint64_t)0xD2511F53u * x0;
+        const uint64_t p1 = round == 2 ? sh.b2 : (uint64_t)0xCD9E8D57u * x2;
         uint32_t y0, y2;
         if (round < 2) {
             y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
             y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        } else if (round == 2) {
+            y0 = pa_bop3<PA_T3(PA_A ^ PA_B ^ PA_C)>((uint32_t)(p1 >> 32), x1, k0);
+            y2 = (uint32_t)(p0 >> 32) ^ (x3 ^ k1);
         } else {
             y0 = pa_bop3<PA_T3(PA_A ^ PA_B ^ PA_C)>((uint32_t)(p1 >> 32), x1, k0);
             y2 = pa_bop3<PA_T3(PA_A ^ PA_B ^ PA_C)>((uint32_t)(p0 >> 32), x3, k1);
@@ -82,6 +104,56 @@ __device__ __forceinline__ pa_philox_out pa_philox(uint32_t k0, uint32_t k1, uin
         k1 += 0xBB67AE85u;
     }
     return {x0, x1, x2, x3};
+}
+
+// K calls that differ in x3 alone, x3 = x3b | k for k < K, their rounds
+// taken in lockstep so that the K independent chains interleave.
+template <int K>
+__device__ __forceinline__ void pa_philox_k(uint32_t k0, uint32_t k1, const pa_philox_shared &sh, uint32_t x1in,
+                                            uint32_t x2in, uint32_t x3b, pa_philox_out out[K])
+{
+    uint32_t x0[K], x1[K], x2[K], x3[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        x0[k] = 0;
+        x1[k] = x1in;
+        x2[k] = x2in;
+        x3[k] = x3b | (uint32_t)k;
+    }
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint64_t p0 = round == 0 ? sh.a0 : (uint64_t)0xD2511F53u * x0[k];
+            const uint64_t p1 = round == 2 ? sh.b2 : (uint64_t)0xCD9E8D57u * x2[k];
+            uint32_t y0, y2;
+            if (round < 2) {
+                y0 = (uint32_t)(p1 >> 32) ^ x1[k] ^ k0;
+                y2 = (uint32_t)(p0 >> 32) ^ x3[k] ^ k1;
+            } else if (round == 2) {
+                y0 = pa_bop3<PA_T3(PA_A ^ PA_B ^ PA_C)>((uint32_t)(p1 >> 32), x1[k], k0);
+                y2 = (uint32_t)(p0 >> 32) ^ (x3[k] ^ k1);
+            } else {
+                y0 = pa_bop3<PA_T3(PA_A ^ PA_B ^ PA_C)>((uint32_t)(p1 >> 32), x1[k], k0);
+                y2 = pa_bop3<PA_T3(PA_A ^ PA_B ^ PA_C)>((uint32_t)(p0 >> 32), x3[k], k1);
+            }
+            x1[k] = (uint32_t)p1;
+            x3[k] = (uint32_t)p0;
+            x0[k] = y0;
+            x2[k] = y2;
+        }
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        out[k] = {x0[k], x1[k], x2[k], x3[k]};
+}
+
+__device__ __forceinline__ pa_philox_out pa_philox(uint32_t k0, uint32_t k1, uint32_t x0, uint32_t x1,
+                                                   uint32_t x2, uint32_t x3)
+{
+    return pa_philox_with(k0, k1, pa_philox_share(k0, k1, x0, x1, x2), x1, x2, x3);
 }
 
 // 1/n! rounded to nearest, n = 0..13 (n! is exact in double).

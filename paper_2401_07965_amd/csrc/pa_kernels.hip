@@ -263,6 +263,19 @@ __device__ __forceinline__ pa_philox_out metro_philox(const PlaneCtx &pc, uint32
     return pa_philox(pc.seed, pc.run_id, s, pc.w, pc.step, (PA_PURPOSE_METRO << 28) | (pc.t << 8) | q);
 }
 
+// The same with the products shared by a site's plane pairs given (one
+// share per site and sweep for its inline pairs).
+__device__ __forceinline__ pa_philox_shared metro_share(const PlaneCtx &pc, uint32_t s)
+{
+    return pa_philox_share(pc.seed, pc.run_id, s, pc.w, pc.step);
+}
+
+__device__ __forceinline__ pa_philox_out metro_philox_with(const PlaneCtx &pc, const pa_philox_shared &sh,
+                                                           uint32_t q)
+{
+    return pa_philox_with(pc.seed, pc.run_id, sh, pc.w, pc.step, (PA_PURPOSE_METRO << 28) | (pc.t << 8) | q);
+}
+
 // A plane pair given its two planes' thresholds T0, T1.  The undecided set
 // comes in as uin (its complement if INV) and leaves in und.
 template <bool INV>
@@ -353,6 +366,7 @@ __device__ __forceinline__ uint32_t queue_push(const WaveQueue &Q, uint32_t head
 }
 
 // One plane pair for up to 64 queued items; the still undecided go back.
+// calls: the wave's Philox evaluations (wave-uniform), n per pass.
 template <int D>
 __device__ __forceinline__ void queue_pass(const WaveQueue &Q, const PlaneCtx &pc, uint64_t *lat, uint32_t &head,
                                            uint32_t &cnt, uint32_t &calls)
@@ -374,9 +388,9 @@ __device__ __forceinline__ void queue_pass(const WaveQueue &Q, const PlaneCtx &p
     head += n;
     cnt -= n;
     const uint32_t s = sq & 0xFFFFu, q = sq >> 16;
+    calls += n;
     if (act) {
         uint64_t acc = 0;
-        ++calls;
         apply_pair_queued<D>(Q.tt, metro_philox(pc, s, q), q, m4, m8, und, acc);
         lat[s] ^= acc;
     }
@@ -387,6 +401,7 @@ __device__ __forceinline__ void queue_pass(const WaveQueue &Q, const PlaneCtx &p
 // The last items of a colour: up to 64 at a time, each lane taking its
 // item's remaining plane pairs in turn until the item is decided, with no
 // requeueing (the site passes leave fewer than 64, so this is one batch).
+// calls: this lane's Philox evaluations.
 template <int D>
 __device__ __forceinline__ void queue_drain(const WaveQueue &Q, const PlaneCtx &pc, uint64_t *lat, uint32_t &head,
                                             uint32_t &cnt, uint32_t &calls)
@@ -512,7 +527,7 @@ __device__ __forceinline__ void recount_column(const uint64_t *lat, const uint8_
 
 // The theta sweeps of one column in LDS.  ALL: every energy-change class has
 // a threshold strictly between 0 and 2^32 (the usual case), so no class is
-// decided without random bits.  Returns the Philox evaluations this lane made.
+// decided without random bits.
 struct SweepGeom {
     int L, N, half, nh, LL;
     uint32_t mhalf, mL; // ceil(2^32 / half), ceil(2^32 / L)
@@ -528,7 +543,12 @@ struct SweepGeom {
 // zp: the number of leading inline plane pairs on which every drawing class's
 // threshold has 0 bits (their planes lie above the largest threshold): there
 // a differing bit can only reject, so such a pair decides as und &= ~(P0 | P1).
-template <int D, bool J, bool ALL, bool FIX>
+// ZU (3D, FIX): every wave's sites share their z in each pass (L^2 / 2 colour
+// sites per z plane, a multiple of 64), so the z neighbours' offsets are
+// wave-uniform: +-L^2, or across the periodic boundary when the wave's
+// plane is the last or the first.
+// Returns the Philox evaluations, summed over the wave's lanes.
+template <int D, bool J, bool ALL, bool FIX, bool ZU = false>
 __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *jl, const SweepGeom &G, PlaneCtx pc,
                                                   const WaveQueue &Q, int theta, uint32_t t0, uint64_t sure4,
                                                   uint64_t sure8, uint64_t sure12, uint64_t draw4, uint64_t draw8,
@@ -548,7 +568,9 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
         tl[i] = (uint32_t)__builtin_amdgcn_sbfe((int)(D == 2 ? pc.t8 : pc.t12), 31u - (uint32_t)i, 1u);
         asm volatile("" : "+v"(tl[i]));
     }
-    uint32_t calls = 0;
+    // Philox evaluations: the wave's count of site and queue passes
+    // (wave-uniform) and this lane's count of its end-of-colour items
+    uint32_t wcalls = 0, calls = 0;
     for (int tt = 0; tt < theta; ++tt) {
         pc.t = t0 + (uint32_t)tt;
         for (int c = 0; c < 2; ++c) {
@@ -571,17 +593,28 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
             auto pass = [&](const int kb, auto ragged) {
                 constexpr bool RAGGED = decltype(ragged)::value;
                 const int k = kb + tid;
-                uint64_t und = 0, m4 = 0, m8 = 0;
-                uint32_t s = 0, q = 0;
+                // a lane without a site (RAGGED) keeps und = 0 and always =
+                // ~0: no pair, no push
+                uint64_t und = 0, m4 = 0, m8 = 0, always = ~0ull, acc = 0, S = 0;
+                uint32_t s = 0;
                 if (!RAGGED || k < nh) {
                     uint64_t n0, n1, n2, n3, n4 = 0, n5 = 0;
                     if (FIX) {
                         s = (uint32_t)sf;
                         n0 = lat[sf + oxp];
                         n1 = lat[sf + oxm];
-                        // (s +- vst) mod N as the unsigned smaller of the two candidates
-                        const uint32_t up = (uint32_t)sf + vst, dn = (uint32_t)sf - vst;
-                        const uint64_t nu = lat[min(up, up - (uint32_t)N)], nd = lat[min(dn, dn + (uint32_t)N)];
+                        uint64_t nu, nd;
+                        if (ZU) { // the wave's z plane decides both offsets
+                            const int s0 = __builtin_amdgcn_readfirstlane(sf);
+                            const uint64_t *ps = lat + sf;
+                            nu = ps[s0 >= N - LL ? LL - N : LL];
+                            nd = ps[s0 < LL ? N - LL : -LL];
+                        } else {
+                            // (s +- vst) mod N as the unsigned smaller of the two candidates
+                            const uint32_t up = (uint32_t)sf + vst, dn = (uint32_t)sf - vst;
+                            nu = lat[min(up, up - (uint32_t)N)];
+                            nd = lat[min(dn, dn + (uint32_t)N)];
+                        }
                         if (D == 2) {
                             n2 = nu;
                             n3 = nd;
@@ -608,12 +641,12 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
                         }
                     }
                     const uint32_t jb = J ? (uint32_t)jl[s] : 0u;
-                    const uint64_t S = lat[s];
+                    S = lat[s];
                     // a_k: bond k unsatisfied (S ^ neighbour ^ [J = -1])
                     const uint64_t a0 = bond<J>(S, n0, jb, 0), a1 = bond<J>(S, n1, jb, D);
                     const uint64_t a2 = bond<J>(S, n2, jb, 1), a3 = bond<J>(S, n3, jb, D + 1);
                     // u = number of unsatisfied bonds among 2d; dE = 4(d - u)
-                    uint64_t always, m12;
+                    uint64_t m12;
                     if (D == 2) {
                         // pair sums s and carries c of (a0, a1) and (a2, a3); without
                         // couplings S cancels from the sums and each carry is one
@@ -641,53 +674,58 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
                         m8 = none & ls;                                               // u == 1
                         m12 = none & ~ls;                                             // u == 0
                     }
-                    uint64_t acc;
                     if (ALL) { // every class draws: the rest of the word (~always) is undecided
                         acc = always;
                     } else {
                         acc = always | (m4 & sure4) | (m8 & sure8) | (m12 & sure12);
                         und = (m4 & draw4) | (m8 & draw8) | (m12 & draw12);
                     }
-                    if (ALL ? always != ~0ull : und != 0) {
-                        // nearly every site needs the first kInlinePairs pairs:
-                        // their Philox outputs are independent and computed together
-                        pa_philox_out o[kInlinePairs];
-#pragma unroll
-                        for (int k = 0; k < kInlinePairs; ++k)
-                            o[k] = metro_philox(pc, s, (uint32_t)k);
-                        const uint64_t l0 = ((uint64_t)tl[0] << 32) | tl[0], l1 = ((uint64_t)tl[1] << 32) | tl[1];
-                        if (zp > 0) { // nothing accepts on these planes
-                            const uint64_t P0 = (uint64_t)o[0].x0 | ((uint64_t)o[0].x1 << 32);
-                            const uint64_t P1 = (uint64_t)o[0].x2 | ((uint64_t)o[0].x3 << 32);
-                            und = ALL ? pa_bop3<PA_T3(~(PA_A | PA_B | PA_C))>(always, P0, P1)
-                                      : pa_bop3<PA_T3(PA_A & ~(PA_B | PA_C))>(und, P0, P1);
-                        } else if (ALL) {
-                            apply_pair<D, true>(pc, o[0], 0u, m4, m8, l0, l1, always, und, acc);
-                        } else {
-                            apply_pair<D>(pc, o[0], 0u, m4, m8, l0, l1, und, und, acc);
-                        }
-                        q = 1;
-#pragma unroll
-                        for (int k = 1; k < kInlinePairs; ++k)
-                            if (und != 0) {
-                                if (k < zp) {
-                                    const uint64_t P0 = (uint64_t)o[k].x0 | ((uint64_t)o[k].x1 << 32);
-                                    const uint64_t P1 = (uint64_t)o[k].x2 | ((uint64_t)o[k].x3 << 32);
-                                    und = pa_bop3<PA_T3(PA_A & ~(PA_B | PA_C))>(und, P0, P1);
-                                } else {
-                                    apply_pair<D>(pc, o[k], (uint32_t)k, m4, m8,
-                                                  ((uint64_t)tl[2 * k] << 32) | tl[2 * k],
-                                                  ((uint64_t)tl[2 * k + 1] << 32) | tl[2 * k + 1], und, und, acc);
-                                }
-                                q = (uint32_t)k + 1;
-                            }
-                        calls += q;
-                    }
-                    lat[s] = S ^ acc;
                 }
-                cnt = queue_push<D>(Q, head, cnt, und != 0, s | (q << 16), und, m4, m8);
+                // the first kInlinePairs plane pairs of the site: their Philox
+                // calls in lockstep (independent chains), then the decisions;
+                // the wave counts each pair's evaluations by a ballot
+                const bool need = ALL ? always != ~0ull : und != 0;
+                wcalls += (uint32_t)__popcll(__ballot(need));
+                if (need) {
+                    pa_philox_out o[kInlinePairs];
+                    pa_philox_k<kInlinePairs>(pc.seed, pc.run_id, metro_share(pc, s), pc.w, pc.step,
+                                              (PA_PURPOSE_METRO << 28) | (pc.t << 8), o);
+                    // keep the calls together (the compiler would otherwise move
+                    // each into the branch of its pair, one chain at a time)
+#pragma unroll
+                    for (int k = 0; k < kInlinePairs; ++k)
+                        asm volatile("" : "+v"(o[k].x0), "+v"(o[k].x1), "+v"(o[k].x2), "+v"(o[k].x3));
+                    const uint64_t l0 = ((uint64_t)tl[0] << 32) | tl[0], l1 = ((uint64_t)tl[1] << 32) | tl[1];
+                    if (zp > 0) { // nothing accepts on these planes
+                        const uint64_t P0 = (uint64_t)o[0].x0 | ((uint64_t)o[0].x1 << 32);
+                        const uint64_t P1 = (uint64_t)o[0].x2 | ((uint64_t)o[0].x3 << 32);
+                        und = ALL ? pa_bop3<PA_T3(~(PA_A | PA_B | PA_C))>(always, P0, P1)
+                                  : pa_bop3<PA_T3(PA_A & ~(PA_B | PA_C))>(und, P0, P1);
+                    } else if (ALL) {
+                        apply_pair<D, true>(pc, o[0], 0u, m4, m8, l0, l1, always, und, acc);
+                    } else {
+                        apply_pair<D>(pc, o[0], 0u, m4, m8, l0, l1, und, und, acc);
+                    }
+                    // a decided lane's pairs change nothing (und = 0)
+#pragma unroll
+                    for (int k = 1; k < kInlinePairs; ++k) {
+                        wcalls += (uint32_t)__popcll(__ballot(und != 0));
+                        if (k < zp) {
+                            const uint64_t P0 = (uint64_t)o[k].x0 | ((uint64_t)o[k].x1 << 32);
+                            const uint64_t P1 = (uint64_t)o[k].x2 | ((uint64_t)o[k].x3 << 32);
+                            und = pa_bop3<PA_T3(PA_A & ~(PA_B | PA_C))>(und, P0, P1);
+                        } else {
+                            apply_pair<D>(pc, o[k], (uint32_t)k, m4, m8, ((uint64_t)tl[2 * k] << 32) | tl[2 * k],
+                                          ((uint64_t)tl[2 * k + 1] << 32) | tl[2 * k + 1], und, und, acc);
+                        }
+                    }
+                }
+                if (!RAGGED || k < nh)
+                    lat[s] = S ^ acc;
+                // an item still undecided has taken all inline pairs
+                cnt = queue_push<D>(Q, head, cnt, und != 0, s | ((uint32_t)kInlinePairs << 16), und, m4, m8);
                 while (cnt >= 64u)
-                    queue_pass<D>(Q, pc, lat, head, cnt, calls);
+                    queue_pass<D>(Q, pc, lat, head, cnt, wcalls);
             };
             int kb = 0;
             for (; kb + bs <= nh; kb += bs, sf += 2 * bs)
@@ -699,7 +737,7 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
         }
     }
 
-    return calls;
+    return calls + ((threadIdx.x & 63) == 0 ? __builtin_amdgcn_readfirstlane(wcalls) : 0u);
 }
 
 // One workgroup = one word column w (64 replicas) of one run; the lattice
@@ -775,13 +813,21 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
     // leading zeros of their thresholds' or (each drawing threshold is < 2^32)
     const uint32_t tor = (uint32_t)((T4 & draw4) | (T8 & draw8) | (D == 3 ? (T12 & draw12) : 0ull));
     const int zp = uni(min(kInlinePairs, (tor ? (int)__builtin_clz(tor) : 32) / 2));
+    // 3D fixed-axis walk with every wave inside one z plane per pass
+    const bool zu = D == 3 && fix && (LL / 2) % 64 == 0;
     uint32_t calls;
-    if (all_draw && fix)
+    if (all_draw && zu)
+        calls = sweep_columns<D, J, true, true, D == 3>(lat, jl, G, pc, Q, theta, t0, sure4, sure8, sure12, draw4,
+                                                        draw8, draw12, zp);
+    else if (all_draw && fix)
         calls = sweep_columns<D, J, true, true>(lat, jl, G, pc, Q, theta, t0, sure4, sure8, sure12, draw4, draw8,
                                                 draw12, zp);
     else if (all_draw)
         calls = sweep_columns<D, J, true, false>(lat, jl, G, pc, Q, theta, t0, sure4, sure8, sure12, draw4, draw8,
                                                  draw12, zp);
+    else if (zu)
+        calls = sweep_columns<D, J, false, true, D == 3>(lat, jl, G, pc, Q, theta, t0, sure4, sure8, sure12, draw4,
+                                                         draw8, draw12, zp);
     else if (fix)
         calls = sweep_columns<D, J, false, true>(lat, jl, G, pc, Q, theta, t0, sure4, sure8, sure12, draw4, draw8,
                                                  draw12, zp);
