@@ -685,8 +685,12 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
                 // calls in lockstep (independent chains), then the decisions;
                 // the wave counts each pair's evaluations by a ballot
                 const bool need = ALL ? always != ~0ull : und != 0;
-                wcalls += (uint32_t)__popcll(__ballot(need));
-                if (need) {
+                const uint64_t needing = __ballot(need);
+                wcalls += (uint32_t)__popcll(needing);
+                // branch for the wave, not the lane: a lane that needs no pair
+                // has und = 0 (always = ~0) and its decisions change nothing,
+                // and the pair counts below stay wave-uniform
+                if (needing != 0ull) {
                     pa_philox_out o[kInlinePairs];
                     pa_philox_k<kInlinePairs>(pc.seed, pc.run_id, metro_share(pc, s), pc.w, pc.step,
                                               (PA_PURPOSE_METRO << 28) | (pc.t << 8), o);

@@ -297,19 +297,25 @@ def test_extinction_matches_oracle_and_leaves_the_state():
     g.close()
 
 
-@pytest.mark.parametrize("d,L,R,scheme,J", [(2, 8, 640, O.SYSTEMATIC, None),
-                                            (3, 4, 256, O.MULTINOMIAL, "glass")])
-def test_work_counters_match_the_oracle_count(d, L, R, scheme, J):
+@pytest.mark.parametrize("d,L,R,scheme,J,beta_f", [(2, 8, 640, O.SYSTEMATIC, None, 1.2),
+                                                   (3, 4, 256, O.MULTINOMIAL, "glass", 1.2),
+                                                   (2, 16, 640, O.SYSTEMATIC, None, 1.2),
+                                                   (3, 16, 128, O.SYSTEMATIC, "glass", 2.6)])
+def test_work_counters_match_the_oracle_count(d, L, R, scheme, J, beta_f):
     """The sweeps' Philox count (the roofline's work figure) equals the oracle's
     count of plane pairs the decisions need, and the site and attempt counts
-    their closed forms (full 64-replica words, fixed-size resampling)."""
+    their closed forms (full 64-replica words, fixed-size resampling).  The
+    ordered ferromagnet and the glass at beta = 2.6 leave most sites with no
+    replica to decide, so within a wave some lanes need pairs and others
+    none (the 3D L = 16 case takes the fixed-axis walk with wave-uniform z
+    offsets)."""
     from paper_2401_07965_amd import pa
     Jc = ea_couplings(d, L, 3) if J else None
-    print(f"[parity] work counters d={d} L={L} R={R} scheme={scheme}", flush=True)
+    print(f"[parity] work counters d={d} L={L} R={R} scheme={scheme} beta_f={beta_f}", flush=True)
     g = pa.PARun(d, L, R, seed=6, run_id=1, couplings=Jc)
     o = O.OracleRun(d, L, R, seed=6, run_id=1, J=Jc)
     theta, steps = 4, 12
-    for beta in schedule(1.2, steps + 1)[1:]:
+    for beta in schedule(beta_f, steps + 1)[1:]:
         g.reweight(beta)
         o.reweight(beta)
         g.resample(scheme)
@@ -320,6 +326,7 @@ def test_work_counters_match_the_oracle_count(d, L, R, scheme, J):
     assert c["philox_calls"] == o.philox_calls > 0
     assert c["site_updates"] == steps * theta * L ** d * (R // 64)
     assert c["spin_attempts"] == steps * theta * L ** d * R
+    compare_state(g, o, f"work counters d={d} L={L}")
     g.close()
 
 
