@@ -295,6 +295,31 @@ __device__ __forceinline__ uint64_t pa_block_sum_u64(uint64_t v, uint64_t *lds /
     return t;
 }
 
+// K block-wide double sums with one exchange through LDS, each in the fixed
+// order of pa_block_sum_f64 (wave tree, then the waves in order).
+template <int K>
+__device__ __forceinline__ void pa_block_sum_f64x(double (&v)[K], double *lds /* >= 16 K */)
+{
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        v[i] = pa_wave_sum_f64(v[i]);
+    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            lds[wave * K + i] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        double t = 0.0;
+        for (int k = 0; k < nwaves; ++k)
+            t = t + lds[k * K + i];
+        v[i] = t;
+    }
+    __syncthreads();
+}
+
 // K block-wide uint64 sums with one exchange through LDS (exact, so any order).
 template <int K>
 __device__ __forceinline__ void pa_block_sum_u64x(uint64_t (&v)[K], uint64_t *lds /* >= 16 K */)

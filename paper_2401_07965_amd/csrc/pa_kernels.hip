@@ -2386,8 +2386,8 @@ constexpr int kObsLevels = 2048;
 __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restrict__ runs,
                                                       const PaBlk *__restrict__ map, int build_hist)
 {
-    __shared__ uint64_t su[16];
-    __shared__ double sd[16];
+    __shared__ uint64_t su[16 * 5];
+    __shared__ double sd[16 * PA_WPARTS];
     __shared__ uint32_t lh[kObsLevels];
     __shared__ int s_lo[kThreads / 64], s_hi[kThreads / 64];
     RepCtx c;
@@ -2476,23 +2476,24 @@ __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restric
             atomicAdd(&dv.fam[lab], (uint32_t)(stop - lane));
         }
     }
-    sE = pa_block_sum_u64(sE, su); // (its barrier also ends the LDS counting)
+    uint64_t sums[5] = {sE, sE2, sA, sM2, sE3};
+    pa_block_sum_u64x(sums, su); // (its barriers also end the LDS counting)
+    sE = sums[0];
+    sE2 = sums[1];
+    sA = sums[2];
+    sM2 = sums[3];
+    sE3 = sums[4];
     if (build_hist && nlh <= kObsLevels)
         for (int k = threadIdx.x; k < nlh; k += blockDim.x)
             if (lh[k])
                 atomicAdd(&dv.hist[hlo + k], lh[k]);
-    sE2 = pa_block_sum_u64(sE2, su);
-    sA = pa_block_sum_u64(sA, su);
-    sM2 = pa_block_sum_u64(sM2, su);
-    sE3 = pa_block_sum_u64(sE3, su);
     if (wt) {
         const int64_t chunks = (c.rd->cap + PA_CHUNK - 1) / PA_CHUNK, k = c.beg / PA_CHUNK;
+        pa_block_sum_f64x(ws, sd);
+        if (threadIdx.x == 0)
 #pragma unroll
-        for (int f = 0; f < PA_WPARTS; ++f) {
-            const double t = pa_block_sum_f64(ws[f], sd);
-            if (threadIdx.x == 0)
-                dv.wpart[f * chunks + k] = t;
-        }
+            for (int f = 0; f < PA_WPARTS; ++f)
+                dv.wpart[f * chunks + k] = ws[f];
     }
     if (threadIdx.x == 0) {
         // 128-bit add of the block's signed sum: low word, then the high word
@@ -2510,7 +2511,7 @@ __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restric
 __global__ __launch_bounds__(kThreads) void k_obs_fam(const PaRunDesc *__restrict__ runs,
                                                       const PaBlk *__restrict__ map)
 {
-    __shared__ uint64_t su[16];
+    __shared__ uint64_t su[16 * 2];
     __shared__ double sd[16];
     const PaBlk b = map[blockIdx.x];
     const PaRunDesc &rd = runs[b.run];
@@ -2530,8 +2531,10 @@ __global__ __launch_bounds__(kThreads) void k_obs_fam(const PaRunDesc *__restric
             cl = cl + (double)c * log((double)c);
         }
     }
-    c2 = pa_block_sum_u64(c2, su);
-    nf = pa_block_sum_u64(nf, su);
+    uint64_t sums[2] = {c2, nf};
+    pa_block_sum_u64x(sums, su);
+    c2 = sums[0];
+    nf = sums[1];
     cl = pa_block_sum_f64(cl, sd);
     if (threadIdx.x == 0) {
         atomicAdd(&rec->accC2, (unsigned long long)c2);
