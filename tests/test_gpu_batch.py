@@ -132,6 +132,37 @@ def test_frozen_run_does_not_disturb_the_others():
     B.close()
 
 
+@pytest.mark.parametrize("scheme", [O.NEAREST_INT, O.POISSON, O.SYSTEMATIC, O.MULTINOMIAL])
+def test_tile_sizes_follow_each_run_not_the_batch(scheme):
+    """The resampling passes tile a run by its own capacity (1024 slots per
+    tile below 2^18, 4096 from 2^18 on), so a small run batched with a large
+    one, and a large run with capacity just past the switch, give exactly the
+    bits of their single runs (copy numbers, sampling variance, state)."""
+    from paper_2401_07965_amd import pa
+    betas = schedule(1.0, 5)
+    cfgs = [dict(dim=2, L=4, R=300, seed=2, run_id=0, couplings=None),
+            dict(dim=2, L=4, R=(1 << 18) - 4096, seed=2, run_id=1, couplings=None, capacity=1 << 18),
+            dict(dim=2, L=4, R=(1 << 18) - 8192, seed=2, run_id=2, couplings=None, capacity=(1 << 18) - 64)]
+    B = pa.PABatch(cfgs, max_points=len(betas))
+    B.anneal(betas, 2, scheme, use_graph=False)
+    rec = B.records()
+    for m, cfg in enumerate(cfgs):
+        g = pa.PARun(cfg["dim"], cfg["L"], cfg["R"], seed=cfg["seed"], run_id=cfg["run_id"],
+                     capacity=cfg.get("capacity", 0))
+        for i, b in enumerate(betas[1:], 1):
+            assert rec[m, i]["lnQ"] == g.reweight(b), (m, i)
+            assert rec[m, i]["R"] == g.resample(scheme), (m, i)
+            g.sweep(2)
+            ob = g.observables()
+            assert rec[m, i]["sv"] == ob["sv"] and rec[m, i]["lnZ"] == g.free_energy(), (m, i)
+        st = g.export()
+        bs = B.export_run(m)
+        for k in ("spins", "energy", "label"):
+            assert np.array_equal(bs[k], st[k]), (m, k)
+        g.close()
+    B.close()
+
+
 def test_weighted_combination_matches_oracle():
     from paper_2401_07965_amd import pa
     betas = schedule(1.0, 8)
