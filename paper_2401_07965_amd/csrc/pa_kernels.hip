@@ -263,17 +263,11 @@ __device__ __forceinline__ pa_philox_out metro_philox(const PlaneCtx &pc, uint32
     return pa_philox(pc.seed, pc.run_id, s, pc.w, pc.step, (PA_PURPOSE_METRO << 28) | (pc.t << 8) | q);
 }
 
-// The same with the products shared by a site's plane pairs given (one
-// share per site and sweep for its inline pairs).
+// The products shared by a site's plane pairs (one share per site and sweep
+// for its inline pairs).
 __device__ __forceinline__ pa_philox_shared metro_share(const PlaneCtx &pc, uint32_t s)
 {
     return pa_philox_share(pc.seed, pc.run_id, s, pc.w, pc.step);
-}
-
-__device__ __forceinline__ pa_philox_out metro_philox_with(const PlaneCtx &pc, const pa_philox_shared &sh,
-                                                           uint32_t q)
-{
-    return pa_philox_with(pc.seed, pc.run_id, sh, pc.w, pc.step, (PA_PURPOSE_METRO << 28) | (pc.t << 8) | q);
 }
 
 // A plane pair given its two planes' thresholds T0, T1.  The undecided set
