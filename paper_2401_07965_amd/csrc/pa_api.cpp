@@ -323,7 +323,7 @@ uint64_t layout(const std::vector<Geometry> &geo, int max_points, char *base, Ba
             tb.hrep.push_back({(uint32_t)m, (uint32_t)c});
         for (int64_t c = 0; c < (g.cap + pa_counts_tile(g.cap) - 1) / pa_counts_tile(g.cap); ++c)
             tb.crep.push_back({(uint32_t)m, (uint32_t)c});
-        for (int64_t c = 0; c < (g.R + PA_CHUNK - 1) / PA_CHUNK; ++c)
+        for (int64_t c = 0; c < (g.R + PA_HCHUNK - 1) / PA_HCHUNK; ++c)
             tb.fam.push_back({(uint32_t)m, (uint32_t)c});
         for (int64_t w = 0; w < g.W; ++w)
             tb.col.push_back({(uint32_t)m, (uint32_t)w});

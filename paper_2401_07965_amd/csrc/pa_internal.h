@@ -174,7 +174,7 @@ struct PaBatchView {
     uint32_t nhrep;
     const PaBlk *crep; // tiles of the copy-number pass (pa_counts_tile slots)
     uint32_t ncrep;
-    const PaBlk *fam;  // chunks of PA_CHUNK families
+    const PaBlk *fam;  // chunks of PA_HCHUNK families
     uint32_t nfam;
     const PaBlk *col;  // all 64-replica columns (capacity)
     uint32_t ncol;

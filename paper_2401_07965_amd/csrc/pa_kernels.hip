@@ -2384,9 +2384,19 @@ __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restric
     __shared__ double sd[16 * PA_WPARTS];
     __shared__ uint32_t lh[kObsLevels];
     __shared__ int s_lo[kThreads / 64], s_hi[kThreads / 64];
+    // PA_HCHUNK replica slots per workgroup (four chunks): fewer workgroups
+    // merge their level counts and sums into the run's, on the same addresses
     RepCtx c;
-    if (!rep_ctx(runs, map, &c))
-        return;
+    {
+        const PaBlk b = map[blockIdx.x];
+        c.rd = runs + b.run;
+        c.rec = c.rd->dv.rec;
+        const int64_t R = (int64_t)c.rec->Rcur;
+        c.beg = (int64_t)b.idx * PA_HCHUNK;
+        c.end = c.beg + PA_HCHUNK < R ? c.beg + PA_HCHUNK : R;
+        if (c.beg >= R || frozen(c.rec))
+            return;
+    }
     const PaDev &dv = c.rd->dv;
     const int cur = c.rec->cur;
     const int DN = c.rd->d * c.rd->N;
@@ -2429,6 +2439,8 @@ __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restric
     // a weighted population: sums of w, wE, wE^2, wE^3, w|M|, wM^2, w^2 with w = pa_exp(lw)
     const bool wt = c.rec->weighted != 0u;
     double ws[PA_WPARTS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    static_assert(PA_HCHUNK % PA_CHUNK == 0 && PA_CHUNK % kThreads == 0, "whole chunks of whole passes");
+    const int64_t chunks = (c.rd->cap + PA_CHUNK - 1) / PA_CHUNK;
     for (int64_t base = c.beg; base < c.end; base += blockDim.x) {
         const int64_t d = base + threadIdx.x;
         const bool valid = d < c.end;
@@ -2469,6 +2481,18 @@ __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restric
             const int stop = above ? __ffsll((long long)above) - 1 : 64;
             atomicAdd(&dv.fam[lab], (uint32_t)(stop - lane));
         }
+        // a weighted population's sums per chunk of PA_CHUNK slots, in the
+        // fixed order of the block sum
+        if (wt && ((base + (int64_t)blockDim.x) % PA_CHUNK == 0 || base + (int64_t)blockDim.x >= c.end)) {
+            pa_block_sum_f64x(ws, sd);
+            if (threadIdx.x == 0)
+#pragma unroll
+                for (int f = 0; f < PA_WPARTS; ++f)
+                    dv.wpart[f * chunks + base / PA_CHUNK] = ws[f];
+#pragma unroll
+            for (int f = 0; f < PA_WPARTS; ++f)
+                ws[f] = 0.0;
+        }
     }
     uint64_t sums[5] = {sE, sE2, sA, sM2, sE3};
     pa_block_sum_u64x(sums, su); // (its barriers also end the LDS counting)
@@ -2481,14 +2505,6 @@ __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restric
         for (int k = threadIdx.x; k < nlh; k += blockDim.x)
             if (lh[k])
                 atomicAdd(&dv.hist[hlo + k], lh[k]);
-    if (wt) {
-        const int64_t chunks = (c.rd->cap + PA_CHUNK - 1) / PA_CHUNK, k = c.beg / PA_CHUNK;
-        pa_block_sum_f64x(ws, sd);
-        if (threadIdx.x == 0)
-#pragma unroll
-            for (int f = 0; f < PA_WPARTS; ++f)
-                dv.wpart[f * chunks + k] = ws[f];
-    }
     if (threadIdx.x == 0) {
         // 128-bit add of the block's signed sum: low word, then the high word
         // with the carry out of the low word (order-free, hence exact)
@@ -2502,6 +2518,10 @@ __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restric
     }
 }
 
+// Family statistics over PA_HCHUNK family slots per workgroup: sum of c^2,
+// the number of families and sum of c ln c (partial[block], in the block's
+// fixed order; k_obs_final adds them in block order); the counts return to
+// zero for the next pass.
 __global__ __launch_bounds__(kThreads) void k_obs_fam(const PaRunDesc *__restrict__ runs,
                                                       const PaBlk *__restrict__ map)
 {
@@ -2512,8 +2532,8 @@ __global__ __launch_bounds__(kThreads) void k_obs_fam(const PaRunDesc *__restric
     PaRecord *rec = rd.dv.rec;
     if (frozen(rec))
         return;
-    const int64_t beg = (int64_t)b.idx * PA_CHUNK;
-    const int64_t end = beg + PA_CHUNK < rd.R0 ? beg + PA_CHUNK : rd.R0;
+    const int64_t beg = (int64_t)b.idx * PA_HCHUNK;
+    const int64_t end = beg + PA_HCHUNK < rd.R0 ? beg + PA_HCHUNK : rd.R0;
     uint64_t c2 = 0, nf = 0;
     double cl = 0.0;
     for (int64_t f = beg + threadIdx.x; f < end; f += blockDim.x) {
@@ -2527,12 +2547,10 @@ __global__ __launch_bounds__(kThreads) void k_obs_fam(const PaRunDesc *__restric
     }
     uint64_t sums[2] = {c2, nf};
     pa_block_sum_u64x(sums, su);
-    c2 = sums[0];
-    nf = sums[1];
     cl = pa_block_sum_f64(cl, sd);
     if (threadIdx.x == 0) {
-        atomicAdd(&rec->accC2, (unsigned long long)c2);
-        atomicAdd(&rec->accFam, (unsigned long long)nf);
+        atomicAdd(&rec->accC2, (unsigned long long)sums[0]);
+        atomicAdd(&rec->accFam, (unsigned long long)sums[1]);
         rd.dv.partial[b.idx] = cl;
     }
 }
@@ -2564,7 +2582,7 @@ __global__ __launch_bounds__(kThreads) void k_obs_final(const PaRunDesc *__restr
     PaRecord *rec = rd.dv.rec;
     const bool fz = frozen(rec);
     const bool wt = !fz && rec->weighted != 0u;
-    const int nparts = (int)((rd.R0 + PA_CHUNK - 1) / PA_CHUNK);
+    const int nparts = (int)((rd.R0 + PA_HCHUNK - 1) / PA_HCHUNK); // k_obs_fam's workgroups
     double v = 0.0;
     if (!fz)
         for (int k = threadIdx.x; k < nparts; k += blockDim.x)
@@ -3013,7 +3031,7 @@ hipError_t pa_b_observables(const PaBatchView &v, int point, int hist_state)
 {
     if (hist_state == PA_HIST_STALE)
         k_hist_prep<<<v.nruns, kThreads, 0, v.stream>>>(v.runs);
-    k_obs_rep<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep, hist_state != PA_HIST_VALID);
+    k_obs_rep<<<v.nhrep, kThreads, 0, v.stream>>>(v.runs, v.hrep, hist_state != PA_HIST_VALID);
     k_obs_fam<<<v.nfam, kThreads, 0, v.stream>>>(v.runs, v.fam);
     k_obs_final<<<v.nruns, kThreads, 0, v.stream>>>(v.runs, point >= 0 ? v.steprec : nullptr, v.npoints,
                                                     point);
