@@ -163,6 +163,28 @@ def test_tile_sizes_follow_each_run_not_the_batch(scheme):
     B.close()
 
 
+def test_3d_L16_walks_at_every_size_match_the_oracle():
+    """3D L = 16 takes the fixed-axis walk with wave-uniform z offsets at 256,
+    512 and 768 lanes (one, two or three z planes of a colour per pass) and
+    the general walk at the other sizes; every size gives the oracle's bits."""
+    from paper_2401_07965_amd import pa
+    betas = [0.0, 0.2, 0.6, 2.6]
+    J = ea_couplings(3, 16, 4)
+    cfg = dict(dim=3, L=16, R=130, seed=4, run_id=2, couplings=J)
+    o = O.OracleRun(3, 16, 130, seed=4, run_id=2, J=J)
+    for b in betas[1:]:
+        o.reweight(b)
+        o.resample(O.SYSTEMATIC)
+        o.sweep(2)
+    B = pa.PABatch([cfg], max_points=len(betas))
+    for t in (256, 512, 768, 192, 640):
+        print(f"[batch] 3D L=16 at {t} lanes", flush=True)
+        B.set_threads(0, t)
+        B.anneal(betas, 2, O.SYSTEMATIC, use_graph=False)
+        compare_state(_Exported(B, 0), o, f"3D L=16, {t} lanes")
+    B.close()
+
+
 def test_weighted_combination_matches_oracle():
     from paper_2401_07965_amd import pa
     betas = schedule(1.0, 8)
