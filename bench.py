@@ -56,9 +56,9 @@ OP_MODEL = {
 
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 COUNTER_PROFILES = {
-    "config5": os.path.join(PROFILE_DIR, "k_sweep_3d_pmj_L16_R1e6_counters.md"),
-    "config3": os.path.join(PROFILE_DIR, "k_sweep_3d_pmj_L10_R5e5_counters.md"),
-    "config2": os.path.join(PROFILE_DIR, "k_sweep_2d_fm_L64_R1e5_counters.md"),
+    "glass3d_L16": os.path.join(PROFILE_DIR, "k_sweep_3d_pmj_L16_R1e6_counters.md"),
+    "glass3d_L10": os.path.join(PROFILE_DIR, "k_sweep_3d_pmj_L10_R5e5_counters.md"),
+    "fm2d_L64": os.path.join(PROFILE_DIR, "k_sweep_2d_fm_L64_R1e5_counters.md"),
 }
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2401_07965_amd", "csrc", f)
                   for f in ("pa_kernels.hip", "pa_device.h", "pa_internal.h")]
@@ -124,10 +124,12 @@ def union_length(intervals):
 
 
 def resample_bytes(N, R_old, R_new):
-    """Algorithmic HBM bytes of reweighting and resampling: per old replica the
-    energy read and the copy number / offset writes and reads (20 B); per new
-    replica its spins read and written (2 N/8 B) plus energy, magnetisation and
-    label read and written and the ancestor read (28 B)."""
+    """Algorithmic HBM bytes of reweighting and resampling (a fixed model of
+    the work, kept across implementations): per old replica 20 B (its energy
+    read, a copy number or weight written and read, the ancestor map
+    written); per new replica its spins read and written (2 N/8 B) plus
+    energy, magnetisation and label read and written and the ancestor read
+    (28 B)."""
     return R_old * (4 + 4 + 4 + 4 + 4) + R_new * (2 * N / 8 + 3 * 4 * 2 + 4)
 
 
@@ -335,7 +337,7 @@ def sweep_roofline(kernel, N, attempts, calls, updates, words, launch_ms, rate, 
     return out
 
 
-def config2_row(steps_timed=None):
+def fm2d_L64_row(steps_timed=None):
     """2D Ising ferromagnet L = 64, R = 10^5, theta = 10, beta_i = 0.6 i/200
     (201 points), one run per resampling scheme (run_id = scheme, seed 1),
     each on its own stream: one whole anneal of the four runs (deferred
@@ -392,7 +394,7 @@ def config2_row(steps_timed=None):
             "by_scheme": by}
 
 
-def config3_row():
+def glass3d_L10_row():
     """3D +-J glass L = 10, R = 5 10^5 per population, theta = 10,
     beta_i = 3 i/300 (301 points), systematic; populations A and B (run_id 0
     and 1, same couplings from seed 1) annealed together as a batch (one HIP
@@ -895,9 +897,9 @@ def profile_run(which, steps, warmup):
     traffic."""
     import torch
     from paper_2401_07965_amd import pa, workloads
-    if which == "config5":
+    if which == "glass3d_L16":
         J, d, Ls, Rs, sched, sc = headline_couplings(), D, L, R, schedule(), SCHEME
-    elif which == "config3":
+    elif which == "glass3d_L10":
         J, d, Ls, Rs, sched, sc = workloads.pm_j_couplings(3, 10, 1), 3, 10, 500000, schedule(3.0, 301), SCHEME
     else:
         J, d, Ls, Rs, sched, sc = None, 2, 64, 100000, schedule(0.6, 201), 3
@@ -955,7 +957,7 @@ def cpu_baseline(budget_s=12.0, budget_1core_s=6.0):
             "sample_1_core": f"{steps1} temperature steps of the same run on one thread ({el1:.1f} s)"}
 
 
-ROWS = ("anneal", "config2", "config3", "resample_scaling", "batched", "learned", "combination",
+ROWS = ("anneal", "fm2d_L64", "glass3d_L10", "resample_scaling", "batched", "learned", "combination",
         "resampling", "conditional", "scheme_errors", "rmsd", "cluster")
 
 
@@ -967,7 +969,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rows", action="store_true", help="only the headline (no other rows)")
     ap.add_argument("--rows", default=",".join(ROWS), help="comma-separated rows to run: " + ",".join(ROWS))
-    ap.add_argument("--profile", choices=("config5", "config3", "config2"),
+    ap.add_argument("--profile", choices=("glass3d_L16", "glass3d_L10", "fm2d_L64"),
                     help="short run for hardware counters: warmup + steps temperature steps of one run "
                          "of the workload, then a 256 MiB device-to-device copy of known size")
     a = ap.parse_args()
@@ -984,9 +986,9 @@ def main():
     r = headline_bench(a.steps, a.warmup)
     rate = philox_rate()
     value = r["attempts"] / r["elapsed"] / 1e9
-    prof = profiled_counters("config5")
+    prof = profiled_counters("glass3d_L16")
     if prof:
-        prof["path"] = COUNTER_PROFILES["config5"]
+        prof["path"] = COUNTER_PROFILES["glass3d_L16"]
     out = {
         "metric": "spin-flip attempts/ns (whole PA temperature step)",
         "value": value,
@@ -1018,7 +1020,7 @@ def main():
     if unknown:
         print(f"unknown rows: {unknown}", file=sys.stderr)
         sys.exit(2)
-    fns = {"anneal": lambda: anneal_row(rate), "config2": config2_row, "config3": config3_row,
+    fns = {"anneal": lambda: anneal_row(rate), "fm2d_L64": fm2d_L64_row, "glass3d_L10": glass3d_L10_row,
            "resample_scaling": resample_scaling, "batched": batched_bench, "learned": learned_bench,
            "combination": combination_study, "resampling": resampling_study,
            "conditional": conditional_study, "scheme_errors": scheme_error_study, "rmsd": rmsd_study,
