@@ -738,6 +738,54 @@ __device__ __forceinline__ uint32_t sweep_columns(uint64_t *lat, const uint8_t *
     return calls + ((threadIdx.x & 63) == 0 ? __builtin_amdgcn_readfirstlane(wcalls) : 0u);
 }
 
+// n elements from global memory into LDS.  A lane issues R loads before its
+// first store, so that they are in flight together: rounds of 8, then of 4,
+// while whole rounds remain, then rounds of 2 (lanes past the end load the
+// last element again and store nothing).  No load is under a branch, which
+// would make each one wait for the one before.
+template <typename T, int R>
+__device__ __forceinline__ int stage_rounds(T *dst, const __attribute__((address_space(1))) T *src, int n, int b0,
+                                            bool whole)
+{
+    const int tid = threadIdx.x, bs = blockDim.x;
+    for (; whole ? b0 + R * bs <= n : b0 < n; b0 += R * bs) {
+        T v[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            v[k] = src[whole ? b0 + tid + k * bs : min(b0 + tid + k * bs, n - 1)];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int i = b0 + tid + k * bs;
+            if (whole || i < n)
+                dst[i] = v[k];
+        }
+    }
+    return b0;
+}
+
+template <typename T>
+__device__ __forceinline__ void stage_to_lds(T *dst, const __attribute__((address_space(1))) T *src, int n)
+{
+    int b0 = stage_rounds<T, 8>(dst, src, n, 0, true);
+    b0 = stage_rounds<T, 4>(dst, src, n, b0, true);
+    stage_rounds<T, 2>(dst, src, n, b0, false);
+}
+
+// A column's N words (16 bytes per load) and, with couplings, its N bond
+// masks (4 bytes per load) into LDS.  N is a multiple of 4 (L even); g is
+// 32-byte and jm 256-byte aligned.
+template <bool J>
+__device__ __forceinline__ void load_column(uint64_t *lat, uint8_t *jl, const uint64_t *g, const uint8_t *jm,
+                                            int N)
+{
+    typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+    stage_to_lds<u64x2>(reinterpret_cast<u64x2 *>(lat), (const __attribute__((address_space(1))) u64x2 *)g,
+                        N >> 1);
+    if (J)
+        stage_to_lds<uint32_t>(reinterpret_cast<uint32_t *>(jl),
+                               (const __attribute__((address_space(1))) uint32_t *)jm, N >> 2);
+}
+
 // One workgroup = one word column w (64 replicas) of one run; the lattice
 // stays in LDS for all theta sweeps, then each replica's unsatisfied-bond
 // count U and number of down spins are counted bit-sliced: E = 2U - dN,
@@ -776,11 +824,7 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
             ttab[ttab_stride<D>() * tid + 2 * c + 1] = (uint32_t)__builtin_amdgcn_sbfe((int)t[c], b0 - 1u, 1u);
         }
     }
-    for (int s = tid; s < N; s += bs) {
-        lat[s] = g[s];
-        if (J)
-            jl[s] = rd.dv.jmask[s];
-    }
+    load_column<J>(lat, jl, g, rd.dv.jmask, N);
     __syncthreads();
 
     const uint64_t two32 = 1ull << 32;
@@ -970,11 +1014,7 @@ __global__ __launch_bounds__(kClusterThreads) void k_cluster(const PaRunDesc *__
     uint8_t *jl = reinterpret_cast<uint8_t *>(qs + nw * kClusterQueue);
     const ClusterQueue Q = {qs + (tid >> 6) * kClusterQueue, qc + (tid >> 6) * kClusterQueue};
     uint64_t *g = rd.dv.spins[cur] + (size_t)w * N;
-    for (int s = tid; s < N; s += bs) {
-        lat[s] = g[s];
-        if (J)
-            jl[s] = rd.dv.jmask[s];
-    }
+    load_column<J>(lat, jl, g, rd.dv.jmask, N);
     const uint32_t mL = uni((uint32_t)(((1ull << 32) + (uint64_t)L - 1) / (uint64_t)L));
     const double p = 1.0 - pa_exp(-(2.0 * rec->beta));
     const double tf = floor(ldexp(p, 32));

@@ -185,6 +185,31 @@ def test_3d_L16_walks_at_every_size_match_the_oracle():
     B.close()
 
 
+def test_small_lattices_at_several_walk_sizes_match_the_oracle():
+    """Small 2D and 3D glasses at workgroup sizes that give a lane one site of
+    a colour (with idle lanes or none) or several, by the fixed-axis walk or
+    the general one: every size gives the oracle's bits."""
+    from paper_2401_07965_amd import pa
+    betas = [0.0, 0.3, 0.9, 2.6]
+    cases = [(3, 10, (512, 576, 64, 256)), (3, 8, (256, 128, 320)), (3, 6, (128, 64)),
+             (2, 8, (64, 128)), (2, 12, (128, 64)), (2, 16, (128, 64, 192))]
+    for d, L, sizes in cases:
+        J = ea_couplings(d, L, 5)
+        cfg = dict(dim=d, L=L, R=130, seed=6, run_id=1, couplings=J)
+        o = O.OracleRun(d, L, 130, seed=6, run_id=1, J=J)
+        for b in betas[1:]:
+            o.reweight(b)
+            o.resample(O.SYSTEMATIC)
+            o.sweep(2)
+        B = pa.PABatch([cfg], max_points=len(betas))
+        for t in sizes:
+            print(f"[batch] {d}D L={L} at {t} lanes", flush=True)
+            B.set_threads(0, t)
+            B.anneal(betas, 2, O.SYSTEMATIC, use_graph=False)
+            compare_state(_Exported(B, 0), o, f"{d}D L={L}, {t} lanes")
+        B.close()
+
+
 def test_weighted_combination_matches_oracle():
     from paper_2401_07965_amd import pa
     betas = schedule(1.0, 8)
