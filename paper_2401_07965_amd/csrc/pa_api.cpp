@@ -93,14 +93,18 @@ bool sweep_threads_ok(int N, int d, int t)
     return t >= 64 && t <= kSweepMaxLanes && t % 64 == 0 && (int64_t)((N + t - 1) / t) * d <= 255;
 }
 
-constexpr int kLdsPerCu = 163840;  // gfx950: 160 KiB of LDS per CU
-constexpr int kSweepWavesPerSimd = 3; // waves per SIMD the size choice assumes (the registers allow 4; workgroups of more than 4 waves measured slower)
+constexpr int kLdsPerCu = 163840; // gfx950: 160 KiB of LDS per CU
 
 // Default sweep workgroup size, by a score: resident sweep waves per CU
-// (limited by the LDS of the lattice and queues and by registers; counted up
-// to 3 per SIMD, beyond which more waves hide no more latency) times the
-// fraction of lanes busy over a colour's sites (N/2 sites in rounds of t
-// lanes).  The smaller size wins ties.  Autotuning refines it for batches.
+// (limited by the LDS of the lattice and queues and by whole workgroups of
+// waves) times the fraction of lanes busy over a colour's sites (N/2 sites in
+// rounds of t lanes).  Waves are counted up to 4 per SIMD (what the sweep's
+// registers allow) for workgroups of one or two waves and up to 3 for larger
+// ones: measured, 3D L = 8 and 10 sweep 3-13 % faster with 16 resident waves
+// of 128-lane workgroups than with 12 of 64 lanes, while larger workgroups
+// gain nothing from a fourth wave per SIMD (their waves meet at the end of
+// every colour).  The smaller size wins ties.  Autotuning refines it for
+// batches.
 int default_sweep_threads(int N, int d, bool J)
 {
     const int lds_max = g_max_lds ? g_max_lds : kLdsPerCu;
@@ -112,12 +116,11 @@ int default_sweep_threads(int N, int d, bool J)
         if (!sweep_threads_ok(N, d, t) || lds > (size_t)lds_max)
             continue;
         const int w = t / 64;
+        const int cap = 4 * (w <= 2 ? 4 : 3); // waves per CU counted
         int blocks = (int)(kLdsPerCu / lds);
-        if (blocks > 4 * kSweepWavesPerSimd / w)
-            blocks = 4 * kSweepWavesPerSimd / w;
-        int waves = blocks * w;
-        if (waves > 4 * kSweepWavesPerSimd)
-            waves = 4 * kSweepWavesPerSimd;
+        if (blocks > cap / w)
+            blocks = cap / w;
+        const int waves = blocks * w;
         const int rounds = (nh + t - 1) / t;
         const double score = waves * ((double)nh / ((double)rounds * t));
         if (score > best_score + 1e-9) {
