@@ -2293,41 +2293,52 @@ __global__ __launch_bounds__(kThreads) void k_gather_spins(const PaRunDesc *__re
     __syncthreads();
     const int ng = uni(s_ngroups);
     const int nt = (int)blockDim.x;
-    // kG sites per thread at a time: their loads are independent and in flight together
-    constexpr int kG = 8;
-    for (int s0 = threadIdx.x; s0 < N; s0 += kG * nt) {
-        uint64_t out[kG], v[kG];
+    // kP site pairs per thread at a time, one 16-byte load each: their loads
+    // are independent and in flight together; a lane past the end loads the
+    // last pair again and stores nothing (no load under a branch)
+    typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+    typedef const __attribute__((address_space(1))) u64x2 g_u64x2;
+    constexpr int kP = 4;
+    const int np = N >> 1; // N is a multiple of 4 (L even)
+    g_u64x2 *src2 = (g_u64x2 *)src;
+    __attribute__((address_space(1))) u64x2 *dst2 = (__attribute__((address_space(1))) u64x2 *)(dst + (size_t)w * N);
+    for (int p0 = threadIdx.x; p0 < np; p0 += kP * nt) {
+        u64x2 out[kP], v[kP];
 #pragma unroll
-        for (int k = 0; k < kG; ++k)
-            out[k] = v[k] = 0;
+        for (int k = 0; k < kP; ++k) {
+            out[k] = u64x2{0ull, 0ull};
+            v[k] = out[k];
+        }
         uint32_t last = 0xFFFFFFFFu;
         for (int i = 0; i < ng; ++i) {
             const uint32_t sw = uni(g_word[i]);
             if (sw != last) {
 #pragma unroll
-                for (int k = 0; k < kG; ++k) {
-                    const int s = s0 + k * nt;
-                    v[k] = s < N ? src[(size_t)sw * N + s] : 0ull;
-                }
+                for (int k = 0; k < kP; ++k)
+                    v[k] = src2[(size_t)sw * np + min(p0 + k * nt, np - 1)];
                 last = sw;
             }
             const int sh = uni(g_shift[i]);
             const uint64_t mask = uni64(g_mask[i]);
             if (sh >= 0) {
 #pragma unroll
-                for (int k = 0; k < kG; ++k)
-                    out[k] = pa_bop3<PA_T3((PA_A & PA_B) | PA_C)>(v[k] >> sh, mask, out[k]);
+                for (int k = 0; k < kP; ++k) {
+                    out[k].x = pa_bop3<PA_T3((PA_A & PA_B) | PA_C)>(v[k].x >> sh, mask, out[k].x);
+                    out[k].y = pa_bop3<PA_T3((PA_A & PA_B) | PA_C)>(v[k].y >> sh, mask, out[k].y);
+                }
             } else {
 #pragma unroll
-                for (int k = 0; k < kG; ++k)
-                    out[k] = pa_bop3<PA_T3((PA_A & PA_B) | PA_C)>(v[k] << -sh, mask, out[k]);
+                for (int k = 0; k < kP; ++k) {
+                    out[k].x = pa_bop3<PA_T3((PA_A & PA_B) | PA_C)>(v[k].x << -sh, mask, out[k].x);
+                    out[k].y = pa_bop3<PA_T3((PA_A & PA_B) | PA_C)>(v[k].y << -sh, mask, out[k].y);
+                }
             }
         }
 #pragma unroll
-        for (int k = 0; k < kG; ++k) {
-            const int s = s0 + k * nt;
-            if (s < N)
-                dst[(size_t)w * N + s] = out[k];
+        for (int k = 0; k < kP; ++k) {
+            const int p = p0 + k * nt;
+            if (p < np)
+                dst2[p] = out[k];
         }
     }
 }
