@@ -2492,57 +2492,79 @@ __global__ __launch_bounds__(kThreads) void k_obs_rep(const PaRunDesc *__restric
     double ws[PA_WPARTS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     static_assert(PA_HCHUNK % PA_CHUNK == 0 && PA_CHUNK % kThreads == 0, "whole chunks of whole passes");
     const int64_t chunks = (c.rd->cap + PA_CHUNK - 1) / PA_CHUNK;
-    for (int64_t base = c.beg; base < c.end; base += blockDim.x) {
-        const int64_t d = base + threadIdx.x;
-        const bool valid = d < c.end;
-        uint32_t lab = 0xFFFFFFFFu;
-        if (valid) {
-            const int64_t e = dv.E[cur][d], m = dv.M[cur][d];
-            if (build_hist) {
-                const int h = ((int)e + DN) >> 2;
-                if (nlh <= kObsLevels)
-                    atomicAdd(&lh[h - hlo], 1u);
-                else
-                    atomicAdd(&dv.hist[h], 1u);
-            }
-            sE += (uint64_t)e;
-            sE2 += (uint64_t)(e * e);
-            sE3 += (uint64_t)(e * e * e);
-            sA += (uint64_t)(m < 0 ? -m : m);
-            sM2 += (uint64_t)(m * m);
-            lab = dv.label[cur][d];
-            if (wt) {
-                const double w = pa_exp(dv.lw[d]), ef = (double)e, mf = (double)(m < 0 ? -m : m);
-                ws[0] = ws[0] + w;
-                ws[1] = ws[1] + w * ef;
-                ws[2] = ws[2] + w * (ef * ef);
-                ws[3] = ws[3] + w * (ef * ef * ef);
-                ws[4] = ws[4] + w * mf;
-                ws[5] = ws[5] + w * (mf * mf);
-                ws[6] = ws[6] + w * w;
-            }
+    // kPre passes' loads are issued before the first pass's atomics (which
+    // the compiler would not let later loads pass); a slot past the end loads
+    // the last slot again and is not counted
+    constexpr int kPre = 4;
+    for (int64_t base0 = c.beg; base0 < c.end; base0 += kPre * (int64_t)blockDim.x) {
+        int32_t pe[kPre], pm[kPre];
+        uint32_t pl[kPre];
+        double plw[kPre];
+#pragma unroll
+        for (int k = 0; k < kPre; ++k) {
+            const int64_t d = base0 + k * (int64_t)blockDim.x + threadIdx.x;
+            const int64_t dc = d < c.end ? d : c.end - 1;
+            pe[k] = dv.E[cur][dc];
+            pm[k] = dv.M[cur][dc];
+            pl[k] = dv.label[cur][dc];
+            plw[k] = wt ? dv.lw[dc] : 0.0;
         }
-        // family counts: one atomic per run of equal labels in the wave (the
-        // resampling keeps copies adjacent, so runs are long)
-        const uint32_t prev = (uint32_t)__shfl_up((int)lab, 1, 64);
-        const bool start = valid && (lane == 0 || lab != prev);
-        const uint64_t sm = __ballot(start), vm = __ballot(valid);
-        if (start) {
-            const uint64_t above = lane == 63 ? 0ull : ((sm | ~vm) & ~((2ull << lane) - 1ull));
-            const int stop = above ? __ffsll((long long)above) - 1 : 64;
-            atomicAdd(&dv.fam[lab], (uint32_t)(stop - lane));
-        }
-        // a weighted population's sums per chunk of PA_CHUNK slots, in the
-        // fixed order of the block sum
-        if (wt && ((base + (int64_t)blockDim.x) % PA_CHUNK == 0 || base + (int64_t)blockDim.x >= c.end)) {
-            pa_block_sum_f64x(ws, sd);
-            if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < kPre; ++k) {
+            const int64_t base = base0 + k * (int64_t)blockDim.x;
+            if (base >= c.end)
+                break;
+            const int64_t d = base + threadIdx.x;
+            const bool valid = d < c.end;
+            uint32_t lab = 0xFFFFFFFFu;
+            if (valid) {
+                const int64_t e = pe[k], m = pm[k];
+                if (build_hist) {
+                    const int h = ((int)e + DN) >> 2;
+                    if (nlh <= kObsLevels)
+                        atomicAdd(&lh[h - hlo], 1u);
+                    else
+                        atomicAdd(&dv.hist[h], 1u);
+                }
+                sE += (uint64_t)e;
+                sE2 += (uint64_t)(e * e);
+                sE3 += (uint64_t)(e * e * e);
+                sA += (uint64_t)(m < 0 ? -m : m);
+                sM2 += (uint64_t)(m * m);
+                lab = pl[k];
+                if (wt) {
+                    const double w = pa_exp(plw[k]), ef = (double)e, mf = (double)(m < 0 ? -m : m);
+                    ws[0] = ws[0] + w;
+                    ws[1] = ws[1] + w * ef;
+                    ws[2] = ws[2] + w * (ef * ef);
+                    ws[3] = ws[3] + w * (ef * ef * ef);
+                    ws[4] = ws[4] + w * mf;
+                    ws[5] = ws[5] + w * (mf * mf);
+                    ws[6] = ws[6] + w * w;
+                }
+            }
+            // family counts: one atomic per run of equal labels in the wave (the
+            // resampling keeps copies adjacent, so runs are long)
+            const uint32_t prev = (uint32_t)__shfl_up((int)lab, 1, 64);
+            const bool start = valid && (lane == 0 || lab != prev);
+            const uint64_t sm = __ballot(start), vm = __ballot(valid);
+            if (start) {
+                const uint64_t above = lane == 63 ? 0ull : ((sm | ~vm) & ~((2ull << lane) - 1ull));
+                const int stop = above ? __ffsll((long long)above) - 1 : 64;
+                atomicAdd(&dv.fam[lab], (uint32_t)(stop - lane));
+            }
+            // a weighted population's sums per chunk of PA_CHUNK slots, in the
+            // fixed order of the block sum
+            if (wt && ((base + (int64_t)blockDim.x) % PA_CHUNK == 0 || base + (int64_t)blockDim.x >= c.end)) {
+                pa_block_sum_f64x(ws, sd);
+                if (threadIdx.x == 0)
+#pragma unroll
+                    for (int f = 0; f < PA_WPARTS; ++f)
+                        dv.wpart[f * chunks + base / PA_CHUNK] = ws[f];
 #pragma unroll
                 for (int f = 0; f < PA_WPARTS; ++f)
-                    dv.wpart[f * chunks + base / PA_CHUNK] = ws[f];
-#pragma unroll
-            for (int f = 0; f < PA_WPARTS; ++f)
-                ws[f] = 0.0;
+                    ws[f] = 0.0;
+            }
         }
     }
     uint64_t sums[5] = {sE, sE2, sA, sM2, sE3};
@@ -2587,13 +2609,26 @@ __global__ __launch_bounds__(kThreads) void k_obs_fam(const PaRunDesc *__restric
     const int64_t end = beg + PA_HCHUNK < rd.R0 ? beg + PA_HCHUNK : rd.R0;
     uint64_t c2 = 0, nf = 0;
     double cl = 0.0;
-    for (int64_t f = beg + threadIdx.x; f < end; f += blockDim.x) {
-        const uint64_t c = rd.dv.fam[f];
-        c2 += c * c;
-        if (c) {
-            rd.dv.fam[f] = 0;
-            nf += 1;
-            cl = cl + (double)c * log((double)c);
+    // four passes' loads before their stores (a slot past the end loads the
+    // last slot again and is not counted)
+    constexpr int kPre = 4;
+    for (int64_t f0 = beg; f0 < end; f0 += kPre * (int64_t)blockDim.x) {
+        uint32_t pc[kPre];
+#pragma unroll
+        for (int k = 0; k < kPre; ++k) {
+            const int64_t f = f0 + k * (int64_t)blockDim.x + threadIdx.x;
+            pc[k] = rd.dv.fam[f < end ? f : end - 1];
+        }
+#pragma unroll
+        for (int k = 0; k < kPre; ++k) {
+            const int64_t f = f0 + k * (int64_t)blockDim.x + threadIdx.x;
+            const uint64_t c = pc[k];
+            if (f < end && c) {
+                c2 += c * c;
+                rd.dv.fam[f] = 0;
+                nf += 1;
+                cl = cl + (double)c * log((double)c);
+            }
         }
     }
     uint64_t sums[2] = {c2, nf};
