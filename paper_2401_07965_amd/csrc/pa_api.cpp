@@ -200,6 +200,10 @@ struct Batch {
     // resampling's flags and status
     int hist_state = PA_HIST_STALE;
     bool rs_prepped = false;
+    // a resampling was launched since the last sweep: its spins may still be
+    // in the other buffer (the device record says whether), taken in by the
+    // next sweep or gathered before anything else reads them
+    bool gather_pending = false;
     // the latest anneal captured as a HIP graph, replayed while the anneal's
     // arguments (schedule, theta, scheme) and the groups' workgroup sizes stay
     // the same
@@ -209,6 +213,7 @@ struct Batch {
     std::vector<int> anneal_threads;
     int anneal_end_hist = PA_HIST_STALE; // bookkeeping after the captured anneal
     bool anneal_end_rs = false;
+    bool anneal_end_gather = false;
 };
 
 namespace {
@@ -219,7 +224,18 @@ hipError_t launch_init(Batch *b)
     hipError_t e = pa_b_init(b->v); // clears the histograms
     b->hist_state = PA_HIST_ZERO;
     b->rs_prepped = false;
+    b->gather_pending = false;
     return e;
+}
+
+// The spins of a resampling that no sweep has taken in yet, gathered before
+// anything other than a sweep reads them.
+hipError_t settle_spins(Batch *b)
+{
+    if (!b->gather_pending)
+        return hipSuccess;
+    b->gather_pending = false;
+    return pa_b_gather(b->v);
 }
 
 hipError_t launch_reweight(Batch *b, double beta_next)
@@ -232,7 +248,10 @@ hipError_t launch_reweight(Batch *b, double beta_next)
 
 hipError_t launch_resample(Batch *b, int scheme, int freeze, int kq)
 {
-    hipError_t e = pa_b_resample(b->v, scheme, freeze, kq, b->rs_prepped);
+    hipError_t e = settle_spins(b); // the ancestors below are of the populations as they are now
+    if (e == hipSuccess)
+        e = pa_b_resample(b->v, scheme, freeze, kq, b->rs_prepped);
+    b->gather_pending = true;
     b->rs_prepped = false;
     if (b->hist_state == PA_HIST_VALID) // a histogram of the replaced population
         b->hist_state = PA_HIST_STALE;
@@ -251,7 +270,15 @@ hipError_t launch_observables(Batch *b, int point)
 // Sweeps (cluster updates: cluster != 0) of every run change the energies.
 hipError_t launch_updates(Batch *b, int n, uint32_t t0, int cluster)
 {
-    hipError_t e = cluster ? pa_b_cluster(b->v, n, t0) : pa_b_sweep(b->v, n, t0);
+    hipError_t e = hipSuccess;
+    if (cluster) {
+        e = settle_spins(b);
+        if (e == hipSuccess)
+            e = pa_b_cluster(b->v, n, t0);
+    } else {
+        e = pa_b_sweep(b->v, n, t0, b->gather_pending ? 1 : 0);
+        b->gather_pending = false;
+    }
     if (b->hist_state == PA_HIST_VALID)
         b->hist_state = PA_HIST_STALE;
     return e;
@@ -269,6 +296,7 @@ void population_replaced(Batch *b)
 {
     b->hist_state = PA_HIST_STALE;
     b->rs_prepped = false;
+    b->gather_pending = false;
 }
 
 } // namespace
@@ -609,6 +637,9 @@ pa_status need_uniform(Batch *b, const char *where)
 
 pa_status export_run(Batch *b, int m, pa_host_state *st)
 {
+    const hipError_t eg = settle_spins(b);
+    if (eg != hipSuccess)
+        return hip_fail(b, eg, "export");
     pa_status s = fetch_records(b, "export");
     if (s != PA_OK)
         return s;
@@ -995,7 +1026,11 @@ pa_status pa_overlap(pa_ctx *a, pa_ctx *c2, int64_t *hist_out)
     if (A->hdesc[0].d != B->hdesc[0].d || A->hdesc[0].L != B->hdesc[0].L)
         return fail(A, PA_E_INVAL, "runs on different lattices");
     const int N = A->hdesc[0].N;
-    hipError_t e = hipStreamSynchronize(B->v.stream);
+    hipError_t e = settle_spins(B);
+    if (e == hipSuccess)
+        e = settle_spins(A);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(B->v.stream);
     if (e == hipSuccess)
         e = pa_launch_overlap(A->ddesc, B->ddesc, N, A->v.ncol, A->hdesc[0].dv.qhist, A->v.stream);
     std::vector<unsigned long long> h((size_t)N + 1);
@@ -1029,6 +1064,10 @@ pa_status pa_overlap_noalloc(pa_ctx *a, pa_ctx *c2, int64_t *hist_out)
     unsigned long long *hist = nullptr;
     if (e == hipSuccess)
         e = pa_noalloc_scratch(dev, &hist);
+    if (e == hipSuccess)
+        e = settle_spins(B);
+    if (e == hipSuccess)
+        e = settle_spins(A);
     if (e == hipSuccess)
         e = hipStreamSynchronize(B->v.stream);
     if (e == hipSuccess) // the fill kernel clears the N + 1 counters this call uses
@@ -1159,7 +1198,9 @@ pa_status pa_batch_tune(pa_batch *p, int32_t theta, double beta, int32_t *thread
     // is deterministic), so tuning leaves no trace.  Every candidate gives the
     // same bits by construction.
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipEventCreate(&e0);
+    hipError_t e = settle_spins(b);
+    if (e == hipSuccess)
+        e = hipEventCreate(&e0);
     if (e == hipSuccess)
         e = hipEventCreate(&e1);
     if (e == hipSuccess)
@@ -1220,6 +1261,11 @@ pa_status pa_batch_set_threads(pa_batch *p, int32_t group, int32_t threads)
         pa_sweep_lds_bytes(b->v.gN[group], b->v.gd[group], threads, b->v.gJ[group] != 0) > (size_t)g_max_lds)
         return fail(b, PA_E_INVAL, "workgroup size not usable for this group (64..768 lanes in steps of 64, "
                                    "within the LDS and the per-lane site bound)");
+    // the size decides which kernel gathers a resampling's spins: none may be
+    // left for the next sweep across the change
+    const hipError_t e = settle_spins(b);
+    if (e != hipSuccess)
+        return hip_fail(b, e, "pa_batch_set_threads");
     b->v.gthreads[group] = threads;
     return PA_OK;
 }
@@ -1268,6 +1314,7 @@ pa_status pa_batch_anneal(pa_batch *p, const double *betas, int32_t npoints, int
             return hip_fail(b, e, "pa_batch_anneal (replay)");
         b->hist_state = b->anneal_end_hist; // as the captured anneal left the bookkeeping
         b->rs_prepped = b->anneal_end_rs;
+        b->gather_pending = b->anneal_end_gather;
         b->anneal_points = npoints;
         return PA_OK;
     }
@@ -1311,6 +1358,7 @@ pa_status pa_batch_anneal(pa_batch *p, const double *betas, int32_t npoints, int
     if (exec) { // kept for replays of the same anneal
         b->anneal_end_hist = b->hist_state;
         b->anneal_end_rs = b->rs_prepped;
+        b->anneal_end_gather = b->gather_pending;
         b->anneal_exec = exec;
         b->anneal_betas = sched;
         b->anneal_theta = theta;
@@ -1360,8 +1408,10 @@ pa_status pa_batch_overlap(pa_batch *p, int32_t run_a, int32_t run_b, int64_t *h
     if (da.d != db.d || da.L != db.L)
         return fail(b, PA_E_INVAL, "runs on different lattices");
     const int N = da.N;
-    hipError_t e = pa_launch_overlap(b->ddesc + run_a, b->ddesc + run_b, N, (uint32_t)b->geo[run_a].W,
-                                     da.dv.qhist, b->v.stream);
+    hipError_t e = settle_spins(b);
+    if (e == hipSuccess)
+        e = pa_launch_overlap(b->ddesc + run_a, b->ddesc + run_b, N, (uint32_t)b->geo[run_a].W, da.dv.qhist,
+                              b->v.stream);
     std::vector<unsigned long long> h((size_t)N + 1);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h.data(), da.dv.qhist, h.size() * 8, hipMemcpyDeviceToHost, b->v.stream);

@@ -25,7 +25,7 @@ struct PaRecord {
     uint32_t skip;    // latest resampling was not applied
     uint32_t step;    // temperature index i
     uint32_t sweeps;  // sweeps done at step i
-    uint32_t pad0;
+    uint32_t gather;  // 1: the latest resampling's spins are still to be gathered from the other buffer
     uint64_t Rcur;    // replicas in the population
     double beta;      // current inverse temperature
     // histogram of the current population (reweight, adaptive step)
@@ -197,7 +197,10 @@ struct PaBatchView {
 
 // launchers (pa_kernels.hip); each returns the first launch error
 hipError_t pa_b_init(const PaBatchView &v);
-hipError_t pa_b_sweep(const PaBatchView &v, int theta, uint32_t t0); // t0: sweeps already done at this beta
+// t0: sweeps already done at this beta; gather: the populations' spins may
+// still be in the other buffer (PaRecord::gather), taken in by the sweep
+hipError_t pa_b_sweep(const PaBatchView &v, int theta, uint32_t t0, int gather);
+hipError_t pa_b_gather(const PaBatchView &v); // gathers the spins a resampling left for the sweeps to gather
 hipError_t pa_b_sweep_group(const PaBatchView &v, int g, int theta, int threads);
 // hist_clean: the level histogram is zero (observables or init ran since it was last built)
 // State of each run's level histogram, tracked by the host: all zero (with

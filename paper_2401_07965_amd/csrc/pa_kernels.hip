@@ -71,6 +71,7 @@ __global__ void k_init_rec(const PaRunDesc *__restrict__ runs)
     rec->skip = 0;
     rec->step = 0;
     rec->sweeps = 0;
+    rec->gather = 0;
     rec->Rcur = (uint64_t)rd.R0;
     rec->beta = 0.0;
     rec->lnQ = 0.0;
@@ -786,6 +787,107 @@ __device__ __forceinline__ void load_column(uint64_t *lat, uint8_t *jl, const ui
                                (const __attribute__((address_space(1))) uint32_t *)jm, N >> 2);
 }
 
+// Destination word column w takes the bits of its 64 ancestors.  Bit b comes
+// from bit (a_b & 63) of source word a_b >> 6, i.e. from that word shifted by
+// delta_b = (a_b & 63) - b.  Bits sharing (source word, delta) form one group:
+// one shift, mask and or per group per site.  Ancestors are non-decreasing, so
+// delta moves by one per dropped or repeated replica and a column has few
+// groups (fewer than its runs of consecutive ancestors), listed in order of
+// source word.  The group lists live in LDS.
+struct GatherGroups {
+    uint64_t *mask; // [64]
+    uint32_t *word; // [64]
+    int *shift;     // [64]
+    int *n;         // [1]
+};
+
+// Wave 0 lists the groups of destination word w (replicas 64 w + b below R,
+// ancestors anc); the caller synchronises the workgroup before they are read.
+__device__ __forceinline__ void gather_groups(const uint32_t *anc, uint32_t w, int64_t R, const GatherGroups &G)
+{
+    if (threadIdx.x >= 64)
+        return;
+    const int b = threadIdx.x;
+    const int64_t d = 64 * (int64_t)w + b;
+    const bool valid = d < R;
+    const uint32_t a = valid ? anc[d] : 0u;
+    const uint32_t q = a >> 6;
+    const int dl = (int)(a & 63u) - b;
+    uint64_t rem = __ballot(valid);
+    int ng = 0;
+    while (rem) { // wave-uniform: one group per pass, led by the lowest remaining lane
+        const int l = __ffsll((long long)rem) - 1;
+        const uint32_t ql = (uint32_t)__shfl((int)q, l, 64);
+        const int dll = __shfl(dl, l, 64);
+        const uint64_t m = __ballot(valid && q == ql && dl == dll);
+        if (b == 0) {
+            G.word[ng] = ql;
+            G.shift[ng] = dll;
+            G.mask[ng] = m;
+        }
+        rem &= ~m;
+        ++ng;
+    }
+    if (b == 0)
+        *G.n = ng;
+}
+
+typedef uint64_t pa_u64x2 __attribute__((ext_vector_type(2)));
+
+// Every thread: the destination word's sites from the source words (column
+// sw at src + sw N), kP site pairs at a time with one 16-byte load each, in
+// flight together (a lane past the end loads the last pair again and stores
+// nothing: no load under a branch); store(p, v) keeps site pair p.
+template <typename Store>
+__device__ __forceinline__ void gather_sites(const uint64_t *src, int N, const GatherGroups &G, Store store)
+{
+    typedef const __attribute__((address_space(1))) pa_u64x2 g_u64x2;
+    constexpr int kP = 4;
+    const int ng = uni(*G.n);
+    const int nt = (int)blockDim.x;
+    const int np = N >> 1; // N is a multiple of 4 (L even)
+    g_u64x2 *src2 = (g_u64x2 *)src;
+    for (int p0 = threadIdx.x; p0 < np; p0 += kP * nt) {
+        pa_u64x2 out[kP], v[kP];
+#pragma unroll
+        for (int k = 0; k < kP; ++k) {
+            out[k] = pa_u64x2{0ull, 0ull};
+            v[k] = out[k];
+        }
+        uint32_t last = 0xFFFFFFFFu;
+        for (int i = 0; i < ng; ++i) {
+            const uint32_t sw = uni(G.word[i]);
+            if (sw != last) {
+#pragma unroll
+                for (int k = 0; k < kP; ++k)
+                    v[k] = src2[(size_t)sw * np + min(p0 + k * nt, np - 1)];
+                last = sw;
+            }
+            const int sh = uni(G.shift[i]);
+            const uint64_t mask = uni64(G.mask[i]);
+            if (sh >= 0) {
+#pragma unroll
+                for (int k = 0; k < kP; ++k) {
+                    out[k].x = pa_bop3<PA_T3((PA_A & PA_B) | PA_C)>(v[k].x >> sh, mask, out[k].x);
+                    out[k].y = pa_bop3<PA_T3((PA_A & PA_B) | PA_C)>(v[k].y >> sh, mask, out[k].y);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < kP; ++k) {
+                    out[k].x = pa_bop3<PA_T3((PA_A & PA_B) | PA_C)>(v[k].x << -sh, mask, out[k].x);
+                    out[k].y = pa_bop3<PA_T3((PA_A & PA_B) | PA_C)>(v[k].y << -sh, mask, out[k].y);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kP; ++k) {
+            const int p = p0 + k * nt;
+            if (p < np)
+                store(p, out[k]);
+        }
+    }
+}
+
 // One workgroup = one word column w (64 replicas) of one run; the lattice
 // stays in LDS for all theta sweeps, then each replica's unsatisfied-bond
 // count U and number of down spins are counted bit-sliced: E = 2U - dN,
@@ -793,7 +895,8 @@ __device__ __forceinline__ void load_column(uint64_t *lat, uint8_t *jl, const ui
 // (per-site bond masks in LDS); without, every bond is ferromagnetic.
 template <int D, bool J>
 __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__restrict__ runs,
-                                                            const PaBlk *__restrict__ map, int theta, uint32_t t0)
+                                                            const PaBlk *__restrict__ map, int theta, uint32_t t0,
+                                                            int gather)
 {
     // dynamic LDS: lattice [N] u64 | queues [waves][3][kQueue] u64 | queue sites [waves][kQueue] u32 |
     // threshold-bit table [16][4 or 8] u32 | jmask [N]
@@ -824,7 +927,23 @@ __global__ __launch_bounds__(kSweepMaxThreads) void k_sweep(const PaRunDesc *__r
             ttab[ttab_stride<D>() * tid + 2 * c + 1] = (uint32_t)__builtin_amdgcn_sbfe((int)t[c], b0 - 1u, 1u);
         }
     }
-    load_column<J>(lat, jl, g, rd.dv.jmask, N);
+    if (gather && uni(rec->gather) != 0u) {
+        // the column of a resampled population, gathered from the other
+        // buffer into LDS (the group lists in wave 0's queue space, unused
+        // until the sweeps)
+        uint64_t *gq = lat + N;
+        uint32_t *gw = reinterpret_cast<uint32_t *>(gq + 64);
+        const GatherGroups G = {gq, gw, reinterpret_cast<int *>(gw + 64), reinterpret_cast<int *>(gw + 128)};
+        gather_groups(rd.dv.anc, w, Rlive, G);
+        __syncthreads();
+        pa_u64x2 *dst = reinterpret_cast<pa_u64x2 *>(lat);
+        gather_sites(rd.dv.spins[cur ^ 1], N, G, [&](int p, pa_u64x2 v) { dst[p] = v; });
+        if (J)
+            stage_to_lds<uint32_t>(reinterpret_cast<uint32_t *>(jl),
+                                   (const __attribute__((address_space(1))) uint32_t *)rd.dv.jmask, N >> 2);
+    } else {
+        load_column<J>(lat, jl, g, rd.dv.jmask, N);
+    }
     __syncthreads();
 
     const uint64_t two32 = 1ull << 32;
@@ -2233,13 +2352,35 @@ __device__ __forceinline__ uint32_t resample_status(const PaRecord *rec, int64_t
 
 // ------------------------------------------------------------------ apply
 
-// Destination word column w takes the bits of its 64 ancestors.  Bit b comes
-// from bit (a_b & 63) of source word a_b >> 6, i.e. from that word shifted by
-// delta_b = (a_b & 63) - b.  Bits sharing (source word, delta) form one group:
-// one shift, mask and or per group per site.  Ancestors are non-decreasing, so
-// delta moves by one per dropped or repeated replica and a column has few
-// groups (fewer than its runs of consecutive ancestors), listed in order of
-// source word.
+// A resampled population's energies, magnetisations and labels, from their
+// ancestors into the other buffer (before the commit swaps the buffers).  Its
+// spins follow later (PaRecord::gather): in the next sweep's column load, or
+// in k_gather_spins when something else reads them first.
+__global__ __launch_bounds__(kThreads) void k_gather_meta(const PaRunDesc *__restrict__ runs,
+                                                          const PaBlk *__restrict__ map)
+{
+    const PaBlk blk = map[blockIdx.x];
+    const PaRunDesc &rd = runs[blk.run];
+    PaRecord *rec = rd.dv.rec;
+    if (frozen(rec) || rec->keep || resample_status(rec, rd.cap) != 0u)
+        return;
+    const int64_t Rnew = (int64_t)rec->Rnew;
+    const int64_t beg = (int64_t)blk.idx * PA_CHUNK, end = beg + PA_CHUNK < Rnew ? beg + PA_CHUNK : Rnew;
+    const int cur = rec->cur;
+    for (int64_t d = beg + threadIdx.x; d < end; d += blockDim.x) {
+        const uint32_t a = rd.dv.anc[d];
+        rd.dv.E[cur ^ 1][d] = rd.dv.E[cur][a];
+        rd.dv.M[cur ^ 1][d] = rd.dv.M[cur][a];
+        rd.dv.label[cur ^ 1][d] = rd.dv.label[cur][a];
+    }
+}
+
+// Word column w of a resampled population from its ancestors.  PRE: before
+// the commit swaps the buffers, from the current buffer into the other one,
+// with the energies, magnetisations and labels (every run's spins move now).
+// Otherwise: after the commit, the spins a resampling left for the sweeps
+// (PaRecord::gather), from the other buffer into the current one.
+template <bool PRE>
 __global__ __launch_bounds__(kThreads) void k_gather_spins(const PaRunDesc *__restrict__ runs,
                                                            const PaBlk *__restrict__ map)
 {
@@ -2252,95 +2393,30 @@ __global__ __launch_bounds__(kThreads) void k_gather_spins(const PaRunDesc *__re
     const PaBlk blk = map[xcd_contiguous(blockIdx.x, gridDim.x)];
     const PaRunDesc &rd = runs[blk.run];
     PaRecord *rec = rd.dv.rec;
-    const int64_t Rnew = (int64_t)rec->Rnew;
+    const int64_t R = PRE ? (int64_t)rec->Rnew : (int64_t)rec->Rcur;
     const uint32_t w = blk.idx;
-    if (frozen(rec) || rec->keep || resample_status(rec, rd.cap) != 0u || (int64_t)w * 64 >= Rnew)
+    if (frozen(rec) || (int64_t)w * 64 >= R)
+        return;
+    if (PRE ? (rec->keep || resample_status(rec, rd.cap) != 0u) : rec->gather == 0u)
         return;
     const int N = rd.N;
     const int cur = rec->cur;
-    const uint64_t *src = rd.dv.spins[cur];
-    uint64_t *dst = rd.dv.spins[cur ^ 1];
-    if (threadIdx.x < 64) {
-        const int b = threadIdx.x;
-        const int64_t d = 64 * (int64_t)w + b;
-        const bool valid = d < Rnew;
-        const uint32_t a = valid ? rd.dv.anc[d] : 0u;
-        if (valid) { // the replica's energy, magnetisation and label
+    const int from = PRE ? cur : cur ^ 1;
+    if (PRE && threadIdx.x < 64) { // the replicas' energies, magnetisations and labels
+        const int64_t d = 64 * (int64_t)w + threadIdx.x;
+        if (d < R) {
+            const uint32_t a = rd.dv.anc[d];
             rd.dv.E[cur ^ 1][d] = rd.dv.E[cur][a];
             rd.dv.M[cur ^ 1][d] = rd.dv.M[cur][a];
             rd.dv.label[cur ^ 1][d] = rd.dv.label[cur][a];
         }
-        const uint32_t q = a >> 6;
-        const int dl = (int)(a & 63u) - b;
-        uint64_t rem = __ballot(valid);
-        int ng = 0;
-        while (rem) { // wave-uniform: one group per pass, led by the lowest remaining lane
-            const int l = __ffsll((long long)rem) - 1;
-            const uint32_t ql = (uint32_t)__shfl((int)q, l, 64);
-            const int dll = __shfl(dl, l, 64);
-            const uint64_t m = __ballot(valid && q == ql && dl == dll);
-            if (b == 0) {
-                g_word[ng] = ql;
-                g_shift[ng] = dll;
-                g_mask[ng] = m;
-            }
-            rem &= ~m;
-            ++ng;
-        }
-        if (b == 0)
-            s_ngroups = ng;
     }
+    const GatherGroups G = {g_mask, g_word, g_shift, &s_ngroups};
+    gather_groups(rd.dv.anc, w, R, G);
     __syncthreads();
-    const int ng = uni(s_ngroups);
-    const int nt = (int)blockDim.x;
-    // kP site pairs per thread at a time, one 16-byte load each: their loads
-    // are independent and in flight together; a lane past the end loads the
-    // last pair again and stores nothing (no load under a branch)
-    typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
-    typedef const __attribute__((address_space(1))) u64x2 g_u64x2;
-    constexpr int kP = 4;
-    const int np = N >> 1; // N is a multiple of 4 (L even)
-    g_u64x2 *src2 = (g_u64x2 *)src;
-    __attribute__((address_space(1))) u64x2 *dst2 = (__attribute__((address_space(1))) u64x2 *)(dst + (size_t)w * N);
-    for (int p0 = threadIdx.x; p0 < np; p0 += kP * nt) {
-        u64x2 out[kP], v[kP];
-#pragma unroll
-        for (int k = 0; k < kP; ++k) {
-            out[k] = u64x2{0ull, 0ull};
-            v[k] = out[k];
-        }
-        uint32_t last = 0xFFFFFFFFu;
-        for (int i = 0; i < ng; ++i) {
-            const uint32_t sw = uni(g_word[i]);
-            if (sw != last) {
-#pragma unroll
-                for (int k = 0; k < kP; ++k)
-                    v[k] = src2[(size_t)sw * np + min(p0 + k * nt, np - 1)];
-                last = sw;
-            }
-            const int sh = uni(g_shift[i]);
-            const uint64_t mask = uni64(g_mask[i]);
-            if (sh >= 0) {
-#pragma unroll
-                for (int k = 0; k < kP; ++k) {
-                    out[k].x = pa_bop3<PA_T3((PA_A & PA_B) | PA_C)>(v[k].x >> sh, mask, out[k].x);
-                    out[k].y = pa_bop3<PA_T3((PA_A & PA_B) | PA_C)>(v[k].y >> sh, mask, out[k].y);
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < kP; ++k) {
-                    out[k].x = pa_bop3<PA_T3((PA_A & PA_B) | PA_C)>(v[k].x << -sh, mask, out[k].x);
-                    out[k].y = pa_bop3<PA_T3((PA_A & PA_B) | PA_C)>(v[k].y << -sh, mask, out[k].y);
-                }
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < kP; ++k) {
-            const int p = p0 + k * nt;
-            if (p < np)
-                dst2[p] = out[k];
-        }
-    }
+    __attribute__((address_space(1))) pa_u64x2 *dst =
+        (__attribute__((address_space(1))) pa_u64x2 *)(rd.dv.spins[from ^ 1] + (size_t)w * N);
+    gather_sites(rd.dv.spins[from], N, G, [&](int p, pa_u64x2 v) { dst[p] = v; });
 }
 
 // A kept population takes its new log-weights x_j + m (m = 0 if it was uniform).
@@ -2362,7 +2438,9 @@ __global__ __launch_bounds__(kThreads) void k_keep(const PaRunDesc *__restrict__
 // order, ln Z_hat += ln Q (Eq. (7)), the new beta and its thresholds, the
 // buffer swap and the step count.  A kept population advances the same way
 // with its members in place, its new log-weights and SV = 0 (nothing drawn).
-__global__ __launch_bounds__(kThreads) void k_commit(const PaRunDesc *__restrict__ runs, int freeze)
+// spins_moved: the spins were gathered before the commit (k_gather_spins<true>).
+__global__ __launch_bounds__(kThreads) void k_commit(const PaRunDesc *__restrict__ runs, int freeze,
+                                                     int spins_moved)
 {
     __shared__ double sd[16];
     const PaRunDesc &rd = runs[blockIdx.x];
@@ -2375,11 +2453,13 @@ __global__ __launch_bounds__(kThreads) void k_commit(const PaRunDesc *__restrict
         if (threadIdx.x == 0) {
             rec->skip = 1;
             rec->status = freeze ? (st | PA_ST_FROZEN) : st;
+            rec->gather = 0;
         }
         return;
     }
     if (rec->keep) {
         if (threadIdx.x == 0) {
+            rec->gather = 0;
             rec->sv = 0.0;
             rec->lnZ = rec->lnZ + rec->lnQ;
             rec->lnq_hist[0] = rec->lnq_hist[1];
@@ -2414,6 +2494,7 @@ __global__ __launch_bounds__(kThreads) void k_commit(const PaRunDesc *__restrict
         rec->Rprev = (uint64_t)Rprev;
         rec->Rcur = rec->Rnew;
         rec->cur ^= 1;
+        rec->gather = spins_moved ? 0 : 1; // else the spins wait in the other buffer
         rec->beta = rec->beta_next;
         rec->step += 1;
         rec->sweeps = 0;
@@ -2877,6 +2958,7 @@ __global__ void k_set_beta(const PaRunDesc *__restrict__ runs, double beta, doub
         rec->skip = 0;
         rec->weighted = 0;
         rec->keep = 0;
+        rec->gather = 0;
     }
 }
 
@@ -2911,19 +2993,40 @@ __global__ __launch_bounds__(kThreads) void k_philox_probe(uint32_t *__restrict_
     out[t] = acc;
 }
 
-hipError_t sweep_launch(const PaBatchView &v, int g, int theta, int threads, uint32_t t0, hipStream_t st)
+// Whether group g's sweeps take in the spins a resampling left in the other
+// buffer (their column load gathers them) or k_gather_spins does it right
+// after the resampling: the gather in the load keeps the workgroup off the
+// VALU for longer, which the other resident workgroups hide only when each
+// SIMD holds four sweep waves (measured: 3D L = 10 and the uneven batch gain
+// 2-6 %, the 3D L = 16 headline with three waves per SIMD loses 1.3 %).  A
+// function of the group's workgroup size, which the host keeps fixed between
+// a resampling and the sweep after it.
+bool sweep_gathers(const PaBatchView &v, int g)
+{
+    constexpr int kLdsPerCu = 163840, kWavesPerCu = 16; // gfx950 LDS; four waves per SIMD (<= 128 VGPRs)
+    const int threads = v.gthreads[g], w = threads / 64;
+    int blocks = (int)(kLdsPerCu / pa_sweep_lds_bytes(v.gN[g], v.gd[g], threads, v.gJ[g] != 0));
+    if (blocks > kWavesPerCu / w)
+        blocks = kWavesPerCu / w;
+    return blocks * w >= kWavesPerCu;
+}
+
+hipError_t sweep_launch(const PaBatchView &v, int g, int theta, int threads, uint32_t t0, hipStream_t st,
+                        int gather)
 {
     if (v.gncol[g] == 0)
         return hipSuccess;
     const size_t lds = pa_sweep_lds_bytes(v.gN[g], v.gd[g], threads, v.gJ[g] != 0);
+    if (gather && !sweep_gathers(v, g)) // gathered after the resampling
+        gather = 0;
     if (v.gd[g] == 2 && v.gJ[g])
-        k_sweep<2, true><<<v.gncol[g], threads, lds, st>>>(v.runs, v.gcol[g], theta, t0);
+        k_sweep<2, true><<<v.gncol[g], threads, lds, st>>>(v.runs, v.gcol[g], theta, t0, gather);
     else if (v.gd[g] == 2)
-        k_sweep<2, false><<<v.gncol[g], threads, lds, st>>>(v.runs, v.gcol[g], theta, t0);
+        k_sweep<2, false><<<v.gncol[g], threads, lds, st>>>(v.runs, v.gcol[g], theta, t0, gather);
     else if (v.gJ[g])
-        k_sweep<3, true><<<v.gncol[g], threads, lds, st>>>(v.runs, v.gcol[g], theta, t0);
+        k_sweep<3, true><<<v.gncol[g], threads, lds, st>>>(v.runs, v.gcol[g], theta, t0, gather);
     else
-        k_sweep<3, false><<<v.gncol[g], threads, lds, st>>>(v.runs, v.gcol[g], theta, t0);
+        k_sweep<3, false><<<v.gncol[g], threads, lds, st>>>(v.runs, v.gcol[g], theta, t0, gather);
     return hipGetLastError();
 }
 
@@ -2983,21 +3086,29 @@ hipError_t pa_b_init(const PaBatchView &v)
     k_init_labels<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
     hipError_t e = hipGetLastError();
     for (int g = 0; g < v.ngroups && e == hipSuccess; ++g)
-        e = sweep_launch(v, g, 0, v.gthreads[g], 0u, v.stream);
+        e = sweep_launch(v, g, 0, v.gthreads[g], 0u, v.stream, 0);
     return e;
 }
 
 hipError_t pa_b_sweep_group(const PaBatchView &v, int g, int theta, int threads)
 {
-    return sweep_launch(v, g, theta, threads, 0u, v.stream);
+    return sweep_launch(v, g, theta, threads, 0u, v.stream, 0);
 }
 
-hipError_t pa_b_sweep(const PaBatchView &v, int theta, uint32_t t0)
+hipError_t pa_b_gather(const PaBatchView &v)
+{
+    for (int g = 0; g < v.ngroups; ++g)
+        if (v.gncol[g] && sweep_gathers(v, g))
+            k_gather_spins<false><<<v.gncol[g], kThreads, 0, v.stream>>>(v.runs, v.gcol[g]);
+    return hipGetLastError();
+}
+
+hipError_t pa_b_sweep(const PaBatchView &v, int theta, uint32_t t0, int gather)
 {
     hipError_t e = hipSuccess;
     if (v.ngroups < 2 || !v.fork) {
         for (int g = 0; g < v.ngroups && e == hipSuccess; ++g)
-            e = sweep_launch(v, g, theta, v.gthreads[g], t0, v.stream);
+            e = sweep_launch(v, g, theta, v.gthreads[g], t0, v.stream, gather);
         return e;
     }
     // the groups are independent: each on its own stream, so that one group's
@@ -3006,7 +3117,7 @@ hipError_t pa_b_sweep(const PaBatchView &v, int theta, uint32_t t0)
     for (int g = 0; g < v.ngroups && e == hipSuccess; ++g) {
         e = hipStreamWaitEvent(v.gstream[g], v.fork, 0);
         if (e == hipSuccess)
-            e = sweep_launch(v, g, theta, v.gthreads[g], t0, v.gstream[g]);
+            e = sweep_launch(v, g, theta, v.gthreads[g], t0, v.gstream[g], gather);
         if (e == hipSuccess)
             e = hipEventRecord(v.join[g], v.gstream[g]);
     }
@@ -3075,7 +3186,9 @@ hipError_t pa_b_check_candidate(const PaBatchView &v, double alpha_star, double 
 // systematic sums the weights and writes the ancestor map from each
 // replica's closed-form copy range in the same pass; multinomial sums the
 // weights, draws, adds the sampling variance and sums the copy numbers.
-// Then the gather and the commit.
+// Then the energies, magnetisations and labels move to the ancestors' order
+// and the commit swaps the buffers; the spins follow at once for groups whose
+// sweeps do not gather them, else in the next sweep or pa_b_gather.
 hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze, int kq, bool prepped)
 {
     hipError_t e;
@@ -3106,10 +3219,22 @@ hipError_t pa_b_resample(const PaBatchView &v, int scheme, int freeze, int kq, b
     }
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
-    k_gather_spins<<<v.ncol, kThreads, 0, v.stream>>>(v.runs, v.col);
+    // with no group whose sweeps gather, every spin moves now in the same pass
+    // as the energies, magnetisations and labels; otherwise those move now and
+    // the spins of the other groups right after the commit
+    bool any = false;
+    for (int g = 0; g < v.ngroups; ++g)
+        any = any || (v.gncol[g] && sweep_gathers(v, g));
+    if (any)
+        k_gather_meta<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
+    else
+        k_gather_spins<true><<<v.ncol, kThreads, 0, v.stream>>>(v.runs, v.col);
     if (kq >= 0)
         k_keep<<<v.nrep, kThreads, 0, v.stream>>>(v.runs, v.rep);
-    k_commit<<<v.nruns, kThreads, 0, v.stream>>>(v.runs, freeze);
+    k_commit<<<v.nruns, kThreads, 0, v.stream>>>(v.runs, freeze, any ? 0 : 1);
+    for (int g = 0; any && g < v.ngroups; ++g)
+        if (v.gncol[g] && !sweep_gathers(v, g))
+            k_gather_spins<false><<<v.gncol[g], kThreads, 0, v.stream>>>(v.runs, v.gcol[g]);
     return hipGetLastError();
 }
 

@@ -210,6 +210,29 @@ def test_small_lattices_at_several_walk_sizes_match_the_oracle():
         B.close()
 
 
+def test_anneal_without_sweeps_then_export_matches_the_oracle():
+    """theta = 0: every step's resampling leaves its spins to be gathered, by
+    the next resampling or by the export, eagerly and from a replayed graph."""
+    from paper_2401_07965_amd import pa
+    betas = [0.0, 0.2, 0.5, 0.9, 1.4]
+    J = ea_couplings(3, 6, 8)
+    cfgs = [dict(dim=3, L=6, R=300, seed=3, run_id=0, couplings=J), dict(dim=2, L=8, R=200, seed=3, run_id=1)]
+    refs = []
+    for c in cfgs:
+        o = O.OracleRun(c["dim"], c["L"], c["R"], seed=3, run_id=c["run_id"], J=c.get("couplings"))
+        for b in betas[1:]:
+            o.reweight(b)
+            o.resample(O.SYSTEMATIC)
+        refs.append(o)
+    B = pa.PABatch(cfgs, max_points=len(betas))
+    for graph in (False, True, True):
+        print(f"[batch] theta = 0, graph={graph}", flush=True)
+        B.anneal(betas, 0, O.SYSTEMATIC, use_graph=graph)
+        for m, o in enumerate(refs):
+            compare_state(_Exported(B, m), o, f"run {m}, theta = 0, graph={graph}")
+    B.close()
+
+
 def test_weighted_combination_matches_oracle():
     from paper_2401_07965_amd import pa
     betas = schedule(1.0, 8)

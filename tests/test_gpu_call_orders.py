@@ -156,3 +156,56 @@ def test_histogram_built_by_split_sweeps_cluster_updates_and_no_sweeps(scheme):
             o.sweep(3)
         compare_state(g, o, f"step {i} ({kind})")
     g.close()
+
+
+@pytest.mark.parametrize("scheme", [O.SYSTEMATIC, O.MULTINOMIAL])
+def test_resampled_spins_reach_every_reader(scheme):
+    """A resampling moves energies, magnetisations and labels at once; its
+    spins are taken in by the next sweep's column load, or gathered first
+    when something else reads them: an export, a second resampling, cluster
+    updates, the overlap, a kept conditional resampling, sweeps split into
+    several calls.  Every order gives the oracle's populations."""
+    print(f"[call orders] readers of a resampled population, scheme={scheme}", flush=True)
+    g, o = pair(R=700, L=8, seed=9, run_id=scheme)
+    h, p = pair(R=640, L=8, seed=9, run_id=10 + scheme)
+    beta = 0.0
+
+    def resample_both(b):
+        assert rel_ok(g.reweight(b), o.reweight(b))
+        assert g.resample(scheme) == o.resample(scheme)
+
+    for i in range(1, 9):
+        beta += 0.12
+        resample_both(beta)
+        if i == 1:  # exported before any sweep, then swept
+            compare_state(g, o, f"step {i}, after the resampling")
+        elif i == 2:  # a second resampling before the sweep
+            beta += 0.05
+            resample_both(beta)
+        elif i == 3:  # cluster updates first
+            g.cluster(1)
+            o.cluster(1)
+        elif i == 4:  # the overlap with another population first
+            assert rel_ok(h.reweight(beta), p.reweight(beta))
+            assert h.resample(scheme) == p.resample(scheme)
+            hist = g.overlap(h)
+            R = min(o.Rcur, p.Rcur)
+            same = (o.spins[:R] == p.spins[:R]).sum(axis=1)
+            assert np.array_equal(hist, np.bincount(same, minlength=o.N + 1))
+            h.sweep(1)
+            p.sweep(1)
+        elif i == 5:  # no sweep: observables, then the next step's reweighting
+            g.observables()
+            continue
+        elif i == 6:  # a conditional resampling that keeps the population
+            beta += 0.01
+            assert rel_ok(g.reweight(beta), o.reweight(beta))
+            assert g.resample_conditional(scheme, 0.0) == o.resample_conditional(scheme, 0.0)
+        g.sweep(0)
+        g.sweep(1)
+        g.sweep(2)
+        o.sweep(3)
+        compare_state(g, o, f"step {i}")
+    compare_state(h, p, "second population")
+    g.close()
+    h.close()
