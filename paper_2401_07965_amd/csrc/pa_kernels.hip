@@ -2994,11 +2994,11 @@ __global__ __launch_bounds__(kThreads) void k_philox_probe(uint32_t *__restrict_
 }
 
 // Whether group g's sweeps take in the spins a resampling left in the other
-// buffer (their column load gathers them) or k_gather_spins does it right
-// after the resampling: the gather in the load keeps the workgroup off the
+// buffer (their column load gathers them) or a k_gather_spins pass of the
+// resampling moves them: the gather in the load keeps the workgroup off the
 // VALU for longer, which the other resident workgroups hide only when each
 // SIMD holds four sweep waves (measured: 3D L = 10 and the uneven batch gain
-// 2-6 %, the 3D L = 16 headline with three waves per SIMD loses 1.3 %).  A
+// 2-6 %, 3D L = 16 at 256 lanes, three waves per SIMD, loses 1.3 %).  A
 // function of the group's workgroup size, which the host keeps fixed between
 // a resampling and the sweep after it.
 bool sweep_gathers(const PaBatchView &v, int g)
