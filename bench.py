@@ -400,7 +400,9 @@ def glass3d_L10_row():
     and 1, same couplings from seed 1) annealed together as a batch (one HIP
     graph): wall time, ln Q per step (every 10th step shown, from the step
     records), the energy per spin at beta = 3 and the overlap distribution
-    P(q) between A and B at beta = 3."""
+    P(q) between A and B at beta = 3; beside it the sweep kernel alone over
+    both populations, as the tuner times it at the thresholds of beta = 0.15
+    and 1.5."""
     import numpy as np
     import torch
     from paper_2401_07965_amd import pa, workloads
@@ -409,7 +411,14 @@ def glass3d_L10_row():
     sched = schedule(3.0, pts)
     cfgs = [dict(dim=d3, L=L3, R=R3, seed=1, run_id=k, couplings=J) for k in (0, 1)]
     B = pa.PABatch(cfgs, max_points=pts)
-    B.tune(THETA, 1.5)
+    # the sweep alone (both populations in one launch, every workgroup size
+    # timed by the tuner) at the thresholds of two temperatures
+    N3 = L3 ** d3
+    sweep_rate = {}
+    for beta in (0.15, 1.5):
+        chosen, tab = B.tune(THETA, beta, times=True)
+        sweep_rate[str(beta)] = {"threads": chosen[0],
+                                 "attempts_per_ns": THETA * N3 * 2 * R3 / (tab[0][chosen[0]] * 1e6)}
     B.anneal(sched, THETA, SCHEME, use_graph=True)  # capture + first launch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -419,7 +428,6 @@ def glass3d_L10_row():
     rec = B.records()
     h = B.overlap(0, 1)
     B.close()
-    N3 = L3 ** d3
     q = (2.0 * np.arange(N3 + 1) - N3) / N3
     P = h / h.sum()
     edges = np.linspace(-1, 1, 21)
@@ -429,6 +437,7 @@ def glass3d_L10_row():
                         "(run_id 0/1), theta=10, beta_i=3 i/300 (301 points), systematic, one batch "
                         "(graph replay)",
             "wall_s": wall, "attempts_per_ns": attempts / wall / 1e9,
+            "sweep_only_by_threshold_beta": sweep_rate,
             "lnQ_every_10th_step": {"A": [float(rec[0, i]["lnQ"]) for i in range(10, pts, 10)],
                                      "B": [float(rec[1, i]["lnQ"]) for i in range(10, pts, 10)]},
             "lnZ_per_spin_final": [float(rec[m, -1]["lnZ"]) / N3 for m in (0, 1)],
