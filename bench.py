@@ -61,7 +61,7 @@ COUNTER_PROFILES = {
     "fm2d_L64": os.path.join(PROFILE_DIR, "k_sweep_2d_fm_L64_R1e5_counters.md"),
 }
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2401_07965_amd", "csrc", f)
-                  for f in ("pa_kernels.hip", "pa_device.h", "pa_internal.h")]
+                  for f in ("pa_kernels.hip", "pa_sweep.h", "pa_sweep3.hip", "pa_device.h", "pa_internal.h")]
 KAUFMAN_L64 = os.path.join(ROOT, "tests", "golden", "kaufman_2d_L64.json")
 
 
@@ -74,13 +74,16 @@ def code_only(text):
 
 
 def kernel_source_hash():
-    """SHA-256 of the kernel sources' code (code_only), so that a profile
-    stays valid across comment edits."""
+    """SHA-256 of the kernel sources' code (code_only) and of the build's
+    code-generation flags, so that a profile stays valid across comment
+    edits and no longer once the generated code can differ."""
     import hashlib
+    from paper_2401_07965_amd import build as B
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(f, encoding="utf-8") as fh:
             h.update(code_only(fh.read()).encode())
+    h.update(repr((B.COMMON, sorted(B.FILE_FLAGS.items()))).encode())
     return h.hexdigest()
 
 
