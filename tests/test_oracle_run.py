@@ -143,3 +143,28 @@ def test_extinction_is_an_error_that_leaves_the_state():
             break
         run.sweep(1)
     assert died  # (1 - e^-1)^40 < 1e-7
+
+
+def test_family_statistics_closed_forms():
+    """rho_t and S_f of label sets whose family sizes are known: one family
+    (rho_t = R, S_f = 0), k equal families (rho_t = R / k, S_f = ln k), and
+    random sizes against the Shannon entropy of the family fractions as
+    scipy computes it and against sum c^2 / R counted directly."""
+    from scipy.stats import entropy
+    N, R0 = 16, 600
+    z = np.zeros(R0, np.int64)
+    one = O.population_observables(N, z, z, np.full(R0, 7, np.uint32), R0, 0.0)
+    assert one["rho_t"] == R0 and one["S_f"] == 0.0 and one["families"] == 1
+    for k in (2, 3, 5, 8):
+        lab = np.repeat(np.arange(k, dtype=np.uint32) * 11, R0 // k)
+        ob = O.population_observables(N, z[:len(lab)], z[:len(lab)], lab, R0, 0.0)
+        assert ob["rho_t"] == len(lab) / k
+        assert abs(ob["S_f"] - math.log(k)) < 1e-12
+    rng = np.random.default_rng(5)
+    for _ in range(5):
+        lab = np.sort(rng.integers(0, R0, size=R0).astype(np.uint32))
+        ob = O.population_observables(N, z, z, lab, R0, 0.0)
+        _, c = np.unique(lab, return_counts=True)
+        assert abs(ob["S_f"] - entropy(c / R0)) < 1e-12
+        assert ob["rho_t"] == sum(int(x) * int(x) for x in c) / R0
+        assert ob["families"] == len(c)
